@@ -1,0 +1,250 @@
+"""FP64 CPU oracle for the flat-sky constrained Gaussian realization fill-in.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the GPU path and imports nothing from it.
+
+Reference: Bucher & Louis, "Filling in CMB map missing data using constrained
+Gaussian realizations" (arXiv:1109.0286).
+
+What is computed (plain definitions, FP64):
+
+* Pixel model (Sec. 2.1): z = (x, y), x the masked pixels, y the observed
+  ones, z ~ N(0, C) with C = P + N.  On the periodic flat domain (Sec. 3) C is
+  circulant: C v = F^-1 [P(k) * F v] with F the unnormalised 2D DFT, so
+  C^a v = irfft2(P^a * rfft2(v)) for any power a.
+* Conditional mean, Sec. 2.1:  x_ML = -((C^-1)_xx)^-1 (C^-1)_xy y
+  = -(Px C^-1 Px)^-1 (Px C^-1 Py) y = M y.
+* Hoffman-Ribak construction, Sec. 2.3: draw an unconstrained s ~ N(0, C);
+  the constrained draw is x = s_x + M (y - s_y), y unchanged.
+* Solve of (Px C^-1 Px) u = v (eq. ModEq) by conjugate gradients on the
+  paper's split-preconditioned system (Sec. 2.4):
+  (E A E) u' = E v,  u = E u',  with A = Px C^-1 Px and E = Px C^{1/2} Px.
+
+Readings of the paper used here (ambiguous or garbled passages):
+
+* the sign of x_ML follows the Sec. 2.1 derivation (with the minus sign); the
+  introduction's version drops it;
+* the residual that decides convergence is the unpreconditioned one,
+  r = v - A u (Sec. 3 defines r = y - A x), 2-norm over masked pixels,
+  relative to ||v||, recomputed from scratch at the end;
+* initial guess u = 0;
+* the white noise is drawn with Philox4x64-10 (Salmon et al., SC'11),
+  key = (seed, stream), counter = (j, 0, 0, 0) for the pixel pair j = i // 2
+  of row-major pixel index i; each block of four words gives two normals by
+  Box-Muller, pixel 2j from words (0, 1) and pixel 2j+1 from words (2, 3),
+  u = ((w >> 11) + 0.5) * 2^-53, n = sqrt(-2 ln u_a) cos(2 pi u_b).
+"""
+
+from __future__ import annotations
+
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.fft as sfft
+
+__all__ = [
+    "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1", "REALIZATION_STREAM",
+    "philox4x64_10", "white_noise", "circulant_apply", "unconstrained_realization",
+    "rhs", "apply_A", "apply_E", "pcg_split", "fill_realize", "fill_mean", "FillResult",
+]
+
+_WORKERS = os.cpu_count() or 1
+
+# Philox4x64 round multipliers and Weyl key increments (Salmon et al. 2011).
+PHILOX_M0 = np.uint64(0xD2E7470EE14C6C93)
+PHILOX_M1 = np.uint64(0xCA5A826395121157)
+PHILOX_W0 = np.uint64(0x9E3779B97F4A7C15)
+PHILOX_W1 = np.uint64(0xBB67AE8584CAA73B)
+REALIZATION_STREAM = 0x52
+
+_LO32 = np.uint64(0xFFFFFFFF)
+_S32 = np.uint64(32)
+
+
+def _mulhilo64(a: np.ndarray, b: np.uint64) -> tuple[np.ndarray, np.ndarray]:
+    """Full 64x64 -> 128-bit product of uint64 arrays, as (hi, lo)."""
+    a0, a1 = a & _LO32, a >> _S32
+    b0, b1 = b & _LO32, b >> _S32
+    p00 = a0 * b0
+    p01 = a0 * b1
+    p10 = a1 * b0
+    p11 = a1 * b1
+    mid = (p00 >> _S32) + (p01 & _LO32) + (p10 & _LO32)
+    hi = p11 + (p01 >> _S32) + (p10 >> _S32) + (mid >> _S32)
+    lo = a * b  # wraps modulo 2^64
+    return hi, lo
+
+
+def philox4x64_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x64 with 10 rounds: counter (c0..c3), key (k0, k1) -> 4 words.
+
+    One round maps (c0, c1, c2, c3) to
+    (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)),
+    and the key is advanced by the Weyl constants between rounds.
+    """
+    with np.errstate(over="ignore"):
+        c0, c1, c2, c3 = (np.asarray(v, dtype=np.uint64).copy() for v in (c0, c1, c2, c3))
+        k0 = np.asarray(k0, dtype=np.uint64).copy()
+        k1 = np.asarray(k1, dtype=np.uint64).copy()
+        for rnd in range(10):
+            hi0, lo0 = _mulhilo64(c0, PHILOX_M0)
+            hi1, lo1 = _mulhilo64(c2, PHILOX_M1)
+            c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+            if rnd < 9:
+                k0 = k0 + PHILOX_W0
+                k1 = k1 + PHILOX_W1
+    return c0, c1, c2, c3
+
+
+def _unit_open(w: np.ndarray) -> np.ndarray:
+    """Top 53 bits of a 64-bit word, mapped to the open interval (0, 1)."""
+    return ((w >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+
+
+def white_noise(nx: int, ny: int, seed: int, stream: int = REALIZATION_STREAM) -> np.ndarray:
+    """w ~ N(0, I) on the (ny, nx) grid, from the counter-based generator above."""
+    n = nx * ny
+    assert n % 2 == 0
+    j = np.arange(n // 2, dtype=np.uint64)
+    z = np.zeros_like(j)
+    w0, w1, w2, w3 = philox4x64_10(j, z, z, z, np.uint64(seed), np.uint64(stream))
+    out = np.empty(n, dtype=np.float64)
+    out[0::2] = np.sqrt(-2.0 * np.log(_unit_open(w0))) * np.cos(2.0 * np.pi * _unit_open(w1))
+    out[1::2] = np.sqrt(-2.0 * np.log(_unit_open(w2))) * np.cos(2.0 * np.pi * _unit_open(w3))
+    return out.reshape(ny, nx)
+
+
+def _workers(n: int) -> int:
+    return _WORKERS if n >= 1 << 16 else 1
+
+
+def circulant_apply(v: np.ndarray, P: np.ndarray, power: float) -> np.ndarray:
+    """C^power v on the torus: C is diagonal, with eigenvalues P(k), in Fourier space."""
+    ny, nx = v.shape
+    wk = _workers(v.size)
+    vk = sfft.rfft2(v, workers=wk)
+    return sfft.irfft2(vk * P ** power, s=(ny, nx), workers=wk)
+
+
+def unconstrained_realization(P: np.ndarray, seed: int, stream: int = REALIZATION_STREAM) -> np.ndarray:
+    """s = C^{1/2} w, an isotropic draw with covariance C (Sec. 2.3)."""
+    ny = P.shape[0]
+    nx = 2 * (P.shape[1] - 1)
+    return circulant_apply(white_noise(nx, ny, seed, stream), P, 0.5)
+
+
+def _Px(v: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Projection onto the masked (unobserved) pixels."""
+    return np.where(mask != 0, v, 0.0)
+
+
+def _Py(v: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Projection onto the observed pixels."""
+    return np.where(mask != 0, 0.0, v)
+
+
+def apply_A(v: np.ndarray, mask: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """A v = Px C^-1 Px v, the operator of eq. ModEq."""
+    return _Px(circulant_apply(_Px(v, mask), P, -1.0), mask)
+
+
+def apply_E(v: np.ndarray, mask: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """E v = Px C^{1/2} Px v, the split preconditioner of Sec. 2.4."""
+    return _Px(circulant_apply(_Px(v, mask), P, 0.5), mask)
+
+
+def rhs(y_minus_sy: np.ndarray, mask: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """v = -Px C^-1 Py t: the right-hand side whose solution is M t (Sec. 2.1)."""
+    return -_Px(circulant_apply(_Py(y_minus_sy, mask), P, -1.0), mask)
+
+
+@dataclass
+class PCGInfo:
+    iterations: int
+    rel_residual: float
+    converged: bool
+    history: list
+
+
+def pcg_split(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
+              max_iter: int = 20000, history: bool = False) -> tuple[np.ndarray, PCGInfo]:
+    """Solve A u = v with CG on the split system (E A E) u' = E v, u = E u' (Sec. 2.4).
+
+    Plain Hestenes-Stiefel CG on the symmetric positive definite operator
+    E A E restricted to the masked pixels.  Alongside u' the routine carries
+    u = E u' and the unpreconditioned residual v - A u (both are linear in the
+    CG updates), stops when that residual is below rtol * ||v||, and then
+    recomputes it from scratch; if the recomputed residual is still too large
+    it restarts CG from the current u.
+    """
+    vnorm = float(np.linalg.norm(v))
+    u = np.zeros_like(v)
+    hist = []
+    total = 0
+    if vnorm == 0.0:
+        return u, PCGInfo(0, 0.0, True, hist)
+    res = v.copy()
+    for _restart in range(20):
+        # CG on E A E d' = E res, accumulating d = E d' into u.
+        r = apply_E(res, mask, P)
+        p = r.copy()
+        rr = float(np.vdot(r, r))
+        done = False
+        while total < max_iter:
+            Ep = apply_E(p, mask, P)
+            AEp = apply_A(Ep, mask, P)
+            q = apply_E(AEp, mask, P)
+            alpha = rr / float(np.vdot(p, q))
+            u += alpha * Ep
+            res -= alpha * AEp
+            r -= alpha * q
+            total += 1
+            rel = float(np.linalg.norm(res)) / vnorm
+            if history:
+                hist.append(rel)
+            if rel <= rtol:
+                done = True
+                break
+            rr_new = float(np.vdot(r, r))
+            p = r + (rr_new / rr) * p
+            rr = rr_new
+        res = v - apply_A(u, mask, P)
+        rel = float(np.linalg.norm(res)) / vnorm
+        if rel <= rtol or not done:
+            return u, PCGInfo(total, rel, rel <= rtol, hist)
+    return u, PCGInfo(total, rel, rel <= rtol, hist)
+
+
+@dataclass
+class FillResult:
+    x_out: np.ndarray   # filled map: observed pixels = d_obs, masked = s + u
+    s: np.ndarray       # unconstrained realization
+    u: np.ndarray       # M (y - s_y), zero outside the mask
+    info: PCGInfo
+
+
+def fill_realize(d_obs: np.ndarray, mask: np.ndarray, P: np.ndarray, seed: int,
+                 rtol: float, max_iter: int = 20000) -> FillResult:
+    """Constrained realization by the Hoffman-Ribak construction (Sec. 2.3).
+
+    s = C^{1/2} w; t = Py (d_obs - s); v = -Px C^-1 t; solve A u = v;
+    x_out = d_obs on observed pixels and s + u on masked pixels.
+    """
+    s = unconstrained_realization(P, seed)
+    t = _Py(d_obs - s, mask)
+    v = rhs(t, mask, P)
+    u, info = pcg_split(v, mask, P, rtol, max_iter)
+    x = np.where(mask != 0, s + u, d_obs)
+    return FillResult(x, s, u, info)
+
+
+def fill_mean(d_obs: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
+              max_iter: int = 20000) -> FillResult:
+    """The conditional mean (Wiener fill) x_ML = M y on masked pixels (Sec. 2.1)."""
+    t = _Py(d_obs, mask)
+    v = rhs(t, mask, P)
+    u, info = pcg_split(v, mask, P, rtol, max_iter)
+    x = np.where(mask != 0, u, d_obs)
+    return FillResult(x, np.zeros_like(d_obs), u, info)
