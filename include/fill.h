@@ -1,0 +1,167 @@
+/*
+ * fill.h -- C ABI of the MI355X (gfx950) constrained-Gaussian-realization
+ * fill-in of masked maps on the periodic flat sky.
+ *
+ * Method: Bucher & Louis, "Filling in CMB map missing data using constrained
+ * Gaussian realizations", arXiv:1109.0286.
+ *
+ * Problem statement (Sec. 2.1): a map z = (x, y) on an nx-by-ny periodic grid
+ * is Gaussian with covariance C = P + N; x are the masked (unobserved)
+ * pixels, y the observed ones.  On the torus (Sec. 3) C is circulant and
+ * diagonal in Fourier space, with eigenvalue P(k) at integer frequency k.
+ * fill_realize returns a draw of x from P(x | y) by the Hoffman-Ribak
+ * construction (Sec. 2.3): an unconstrained draw s ~ N(0, C), then
+ * x = s_x + M (y - s_y) with M = -(Px C^-1 Px)^-1 (Px C^-1 Py) (Sec. 2.1),
+ * where the masked-pixel system (Px C^-1 Px) u = v (eq. ModEq) is solved by
+ * conjugate gradients preconditioned with E = Px C^{1/2} Px (Sec. 2.4).
+ *
+ * Layouts and ownership (all calls):
+ *   - maps are double, ny rows of nx pixels, row-major, pixel (y, x) at
+ *     index y*nx + x;
+ *   - mask is uint8, same layout, nonzero = masked (unobserved);
+ *   - the spectrum table Pk is double, ny rows of nx/2+1 entries: entry
+ *     [iy*(nx/2+1) + ix] is P at frequency (ky, kx) with kx = ix and
+ *     ky = iy for iy <= ny/2, iy - ny otherwise; P(k) is the eigenvalue of C
+ *     under the unnormalised 2D DFT (pixel variance = mean of P over the
+ *     full frequency grid);
+ *   - "host" pointers are read during the call and copied; the library keeps
+ *     no reference to them;
+ *   - "device" pointers are HIP device memory owned by the caller (e.g. torch
+ *     tensors), valid for the duration of the call; the library never frees
+ *     them;
+ *   - every GPU step runs on the stream given at plan creation; calls that
+ *     return a result synchronise that stream before returning.
+ *
+ * Errors: negative return codes (enum fill_status), never exceptions; the
+ * text of a code is fill_strerror(code); fill_last_error() gives details of
+ * the last failure on the calling thread.
+ */
+#ifndef FILL_H
+#define FILL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fill_plan_s* fill_plan;
+
+enum fill_status {
+  FILL_OK = 0,
+  FILL_EINVAL = -1,             /* bad argument (null pointer, size, rtol <= 0, ...) */
+  FILL_ENOMEM = -2,             /* device or host allocation failed */
+  FILL_EHIP = -3,               /* a HIP runtime call failed */
+  FILL_ENOCONV = -4,            /* max iterations reached; outputs hold the best iterate */
+  FILL_EUNSUPPORTED_SIZE = -5,  /* nx or ny not a supported FFT length */
+  FILL_ENOTSPD = -6             /* P(k) <= 0 or not finite, or p.Ap <= 0 in CG */
+};
+
+enum fill_precision {
+  FILL_PREC_FP64 = 0,    /* every operator apply, vector and scalar in FP64 */
+  FILL_PREC_FP32_OP = 1  /* FP32 FFT/operator/CG vectors inside CG; FP64 dot products,
+                            scalars, true residual and refinement correction */
+};
+
+/* Operators on full maps for fill_apply (Sec. 2.4 notation). */
+enum fill_op {
+  FILL_OP_CINV = 0,   /* out = C^-1 in */
+  FILL_OP_CHALF = 1,  /* out = C^{1/2} in */
+  FILL_OP_A = 2,      /* out = Px C^-1 Px in   (zero on observed pixels) */
+  FILL_OP_E = 3       /* out = Px C^{1/2} Px in (zero on observed pixels) */
+};
+
+typedef struct fill_stats {
+  int iters_inner;       /* CG iterations summed over refinement steps, last solve */
+  int iters_outer;       /* refinement (true-residual) steps, last solve */
+  int n_masked;          /* masked pixel count of the plan */
+  int status;            /* fill_status of the last solve */
+  double rel_resid;      /* true FP64 ||v - A u|| / ||v|| at return, last solve */
+  double solve_ms;       /* wall time of the last solve, host clock */
+} fill_stats;
+
+/*
+ * Supported grid sizes: nx and ny each one of 16, 32, 64, 128, 256, 512,
+ * 768, 1024, 2048, 4096 (FFT lengths built into the library); else
+ * FILL_EUNSUPPORTED_SIZE.
+ */
+int fill_supported_size(int n);
+
+/*
+ * Create a plan for an nx-by-ny grid (Sec. 2.1 problem statement; Sec. 3
+ * periodic flat domain).
+ *   mask      host, ny*nx uint8, nonzero = masked.
+ *   Pk        host, ny*(nx/2+1) doubles, every entry > 0 and finite
+ *             (else FILL_ENOTSPD).  Must satisfy P(-k) = P(k) on the
+ *             kx = 0 and kx = nx/2 columns (any function of |k| does).
+ *   prec      enum fill_precision.
+ *   stream    hipStream_t to run on (NULL = the null stream).
+ *   out       receives the plan; *out is NULL on error.
+ * The plan holds the device copies of the mask, the spectral tables 1/P and
+ * sqrt(P) in FP64 and FP32, and all workspaces; it is used from one host
+ * thread at a time.
+ */
+int fill_plan_create(int nx, int ny, const uint8_t* mask, const double* Pk, int prec,
+                     void* stream, fill_plan* out);
+
+/* Replace the spectrum of an existing plan (host Pk, same layout/rules). */
+int fill_plan_set_pk(fill_plan plan, const double* Pk);
+
+/* Iteration cap of the CG solves (default 20000 summed over refinement steps). */
+int fill_plan_set_max_iter(fill_plan plan, int max_iter);
+
+/* Release every resource of the plan (NULL is accepted). */
+void fill_plan_destroy(fill_plan plan);
+
+/*
+ * Constrained Gaussian realization (Sec. 2.3, Hoffman-Ribak construction).
+ *   d_obs   device, ny*nx doubles; values on masked pixels are ignored (may be
+ *           0 or NaN, Sec. 3 sets them to zero).
+ *   seed    key of the white noise: Philox4x64-10, key (seed, 0x52), counter
+ *           (j, 0, 0, 0) for pixel pair j = i/2 of row-major index i, two
+ *           normals per block by Box-Muller (words 0,1 -> pixel 2j,
+ *           words 2,3 -> pixel 2j+1, u = ((w >> 11) + 0.5) 2^-53).
+ *   x_out   device, ny*nx doubles (may not alias d_obs): observed pixels are
+ *           bitwise copies of d_obs; masked pixels are s + u with s = C^{1/2} w
+ *           and u = M (y - s_y).
+ *   rtol    > 0: stop when the true FP64 residual ||v - A u||_2 <= rtol ||v||_2
+ *           over masked pixels, v = -Px C^-1 Py (y - s).
+ * Returns FILL_OK, FILL_ENOCONV (x_out holds the best iterate) or an error.
+ */
+int fill_realize(fill_plan plan, const double* d_obs, uint64_t seed, double* x_out, double rtol);
+
+/* Conditional mean / Wiener fill x_ML = M y (Sec. 2.1): as fill_realize with s = 0. */
+int fill_mean(fill_plan plan, const double* d_obs, double* x_out, double rtol);
+
+/* Statistics of the last solve on this plan. */
+int fill_get_stats(fill_plan plan, fill_stats* out);
+
+/*
+ * Apply one operator of enum fill_op to a full map (device in/out, ny*nx
+ * doubles, may not alias) in precision prec (enum fill_precision; FP32
+ * rounds the input to float and returns the float result widened).  The
+ * operators are the ones every CG iteration applies (Sec. 2.4).
+ */
+int fill_apply(fill_plan plan, int op, int prec, const double* in, double* out);
+
+/* The unconstrained draw s = C^{1/2} w for a seed (device out, ny*nx). */
+int fill_realize_unconstrained(fill_plan plan, uint64_t seed, double* out);
+
+/*
+ * Raw Philox4x64-10 words (Salmon et al. 2011) for counters (j, 0, 0, 0),
+ * j = 0..n_blocks-1, key (seed, stream): out is device, 4*n_blocks uint64,
+ * block j at out[4j..4j+3].  Runs on the null stream and synchronises.
+ */
+int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t* out);
+
+/* Text for a status code. */
+const char* fill_strerror(int code);
+
+/* Detail of the last error raised on this host thread ("" if none). */
+const char* fill_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FILL_H */

@@ -1,0 +1,329 @@
+// Device-side building blocks of the 2D real FFT used by every operator apply
+// of the fill-in (Sec. 2.4: each apply of C^-1, C^{1/2} on the torus is a
+// forward FFT, a diagonal multiply and an inverse FFT; the torus DFT is exactly
+// unitary, Sec. 4).
+//
+// One "line" is a complex sequence of length N held across TPL = N/E threads,
+// E elements per thread, thread tid holding elements tid + e*TPL (e < E).  A
+// transform is a sequence of Stockham autosort passes of radix R (R | E): each
+// thread runs E/R radix-R butterflies in registers on its own elements, and
+// between passes the line is exchanged through LDS into the next pass's order.
+// The first pass consumes, and the last pass produces, the natural strided
+// order, so global loads/stores before and after a transform are coalesced and
+// need no LDS round trip.  Forward transforms use exp(-2 pi i jk/N), inverse
+// ones exp(+2 pi i jk/N), both unnormalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fillk {
+
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <typename T> using cplx = typename cvec<T>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+
+// a * (DIR * i): DIR = -1 forward, +1 inverse
+template <int DIR, typename C> __device__ __forceinline__ C mul_di(C a) {
+  if constexpr (DIR < 0) return C{a.y, -a.x};
+  else return C{-a.y, a.x};
+}
+
+// a * w (forward) or a * conj(w) (inverse), w from the table exp(-2 pi i t/N)
+template <int DIR, typename C> __device__ __forceinline__ C twmul(C a, C w) {
+  if constexpr (DIR < 0) return C{a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x};
+  else return C{a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+
+// ---------------------------------------------------------------------------
+// small DFT kernels on registers, sign DIR
+// ---------------------------------------------------------------------------
+
+template <int DIR, typename C> __device__ __forceinline__ void dft2(C& a0, C& a1) {
+  C t = a0;
+  a0 = cadd(t, a1);
+  a1 = csub(t, a1);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+  C t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  C t2 = cadd(a1, a3), t3 = mul_di<DIR>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft3(C& a0, C& a1, C& a2) {
+  using T = decltype(a0.x);
+  const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+  C t1 = cadd(a1, a2);
+  C t2 = mul_di<DIR>(csub(a1, a2));
+  t2.x *= h;
+  t2.y *= h;
+  C m = C{a0.x - T(0.5) * t1.x, a0.y - T(0.5) * t1.y};
+  a0 = cadd(a0, t1);
+  a1 = cadd(m, t2);
+  a2 = csub(m, t2);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C (&a)[8]) {
+  using T = decltype(a[0].x);
+  const T r = T(0.70710678118654752440084436210485);  // 1/sqrt(2)
+  // even and odd halves as radix-4 transforms
+  dft4<DIR>(a[0], a[2], a[4], a[6]);
+  dft4<DIR>(a[1], a[3], a[5], a[7]);
+  // odd half times w8^k, w8 = exp(DIR 2 pi i / 8)
+  C o1 = a[3], o2 = a[5], o3 = a[7];
+  // w8^1 = (r, DIR r)
+  o1 = C{r * (o1.x - T(DIR) * o1.y), r * (o1.y + T(DIR) * o1.x)};
+  // w8^2 = DIR i
+  o2 = mul_di<DIR>(o2);
+  // w8^3 = (-r, DIR r)
+  o3 = C{-r * (o3.x + T(DIR) * o3.y), r * (T(DIR) * o3.x - o3.y)};
+  C e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  C o0 = a[1];
+  a[0] = cadd(e0, o0);
+  a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1);
+  a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2);
+  a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3);
+  a[7] = csub(e3, o3);
+}
+
+template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C (&a)[R]) {
+  if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
+  else if constexpr (R == 3) dft3<DIR>(a[0], a[1], a[2]);
+  else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
+  else if constexpr (R == 8) dft8<DIR>(a);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// radix plans: E elements per thread, radices dividing E, product = N
+// ---------------------------------------------------------------------------
+
+template <int... Rs> struct RadixList {
+  static constexpr int NP = sizeof...(Rs);
+  static constexpr int radix(int p) {
+    constexpr int r[] = {Rs...};
+    return r[p];
+  }
+};
+template <int N> struct FFTPlan;
+template <> struct FFTPlan<16> : RadixList<4, 4> { static constexpr int E = 8; };
+template <> struct FFTPlan<32> : RadixList<8, 4> { static constexpr int E = 8; };
+template <> struct FFTPlan<64> : RadixList<8, 8> { static constexpr int E = 8; };
+template <> struct FFTPlan<128> : RadixList<8, 8, 2> { static constexpr int E = 16; };
+template <> struct FFTPlan<256> : RadixList<8, 8, 4> { static constexpr int E = 16; };
+template <> struct FFTPlan<512> : RadixList<8, 8, 8> { static constexpr int E = 16; };
+template <> struct FFTPlan<768> : RadixList<8, 8, 4, 3> { static constexpr int E = 24; };
+template <> struct FFTPlan<1024> : RadixList<8, 8, 4, 4> { static constexpr int E = 16; };
+template <> struct FFTPlan<2048> : RadixList<8, 8, 8, 4> { static constexpr int E = 16; };
+template <> struct FFTPlan<4096> : RadixList<8, 8, 8, 8> { static constexpr int E = 16; };
+
+template <int N, int P = 0> constexpr int plan_product() {
+  if constexpr (P == FFTPlan<N>::NP) return 1;
+  else return FFTPlan<N>::radix(P) * plan_product<N, P + 1>();
+}
+template <int N, int P = 0> constexpr bool plan_divides_E() {
+  if constexpr (P == FFTPlan<N>::NP) return true;
+  else return (FFTPlan<N>::E % FFTPlan<N>::radix(P) == 0) && plan_divides_E<N, P + 1>();
+}
+
+// LDS index padding: one spare element every 32 breaks the power-of-two
+// strides of the Stockham scatter across LDS banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+template <int N> constexpr int lds_line_elems() { return N + N / 32; }
+
+// One Stockham pass in registers (butterflies j = tid + b*TPL, b < E/R).
+template <typename C, int N, int E, int R, int NS, int DIR>
+__device__ __forceinline__ void stockham_pass(C (&v)[E], int tid, const C* __restrict__ tw) {
+  constexpr int TPL = N / E;
+  constexpr int B = E / R;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    C a[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[i] = v[b + i * B];
+    if constexpr (NS > 1) {
+      const int j = tid + b * TPL;
+      const int k = j % NS;
+      constexpr int STRIDE = N / (NS * R);
+#pragma unroll
+      for (int i = 1; i < R; ++i) a[i] = twmul<DIR>(a[i], tw[i * k * STRIDE]);
+    }
+    dft<R, DIR>(a);
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[b + i * B] = a[i];
+  }
+}
+
+// Scatter the pass outputs y[(j/NS)*NS*R + j%NS + i*NS] to LDS, gather the
+// next pass's inputs x[tid + e*TPL].
+template <typename C, int N, int E, int R, int NS>
+__device__ __forceinline__ void stockham_exchange(C (&v)[E], int tid, C* lds) {
+  constexpr int TPL = N / E;
+  constexpr int B = E / R;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = tid + b * TPL;
+    const int k = j % NS;
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int i = 0; i < R; ++i) lds[lpad(base + i * NS)] = v[b + i * B];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = lds[lpad(tid + e * TPL)];
+  __syncthreads();
+}
+
+// Full length-N transform of one line; v holds x[tid + e*TPL] on entry and
+// X[tid + e*TPL] on exit.  Every thread of the workgroup must call it (it
+// contains workgroup barriers).
+template <typename C, int N, int DIR, int P = 0, int NS = 1>
+__device__ __forceinline__ void fft_line(C (&v)[FFTPlan<N>::E], int tid, C* lds, const C* __restrict__ tw) {
+  using PL = FFTPlan<N>;
+  static_assert(plan_product<N>() == N, "radix plan does not multiply to N");
+  static_assert(plan_divides_E<N>(), "every radix must divide E");
+  constexpr int R = PL::radix(P);
+  stockham_pass<C, N, PL::E, R, NS, DIR>(v, tid, tw);
+  if constexpr (P + 1 < PL::NP) {
+    stockham_exchange<C, N, PL::E, R, NS>(v, tid, lds);
+    fft_line<C, N, DIR, P + 1, NS * R>(v, tid, lds, tw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch geometry per (precision, length)
+// ---------------------------------------------------------------------------
+
+// Row kernels: ROWS image rows per workgroup (two rows per complex line), the
+// workgroup's LDS held near 64 KiB so two workgroups fit a CU.
+template <typename T, int N> struct RowCfg {
+  static constexpr int E = FFTPlan<N>::E;
+  static constexpr int TPL = N / E;
+  static constexpr int RAW = (64 * 1024) / (N * (int)sizeof(T));
+  static constexpr int ROWS = RAW >= 16 ? 16 : RAW >= 8 ? 8 : RAW >= 4 ? 4 : 2;  // power of two
+  static constexpr int LINES = ROWS / 2;
+  static constexpr int THREADS = LINES * TPL;
+  static constexpr int H = N / 2 + 1;
+};
+
+// Column kernel: W spectral columns (lines of length N = ny) per workgroup.
+template <typename T, int N> struct ColCfg {
+  static constexpr int E = FFTPlan<N>::E;
+  static constexpr int TPL = N / E;
+  static constexpr int RAW = (64 * 1024) / (N * 2 * (int)sizeof(T));
+  static constexpr int W0 = RAW > 16 ? 16 : (RAW < 1 ? 1 : RAW);
+  static constexpr int W = (W0 * TPL > 1024) ? (1024 / TPL) : W0;
+  static constexpr int THREADS = W * TPL;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of work items so neighbouring row blocks (which share
+// cache lines of the transposed spectrum) meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  constexpr int NX = 8;
+  const int q = nblk / NX, r = nblk % NX;
+  const int xcd = bid % NX, slot = bid / NX;
+  return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller normals
+// ---------------------------------------------------------------------------
+
+struct u64x4 { uint64_t w0, w1, w2, w3; };
+
+__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  return u64x4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ double unit_open(uint64_t w) {
+  return ((double)(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+// Standard normal at row-major pixel index i for (seed, stream).
+__device__ __forceinline__ double white_noise_at(uint64_t i, uint64_t seed, uint64_t stream) {
+  const u64x4 w = philox4x64_10(i >> 1, 0, 0, 0, seed, stream);
+  const uint64_t a = (i & 1) ? w.w2 : w.w0;
+  const uint64_t b = (i & 1) ? w.w3 : w.w1;
+  return sqrt(-2.0 * log(unit_open(a))) * cos(2.0 * 3.14159265358979323846 * unit_open(b));
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic workgroup sum of two values; result valid in thread 0.
+// Workgroups narrower than a wave go through LDS only (a 64-lane shuffle
+// would read inactive lanes).
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  if constexpr (NT % 64 == 0) {
+    constexpr int NW = NT / 64;
+    __shared__ double red[2][NW];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+      red[0][w] = a;
+      red[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sa = 0.0, sb = 0.0;
+      for (int i = 0; i < NW; ++i) {
+        sa += red[0][i];
+        sb += red[1][i];
+      }
+      a = sa;
+      b = sb;
+    }
+  } else {
+    __shared__ double red[2][NT];
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sa = 0.0, sb = 0.0;
+      for (int i = 0; i < NT; ++i) {
+        sa += red[0][i];
+        sb += red[1][i];
+      }
+      a = sa;
+      b = sb;
+    }
+  }
+}
+
+}  // namespace fillk

@@ -1,0 +1,249 @@
+"""ctypes binding of libfill.so (the C ABI declared in include/fill.h).
+
+Argument marshalling only: every step of the fill runs in the HIP kernels of
+the library.  The functions keep the C names; `Plan` is a small owner of a
+fill_plan handle that passes torch tensors' device pointers and the current
+HIP stream through.  If the library is missing this module raises at import:
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfill.so")
+
+FILL_OK = 0
+FILL_EINVAL = -1
+FILL_ENOMEM = -2
+FILL_EHIP = -3
+FILL_ENOCONV = -4
+FILL_EUNSUPPORTED_SIZE = -5
+FILL_ENOTSPD = -6
+
+FILL_PREC_FP64 = 0
+FILL_PREC_FP32_OP = 1
+
+FILL_OP_CINV = 0
+FILL_OP_CHALF = 1
+FILL_OP_A = 2
+FILL_OP_E = 3
+
+# every symbol include/fill.h declares
+EXPORTS = (
+    "fill_supported_size", "fill_plan_create", "fill_plan_set_pk", "fill_plan_set_max_iter",
+    "fill_plan_destroy", "fill_realize", "fill_mean", "fill_get_stats", "fill_apply",
+    "fill_realize_unconstrained", "fill_philox_words", "fill_strerror", "fill_last_error",
+)
+
+
+class fill_stats(C.Structure):
+    _fields_ = [("iters_inner", C.c_int), ("iters_outer", C.c_int), ("n_masked", C.c_int),
+                ("status", C.c_int), ("rel_resid", C.c_double), ("solve_ms", C.c_double)]
+
+
+class FillError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {_strerror(code)} ({code}): {detail}")
+        self.code = code
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1109_0286_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, u64, dbl = C.c_void_p, C.c_int, C.c_uint64, C.c_double
+    sig = {
+        "fill_supported_size": (i32, [i32]),
+        "fill_plan_create": (i32, [i32, i32, vp, vp, i32, vp, C.POINTER(vp)]),
+        "fill_plan_set_pk": (i32, [vp, vp]),
+        "fill_plan_set_max_iter": (i32, [vp, i32]),
+        "fill_plan_destroy": (None, [vp]),
+        "fill_realize": (i32, [vp, vp, u64, vp, dbl]),
+        "fill_mean": (i32, [vp, vp, vp, dbl]),
+        "fill_get_stats": (i32, [vp, C.POINTER(fill_stats)]),
+        "fill_apply": (i32, [vp, i32, i32, vp, vp]),
+        "fill_realize_unconstrained": (i32, [vp, u64, vp]),
+        "fill_philox_words": (i32, [u64, u64, C.c_int64, vp]),
+        "fill_strerror": (C.c_char_p, [i32]),
+        "fill_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _strerror(code: int) -> str:
+    return _lib.fill_strerror(code).decode()
+
+
+def _check(code: int, where: str, ok=(FILL_OK,)) -> int:
+    if code not in ok:
+        raise FillError(code, where, _lib.fill_last_error().decode())
+    return code
+
+
+# ---- raw C names -----------------------------------------------------------
+
+def fill_supported_size(n: int) -> bool:
+    return bool(_lib.fill_supported_size(int(n)))
+
+
+def fill_plan_create(nx, ny, mask, Pk, prec, stream) -> int:
+    """mask: host uint8 (ny, nx); Pk: host float64 (ny, nx//2+1); stream: int handle or None."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    p = np.ascontiguousarray(Pk, dtype=np.float64)
+    if m.shape != (ny, nx) or p.shape != (ny, nx // 2 + 1):
+        raise ValueError(f"mask {m.shape} / Pk {p.shape} do not match grid {nx}x{ny}")
+    h = C.c_void_p()
+    _check(_lib.fill_plan_create(nx, ny, m.ctypes.data, p.ctypes.data, prec, stream or None, C.byref(h)),
+           "fill_plan_create")
+    return h.value
+
+
+def fill_plan_set_pk(plan, Pk):
+    p = np.ascontiguousarray(Pk, dtype=np.float64)
+    return _check(_lib.fill_plan_set_pk(plan, p.ctypes.data), "fill_plan_set_pk")
+
+
+def fill_plan_set_max_iter(plan, max_iter):
+    return _check(_lib.fill_plan_set_max_iter(plan, int(max_iter)), "fill_plan_set_max_iter")
+
+
+def fill_plan_destroy(plan):
+    _lib.fill_plan_destroy(plan)
+
+
+def fill_realize(plan, d_obs_ptr, seed, x_out_ptr, rtol, allow_noconv=False):
+    ok = (FILL_OK, FILL_ENOCONV) if allow_noconv else (FILL_OK,)
+    return _check(_lib.fill_realize(plan, d_obs_ptr, C.c_uint64(seed), x_out_ptr, float(rtol)), "fill_realize", ok)
+
+
+def fill_mean(plan, d_obs_ptr, x_out_ptr, rtol, allow_noconv=False):
+    ok = (FILL_OK, FILL_ENOCONV) if allow_noconv else (FILL_OK,)
+    return _check(_lib.fill_mean(plan, d_obs_ptr, x_out_ptr, float(rtol)), "fill_mean", ok)
+
+
+def fill_get_stats(plan) -> dict:
+    s = fill_stats()
+    _check(_lib.fill_get_stats(plan, C.byref(s)), "fill_get_stats")
+    return {k: getattr(s, k) for k, _ in fill_stats._fields_}
+
+
+def fill_apply(plan, op, prec, in_ptr, out_ptr):
+    return _check(_lib.fill_apply(plan, op, prec, in_ptr, out_ptr), "fill_apply")
+
+
+def fill_realize_unconstrained(plan, seed, out_ptr):
+    return _check(_lib.fill_realize_unconstrained(plan, C.c_uint64(seed), out_ptr), "fill_realize_unconstrained")
+
+
+def fill_philox_words(seed, stream, n_blocks, out_ptr):
+    return _check(_lib.fill_philox_words(C.c_uint64(seed), C.c_uint64(stream), int(n_blocks), out_ptr),
+                  "fill_philox_words")
+
+
+def fill_strerror(code: int) -> str:
+    return _strerror(code)
+
+
+def fill_last_error() -> str:
+    return _lib.fill_last_error().decode()
+
+
+# ---- torch convenience -----------------------------------------------------
+
+def _dev_ptr(t, dtype=None):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+class Plan:
+    """Owner of a fill_plan bound to a torch device stream."""
+
+    def __init__(self, nx, ny, mask, Pk, prec=FILL_PREC_FP64, stream=None, device=None):
+        import torch
+        self.device = torch.device(device or "cuda")
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = s
+            if hasattr(mask, "cpu"):
+                mask = mask.cpu().numpy()
+            if hasattr(Pk, "cpu"):
+                Pk = Pk.cpu().numpy()
+            self.nx, self.ny, self.prec = nx, ny, prec
+            self.handle = fill_plan_create(nx, ny, mask, Pk, prec, s.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fill_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_pk(self, Pk):
+        if hasattr(Pk, "cpu"):
+            Pk = Pk.cpu().numpy()
+        fill_plan_set_pk(self.handle, Pk)
+
+    def set_max_iter(self, n):
+        fill_plan_set_max_iter(self.handle, n)
+
+    def _new_map(self):
+        import torch
+        return torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+    def realize(self, d_obs, seed, rtol, out=None, allow_noconv=False):
+        import torch
+        out = self._new_map() if out is None else out
+        fill_realize(self.handle, _dev_ptr(d_obs, torch.float64), seed, _dev_ptr(out, torch.float64), rtol,
+                     allow_noconv)
+        return out
+
+    def mean(self, d_obs, rtol, out=None, allow_noconv=False):
+        import torch
+        out = self._new_map() if out is None else out
+        fill_mean(self.handle, _dev_ptr(d_obs, torch.float64), _dev_ptr(out, torch.float64), rtol, allow_noconv)
+        return out
+
+    def apply(self, op, x, prec=None, out=None):
+        import torch
+        out = self._new_map() if out is None else out
+        fill_apply(self.handle, op, self.prec if prec is None else prec, _dev_ptr(x, torch.float64),
+                   _dev_ptr(out, torch.float64))
+        return out
+
+    def realize_unconstrained(self, seed, out=None):
+        import torch
+        out = self._new_map() if out is None else out
+        fill_realize_unconstrained(self.handle, seed, _dev_ptr(out, torch.float64))
+        return out
+
+    def stats(self) -> dict:
+        return fill_get_stats(self.handle)
+
+
+def philox_words(seed, stream, n_blocks, device="cuda"):
+    import torch
+    out = torch.empty(4 * n_blocks, dtype=torch.int64, device=device)
+    fill_philox_words(seed, stream, n_blocks, out.data_ptr())
+    return out
