@@ -110,6 +110,13 @@ int fill_plan_set_pk(fill_plan plan, const double* Pk);
 /* Iteration cap of the CG solves (default 20000 summed over refinement steps). */
 int fill_plan_set_max_iter(fill_plan plan, int max_iter);
 
+/*
+ * Relative tolerance of each FP32-operator inner CG solve between FP64
+ * residual recomputations (FILL_PREC_FP32_OP only; default 1e-4, must lie in
+ * (0, 1)).  Smaller values mean fewer refinement steps, each longer.
+ */
+int fill_plan_set_inner_tol(fill_plan plan, double tol);
+
 /* Release every resource of the plan (NULL is accepted). */
 void fill_plan_destroy(fill_plan plan);
 
@@ -153,6 +160,22 @@ int fill_realize_unconstrained(fill_plan plan, uint64_t seed, double* out);
  * block j at out[4j..4j+3].  Runs on the null stream and synchronises.
  */
 int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t* out);
+
+/* Kernels that fill_time_kernel can time (one operator apply, Sec. 2.4). */
+enum fill_kernel {
+  FILL_K_R2C = 0,    /* row pass: compact masked vector -> transposed half spectrum */
+  FILL_K_COL = 1,    /* column pass: FFT along y, times 1/P, inverse FFT along y */
+  FILL_K_C2R = 2,    /* row pass: half spectrum -> masked pixels (compact) */
+  FILL_K_APPLY = 3   /* the three in sequence: one apply of A = Px C^-1 Px */
+};
+
+/*
+ * Measurement helper: launch one kernel of the A apply `reps` times on the
+ * plan's stream with the arguments a CG iteration uses, bracketed by HIP
+ * events on that stream; *avg_ms = elapsed / reps.  prec selects the FP64 or
+ * FP32 kernels.  Overwrites the plan's workspaces (not d_obs/x_out).
+ */
+int fill_time_kernel(fill_plan plan, int kernel, int prec, int reps, double* avg_ms);
 
 /* Text for a status code. */
 const char* fill_strerror(int code);

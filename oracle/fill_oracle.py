@@ -50,7 +50,8 @@ __all__ = [
     "rhs", "apply_A", "apply_E", "pcg_split", "fill_realize", "fill_mean", "FillResult",
 ]
 
-_WORKERS = os.cpu_count() or 1
+# FFT threads: ORACLE_WORKERS if set, else every core this process may run on.
+_WORKERS = int(os.environ.get("ORACLE_WORKERS", "0")) or len(os.sched_getaffinity(0)) or 1
 
 # Philox4x64 round multipliers and Weyl key increments (Salmon et al. 2011).
 PHILOX_M0 = np.uint64(0xD2E7470EE14C6C93)

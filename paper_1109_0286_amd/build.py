@@ -2,7 +2,7 @@
 
 Every source under csrc/ is compiled with hipcc for gfx950 into
 _build/*.o (in parallel) and linked into libfill.so next to this file.
-Usage: python -m paper_1109_0286_amd.build  (or build() from Python).
+Usage: python paper_1109_0286_amd/build.py  (runs without importing the package).
 """
 
 from __future__ import annotations

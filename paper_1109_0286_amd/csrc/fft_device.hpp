@@ -97,11 +97,49 @@ template <int DIR, typename C> __device__ __forceinline__ void dft8(C (&a)[8]) {
   a[7] = csub(e3, o3);
 }
 
+// a * (cr + i*DIR*ci), a constant twiddle of sign DIR
+template <int DIR, typename C, typename T>
+__device__ __forceinline__ C cmulc(C a, T cr, T ci) {
+  return C{a.x * cr - T(DIR) * ci * a.y, a.y * cr + T(DIR) * ci * a.x};
+}
+
+// 16-point DFT as 4 x 4: inner DFT4 over n1 (n = 4 n1 + n2), twiddle
+// w16^(n2 k1), outer DFT4 over n2; output index k = k1 + 4 k2.
+template <int DIR, typename C> __device__ __forceinline__ void dft16(C (&a)[16]) {
+  using T = decltype(a[0].x);
+  const T c1 = T(0.92387953251128675612818318939679);  // cos(pi/8)
+  const T s1 = T(0.38268343236508977172845998403040);  // sin(pi/8)
+  const T r = T(0.70710678118654752440084436210485);   // cos(pi/4)
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<DIR>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
+  // a[4*k1 + n2] now holds Y[n2][k1]; apply w16^(n2 k1) = exp(DIR 2 pi i n2 k1 / 16)
+  a[5] = cmulc<DIR>(a[5], c1, s1);     // n2=1,k1=1: w^1
+  a[9] = cmulc<DIR>(a[9], r, r);       // n2=1,k1=2: w^2
+  a[13] = cmulc<DIR>(a[13], s1, c1);   // n2=1,k1=3: w^3
+  a[6] = cmulc<DIR>(a[6], r, r);       // n2=2,k1=1: w^2
+  a[10] = mul_di<DIR>(a[10]);          // n2=2,k1=2: w^4
+  a[14] = cmulc<DIR>(a[14], -r, r);    // n2=2,k1=3: w^6
+  a[7] = cmulc<DIR>(a[7], s1, c1);     // n2=3,k1=1: w^3
+  a[11] = cmulc<DIR>(a[11], -r, r);    // n2=3,k1=2: w^6
+  a[15] = cmulc<DIR>(a[15], -c1, -s1); // n2=3,k1=3: w^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<DIR>(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+  // a[4*k1 + k2] holds X[k1 + 4 k2]: transpose the 4x4 index
+  C t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = a[i];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[4 * k1 + k2];
+}
+
 template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C (&a)[R]) {
   if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
   else if constexpr (R == 3) dft3<DIR>(a[0], a[1], a[2]);
   else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
   else if constexpr (R == 8) dft8<DIR>(a);
+  else if constexpr (R == 16) dft16<DIR>(a);
   else static_assert(R == 2, "unsupported radix");
 }
 
@@ -117,16 +155,16 @@ template <int... Rs> struct RadixList {
   }
 };
 template <int N> struct FFTPlan;
-template <> struct FFTPlan<16> : RadixList<4, 4> { static constexpr int E = 8; };
+template <> struct FFTPlan<16> : RadixList<16> { static constexpr int E = 16; };
 template <> struct FFTPlan<32> : RadixList<8, 4> { static constexpr int E = 8; };
 template <> struct FFTPlan<64> : RadixList<8, 8> { static constexpr int E = 8; };
-template <> struct FFTPlan<128> : RadixList<8, 8, 2> { static constexpr int E = 16; };
-template <> struct FFTPlan<256> : RadixList<8, 8, 4> { static constexpr int E = 16; };
-template <> struct FFTPlan<512> : RadixList<8, 8, 8> { static constexpr int E = 16; };
+template <> struct FFTPlan<128> : RadixList<16, 8> { static constexpr int E = 16; };
+template <> struct FFTPlan<256> : RadixList<16, 16> { static constexpr int E = 16; };
+template <> struct FFTPlan<512> : RadixList<16, 16, 2> { static constexpr int E = 16; };
 template <> struct FFTPlan<768> : RadixList<8, 8, 4, 3> { static constexpr int E = 24; };
-template <> struct FFTPlan<1024> : RadixList<8, 8, 4, 4> { static constexpr int E = 16; };
-template <> struct FFTPlan<2048> : RadixList<8, 8, 8, 4> { static constexpr int E = 16; };
-template <> struct FFTPlan<4096> : RadixList<8, 8, 8, 8> { static constexpr int E = 16; };
+template <> struct FFTPlan<1024> : RadixList<16, 16, 4> { static constexpr int E = 16; };
+template <> struct FFTPlan<2048> : RadixList<16, 16, 8> { static constexpr int E = 16; };
+template <> struct FFTPlan<4096> : RadixList<16, 16, 16> { static constexpr int E = 16; };
 
 template <int N, int P = 0> constexpr int plan_product() {
   if constexpr (P == FFTPlan<N>::NP) return 1;
@@ -137,14 +175,49 @@ template <int N, int P = 0> constexpr bool plan_divides_E() {
   else return (FFTPlan<N>::E % FFTPlan<N>::radix(P) == 0) && plan_divides_E<N, P + 1>();
 }
 
-// LDS index padding: one spare element every 32 breaks the power-of-two
-// strides of the Stockham scatter across LDS banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
-template <int N> constexpr int lds_line_elems() { return N + N / 32; }
+// LDS index padding: one spare element every R0 elements (R0 = the first
+// radix) turns the first pass's stride-R0 scatter into distinct banks.
+template <int N> constexpr int lds_pad_shift() { return FFTPlan<N>::radix(0) >= 16 ? 4 : 3; }
+template <int N> __device__ __forceinline__ int lpad(int i) { return i + (i >> lds_pad_shift<N>()); }
+template <int N> constexpr int lds_line_elems() { return N + (N >> lds_pad_shift<N>()); }
+
+// Twiddles.  Pass p (radix R, NS = product of the earlier radices, S =
+// N/(NS R)) needs w(i, k) = exp(-2 pi i * i k S / N) for k = j mod NS.  With
+// k = klo + 16 khi the table stores LO[i][klo] = w(i, klo) and, when NS > 16,
+// HI[i][khi] = w(i, 16 khi), so w(i, k) = LO[i][klo] * HI[i][khi]: lanes with
+// consecutive j read consecutive LO entries and share HI entries, which keeps
+// the LDS reads free of bank conflicts.  Passes with NS = 1 need no table.
+template <int N> constexpr int pass_ns(int p) {
+  int s = 1;
+  for (int q = 0; q < p; ++q) s *= FFTPlan<N>::radix(q);
+  return s;
+}
+template <int N> constexpr int tw_pass_size(int p) {
+  const int R = FFTPlan<N>::radix(p), ns = pass_ns<N>(p);
+  if (ns == 1) return 0;
+  return R * 16 + (ns > 16 ? R * (ns / 16) : 0);
+}
+template <int N> constexpr int tw_pass_off(int p) {
+  int o = 0;
+  for (int q = 0; q < p; ++q) o += tw_pass_size<N>(q);
+  return o;
+}
+template <int N> constexpr int tw_elems() { return tw_pass_off<N>(FFTPlan<N>::NP); }
+
+// Copy the whole twiddle table from global memory into LDS; callers place a
+// barrier between this and the first use.
+template <int N, typename C>
+__device__ __forceinline__ void tw_stage(C* q, const C* __restrict__ tw, int t, int nt) {
+  for (int i = t; i < tw_elems<N>(); i += nt) q[i] = tw[i];
+}
+
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
 
 // One Stockham pass in registers (butterflies j = tid + b*TPL, b < E/R).
-template <typename C, int N, int E, int R, int NS, int DIR>
-__device__ __forceinline__ void stockham_pass(C (&v)[E], int tid, const C* __restrict__ tw) {
+template <typename C, int N, int E, int P, int R, int NS, int DIR>
+__device__ __forceinline__ void stockham_pass(C (&v)[E], int tid, const C* tw) {
   constexpr int TPL = N / E;
   constexpr int B = E / R;
 #pragma unroll
@@ -155,9 +228,13 @@ __device__ __forceinline__ void stockham_pass(C (&v)[E], int tid, const C* __res
     if constexpr (NS > 1) {
       const int j = tid + b * TPL;
       const int k = j % NS;
-      constexpr int STRIDE = N / (NS * R);
+      const C* lo = tw + tw_pass_off<N>(P) + (k & 15);
 #pragma unroll
-      for (int i = 1; i < R; ++i) a[i] = twmul<DIR>(a[i], tw[i * k * STRIDE]);
+      for (int i = 1; i < R; ++i) {
+        C w = lo[16 * i];
+        if constexpr (NS > 16) w = cmul(w, tw[tw_pass_off<N>(P) + 16 * R + i * (NS / 16) + (k >> 4)]);
+        a[i] = twmul<DIR>(a[i], w);
+      }
     }
     dft<R, DIR>(a);
 #pragma unroll
@@ -177,24 +254,24 @@ __device__ __forceinline__ void stockham_exchange(C (&v)[E], int tid, C* lds) {
     const int k = j % NS;
     const int base = (j / NS) * NS * R + k;
 #pragma unroll
-    for (int i = 0; i < R; ++i) lds[lpad(base + i * NS)] = v[b + i * B];
+    for (int i = 0; i < R; ++i) lds[lpad<N>(base + i * NS)] = v[b + i * B];
   }
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = lds[lpad(tid + e * TPL)];
+  for (int e = 0; e < E; ++e) v[e] = lds[lpad<N>(tid + e * TPL)];
   __syncthreads();
 }
 
 // Full length-N transform of one line; v holds x[tid + e*TPL] on entry and
-// X[tid + e*TPL] on exit.  Every thread of the workgroup must call it (it
-// contains workgroup barriers).
+// X[tid + e*TPL] on exit; tw is the LDS twiddle table.  Every thread of
+// the workgroup must call it (it contains workgroup barriers).
 template <typename C, int N, int DIR, int P = 0, int NS = 1>
-__device__ __forceinline__ void fft_line(C (&v)[FFTPlan<N>::E], int tid, C* lds, const C* __restrict__ tw) {
+__device__ __forceinline__ void fft_line(C (&v)[FFTPlan<N>::E], int tid, C* lds, const C* tw) {
   using PL = FFTPlan<N>;
   static_assert(plan_product<N>() == N, "radix plan does not multiply to N");
   static_assert(plan_divides_E<N>(), "every radix must divide E");
   constexpr int R = PL::radix(P);
-  stockham_pass<C, N, PL::E, R, NS, DIR>(v, tid, tw);
+  stockham_pass<C, N, PL::E, P, R, NS, DIR>(v, tid, tw);
   if constexpr (P + 1 < PL::NP) {
     stockham_exchange<C, N, PL::E, R, NS>(v, tid, lds);
     fft_line<C, N, DIR, P + 1, NS * R>(v, tid, lds, tw);
@@ -210,32 +287,47 @@ __device__ __forceinline__ void fft_line(C (&v)[FFTPlan<N>::E], int tid, C* lds,
 template <typename T, int N> struct RowCfg {
   static constexpr int E = FFTPlan<N>::E;
   static constexpr int TPL = N / E;
-  static constexpr int RAW = (64 * 1024) / (N * (int)sizeof(T));
+  static constexpr int RAW = (64 * 1024) / (N * 8);
   static constexpr int ROWS = RAW >= 16 ? 16 : RAW >= 8 ? 8 : RAW >= 4 ? 4 : 2;  // power of two
+  // consecutive row blocks that share a 128-byte line of the transposed spectrum
+  static constexpr int XG0 = 128 / (ROWS * 2 * (int)sizeof(T));
+  static constexpr int XG = XG0 < 1 ? 1 : XG0;
   static constexpr int LINES = ROWS / 2;
   static constexpr int THREADS = LINES * TPL;
   static constexpr int H = N / 2 + 1;
+  // Row stride of the transposed-spectrum staging buffer in LDS.  Lanes of
+  // one LDS cycle (256 bytes: G complex values) read ROWS rows at G/ROWS
+  // consecutive kx; a stride congruent to G/ROWS modulo G puts them in
+  // distinct banks.
+  static constexpr int G = 256 / (2 * (int)sizeof(T));
+  static constexpr int GR = G / ROWS > 0 ? G / ROWS : 1;
+  static constexpr int HS = H + ((GR - H % G) % G + G) % G;
 };
 
 // Column kernel: W spectral columns (lines of length N = ny) per workgroup.
 template <typename T, int N> struct ColCfg {
   static constexpr int E = FFTPlan<N>::E;
   static constexpr int TPL = N / E;
-  static constexpr int RAW = (64 * 1024) / (N * 2 * (int)sizeof(T));
+  static constexpr int RAW = (64 * 1024) / (N * 16);
   static constexpr int W0 = RAW > 16 ? 16 : (RAW < 1 ? 1 : RAW);
   static constexpr int W = (W0 * TPL > 1024) ? (1024 / TPL) : W0;
   static constexpr int THREADS = W * TPL;
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of work items so neighbouring row blocks (which share
-// cache lines of the transposed spectrum) meet in the same L2.
+// Workgroups are dispatched round-robin over the 8 XCDs.  Row blocks are
+// handed out in groups of G neighbours (G blocks fill whole 128-byte lines of
+// the transposed spectrum, so a group meets in one XCD's L2) and the groups go
+// round-robin over the XCDs, which spreads a band of heavy rows over all of
+// them.  Grids that are not a multiple of 8 G blocks keep the identity map.
+template <int G>
 __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
-  constexpr int NX = 8;
-  const int q = nblk / NX, r = nblk % NX;
-  const int xcd = bid % NX, slot = bid / NX;
-  return xcd * q + (xcd < r ? xcd : r) + slot;
+  if (nblk % (8 * G)) return bid;
+  const int x = bid & 7, s = bid >> 3;
+  return G * ((s / G) * 8 + x) + (s % G);
 }
+
+// Loads batched ahead of their uses: U elements per thread in flight.
+constexpr int kBatch = 8;
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller normals

@@ -93,6 +93,7 @@ struct fill_plan_s {
   Vecs<float> v32;
   double* part0 = nullptr;
   double* part1 = nullptr;
+  double* part2 = nullptr;
   double* dsum = nullptr;
   CGScalars* sc = nullptr;
   CGScalars* h_sc = nullptr;
@@ -155,12 +156,32 @@ int apply3(fill_plan p, int rm, const RowArgs<T>& ai, const T* D, int cm, const 
   ColArgs<T> ca;
   ca.Xt = static_cast<cplx<T>*>(p->Xt);
   ca.ldx = p->ny;
-  ca.ncol = p->ncol;
+  ca.ncol = p->nx / 2;  // the Nyquist column travels in column 0
   ca.D = D;
   ca.tw = TypeSel<T>::twy(p);
   ca.sc = sc;
   HIP_TRY(launch_col<T>(p->ny, ca, p->stream));
   HIP_TRY(launch_c2r<T>(cm, ao, p->stream));
+  return FILL_OK;
+}
+
+// Two applies of E in a row, E (E u): r2c (mode rm) -> column pass (sqrt P)
+// -> projection row pass -> column pass (sqrt P) -> c2r (C2R_DOT2).
+template <typename T>
+int apply_EE(fill_plan p, int rm, const RowArgs<T>& ai, const RowArgs<T>& amid, const RowArgs<T>& ao,
+             const CGScalars* sc) {
+  HIP_TRY(launch_r2c<T>(rm, ai, p->stream));
+  ColArgs<T> ca;
+  ca.Xt = static_cast<cplx<T>*>(p->Xt);
+  ca.ldx = p->ny;
+  ca.ncol = p->nx / 2;
+  ca.D = TypeSel<T>::Dhalf(p);
+  ca.tw = TypeSel<T>::twy(p);
+  ca.sc = sc;
+  HIP_TRY(launch_col<T>(p->ny, ca, p->stream));
+  HIP_TRY(launch_proj<T>(amid, p->stream));
+  HIP_TRY(launch_col<T>(p->ny, ca, p->stream));
+  HIP_TRY(launch_c2r<T>(C2R_DOT2, ao, p->stream));
   return FILL_OK;
 }
 
@@ -183,52 +204,57 @@ int inner_pcg(fill_plan p, double tol, int cap, int* iters, int* status) {
   HIP_TRY(hipMemsetAsync(v.x, 0, vb, p->stream));
   HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
 
-  // z = E (E r), rho = r.z, rr = r.r
-  RowArgs<T> a_in = row_base<T>(p), a_out = row_base<T>(p);
+  // z = E (E r); its partial sums (r.z, r.r) feed the first iteration
+  RowArgs<T> a_in = row_base<T>(p), a_mid = row_base<T>(p), a_out = row_base<T>(p);
   a_in.v0 = v.r;
-  a_out.v0 = v.t;
-  FILL_TRY(apply3<T>(p, R2C_COMPACT, a_in, Dhalf, C2R_COMPACT, a_out, nullptr));
-  a_in.v0 = v.t;
   a_out.v0 = v.z;
   a_out.v1 = v.r;
   a_out.part0 = p->part0;
   a_out.part1 = p->part1;
-  FILL_TRY(apply3<T>(p, R2C_COMPACT, a_in, Dhalf, C2R_DOT2, a_out, nullptr));
-  HIP_TRY(launch_cg_init(p->sc, p->part0, p->part1, nb, tol * tol, cap, p->stream));
+  FILL_TRY(apply_EE<T>(p, R2C_COMPACT, a_in, a_mid, a_out, nullptr));
+  HIP_TRY(launch_cg_init(p->sc, tol * tol, cap, p->stream));
 
-  // per-iteration argument sets (all read the device scalars)
-  RowArgs<T> pa_in = row_base<T>(p), pa_out = row_base<T>(p);
-  pa_in.v0 = v.z;
-  pa_in.v1 = v.p;
-  pa_in.sc = p->sc;
+  // Iteration k (parity k % 2), all scalars on the device:
+  //   q = A p, with beta = (r.z)/rho and p = z + beta p fused in front
+  //       (partials of r.z, r.r from the previous E E r pass), p.q behind;
+  //   z = E E r, with alpha = rho/(p.q), x += alpha p, r -= alpha q fused in
+  //       front, r.z and r.r behind.
+  RowArgs<T> pa_in[2], pa_out = row_base<T>(p), e_in[2], e_mid = row_base<T>(p), e_out = row_base<T>(p);
+  for (int par = 0; par < 2; ++par) {
+    pa_in[par] = row_base<T>(p);
+    pa_in[par].v0 = v.z;
+    pa_in[par].v1 = v.p;
+    pa_in[par].sc = p->sc;
+    pa_in[par].red0 = p->part0;
+    pa_in[par].red1 = p->part1;
+    pa_in[par].nred = nb;
+    pa_in[par].parity = par;
+    e_in[par] = row_base<T>(p);
+    e_in[par].v0 = v.x;
+    e_in[par].v1 = v.r;
+    e_in[par].v2 = v.p;
+    e_in[par].v3 = v.q;
+    e_in[par].sc = p->sc;
+    e_in[par].red0 = p->part2;
+    e_in[par].nred = nb;
+    e_in[par].parity = par;
+  }
   pa_out.v0 = v.q;
   pa_out.v1 = v.p;
-  pa_out.part0 = p->part0;
+  pa_out.part0 = p->part2;
   pa_out.sc = p->sc;
-  RowArgs<T> e1_in = row_base<T>(p), e1_out = row_base<T>(p);
-  e1_in.v0 = v.x;
-  e1_in.v1 = v.r;
-  e1_in.v2 = v.p;
-  e1_in.v3 = v.q;
-  e1_in.sc = p->sc;
-  e1_out.v0 = v.t;
-  e1_out.sc = p->sc;
-  RowArgs<T> e2_in = row_base<T>(p), e2_out = row_base<T>(p);
-  e2_in.v0 = v.t;
-  e2_in.sc = p->sc;
-  e2_out.v0 = v.z;
-  e2_out.v1 = v.r;
-  e2_out.part0 = p->part0;
-  e2_out.part1 = p->part1;
-  e2_out.sc = p->sc;
+  e_mid.sc = p->sc;
+  e_out.v0 = v.z;
+  e_out.v1 = v.r;
+  e_out.part0 = p->part0;
+  e_out.part1 = p->part1;
+  e_out.sc = p->sc;
 
   for (;;) {
     for (int k = 0; k < kChunk; ++k) {
-      FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in, Dinv, C2R_COMPACT, pa_out, p->sc));
-      HIP_TRY(launch_cg_alpha(p->sc, p->part0, nb, p->stream));
-      FILL_TRY(apply3<T>(p, R2C_XRUPDATE, e1_in, Dhalf, C2R_COMPACT, e1_out, p->sc));
-      FILL_TRY(apply3<T>(p, R2C_COMPACT, e2_in, Dhalf, C2R_DOT2, e2_out, p->sc));
-      HIP_TRY(launch_cg_beta(p->sc, p->part0, p->part1, nb, p->stream));
+      const int par = k & 1;
+      FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc));
+      FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
     }
     HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -304,17 +330,43 @@ bool size_ok(int n) {
   return false;
 }
 
-// exp(-2 pi i t / n), t = 0..n-1, to double rounding (long double evaluation).
-void twiddles(int n, std::vector<double2>& w64, std::vector<float2>& w32) {
-  w64.resize(n);
-  w32.resize(n);
+// Twiddle table of the length-N transform in the per-pass LO/HI layout the
+// kernels read (see fft_device.hpp), each entry exp(-2 pi i t/N) evaluated in
+// long double and rounded to double (and to float for the FP32 kernels).
+template <int N> void make_twiddles(std::vector<double2>& w64, std::vector<float2>& w32) {
+  const int total = std::max(tw_elems<N>(), 1);
+  w64.assign(total, double2{1.0, 0.0});
+  w32.assign(total, float2{1.0f, 0.0f});
   const long double pi = 3.141592653589793238462643383279502884L;
-  for (int t = 0; t < n; ++t) {
-    const long double a = 2.0L * pi * (long double)t / (long double)n;
-    const double c = (double)cosl(a), s = (double)-sinl(a);
-    w64[t] = double2{c, s};
-    w32[t] = float2{(float)c, (float)s};
+  auto put = [&](int idx, long long t) {
+    t %= N;
+    const long double a = 2.0L * pi * (long double)t / (long double)N;
+    const double c = (double)cosl(a), sn = (double)-sinl(a);
+    w64[idx] = double2{c, sn};
+    w32[idx] = float2{(float)c, (float)sn};
+  };
+  for (int p = 0; p < FFTPlan<N>::NP; ++p) {
+    const int ns = pass_ns<N>(p);
+    if (ns == 1) continue;
+    const int R = FFTPlan<N>::radix(p), S = N / (ns * R), off = tw_pass_off<N>(p);
+    for (int i = 0; i < R; ++i)
+      for (int klo = 0; klo < 16; ++klo) put(off + 16 * i + klo, (long long)i * klo * S);
+    if (ns > 16)
+      for (int i = 0; i < R; ++i)
+        for (int khi = 0; khi < ns / 16; ++khi) put(off + 16 * R + i * (ns / 16) + khi, 16LL * i * khi * S);
   }
+}
+
+int twiddles(int n, std::vector<double2>& w64, std::vector<float2>& w32) {
+  switch (n) {
+#define FILL_CASE(nn) \
+  case nn:            \
+    make_twiddles<nn>(w64, w32); \
+    return FILL_OK;
+    FILL_FOR_EACH_N(FILL_CASE)
+#undef FILL_CASE
+  }
+  return fail(FILL_EUNSUPPORTED_SIZE, "no FFT plan for length " + std::to_string(n));
 }
 
 int upload_pk(fill_plan p, const double* Pk) {
@@ -369,10 +421,14 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   FILL_TRY(dalloc(p, &p->Dhalf64, nt));
   FILL_TRY(dalloc(p, &p->Dinv32, nt));
   FILL_TRY(dalloc(p, &p->Dhalf32, nt));
-  FILL_TRY(dalloc(p, &p->twx64, nx));
-  FILL_TRY(dalloc(p, &p->twy64, ny));
-  FILL_TRY(dalloc(p, &p->twx32, nx));
-  FILL_TRY(dalloc(p, &p->twy32, ny));
+  std::vector<double2> twx64, twy64;
+  std::vector<float2> twx32, twy32;
+  FILL_TRY(twiddles(nx, twx64, twx32));
+  FILL_TRY(twiddles(ny, twy64, twy32));
+  FILL_TRY(dalloc(p, &p->twx64, twx64.size()));
+  FILL_TRY(dalloc(p, &p->twy64, twy64.size()));
+  FILL_TRY(dalloc(p, &p->twx32, twx32.size()));
+  FILL_TRY(dalloc(p, &p->twy32, twy32.size()));
   double2* xt = nullptr;
   FILL_TRY(dalloc(p, &xt, nt));
   p->Xt = xt;
@@ -384,6 +440,7 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   for (float** q : {&p->v32.x, &p->v32.r, &p->v32.z, &p->v32.p, &p->v32.q, &p->v32.t}) FILL_TRY(dalloc(p, q, nm));
   FILL_TRY(dalloc(p, &p->part0, ny));
   FILL_TRY(dalloc(p, &p->part1, ny));
+  FILL_TRY(dalloc(p, &p->part2, ny));
   FILL_TRY(dalloc(p, &p->dsum, 4));
   FILL_TRY(dalloc(p, &p->sc, 1));
   HIP_TRY(hipHostMalloc((void**)&p->h_sc, sizeof(CGScalars), hipHostMallocDefault));
@@ -392,14 +449,10 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   HIP_TRY(hipMemcpy(p->mask, m01.data(), npix, hipMemcpyHostToDevice));
   if (!pos.empty()) HIP_TRY(hipMemcpy(p->pos, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->row_off, row_off.data(), (ny + 1) * sizeof(int), hipMemcpyHostToDevice));
-  std::vector<double2> w64;
-  std::vector<float2> w32;
-  twiddles(nx, w64, w32);
-  HIP_TRY(hipMemcpy(p->twx64, w64.data(), nx * sizeof(double2), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->twx32, w32.data(), nx * sizeof(float2), hipMemcpyHostToDevice));
-  twiddles(ny, w64, w32);
-  HIP_TRY(hipMemcpy(p->twy64, w64.data(), ny * sizeof(double2), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->twy32, w32.data(), ny * sizeof(float2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->twx64, twx64.data(), twx64.size() * sizeof(double2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->twx32, twx32.data(), twx32.size() * sizeof(float2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->twy64, twy64.data(), twy64.size() * sizeof(double2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->twy32, twy32.data(), twy32.size() * sizeof(float2), hipMemcpyHostToDevice));
   return upload_pk(p, Pk);
 }
 
@@ -422,6 +475,49 @@ int rhs_solve_assemble(fill_plan p, double* x_out, double rtol) {
 
 using clk = std::chrono::steady_clock;
 
+}  // namespace
+
+namespace {
+template <typename T>
+int time_kernel(fill_plan p, int kernel, int reps, double* avg_ms) {
+  Vecs<T>& v = TypeSel<T>::vecs(p);
+  const size_t vb = (size_t)std::max(p->n_m, 1) * sizeof(T);
+  HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
+  RowArgs<T> ai = row_base<T>(p), ao = row_base<T>(p);
+  ai.v0 = v.p;
+  ao.v0 = v.q;
+  ao.v1 = v.p;
+  ao.part0 = p->part0;
+  ColArgs<T> ca;
+  ca.Xt = static_cast<cplx<T>*>(p->Xt);
+  ca.ldx = p->ny;
+  ca.ncol = p->nx / 2;
+  ca.D = TypeSel<T>::Dinv(p);
+  ca.tw = TypeSel<T>::twy(p);
+  ca.sc = nullptr;
+  auto launch = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (kernel == FILL_K_R2C || kernel == FILL_K_APPLY) e = launch_r2c<T>(R2C_COMPACT, ai, p->stream);
+    if (e == hipSuccess && (kernel == FILL_K_COL || kernel == FILL_K_APPLY)) e = launch_col<T>(p->ny, ca, p->stream);
+    if (e == hipSuccess && (kernel == FILL_K_C2R || kernel == FILL_K_APPLY))
+      e = launch_c2r<T>(C2R_COMPACT, ao, p->stream);
+    return e;
+  };
+  HIP_TRY(launch());  // warm-up
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, p->stream));
+  for (int i = 0; i < reps; ++i) HIP_TRY(launch());
+  HIP_TRY(hipEventRecord(e1, p->stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return FILL_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -472,6 +568,12 @@ int fill_plan_set_pk(fill_plan p, const double* Pk) {
 int fill_plan_set_max_iter(fill_plan p, int max_iter) {
   if (!p || max_iter < 1) return fail(FILL_EINVAL, "bad argument");
   p->max_iter = max_iter;
+  return FILL_OK;
+}
+
+int fill_plan_set_inner_tol(fill_plan p, double tol) {
+  if (!p || !(tol > 0.0) || !(tol < 1.0)) return fail(FILL_EINVAL, "inner tolerance must be in (0, 1)");
+  p->inner_tol32 = tol;
   return FILL_OK;
 }
 
@@ -597,6 +699,15 @@ int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t
   HIP_TRY(launch_philox_words(out, seed, stream, n_blocks, nullptr));
   HIP_TRY(hipStreamSynchronize(nullptr));
   return FILL_OK;
+}
+
+int fill_time_kernel(fill_plan p, int kernel, int prec, int reps, double* avg_ms) {
+  g_last_error.clear();
+  if (!p || !avg_ms || reps < 1) return fail(FILL_EINVAL, "bad argument");
+  if (kernel < FILL_K_R2C || kernel > FILL_K_APPLY) return fail(FILL_EINVAL, "unknown kernel");
+  if (prec == FILL_PREC_FP64) return time_kernel<double>(p, kernel, reps, avg_ms);
+  if (prec == FILL_PREC_FP32_OP) return time_kernel<float>(p, kernel, reps, avg_ms);
+  return fail(FILL_EINVAL, "unknown precision");
 }
 
 const char* fill_strerror(int code) {

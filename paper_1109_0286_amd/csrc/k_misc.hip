@@ -16,73 +16,23 @@ __device__ double fixed_sum(const double* part, int n) {
   block_sum2<RT>(v, w);
   return v;  // valid in thread 0
 }
-__device__ void fixed_sum2(const double* p0, const double* p1, int n, double& a, double& b) {
-  a = 0.0;
-  b = 0.0;
-  for (int i = threadIdx.x; i < n; i += RT) {
-    a += p0[i];
-    b += p1[i];
-  }
-  block_sum2<RT>(a, b);
-}
 }  // namespace
 
-__global__ __launch_bounds__(RT) void k_cg_init(CGScalars* sc, const double* rz, const double* rr, int n,
-                                                double tol2, int max_iter) {
-  double a, b;
-  fixed_sum2(rz, rr, n, a, b);
+// Start of an inner solve: rho[0] = 1 so that the first iteration's
+// p = z + beta p (p = 0) is p = z for any finite beta.
+__global__ void k_cg_init(CGScalars* sc, double tol2, int max_iter) {
   if (threadIdx.x == 0) {
-    sc->rho = a;
-    sc->rr = b;
+    sc->rho[0] = 1.0;
+    sc->rho[1] = 1.0;
     sc->alpha = 0.0;
     sc->beta = 0.0;
-    sc->pq = 0.0;
+    sc->rr = 0.0;
     sc->tol2 = tol2;
+    sc->done = 0;
     sc->iter = 0;
     sc->max_iter = max_iter;
     sc->status = 0;
-    sc->done = 0;
-    if (b <= tol2) sc->done = 1;
-    else if (!(a > 0.0)) {
-      sc->done = 1;
-      sc->status = -6;
-    }
-  }
-}
-
-__global__ __launch_bounds__(RT) void k_cg_alpha(CGScalars* sc, const double* pq, int n) {
-  if (sc->done) return;
-  const double s = fixed_sum(pq, n);
-  if (threadIdx.x == 0) {
-    sc->pq = s;
-    if (!(s > 0.0)) {  // A not positive definite on this direction, or NaN
-      sc->done = 1;
-      sc->status = -6;
-    } else {
-      sc->alpha = sc->rho / s;
-    }
-  }
-}
-
-__global__ __launch_bounds__(RT) void k_cg_beta(CGScalars* sc, const double* rz, const double* rr, int n) {
-  if (sc->done) return;
-  double a, b;
-  fixed_sum2(rz, rr, n, a, b);
-  if (threadIdx.x == 0) {
-    sc->iter += 1;
-    sc->rr = b;
-    if (b <= sc->tol2) {
-      sc->done = 1;
-    } else if (!(a > 0.0)) {
-      sc->done = 1;
-      sc->status = -6;
-    } else if (sc->iter >= sc->max_iter) {
-      sc->done = 1;
-      sc->status = -4;
-    } else {
-      sc->beta = a / sc->rho;
-      sc->rho = a;
-    }
+    sc->cap = 0;
   }
 }
 
@@ -147,17 +97,8 @@ inline dim3 grid_for(size_t n) {
 }
 }  // namespace
 
-hipError_t launch_cg_init(CGScalars* sc, const double* rz, const double* rr, int n, double tol2, int max_iter,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(RT), 0, s, sc, rz, rr, n, tol2, max_iter);
-  return hipGetLastError();
-}
-hipError_t launch_cg_alpha(CGScalars* sc, const double* pq, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(RT), 0, s, sc, pq, n);
-  return hipGetLastError();
-}
-hipError_t launch_cg_beta(CGScalars* sc, const double* rz, const double* rr, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(RT), 0, s, sc, rz, rr, n);
+hipError_t launch_cg_init(CGScalars* sc, double tol2, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, s, sc, tol2, max_iter);
   return hipGetLastError();
 }
 hipError_t launch_sum(double* out, const double* part, int n, hipStream_t s) {

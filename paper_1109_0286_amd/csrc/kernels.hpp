@@ -20,19 +20,21 @@
 
 namespace fillk {
 
-// Scalars of one conjugate-gradient solve, resident on the device.
+// Scalars of one conjugate-gradient solve, resident on the device.  rho is
+// double-buffered by iteration parity: the kernel that forms rho_new reads
+// rho[parity] while its workgroup 0 stores rho[parity ^ 1].
 struct CGScalars {
-  double rho;    // r.z
-  double alpha;  // rho / (p.q)
-  double beta;   // rho_new / rho_old
-  double pq;
-  double rr;     // r.r of the recursive residual
-  double tol2;   // stop when rr <= tol2
-  double spare0, spare1;
-  int done;      // set when converged, failed or capped: every kernel then returns at once
-  int iter;
+  double rho[2];  // r.z
+  double alpha;   // rho / (p.q)
+  double beta;    // rho_new / rho_old
+  double rr;      // r.r of the recursive residual
+  double tol2;    // stop when rr <= tol2
+  int done;       // set when converged, failed or capped: every kernel then returns at once
+  int iter;       // completed iterations
   int max_iter;
-  int status;    // 0 ok, -4 iteration cap, -6 p.q <= 0 or r.z <= 0
+  int status;     // 0 ok, -4 iteration cap, -6 p.q <= 0 or r.z <= 0
+  int cap;        // iteration cap reached; the next iteration stops
+  int pad;
 };
 
 enum R2CMode {
@@ -44,7 +46,7 @@ enum R2CMode {
 };
 
 enum C2RMode {
-  C2R_COMPACT = 0,   // v0[c] = scale*val; part0 += v0[c] * (v1 ? v1[c] : v0[c])
+  C2R_COMPACT = 0,   // v0[c] = scale*val; if part0: part0 += v0[c] * (v1 ? v1[c] : v0[c])
   C2R_DOT2 = 1,      // v0[c] = val; part0 += v1[c]*val, part1 += v1[c]^2
   C2R_RESID = 2,     // v0[c] = v1[c] - val; part0 += v0[c]^2
   C2R_REALIZE = 3,   // s = val; full_out = mask ? s : d, full_out2 = mask ? 0 : d - s (d = full_in)
@@ -62,9 +64,13 @@ template <typename T> struct RowArgs {
   T* v2;
   T* v3;
   T scale;
-  const CGScalars* sc;
+  CGScalars* sc;
   double* part0;
   double* part1;
+  const double* red0;  // partial sums of the previous row pass (CG scalar inputs)
+  const double* red1;
+  int nred;
+  int parity;          // iteration parity (selects the rho buffer)
   const double* full_in;
   double* full_out;
   double* full_out2;
@@ -80,6 +86,70 @@ template <typename T> struct ColArgs {
   const CGScalars* sc;
 };
 
+// One CG scalar step, taken redundantly by every workgroup of the row pass
+// that needs it: the previous pass's per-workgroup partial sums are added in
+// a fixed order, so every workgroup obtains the same bits; workgroup 0 alone
+// persists the new state.  Returns the coefficient (beta or alpha), or sets
+// *stop when the solve ends here.
+//   PUPDATE (start of an iteration): rz = r.z, rr = r.r from the previous
+//     E E r pass; stop if rr <= tol2, if the cap was reached or rz <= 0;
+//     beta = rz / rho[parity]; rho[parity^1] = rz.
+//   XRUPDATE: pq = p.q from the A apply; stop if pq <= 0;
+//     alpha = rho[parity^1] / pq; iter += 1.
+template <int MODE, int NT, typename T>
+__device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop) {
+  __shared__ double s_coef;
+  __shared__ int s_stop;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < a.nred; i += NT) {
+    s0 += a.red0[i];
+    if constexpr (MODE == 1) s1 += a.red1[i];
+  }
+  block_sum2<NT>(s0, s1);
+  if (threadIdx.x == 0) {
+    CGScalars* sc = a.sc;
+    const bool w = (blockIdx.x == 0);
+    int st = 0, stat = 0;
+    double coef = 0.0;
+    if constexpr (MODE == 1) {  // PUPDATE
+      const double rz = s0, rr = s1;
+      if (rr <= sc->tol2) st = 1;
+      else if (sc->cap) { st = 1; stat = -4; }
+      else if (!(rz > 0.0)) { st = 1; stat = -6; }
+      coef = rz / sc->rho[a.parity];
+      if (w) {
+        sc->rr = rr;
+        if (st) {
+          sc->status = stat;
+          sc->done = 1;
+        } else {
+          sc->rho[a.parity ^ 1] = rz;
+          sc->beta = coef;
+        }
+      }
+    } else {  // XRUPDATE
+      const double pq = s0;
+      if (!(pq > 0.0)) { st = 1; stat = -6; }
+      coef = sc->rho[a.parity ^ 1] / pq;
+      if (w) {
+        if (st) {
+          sc->status = stat;
+          sc->done = 1;
+        } else {
+          sc->alpha = coef;
+          sc->iter += 1;
+          if (sc->iter >= sc->max_iter) sc->cap = 1;
+        }
+      }
+    }
+    s_coef = coef;
+    s_stop = st;
+  }
+  __syncthreads();
+  *stop = s_stop != 0;
+  return s_coef;
+}
+
 template <int MODE> constexpr bool r2c_is_compact() { return MODE <= R2C_XRUPDATE; }
 template <int MODE> constexpr bool c2r_is_compact() { return MODE <= C2R_RESID; }
 
@@ -94,10 +164,11 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   constexpr int LE = lds_line_elems<N>();
   constexpr int LDS_C = (CF::LINES * LE > (ROWS * N) / 2) ? CF::LINES * LE : (ROWS * N) / 2;
   __shared__ C lds[LDS_C];
+  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
   T* ldr = reinterpret_cast<T*>(lds);
   if (a.sc != nullptr && a.sc->done) return;
 
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
   const int y0 = blk * ROWS;
   const int t = threadIdx.x;
   const int l = t / TPL, tid = t % TPL;
@@ -105,30 +176,51 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   C v[E];
 
   if constexpr (r2c_is_compact<MODE>()) {
+    T coef = T(0);
+    if constexpr (MODE == R2C_PUPDATE || MODE == R2C_XRUPDATE) {
+      bool stop = false;
+      coef = (T)cg_scalar_step<MODE, NT>(a, &stop);
+      if (stop) return;
+    }
     const int c0 = a.row_off[y0], c1 = a.row_off[y0 + ROWS];
     if (c0 == c1) {  // no masked pixel in these rows: the spectrum is zero
-      for (int o = t; o < ROWS * H; o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
+      for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
       return;
     }
+    tw_stage<N>(twq, a.tw, t, NT);
     for (int i = t; i < ROWS * N; i += NT) ldr[i] = T(0);
     __syncthreads();
-    T coef = T(0);
-    if constexpr (MODE == R2C_PUPDATE) coef = (T)a.sc->beta;
-    if constexpr (MODE == R2C_XRUPDATE) coef = (T)a.sc->alpha;
     const int base = y0 * a.nx;
-    for (int c = c0 + t; c < c1; c += NT) {
-      T val;
-      if constexpr (MODE == R2C_COMPACT) {
-        val = a.v0[c];
-      } else if constexpr (MODE == R2C_PUPDATE) {
-        val = a.v0[c] + coef * a.v1[c];
-        a.v1[c] = val;
-      } else {
-        a.v0[c] = a.v0[c] + coef * a.v2[c];
-        val = a.v1[c] - coef * a.v3[c];
-        a.v1[c] = val;
+    for (int cb = c0 + t; cb < c1; cb += NT * kBatch) {
+      int pp[kBatch];
+      T val[kBatch], xv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int c = cb + u * NT;
+        if (c < c1) {
+          pp[u] = a.pos[c];
+          if constexpr (MODE == R2C_COMPACT) {
+            val[u] = a.v0[c];
+          } else if constexpr (MODE == R2C_PUPDATE) {
+            val[u] = a.v0[c] + coef * a.v1[c];
+          } else {
+            val[u] = a.v1[c] - coef * a.v3[c];
+            xv[u] = a.v0[c] + coef * a.v2[c];
+          }
+        }
       }
-      ldr[a.pos[c] - base] = val;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int c = cb + u * NT;
+        if (c < c1) {
+          if constexpr (MODE == R2C_PUPDATE) a.v1[c] = val[u];
+          if constexpr (MODE == R2C_XRUPDATE) {
+            a.v1[c] = val[u];
+            a.v0[c] = xv[u];
+          }
+          ldr[pp[u] - base] = val[u];
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -138,6 +230,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     }
     __syncthreads();
   } else {
+    tw_stage<N>(twq, a.tw, t, NT);
     const size_t ra = (size_t)(y0 + 2 * l) * a.nx, rb = ra + a.nx;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -151,19 +244,25 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   }
 
   C* line = lds + l * LE;
-  fft_line<C, N, -1>(v, tid, line, a.tw);
+  fft_line<C, N, -1>(v, tid, line, twq);
 #pragma unroll
-  for (int e = 0; e < E; ++e) line[lpad(tid + e * TPL)] = v[e];
+  for (int e = 0; e < E; ++e) line[lpad<N>(tid + e * TPL)] = v[e];
   __syncthreads();
-  // Separate the two packed rows: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
-  for (int o = t; o < ROWS * H; o += NT) {
+  // Separate the two packed rows: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i).
+  // The real DC and Nyquist bins of a row share column 0: (A_0, A_{N/2}).
+  for (int o = t; o < ROWS * (N / 2); o += NT) {
     const int kx = o / ROWS, r = o % ROWS;
     const C* ln = lds + (r >> 1) * LE;
-    const C zk = ln[lpad(kx)];
-    const C zm = ln[lpad(kx == 0 ? 0 : N - kx)];
     C out;
-    if (r & 1) out = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
-    else out = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    if (kx == 0) {
+      const C z0 = ln[lpad<N>(0)], zh = ln[lpad<N>(N / 2)];
+      out = (r & 1) ? C{z0.y, zh.y} : C{z0.x, zh.x};
+    } else {
+      const C zk = ln[lpad<N>(kx)];
+      const C zm = ln[lpad<N>(N - kx)];
+      if (r & 1) out = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+      else out = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    }
     a.Xt[(size_t)kx * ldx + y0 + r] = out;
   }
 }
@@ -177,12 +276,14 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
   using CF = RowCfg<T, N>;
   constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS, H = CF::H;
   constexpr int LE = lds_line_elems<N>();
-  constexpr int LDS_C = (CF::LINES * LE > ROWS * H) ? CF::LINES * LE : ROWS * H;
+  constexpr int HS = CF::HS;
+  constexpr int LDS_C = (CF::LINES * LE > ROWS * HS) ? CF::LINES * LE : ROWS * HS;
   __shared__ C lds[LDS_C];
+  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
   T* ldr = reinterpret_cast<T*>(lds);
   if (a.sc != nullptr && a.sc->done) return;
 
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
   const int y0 = blk * ROWS;
   const int t = threadIdx.x;
   const int l = t / TPL, tid = t % TPL;
@@ -199,9 +300,10 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
       return;
     }
   }
-  for (int o = t; o < ROWS * H; o += NT) {
+  tw_stage<N>(twq, a.tw, t, NT);
+  for (int o = t; o < ROWS * (N / 2); o += NT) {
     const int kx = o / ROWS, r = o % ROWS;
-    lds[r * H + kx] = a.Xt[(size_t)kx * ldx + y0 + r];
+    lds[r * HS + kx] = a.Xt[(size_t)kx * ldx + y0 + r];
   }
   __syncthreads();
   C v[E];
@@ -209,15 +311,15 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
   for (int e = 0; e < E; ++e) {
     const int k = tid + e * TPL;
     C A, B;
-    if (k <= N / 2) {
-      A = lds[(2 * l) * H + k];
-      B = lds[(2 * l + 1) * H + k];
-      if (k == 0 || k == N / 2) {  // real bins of a real row
-        A.y = T(0);
-        B.y = T(0);
-      }
+    if (k == 0 || k == N / 2) {  // real DC / Nyquist bins, packed in column 0
+      const C p0 = lds[(2 * l) * HS], q0 = lds[(2 * l + 1) * HS];
+      A = C{k == 0 ? p0.x : p0.y, T(0)};
+      B = C{k == 0 ? q0.x : q0.y, T(0)};
+    } else if (k < N / 2) {
+      A = lds[(2 * l) * HS + k];
+      B = lds[(2 * l + 1) * HS + k];
     } else {
-      const C a0 = lds[(2 * l) * H + (N - k)], b0 = lds[(2 * l + 1) * H + (N - k)];
+      const C a0 = lds[(2 * l) * HS + (N - k)], b0 = lds[(2 * l + 1) * HS + (N - k)];
       A = C{a0.x, -a0.y};
       B = C{b0.x, -b0.y};
     }
@@ -225,7 +327,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
   }
   __syncthreads();
   C* line = lds + l * LE;
-  fft_line<C, N, +1>(v, tid, line, a.tw);
+  fft_line<C, N, +1>(v, tid, line, twq);
 
   if constexpr (c2r_is_compact<MODE>()) {
 #pragma unroll
@@ -237,21 +339,38 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
     __syncthreads();
     const int base = y0 * a.nx;
     double acc0 = 0.0, acc1 = 0.0;
-    for (int c = c0 + t; c < c1; c += NT) {
-      const T val = ldr[a.pos[c] - base];
-      if constexpr (MODE == C2R_COMPACT) {
-        const T o = a.scale * val;
-        a.v0[c] = o;
-        if (a.part0) acc0 += (double)o * (double)(a.v1 ? a.v1[c] : o);
-      } else if constexpr (MODE == C2R_DOT2) {
-        a.v0[c] = val;
-        const double r = (double)a.v1[c];
-        acc0 += r * (double)val;
-        acc1 += r * r;
-      } else {
-        const T r = a.v1[c] - val;
-        a.v0[c] = r;
-        acc0 += (double)r * (double)r;
+    const bool dot_self = (a.v1 == nullptr);
+    for (int cb = c0 + t; cb < c1; cb += NT * kBatch) {
+      int pp[kBatch];
+      T w[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int c = cb + u * NT;
+        if (c < c1) {
+          pp[u] = a.pos[c];
+          w[u] = dot_self ? T(0) : a.v1[c];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int c = cb + u * NT;
+        if (c < c1) {
+          const T val = ldr[pp[u] - base];
+          if constexpr (MODE == C2R_COMPACT) {
+            const T o = a.scale * val;
+            a.v0[c] = o;
+            acc0 += (double)o * (double)(dot_self ? o : w[u]);
+          } else if constexpr (MODE == C2R_DOT2) {
+            a.v0[c] = val;
+            const double r = (double)w[u];
+            acc0 += r * (double)val;
+            acc1 += r * r;
+          } else {
+            const T r = w[u] - val;
+            a.v0[c] = r;
+            acc0 += (double)r * (double)r;
+          }
+        }
       }
     }
     if (a.part0) {
@@ -288,6 +407,91 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
 }
 
 // ---------------------------------------------------------------------------
+// proj: the row pass between two applies of C^{1/2} in E E r (Sec. 2.4):
+// inverse real FFT along x, projection Px (masked pixels kept, observed ones
+// zeroed), forward real FFT along x, transposed half spectrum written back.
+// The projected map never leaves the chip.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T> a) {
+  using C = cplx<T>;
+  using CF = RowCfg<T, N>;
+  constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS;
+  constexpr int LE = lds_line_elems<N>();
+  constexpr int HS = CF::HS;
+  constexpr int LDS_C = (CF::LINES * LE > ROWS * HS) ? CF::LINES * LE : ROWS * HS;
+  __shared__ C lds[LDS_C];
+  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
+  if (a.sc != nullptr && a.sc->done) return;
+
+  const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
+  const int y0 = blk * ROWS;
+  const int t = threadIdx.x;
+  const int l = t / TPL, tid = t % TPL;
+  const size_t ldx = (size_t)a.ldx;
+  if (a.row_off[y0] == a.row_off[y0 + ROWS]) {  // no masked pixel: the projection is zero
+    for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
+    return;
+  }
+  const size_t ra = (size_t)(y0 + 2 * l) * a.nx, rb = ra + a.nx;
+  uint8_t ma[E], mb[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    ma[e] = a.mask[ra + tid + e * TPL];
+    mb[e] = a.mask[rb + tid + e * TPL];
+  }
+  tw_stage<N>(twq, a.tw, t, NT);
+  for (int o = t; o < ROWS * (N / 2); o += NT) {
+    const int kx = o / ROWS, r = o % ROWS;
+    lds[r * HS + kx] = a.Xt[(size_t)kx * ldx + y0 + r];
+  }
+  __syncthreads();
+  C v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = tid + e * TPL;
+    C A, B;
+    if (k == 0 || k == N / 2) {
+      const C p0 = lds[(2 * l) * HS], q0 = lds[(2 * l + 1) * HS];
+      A = C{k == 0 ? p0.x : p0.y, T(0)};
+      B = C{k == 0 ? q0.x : q0.y, T(0)};
+    } else if (k < N / 2) {
+      A = lds[(2 * l) * HS + k];
+      B = lds[(2 * l + 1) * HS + k];
+    } else {
+      const C a0 = lds[(2 * l) * HS + (N - k)], b0 = lds[(2 * l + 1) * HS + (N - k)];
+      A = C{a0.x, -a0.y};
+      B = C{b0.x, -b0.y};
+    }
+    v[e] = C{A.x - B.y, A.y + B.x};
+  }
+  __syncthreads();
+  C* line = lds + l * LE;
+  fft_line<C, N, +1>(v, tid, line, twq);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = C{ma[e] ? v[e].x : T(0), mb[e] ? v[e].y : T(0)};
+  fft_line<C, N, -1>(v, tid, line, twq);
+#pragma unroll
+  for (int e = 0; e < E; ++e) line[lpad<N>(tid + e * TPL)] = v[e];
+  __syncthreads();
+  for (int o = t; o < ROWS * (N / 2); o += NT) {
+    const int kx = o / ROWS, r = o % ROWS;
+    const C* ln = lds + (r >> 1) * LE;
+    C out;
+    if (kx == 0) {
+      const C z0 = ln[lpad<N>(0)], zh = ln[lpad<N>(N / 2)];
+      out = (r & 1) ? C{z0.y, zh.y} : C{z0.x, zh.x};
+    } else {
+      const C zk = ln[lpad<N>(kx)];
+      const C zm = ln[lpad<N>(N - kx)];
+      if (r & 1) out = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+      else out = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    }
+    a.Xt[(size_t)kx * ldx + y0 + r] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column pass: forward FFT along y, multiply by D, inverse FFT along y
 // ---------------------------------------------------------------------------
 template <typename T, int N>
@@ -297,6 +501,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
   constexpr int E = CF::E, TPL = CF::TPL, W = CF::W;
   constexpr int LE = lds_line_elems<N>();
   __shared__ C lds[W * LE];
+  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
   if (a.sc != nullptr && a.sc->done) return;
   const int l = threadIdx.x / TPL, tid = threadIdx.x % TPL;
   const int kx = blockIdx.x * W + l;
@@ -304,17 +509,50 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
   C* g = a.Xt + (size_t)(valid ? kx : 0) * a.ldx;
   const T* d = a.D + (size_t)(valid ? kx : 0) * a.ldx;
   C v[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = valid ? g[tid + e * TPL] : C{T(0), T(0)};
-  C* line = lds + l * LE;
-  fft_line<C, N, -1>(v, tid, line, a.tw);
+  T dv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const T dv = valid ? d[tid + e * TPL] : T(0);
-    v[e].x *= dv;
-    v[e].y *= dv;
+    v[e] = valid ? g[tid + e * TPL] : C{T(0), T(0)};
+    dv[e] = valid ? d[tid + e * TPL] : T(0);
   }
-  fft_line<C, N, +1>(v, tid, line, a.tw);
+  tw_stage<N>(twq, a.tw, threadIdx.x, CF::THREADS);
+  C* line = lds + l * LE;
+  fft_line<C, N, -1>(v, tid, line, twq);
+  if (blockIdx.x == 0) {
+    // Column 0 carries two real sequences, DC (real part) and Nyquist
+    // (imaginary part) of every row: Z = U + iV.  Separate them in frequency,
+    // U_k = (Z_k + conj Z_-k)/2, V_k = (Z_k - conj Z_-k)/(2i), apply each its
+    // own table column, and recombine Z' = U' + i V'.
+    T dn[E];
+    const T* dnyq = a.D + (size_t)a.ncol * a.ldx;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dn[e] = (l == 0) ? dnyq[tid + e * TPL] : T(0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) line[lpad<N>(tid + e * TPL)] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int ky = tid + e * TPL;
+      if (l == 0) {
+        const C zk = v[e], zm = line[lpad<N>(ky == 0 ? 0 : N - ky)];
+        const C u{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+        const C w{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+        const C u2{u.x * dv[e], u.y * dv[e]}, w2{w.x * dn[e], w.y * dn[e]};
+        v[e] = C{u2.x - w2.y, u2.y + w2.x};
+      } else {
+        v[e].x *= dv[e];
+        v[e].y *= dv[e];
+      }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v[e].x *= dv[e];
+      v[e].y *= dv[e];
+    }
+  }
+  fft_line<C, N, +1>(v, tid, line, twq);
   if (valid) {
 #pragma unroll
     for (int e = 0; e < E; ++e) g[tid + e * TPL] = v[e];
@@ -335,6 +573,12 @@ template <typename T, int N, int MODE>
 hipError_t launch_c2r_nm(const RowArgs<T>& a, hipStream_t s) {
   using CF = RowCfg<T, N>;
   hipLaunchKernelGGL((c2r_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T, int N>
+hipError_t launch_proj_n(const RowArgs<T>& a, hipStream_t s) {
+  using CF = RowCfg<T, N>;
+  hipLaunchKernelGGL((proj_kernel<T, N>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, int N>
@@ -380,6 +624,14 @@ template <typename T> hipError_t launch_r2c(int mode, const RowArgs<T>& a, hipSt
 template <typename T> hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s) {
   switch (a.nx) {
 #define FILL_CASE(n) case n: return launch_c2r_n<T, n>(mode, a, s);
+    FILL_FOR_EACH_N(FILL_CASE)
+#undef FILL_CASE
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T> hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s) {
+  switch (a.nx) {
+#define FILL_CASE(n) case n: return launch_proj_n<T, n>(a, s);
     FILL_FOR_EACH_N(FILL_CASE)
 #undef FILL_CASE
   }

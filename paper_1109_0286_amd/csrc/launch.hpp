@@ -14,13 +14,11 @@ template <typename T> struct ColArgs;
 template <typename T> hipError_t launch_r2c(int mode, const RowArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_col(int ny, const ColArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s);
 template <typename T> int row_block_rows(int nx);
 
-// CG scalar updates from per-workgroup partial sums (one workgroup, fixed order).
-hipError_t launch_cg_init(CGScalars* sc, const double* rz, const double* rr, int n, double tol2,
-                          int max_iter, hipStream_t s);
-hipError_t launch_cg_alpha(CGScalars* sc, const double* pq, int n, hipStream_t s);
-hipError_t launch_cg_beta(CGScalars* sc, const double* rz, const double* rr, int n, hipStream_t s);
+// Reset the device CG scalars at the start of an inner solve.
+hipError_t launch_cg_init(CGScalars* sc, double tol2, int max_iter, hipStream_t s);
 hipError_t launch_sum(double* out, const double* part, int n, hipStream_t s);
 
 // Elementwise helpers.

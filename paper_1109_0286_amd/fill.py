@@ -36,9 +36,16 @@ FILL_OP_E = 3
 # every symbol include/fill.h declares
 EXPORTS = (
     "fill_supported_size", "fill_plan_create", "fill_plan_set_pk", "fill_plan_set_max_iter",
+    "fill_plan_set_inner_tol",
     "fill_plan_destroy", "fill_realize", "fill_mean", "fill_get_stats", "fill_apply",
-    "fill_realize_unconstrained", "fill_philox_words", "fill_strerror", "fill_last_error",
+    "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_strerror",
+    "fill_last_error",
 )
+
+FILL_K_R2C = 0
+FILL_K_COL = 1
+FILL_K_C2R = 2
+FILL_K_APPLY = 3
 
 
 class fill_stats(C.Structure):
@@ -54,7 +61,7 @@ class FillError(RuntimeError):
 
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1109_0286_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1109_0286_amd/build.py`")
     lib = C.CDLL(LIB_PATH)
     vp, i32, u64, dbl = C.c_void_p, C.c_int, C.c_uint64, C.c_double
     sig = {
@@ -62,6 +69,7 @@ def _load() -> C.CDLL:
         "fill_plan_create": (i32, [i32, i32, vp, vp, i32, vp, C.POINTER(vp)]),
         "fill_plan_set_pk": (i32, [vp, vp]),
         "fill_plan_set_max_iter": (i32, [vp, i32]),
+        "fill_plan_set_inner_tol": (i32, [vp, dbl]),
         "fill_plan_destroy": (None, [vp]),
         "fill_realize": (i32, [vp, vp, u64, vp, dbl]),
         "fill_mean": (i32, [vp, vp, vp, dbl]),
@@ -69,6 +77,7 @@ def _load() -> C.CDLL:
         "fill_apply": (i32, [vp, i32, i32, vp, vp]),
         "fill_realize_unconstrained": (i32, [vp, u64, vp]),
         "fill_philox_words": (i32, [u64, u64, C.c_int64, vp]),
+        "fill_time_kernel": (i32, [vp, i32, i32, i32, C.POINTER(dbl)]),
         "fill_strerror": (C.c_char_p, [i32]),
         "fill_last_error": (C.c_char_p, []),
     }
@@ -119,6 +128,10 @@ def fill_plan_set_max_iter(plan, max_iter):
     return _check(_lib.fill_plan_set_max_iter(plan, int(max_iter)), "fill_plan_set_max_iter")
 
 
+def fill_plan_set_inner_tol(plan, tol):
+    return _check(_lib.fill_plan_set_inner_tol(plan, float(tol)), "fill_plan_set_inner_tol")
+
+
 def fill_plan_destroy(plan):
     _lib.fill_plan_destroy(plan)
 
@@ -150,6 +163,12 @@ def fill_realize_unconstrained(plan, seed, out_ptr):
 def fill_philox_words(seed, stream, n_blocks, out_ptr):
     return _check(_lib.fill_philox_words(C.c_uint64(seed), C.c_uint64(stream), int(n_blocks), out_ptr),
                   "fill_philox_words")
+
+
+def fill_time_kernel(plan, kernel, prec, reps) -> float:
+    ms = C.c_double()
+    _check(_lib.fill_time_kernel(plan, kernel, prec, int(reps), C.byref(ms)), "fill_time_kernel")
+    return ms.value
 
 
 def fill_strerror(code: int) -> str:
@@ -208,6 +227,9 @@ class Plan:
     def set_max_iter(self, n):
         fill_plan_set_max_iter(self.handle, n)
 
+    def set_inner_tol(self, tol):
+        fill_plan_set_inner_tol(self.handle, tol)
+
     def _new_map(self):
         import torch
         return torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
@@ -240,6 +262,10 @@ class Plan:
 
     def stats(self) -> dict:
         return fill_get_stats(self.handle)
+
+    def time_kernel(self, kernel, reps=50, prec=None) -> float:
+        """Average milliseconds per launch of one kernel of the A apply."""
+        return fill_time_kernel(self.handle, kernel, self.prec if prec is None else prec, reps)
 
 
 def philox_words(seed, stream, n_blocks, device="cuda"):
