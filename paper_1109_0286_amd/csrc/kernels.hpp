@@ -188,9 +188,42 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
       return;
     }
     tw_stage<N>(twq, a.tw, t, NT);
+    const int base = y0 * a.nx;
+    if (c1 - c0 == ROWS * N) {
+      // Every pixel of these rows is masked (a band): compact element c0 + i
+      // is pixel i of the block, so no index loads and no zero fill.
+      constexpr int PER = ROWS * N / NT, FB = sizeof(T) == 4 ? 16 : 8;
+      static_assert(PER % FB == 0, "chunking");
+#pragma unroll 1
+      for (int ch = 0; ch < PER; ch += FB) {
+        T val[FB], xv[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+          const int c = c0 + t + (ch + u) * NT;
+          if constexpr (MODE == R2C_COMPACT) {
+            val[u] = a.v0[c];
+          } else if constexpr (MODE == R2C_PUPDATE) {
+            val[u] = a.v0[c] + coef * a.v1[c];
+          } else {
+            val[u] = a.v1[c] - coef * a.v3[c];
+            xv[u] = a.v0[c] + coef * a.v2[c];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+          const int i = t + (ch + u) * NT, c = c0 + i;
+          if constexpr (MODE == R2C_PUPDATE) a.v1[c] = val[u];
+          if constexpr (MODE == R2C_XRUPDATE) {
+            a.v1[c] = val[u];
+            a.v0[c] = xv[u];
+          }
+          ldr[i] = val[u];
+        }
+      }
+      __syncthreads();
+    } else {
     for (int i = t; i < ROWS * N; i += NT) ldr[i] = T(0);
     __syncthreads();
-    const int base = y0 * a.nx;
     for (int cb = c0 + t; cb < c1; cb += NT * kBatch) {
       int pp[kBatch];
       T val[kBatch], xv[kBatch];
@@ -223,6 +256,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
       }
     }
     __syncthreads();
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int x = tid + e * TPL;
@@ -340,6 +374,35 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
     const int base = y0 * a.nx;
     double acc0 = 0.0, acc1 = 0.0;
     const bool dot_self = (a.v1 == nullptr);
+    if (c1 - c0 == ROWS * N) {
+      // fully masked rows: compact element c0 + i is pixel i of the block
+      constexpr int PER = ROWS * N / NT, FB = sizeof(T) == 4 ? 16 : 8;
+#pragma unroll 1
+      for (int ch = 0; ch < PER; ch += FB) {
+        T w[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) w[u] = dot_self ? T(0) : a.v1[c0 + t + (ch + u) * NT];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+          const int i = t + (ch + u) * NT, c = c0 + i;
+          const T val = ldr[i];
+          if constexpr (MODE == C2R_COMPACT) {
+            const T o = a.scale * val;
+            a.v0[c] = o;
+            acc0 += (double)o * (double)(dot_self ? o : w[u]);
+          } else if constexpr (MODE == C2R_DOT2) {
+            a.v0[c] = val;
+            const double r = (double)w[u];
+            acc0 += r * (double)val;
+            acc1 += r * r;
+          } else {
+            const T r = w[u] - val;
+            a.v0[c] = r;
+            acc0 += (double)r * (double)r;
+          }
+        }
+      }
+    } else
     for (int cb = c0 + t; cb < c1; cb += NT * kBatch) {
       int pp[kBatch];
       T w[kBatch];
