@@ -18,6 +18,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+CALIB_BYTES = 256 << 20  # plain device copy used to scale the rocprofv3 byte counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "col_kernel_f32_2048_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1109_0286_amd", "csrc", f) for f in ("fft_device.hpp", "kernels.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    runs, or None if the kernel sources changed since they were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    return t["traffic_bytes"] if t.get("source_hash") == kernel_source_hash() else None
 
 
 def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int) -> float:
@@ -46,18 +67,23 @@ def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int) -> fl
     return 2.0 * s * H + (s + 4.0) * n_m
 
 
-def time_solves(F, plan, d, seed, rtol, steps, warmup):
+def time_solves(F, plan, d, seed, rtol, steps, warmup, timed_kernel):
+    """Time `steps` solves; every launch of `timed_kernel` inside the timed
+    region is bracketed by HIP events on the plan's stream."""
     import torch
     x = torch.empty_like(d)
     for _ in range(warmup):
         plan.realize(d, seed, rtol, out=x)
     torch.cuda.synchronize()
+    plan.kernel_timing(timed_kernel)
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.realize(d, seed, rtol, out=x)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, plan.stats(), x
+    k_ms, k_n = plan.kernel_timing_read()
+    plan.kernel_timing(-1)
+    return dt, plan.stats(), k_ms / max(k_n, 1), k_n
 
 
 def cpu_baseline(prob, iters_fp64: int, budget_s: float = 20.0) -> dict:
@@ -93,7 +119,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--reps", type=int, default=50, help="launches per kernel timing")
+    ap.add_argument("--kernel-ms", action="store_true",
+                    help="also time each kernel in isolation (back-to-back launches)")
+    ap.add_argument("--reps", type=int, default=50, help="launches per isolated kernel timing")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="finish with three plain 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); batches and Monte-Carlo "
@@ -112,18 +142,21 @@ def main() -> int:
     plan64 = F.Plan(nx, ny, prob.mask, prob.P, F.FILL_PREC_FP64)
     n_m = prob.n_masked
 
-    dt64, st64, _ = time_solves(F, plan64, d, seed, rtol, args.steps, args.warmup)
+    dt64, st64, col64_ms, _ = time_solves(F, plan64, d, seed, rtol, args.steps, args.warmup, F.FILL_K_COL)
     print(f"# fp64: {args.steps / dt64:.2f} solves/s, {st64['iters_inner']} iterations", file=sys.stderr, flush=True)
-    dt32, st32, _ = time_solves(F, plan32, d, seed, rtol, args.steps, args.warmup)
+    dt32, st32, col32_ms, col32_n = time_solves(F, plan32, d, seed, rtol, args.steps, args.warmup, F.FILL_K_COL)
     print(f"# mixed: {args.steps / dt32:.2f} solves/s, {st32['iters_inner']} inner iterations, "
           f"{st32['iters_outer']} refinements", file=sys.stderr, flush=True)
 
-    # dominant kernel of the mixed path: per-launch time with HIP events on the plan's stream
-    kt = {k: plan32.time_kernel(getattr(F, f"FILL_K_{k.upper()}"), args.reps) for k in ("r2c", "col", "c2r")}
-    kt64 = {k: plan64.time_kernel(getattr(F, f"FILL_K_{k.upper()}"), args.reps) for k in ("r2c", "col", "c2r")}
-    dom = max(kt, key=kt.get)
-    nbytes = kernel_bytes(dom, 4, nx, ny, n_m)
-    achieved = nbytes / (kt[dom] * 1e-3) / 1e9
+    # dominant kernel of the mixed path: the FP32 column pass, average launch
+    # duration over the timed region (HIP events on the plan's stream)
+    nbytes = kernel_bytes("col", 4, nx, ny, n_m)
+    achieved = nbytes / (col32_ms * 1e-3) / 1e9
+    kernel_ms = None
+    if args.kernel_ms:
+        kernel_ms = {name: {k: pl.time_kernel(getattr(F, f"FILL_K_{k.upper()}"), args.reps)
+                            for k in ("r2c", "col", "c2r", "proj")}
+                     for name, pl in (("f32", plan32), ("f64", plan64))}
     out = {
         "metric": "PCG fill-in solves/s at 2048^2 (rel resid 1e-8) + achieved HBM GB/s vs peak",
         "value": args.steps / dt32,
@@ -143,14 +176,22 @@ def main() -> int:
                    "rel_resid": st32["rel_resid"]},
         "fp64_path": {"value": args.steps / dt64, "unit": "solves/s", "ms_per_step": dt64 / args.steps * 1e3,
                       "iters": st64["iters_inner"], "rel_resid": st64["rel_resid"]},
-        "kernel_ms": {"f32": kt, "f64": kt64},
-        "roofline": {"bound": "hbm", "kernel": f"{dom}_kernel<float,2048>", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": nbytes},
+        "col_kernel_ms_in_solve": {"f32": col32_ms, "f64": col64_ms},
+        "kernel_ms_isolated": kernel_ms,
+        "roofline": {"bound": "hbm", "kernel": "col_kernel<float,2048>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(), "bytes_per_launch": nbytes, "launches_timed": col32_n,
+                     "kernel_source_hash": kernel_source_hash()},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, st64["iters_inner"])
     print(json.dumps(out), flush=True)
+    if args.calib_copy:
+        a = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
     return 0
 
 

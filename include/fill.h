@@ -166,7 +166,8 @@ enum fill_kernel {
   FILL_K_R2C = 0,    /* row pass: compact masked vector -> transposed half spectrum */
   FILL_K_COL = 1,    /* column pass: FFT along y, times 1/P, inverse FFT along y */
   FILL_K_C2R = 2,    /* row pass: half spectrum -> masked pixels (compact) */
-  FILL_K_APPLY = 3   /* the three in sequence: one apply of A = Px C^-1 Px */
+  FILL_K_APPLY = 3,  /* the three in sequence: one apply of A = Px C^-1 Px */
+  FILL_K_PROJ = 4    /* row pass between the two C^{1/2} applies of E E r */
 };
 
 /*
@@ -176,6 +177,21 @@ enum fill_kernel {
  * FP32 kernels.  Overwrites the plan's workspaces (not d_obs/x_out).
  */
 int fill_time_kernel(fill_plan plan, int kernel, int prec, int reps, double* avg_ms);
+
+/*
+ * Measurement helper: from now on, bracket every launch of one kernel
+ * (FILL_K_R2C, FILL_K_COL, FILL_K_C2R or FILL_K_PROJ; -1 = off) in precision
+ * prec during solves on this plan with a pair of HIP events on the plan's
+ * stream.  Resets the accumulated totals.
+ */
+int fill_kernel_timing(fill_plan plan, int kernel, int prec);
+
+/*
+ * Sum of the event-measured durations (ms) and the number of timed launches
+ * since the last read or fill_kernel_timing call; synchronises the stream and
+ * resets the totals.
+ */
+int fill_kernel_timing_read(fill_plan plan, double* total_ms, int64_t* count);
 
 /* Text for a status code. */
 const char* fill_strerror(int code);

@@ -100,6 +100,13 @@ struct fill_plan_s {
   double* h_sum = nullptr;
   fill_stats stats{};
   std::vector<void*> allocs;
+  // optional HIP-event timing of every launch of one kernel during solves
+  int timed_kernel = -1;
+  int timed_prec = 0;
+  std::vector<hipEvent_t> events;  // start/stop pairs
+  size_t events_used = 0;
+  double timed_ms = 0.0;
+  long long timed_count = 0;
 };
 
 namespace {
@@ -148,11 +155,48 @@ template <typename T> RowArgs<T> row_base(fill_plan p) {
   return a;
 }
 
+// Sum the elapsed times of the recorded event pairs (stream synchronised) and recycle them.
+int drain_timing(fill_plan p) {
+  if (p->events_used == 0) return FILL_OK;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (size_t i = 0; i + 1 < p->events_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->events[i], p->events[i + 1]));
+    p->timed_ms += ms;
+    p->timed_count += 1;
+  }
+  p->events_used = 0;
+  return FILL_OK;
+}
+
+// Launch wrapper: when this kernel is the timed one, hand the launch a pair
+// of events that the dispatch itself timestamps at its start and end.
+template <typename T, typename F>
+int timed_launch(fill_plan p, int kernel, F&& launch) {
+  const bool on = p->timed_kernel == kernel && p->timed_prec == (sizeof(T) == 4 ? FILL_PREC_FP32_OP : FILL_PREC_FP64);
+  if (!on) {
+    HIP_TRY(launch(nullptr, nullptr));
+    return FILL_OK;
+  }
+  if (p->events_used + 2 > p->events.size()) {
+    FILL_TRY(drain_timing(p));
+    while (p->events.size() < 2048) {
+      // timing-only events: no system-scope fence (no cache write-back on record)
+      hipEvent_t e;
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+      p->events.push_back(e);
+    }
+  }
+  HIP_TRY(launch(p->events[p->events_used], p->events[p->events_used + 1]));
+  p->events_used += 2;
+  return FILL_OK;
+}
+
 // One operator apply: r2c (mode rm, args ai) -> column pass with table D -> c2r (mode cm, args ao).
 template <typename T>
 int apply3(fill_plan p, int rm, const RowArgs<T>& ai, const T* D, int cm, const RowArgs<T>& ao,
            const CGScalars* sc) {
-  HIP_TRY(launch_r2c<T>(rm, ai, p->stream));
+  FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(rm, ai, p->stream, a, b); }));
   ColArgs<T> ca;
   ca.Xt = static_cast<cplx<T>*>(p->Xt);
   ca.ldx = p->ny;
@@ -160,8 +204,8 @@ int apply3(fill_plan p, int rm, const RowArgs<T>& ai, const T* D, int cm, const 
   ca.D = D;
   ca.tw = TypeSel<T>::twy(p);
   ca.sc = sc;
-  HIP_TRY(launch_col<T>(p->ny, ca, p->stream));
-  HIP_TRY(launch_c2r<T>(cm, ao, p->stream));
+  FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
+  FILL_TRY(timed_launch<T>(p, FILL_K_C2R, [&](hipEvent_t a, hipEvent_t b) { return launch_c2r<T>(cm, ao, p->stream, a, b); }));
   return FILL_OK;
 }
 
@@ -170,7 +214,7 @@ int apply3(fill_plan p, int rm, const RowArgs<T>& ai, const T* D, int cm, const 
 template <typename T>
 int apply_EE(fill_plan p, int rm, const RowArgs<T>& ai, const RowArgs<T>& amid, const RowArgs<T>& ao,
              const CGScalars* sc) {
-  HIP_TRY(launch_r2c<T>(rm, ai, p->stream));
+  FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(rm, ai, p->stream, a, b); }));
   ColArgs<T> ca;
   ca.Xt = static_cast<cplx<T>*>(p->Xt);
   ca.ldx = p->ny;
@@ -178,10 +222,10 @@ int apply_EE(fill_plan p, int rm, const RowArgs<T>& ai, const RowArgs<T>& amid, 
   ca.D = TypeSel<T>::Dhalf(p);
   ca.tw = TypeSel<T>::twy(p);
   ca.sc = sc;
-  HIP_TRY(launch_col<T>(p->ny, ca, p->stream));
-  HIP_TRY(launch_proj<T>(amid, p->stream));
-  HIP_TRY(launch_col<T>(p->ny, ca, p->stream));
-  HIP_TRY(launch_c2r<T>(C2R_DOT2, ao, p->stream));
+  FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
+  FILL_TRY(timed_launch<T>(p, FILL_K_PROJ, [&](hipEvent_t a, hipEvent_t b) { return launch_proj<T>(amid, p->stream, a, b); }));
+  FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
+  FILL_TRY(timed_launch<T>(p, FILL_K_C2R, [&](hipEvent_t a, hipEvent_t b) { return launch_c2r<T>(C2R_DOT2, ao, p->stream, a, b); }));
   return FILL_OK;
 }
 
@@ -580,6 +624,7 @@ int fill_plan_set_inner_tol(fill_plan p, double tol) {
 void fill_plan_destroy(fill_plan p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->stream);
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   for (void* a : p->allocs) (void)hipFree(a);
   if (p->h_sc) (void)hipHostFree(p->h_sc);
   if (p->h_sum) (void)hipHostFree(p->h_sum);
@@ -708,6 +753,30 @@ int fill_time_kernel(fill_plan p, int kernel, int prec, int reps, double* avg_ms
   if (prec == FILL_PREC_FP64) return time_kernel<double>(p, kernel, reps, avg_ms);
   if (prec == FILL_PREC_FP32_OP) return time_kernel<float>(p, kernel, reps, avg_ms);
   return fail(FILL_EINVAL, "unknown precision");
+}
+
+int fill_kernel_timing(fill_plan p, int kernel, int prec) {
+  g_last_error.clear();
+  if (!p) return fail(FILL_EINVAL, "NULL plan");
+  if (kernel < -1 || kernel > FILL_K_PROJ || kernel == FILL_K_APPLY) return fail(FILL_EINVAL, "unknown kernel");
+  if (prec != FILL_PREC_FP64 && prec != FILL_PREC_FP32_OP) return fail(FILL_EINVAL, "unknown precision");
+  FILL_TRY(drain_timing(p));
+  p->timed_kernel = kernel;
+  p->timed_prec = prec;
+  p->timed_ms = 0.0;
+  p->timed_count = 0;
+  return FILL_OK;
+}
+
+int fill_kernel_timing_read(fill_plan p, double* total_ms, int64_t* count) {
+  g_last_error.clear();
+  if (!p || !total_ms || !count) return fail(FILL_EINVAL, "NULL argument");
+  FILL_TRY(drain_timing(p));
+  *total_ms = p->timed_ms;
+  *count = p->timed_count;
+  p->timed_ms = 0.0;
+  p->timed_count = 0;
+  return FILL_OK;
 }
 
 const char* fill_strerror(int code) {

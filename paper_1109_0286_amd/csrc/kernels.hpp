@@ -16,6 +16,8 @@
 // iteration are fused into the row passes (prologue of r2c, epilogue of c2r).
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "fft_device.hpp"
 
 namespace fillk {
@@ -626,83 +628,95 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
 // host-side launchers (instantiated per precision)
 // ---------------------------------------------------------------------------
 
+// Launch with optional start/stop events timestamped by the dispatch itself
+// (hipExtLaunchKernelGGL), so a timed launch adds no packets to the stream.
+#define FILL_LAUNCH(kern, grid, block, s, ev0, ev1, ...)                                   \
+  do {                                                                                     \
+    if (ev0) hipExtLaunchKernelGGL(kern, grid, block, 0, s, ev0, ev1, 0, __VA_ARGS__);     \
+    else hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);                         \
+  } while (0)
+
 template <typename T, int N, int MODE>
-hipError_t launch_r2c_nm(const RowArgs<T>& a, hipStream_t s) {
+hipError_t launch_r2c_nm(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = RowCfg<T, N>;
-  hipLaunchKernelGGL((r2c_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), 0, s, a);
+  FILL_LAUNCH((r2c_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 template <typename T, int N, int MODE>
-hipError_t launch_c2r_nm(const RowArgs<T>& a, hipStream_t s) {
+hipError_t launch_c2r_nm(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = RowCfg<T, N>;
-  hipLaunchKernelGGL((c2r_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), 0, s, a);
+  FILL_LAUNCH((c2r_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 template <typename T, int N>
-hipError_t launch_proj_n(const RowArgs<T>& a, hipStream_t s) {
+hipError_t launch_proj_n(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = RowCfg<T, N>;
-  hipLaunchKernelGGL((proj_kernel<T, N>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), 0, s, a);
+  FILL_LAUNCH((proj_kernel<T, N>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 template <typename T, int N>
-hipError_t launch_col_n(const ColArgs<T>& a, hipStream_t s) {
+hipError_t launch_col_n(const ColArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = ColCfg<T, N>;
-  hipLaunchKernelGGL((col_kernel<T, N>), dim3((a.ncol + CF::W - 1) / CF::W), dim3(CF::THREADS), 0, s, a);
+  FILL_LAUNCH((col_kernel<T, N>), dim3((a.ncol + CF::W - 1) / CF::W), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t launch_r2c_n(int mode, const RowArgs<T>& a, hipStream_t s) {
+hipError_t launch_r2c_n(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (mode) {
-    case R2C_COMPACT: return launch_r2c_nm<T, N, R2C_COMPACT>(a, s);
-    case R2C_PUPDATE: return launch_r2c_nm<T, N, R2C_PUPDATE>(a, s);
-    case R2C_XRUPDATE: return launch_r2c_nm<T, N, R2C_XRUPDATE>(a, s);
-    case R2C_FULL: return launch_r2c_nm<T, N, R2C_FULL>(a, s);
-    case R2C_NOISE: return launch_r2c_nm<T, N, R2C_NOISE>(a, s);
+    case R2C_COMPACT: return launch_r2c_nm<T, N, R2C_COMPACT>(a, s, e0, e1);
+    case R2C_PUPDATE: return launch_r2c_nm<T, N, R2C_PUPDATE>(a, s, e0, e1);
+    case R2C_XRUPDATE: return launch_r2c_nm<T, N, R2C_XRUPDATE>(a, s, e0, e1);
+    case R2C_FULL: return launch_r2c_nm<T, N, R2C_FULL>(a, s, e0, e1);
+    case R2C_NOISE: return launch_r2c_nm<T, N, R2C_NOISE>(a, s, e0, e1);
   }
   return hipErrorInvalidValue;
 }
 template <typename T, int N>
-hipError_t launch_c2r_n(int mode, const RowArgs<T>& a, hipStream_t s) {
+hipError_t launch_c2r_n(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (mode) {
-    case C2R_COMPACT: return launch_c2r_nm<T, N, C2R_COMPACT>(a, s);
-    case C2R_DOT2: return launch_c2r_nm<T, N, C2R_DOT2>(a, s);
-    case C2R_RESID: return launch_c2r_nm<T, N, C2R_RESID>(a, s);
-    case C2R_REALIZE: return launch_c2r_nm<T, N, C2R_REALIZE>(a, s);
-    case C2R_FULL: return launch_c2r_nm<T, N, C2R_FULL>(a, s);
+    case C2R_COMPACT: return launch_c2r_nm<T, N, C2R_COMPACT>(a, s, e0, e1);
+    case C2R_DOT2: return launch_c2r_nm<T, N, C2R_DOT2>(a, s, e0, e1);
+    case C2R_RESID: return launch_c2r_nm<T, N, C2R_RESID>(a, s, e0, e1);
+    case C2R_REALIZE: return launch_c2r_nm<T, N, C2R_REALIZE>(a, s, e0, e1);
+    case C2R_FULL: return launch_c2r_nm<T, N, C2R_FULL>(a, s, e0, e1);
   }
   return hipErrorInvalidValue;
 }
 
 #define FILL_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(768) X(1024) X(2048) X(4096)
 
-template <typename T> hipError_t launch_r2c(int mode, const RowArgs<T>& a, hipStream_t s) {
+template <typename T>
+hipError_t launch_r2c(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   switch (a.nx) {
-#define FILL_CASE(n) case n: return launch_r2c_n<T, n>(mode, a, s);
+#define FILL_CASE(n) case n: return launch_r2c_n<T, n>(mode, a, s, e0, e1);
     FILL_FOR_EACH_N(FILL_CASE)
 #undef FILL_CASE
   }
   return hipErrorInvalidValue;
 }
-template <typename T> hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s) {
+template <typename T>
+hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   switch (a.nx) {
-#define FILL_CASE(n) case n: return launch_c2r_n<T, n>(mode, a, s);
+#define FILL_CASE(n) case n: return launch_c2r_n<T, n>(mode, a, s, e0, e1);
     FILL_FOR_EACH_N(FILL_CASE)
 #undef FILL_CASE
   }
   return hipErrorInvalidValue;
 }
-template <typename T> hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s) {
+template <typename T>
+hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   switch (a.nx) {
-#define FILL_CASE(n) case n: return launch_proj_n<T, n>(a, s);
+#define FILL_CASE(n) case n: return launch_proj_n<T, n>(a, s, e0, e1);
     FILL_FOR_EACH_N(FILL_CASE)
 #undef FILL_CASE
   }
   return hipErrorInvalidValue;
 }
-template <typename T> hipError_t launch_col(int ny, const ColArgs<T>& a, hipStream_t s) {
+template <typename T>
+hipError_t launch_col(int ny, const ColArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   switch (ny) {
-#define FILL_CASE(n) case n: return launch_col_n<T, n>(a, s);
+#define FILL_CASE(n) case n: return launch_col_n<T, n>(a, s, e0, e1);
     FILL_FOR_EACH_N(FILL_CASE)
 #undef FILL_CASE
   }

@@ -11,10 +11,15 @@ struct CGScalars;
 template <typename T> struct RowArgs;
 template <typename T> struct ColArgs;
 
-template <typename T> hipError_t launch_r2c(int mode, const RowArgs<T>& a, hipStream_t s);
-template <typename T> hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s);
-template <typename T> hipError_t launch_col(int ny, const ColArgs<T>& a, hipStream_t s);
-template <typename T> hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s);
+// e0/e1 (may be null): events timestamped at the start and end of the dispatch.
+template <typename T>
+hipError_t launch_r2c(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_col(int ny, const ColArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> int row_block_rows(int nx);
 
 // Reset the device CG scalars at the start of an inner solve.

@@ -38,7 +38,8 @@ EXPORTS = (
     "fill_supported_size", "fill_plan_create", "fill_plan_set_pk", "fill_plan_set_max_iter",
     "fill_plan_set_inner_tol",
     "fill_plan_destroy", "fill_realize", "fill_mean", "fill_get_stats", "fill_apply",
-    "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_strerror",
+    "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_kernel_timing",
+    "fill_kernel_timing_read", "fill_strerror",
     "fill_last_error",
 )
 
@@ -46,6 +47,7 @@ FILL_K_R2C = 0
 FILL_K_COL = 1
 FILL_K_C2R = 2
 FILL_K_APPLY = 3
+FILL_K_PROJ = 4
 
 
 class fill_stats(C.Structure):
@@ -78,6 +80,8 @@ def _load() -> C.CDLL:
         "fill_realize_unconstrained": (i32, [vp, u64, vp]),
         "fill_philox_words": (i32, [u64, u64, C.c_int64, vp]),
         "fill_time_kernel": (i32, [vp, i32, i32, i32, C.POINTER(dbl)]),
+        "fill_kernel_timing": (i32, [vp, i32, i32]),
+        "fill_kernel_timing_read": (i32, [vp, C.POINTER(dbl), C.POINTER(C.c_int64)]),
         "fill_strerror": (C.c_char_p, [i32]),
         "fill_last_error": (C.c_char_p, []),
     }
@@ -171,6 +175,16 @@ def fill_time_kernel(plan, kernel, prec, reps) -> float:
     return ms.value
 
 
+def fill_kernel_timing(plan, kernel, prec):
+    return _check(_lib.fill_kernel_timing(plan, int(kernel), int(prec)), "fill_kernel_timing")
+
+
+def fill_kernel_timing_read(plan):
+    ms, n = C.c_double(), C.c_int64()
+    _check(_lib.fill_kernel_timing_read(plan, C.byref(ms), C.byref(n)), "fill_kernel_timing_read")
+    return ms.value, n.value
+
+
 def fill_strerror(code: int) -> str:
     return _strerror(code)
 
@@ -262,6 +276,14 @@ class Plan:
 
     def stats(self) -> dict:
         return fill_get_stats(self.handle)
+
+    def kernel_timing(self, kernel, prec=None):
+        """Time every launch of `kernel` during later solves with HIP events (-1 = off)."""
+        fill_kernel_timing(self.handle, kernel, self.prec if prec is None else prec)
+
+    def kernel_timing_read(self):
+        """(total ms, launches) since the last read; synchronises the plan's stream."""
+        return fill_kernel_timing_read(self.handle)
 
     def time_kernel(self, kernel, reps=50, prec=None) -> float:
         """Average milliseconds per launch of one kernel of the A apply."""
