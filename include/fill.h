@@ -104,7 +104,25 @@ int fill_supported_size(int n);
 int fill_plan_create(int nx, int ny, const uint8_t* mask, const double* Pk, int prec,
                      void* stream, fill_plan* out);
 
-/* Replace the spectrum of an existing plan (host Pk, same layout/rules). */
+/*
+ * Batched plan: nprob problems on the same nx-by-ny grid, solved together
+ * (Monte-Carlo draws, many masks; each problem has its own mask, data, seed
+ * and CG state, and stops on its own residual).  Every GPU step of a solve
+ * covers all problems in one launch.
+ *   masks     host, nprob*ny*nx uint8 (problem b at offset b*ny*nx).
+ *   Pk        host, n_pk*ny*(nx/2+1) doubles: n_pk = 1 (one spectrum shared by
+ *             all problems) or n_pk = nprob (one per problem).
+ * Other arguments and errors as fill_plan_create.  A plan from
+ * fill_plan_create is a batched plan with nprob = 1.
+ */
+int fill_plan_create_batch(int nx, int ny, int nprob, const uint8_t* masks, const double* Pk, int n_pk,
+                           int prec, void* stream, fill_plan* out);
+
+/* Number of problems of a plan (0 for NULL). */
+int fill_plan_nprob(fill_plan plan);
+
+/* Replace the spectrum of an existing plan (host Pk, same layout/rules; n_pk
+ * tables as at creation). */
 int fill_plan_set_pk(fill_plan plan, const double* Pk);
 
 /* Iteration cap of the CG solves (default 20000 summed over refinement steps). */
@@ -140,18 +158,45 @@ int fill_realize(fill_plan plan, const double* d_obs, uint64_t seed, double* x_o
 /* Conditional mean / Wiener fill x_ML = M y (Sec. 2.1): as fill_realize with s = 0. */
 int fill_mean(fill_plan plan, const double* d_obs, double* x_out, double rtol);
 
-/* Statistics of the last solve on this plan. */
-int fill_get_stats(fill_plan plan, fill_stats* out);
+/*
+ * fill_realize / fill_mean for every problem of a batched plan.
+ *   d_obs, x_out  host arrays of nprob device pointers (ny*nx doubles each;
+ *                 x_out[b] may not alias d_obs[b]).
+ *   seeds         host array of nprob seeds (key (seeds[b], 0x52)).
+ * Each problem stops when its own true residual is <= rtol.  Returns
+ * FILL_OK, FILL_ENOCONV if any problem did not converge (its x_out holds the
+ * best iterate), or an error.  fill_realize/fill_mean require nprob = 1.
+ */
+int fill_realize_batch(fill_plan plan, const double* const* d_obs, const uint64_t* seeds,
+                       double* const* x_out, double rtol);
+int fill_mean_batch(fill_plan plan, const double* const* d_obs, double* const* x_out, double rtol);
 
 /*
- * Apply one operator of enum fill_op to a full map (device in/out, ny*nx
- * doubles, may not alias) in precision prec (enum fill_precision; FP32
+ * Several batched plans at once (for example one per grid size of a
+ * Monte-Carlo study with uneven sizes): plan i runs fill_realize_batch with
+ * d_obs[i], seeds[i], x_out[i] on its own host thread, so plans created on
+ * different streams overlap on the GPU.  Returns the worst status;
+ * fill_last_error names the plan.
+ */
+int fill_realize_multi(int nplans, const fill_plan* plans, const double* const* const* d_obs,
+                       const uint64_t* const* seeds, double* const* const* x_out, double rtol);
+
+/* Statistics of the last solve on this plan (for a batch: iteration counts
+ * and residual are the maxima over problems, n_masked the total). */
+int fill_get_stats(fill_plan plan, fill_stats* out);
+
+/* Per-problem statistics of the last solve: out has nprob entries. */
+int fill_get_stats_batch(fill_plan plan, fill_stats* out);
+
+/*
+ * Apply one operator of enum fill_op (with problem 0's mask and spectrum) to
+ * a full map (device in/out, ny*nx doubles, may not alias) in precision prec (enum fill_precision; FP32
  * rounds the input to float and returns the float result widened).  The
  * operators are the ones every CG iteration applies (Sec. 2.4).
  */
 int fill_apply(fill_plan plan, int op, int prec, const double* in, double* out);
 
-/* The unconstrained draw s = C^{1/2} w for a seed (device out, ny*nx). */
+/* The unconstrained draw s = C^{1/2} w for a seed (problem 0's spectrum; device out, ny*nx). */
 int fill_realize_unconstrained(fill_plan plan, uint64_t seed, double* out);
 
 /*

@@ -7,4 +7,4 @@ The package is a thin binding of libfill.so (C ABI, include/fill.h).
 """
 
 from .fill import *  # noqa: F401,F403
-from .fill import Plan, philox_words, EXPORTS, LIB_PATH  # noqa: F401
+from .fill import Plan, BatchPlan, realize_multi, philox_words, EXPORTS, LIB_PATH  # noqa: F401

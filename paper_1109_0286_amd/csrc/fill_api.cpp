@@ -1,14 +1,17 @@
-// C ABI of the constrained-realization fill-in: plan, solve driver, entry
-// points (declarations and contracts in include/fill.h).
+// C ABI of the constrained-realization fill-in: plans, the batched solve
+// driver and the entry points (contracts in include/fill.h).
 //
-// A solve (Sec. 2.3 / 2.4):
+// A plan holds nprob problems on the same nx x ny grid (own mask, seed, data
+// and CG state; one shared spectrum or one per problem).  Every GPU step
+// covers all problems of the plan in one launch.  A solve (Sec. 2.3 / 2.4):
 //   1. s = C^{1/2} w from counter-based white noise (one apply, noise generated
 //      inside the first row pass); the same pass writes x_out = d on observed
 //      pixels and s on masked ones, and t = Py (d - s);
-//   2. v = -Px C^-1 t (one apply), ||v|| on the host;
+//   2. v = -Px C^-1 t (one apply), ||v|| per problem on the host;
 //   3. refinement loop in FP64: r = v - A u (FP64 apply), then an inner
 //      preconditioned CG on A d = r / ||r|| in the plan's precision (FP64, or
 //      FP32 operators with FP64 dot products and scalars), u += ||r|| d;
+//      each problem stops on its own true residual;
 //   4. x_out += u on masked pixels.
 // Inner CG (Hestenes-Stiefel) with M^-1 = E E, E = Px C^{1/2} Px: the paper's
 // split form E A E u' = E v, u = E u', has the same iterates u.
@@ -20,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fill.h"
@@ -51,7 +55,8 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 constexpr uint64_t kRealizationStream = 0x52;
-constexpr int kChunk = 16;  // CG iterations between host polls of the convergence flag
+constexpr int kChunk = 16;  // CG iterations between host polls (even: keeps the rho parity)
+constexpr int kMaxOuter = 60;
 
 template <typename T> struct Vecs {
   T* x = nullptr;
@@ -62,13 +67,26 @@ template <typename T> struct Vecs {
   T* t = nullptr;
 };
 
+// Per-call parameters, mirrored host (pinned) -> device in one copy.
+struct Params {
+  double* scale;      // r_in = res * scale
+  double* unscale;    // u += unscale * x
+  double* tol2;
+  int* cap;
+  int* active;
+  const double** in_tab;
+  double** out_tab;
+  uint64_t* seeds;
+};
+
 }  // namespace
 
 struct fill_plan_s {
-  int nx = 0, ny = 0, ncol = 0, prec = 0;
-  size_t npix = 0;
+  int nx = 0, ny = 0, ncol = 0, prec = 0, nprob = 1, npk = 1;
+  size_t npix = 0, nt = 0;
   hipStream_t stream = nullptr;
-  int n_m = 0;
+  std::vector<int> n_m, coff;
+  int n_m_total = 0, n_m_max = 0;
   int max_iter = 20000;
   double inner_tol32 = 1e-4;
   int nblk64 = 0, nblk32 = 0;
@@ -76,6 +94,7 @@ struct fill_plan_s {
   uint8_t* mask = nullptr;
   int* pos = nullptr;
   int* row_off = nullptr;
+  int* comp_off = nullptr;
   double* Dinv64 = nullptr;
   double* Dhalf64 = nullptr;
   float* Dinv32 = nullptr;
@@ -96,8 +115,13 @@ struct fill_plan_s {
   double* part2 = nullptr;
   double* dsum = nullptr;
   CGScalars* sc = nullptr;
+  void* par_dev = nullptr;
+  void* par_host = nullptr;
+  size_t par_bytes = 0;
+  Params dp{}, hp{};
   CGScalars* h_sc = nullptr;
   double* h_sum = nullptr;
+  std::vector<fill_stats> pstats;
   fill_stats stats{};
   std::vector<void*> allocs;
   // optional HIP-event timing of every launch of one kernel during solves
@@ -140,12 +164,18 @@ template <> struct TypeSel<float> {
   static Vecs<float>& vecs(fill_plan p) { return p->v32; }
 };
 
-template <typename T> RowArgs<T> row_base(fill_plan p) {
+// Row-pass arguments covering problems 0..nprob-1 of the plan.
+template <typename T> RowArgs<T> row_base(fill_plan p, int nprob) {
   RowArgs<T> a;
   std::memset(&a, 0, sizeof(a));
   a.nx = p->nx;
   a.ny = p->ny;
   a.ldx = p->ny;
+  a.nprob = nprob;
+  a.comp_off = p->comp_off;
+  a.xt_stride = p->nt;
+  a.part_stride = (size_t)p->ny;
+  a.pix_stride = p->npix;
   a.row_off = p->row_off;
   a.pos = p->pos;
   a.Xt = static_cast<cplx<T>*>(p->Xt);
@@ -153,6 +183,19 @@ template <typename T> RowArgs<T> row_base(fill_plan p) {
   a.scale = T(1);
   a.mask = p->mask;
   return a;
+}
+template <typename T> ColArgs<T> col_base(fill_plan p, int nprob, const T* D, const CGScalars* sc) {
+  ColArgs<T> ca;
+  ca.Xt = static_cast<cplx<T>*>(p->Xt);
+  ca.ldx = p->ny;
+  ca.ncol = p->nx / 2;  // the Nyquist column travels in column 0
+  ca.D = D;
+  ca.tw = TypeSel<T>::twy(p);
+  ca.sc = sc;
+  ca.nprob = nprob;
+  ca.xt_stride = p->nt;
+  ca.d_stride = p->npk > 1 ? p->nt : 0;
+  return ca;
 }
 
 // Sum the elapsed times of the recorded event pairs (stream synchronised) and recycle them.
@@ -197,13 +240,7 @@ template <typename T>
 int apply3(fill_plan p, int rm, const RowArgs<T>& ai, const T* D, int cm, const RowArgs<T>& ao,
            const CGScalars* sc) {
   FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(rm, ai, p->stream, a, b); }));
-  ColArgs<T> ca;
-  ca.Xt = static_cast<cplx<T>*>(p->Xt);
-  ca.ldx = p->ny;
-  ca.ncol = p->nx / 2;  // the Nyquist column travels in column 0
-  ca.D = D;
-  ca.tw = TypeSel<T>::twy(p);
-  ca.sc = sc;
+  const ColArgs<T> ca = col_base<T>(p, ai.nprob, D, sc);
   FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
   FILL_TRY(timed_launch<T>(p, FILL_K_C2R, [&](hipEvent_t a, hipEvent_t b) { return launch_c2r<T>(cm, ao, p->stream, a, b); }));
   return FILL_OK;
@@ -215,13 +252,7 @@ template <typename T>
 int apply_EE(fill_plan p, int rm, const RowArgs<T>& ai, const RowArgs<T>& amid, const RowArgs<T>& ao,
              const CGScalars* sc) {
   FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(rm, ai, p->stream, a, b); }));
-  ColArgs<T> ca;
-  ca.Xt = static_cast<cplx<T>*>(p->Xt);
-  ca.ldx = p->ny;
-  ca.ncol = p->nx / 2;
-  ca.D = TypeSel<T>::Dhalf(p);
-  ca.tw = TypeSel<T>::twy(p);
-  ca.sc = sc;
+  const ColArgs<T> ca = col_base<T>(p, ai.nprob, TypeSel<T>::Dhalf(p), sc);
   FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
   FILL_TRY(timed_launch<T>(p, FILL_K_PROJ, [&](hipEvent_t a, hipEvent_t b) { return launch_proj<T>(amid, p->stream, a, b); }));
   FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
@@ -229,43 +260,51 @@ int apply_EE(fill_plan p, int rm, const RowArgs<T>& ai, const RowArgs<T>& amid, 
   return FILL_OK;
 }
 
-int read_sum(fill_plan p, const double* part, int n, double* out) {
-  HIP_TRY(launch_sum(p->dsum, part, n, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->h_sum, p->dsum, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+// Per-problem sums of the FP64 partials of a row pass -> host (synchronises).
+int read_sums(fill_plan p, const double* part, int nblk, std::vector<double>& out) {
+  HIP_TRY(launch_sum(p->dsum, part, (size_t)p->ny, nblk, p->nprob, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->h_sum, p->dsum, p->nprob * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
-  *out = *p->h_sum;
+  out.assign(p->h_sum, p->h_sum + p->nprob);
   return FILL_OK;
 }
 
-// Inner preconditioned CG on A d = r (r already in v.r, ||r|| = 1), d in v.x.
+int upload_params(fill_plan p) {
+  HIP_TRY(hipMemcpyAsync(p->par_dev, p->par_host, p->par_bytes, hipMemcpyHostToDevice, p->stream));
+  return FILL_OK;
+}
+
+// Inner preconditioned CG for every active problem on A d = r (r in v.r with
+// ||r|| = 1, d in v.x); tolerances, caps and the active set are in the device
+// parameters.  Returns per-problem iteration counts and statuses.
 template <typename T>
-int inner_pcg(fill_plan p, double tol, int cap, int* iters, int* status) {
+int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status) {
   Vecs<T>& v = TypeSel<T>::vecs(p);
-  const int nb = TypeSel<T>::nblk(p);
+  const int nb = TypeSel<T>::nblk(p), np = p->nprob;
   const T* Dinv = TypeSel<T>::Dinv(p);
-  const T* Dhalf = TypeSel<T>::Dhalf(p);
-  const size_t vb = (size_t)p->n_m * sizeof(T);
+  const size_t vb = (size_t)std::max(p->n_m_total, 1) * sizeof(T);
   HIP_TRY(hipMemsetAsync(v.x, 0, vb, p->stream));
   HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
 
   // z = E (E r); its partial sums (r.z, r.r) feed the first iteration
-  RowArgs<T> a_in = row_base<T>(p), a_mid = row_base<T>(p), a_out = row_base<T>(p);
+  RowArgs<T> a_in = row_base<T>(p, np), a_mid = row_base<T>(p, np), a_out = row_base<T>(p, np);
   a_in.v0 = v.r;
   a_out.v0 = v.z;
   a_out.v1 = v.r;
   a_out.part0 = p->part0;
   a_out.part1 = p->part1;
   FILL_TRY(apply_EE<T>(p, R2C_COMPACT, a_in, a_mid, a_out, nullptr));
-  HIP_TRY(launch_cg_init(p->sc, tol * tol, cap, p->stream));
+  HIP_TRY(launch_cg_init(p->sc, p->dp.tol2, p->dp.cap, p->dp.active, np, p->stream));
 
   // Iteration k (parity k % 2), all scalars on the device:
   //   q = A p, with beta = (r.z)/rho and p = z + beta p fused in front
   //       (partials of r.z, r.r from the previous E E r pass), p.q behind;
   //   z = E E r, with alpha = rho/(p.q), x += alpha p, r -= alpha q fused in
   //       front, r.z and r.r behind.
-  RowArgs<T> pa_in[2], pa_out = row_base<T>(p), e_in[2], e_mid = row_base<T>(p), e_out = row_base<T>(p);
+  RowArgs<T> pa_in[2], e_in[2];
+  RowArgs<T> pa_out = row_base<T>(p, np), e_mid = row_base<T>(p, np), e_out = row_base<T>(p, np);
   for (int par = 0; par < 2; ++par) {
-    pa_in[par] = row_base<T>(p);
+    pa_in[par] = row_base<T>(p, np);
     pa_in[par].v0 = v.z;
     pa_in[par].v1 = v.p;
     pa_in[par].sc = p->sc;
@@ -273,7 +312,7 @@ int inner_pcg(fill_plan p, double tol, int cap, int* iters, int* status) {
     pa_in[par].red1 = p->part1;
     pa_in[par].nred = nb;
     pa_in[par].parity = par;
-    e_in[par] = row_base<T>(p);
+    e_in[par] = row_base<T>(p, np);
     e_in[par].v0 = v.x;
     e_in[par].v1 = v.r;
     e_in[par].v2 = v.p;
@@ -300,70 +339,117 @@ int inner_pcg(fill_plan p, double tol, int cap, int* iters, int* status) {
       FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc));
       FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
     }
-    HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
-    if (p->h_sc->done) break;
+    bool all = true;
+    for (int b = 0; b < np; ++b) all = all && p->h_sc[b].done;
+    if (all) break;
   }
-  *iters = p->h_sc->iter;
-  *status = p->h_sc->status;
+  iters.resize(np);
+  status.resize(np);
+  for (int b = 0; b < np; ++b) {
+    iters[b] = p->h_sc[b].iter;
+    status[b] = p->h_sc[b].status;
+  }
   return FILL_OK;
 }
 
-// Solve A u = b (b, u compact FP64) to true relative residual rtol.
-int solve(fill_plan p, double bnorm2, double rtol) {
-  const int n = p->n_m;
-  HIP_TRY(hipMemsetAsync(p->u, 0, (size_t)n * sizeof(double), p->stream));
-  p->stats.iters_inner = 0;
-  p->stats.iters_outer = 0;
-  p->stats.rel_resid = 0.0;
-  if (bnorm2 == 0.0) return FILL_OK;
-  HIP_TRY(hipMemcpyAsync(p->res, p->b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-  double rnorm2 = bnorm2;
-  int total = 0, outer = 0, status = FILL_OK;
-  double prev_rel = 1.0;
+// Solve A u = v for every problem (v, u compact FP64), each to true relative residual rtol.
+int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
+  const int np = p->nprob;
+  const size_t nb8 = (size_t)std::max(p->n_m_total, 1) * sizeof(double);
+  HIP_TRY(hipMemsetAsync(p->u, 0, nb8, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->res, p->b, nb8, hipMemcpyDeviceToDevice, p->stream));
+  std::vector<double> rnorm2 = bnorm2, prev(np, 1.0);
+  std::vector<int> total(np, 0), outer(np, 0), done(np, 0), status(np, FILL_OK);
+  std::vector<int> it, st;
+  for (int b = 0; b < np; ++b) {
+    p->pstats[b].iters_inner = 0;
+    p->pstats[b].iters_outer = 0;
+    p->pstats[b].rel_resid = 0.0;
+  }
   for (;;) {
-    const double rel = std::sqrt(rnorm2 / bnorm2);
-    p->stats.rel_resid = rel;
-    if (!(rel == rel)) return fail(FILL_ENOTSPD, "residual is not finite");
-    if (rel <= rtol) {
-      status = FILL_OK;
-      break;
+    int nactive = 0;
+    for (int b = 0; b < np; ++b) {
+      p->hp.active[b] = 0;
+      p->hp.scale[b] = 0.0;
+      p->hp.unscale[b] = 0.0;
+      p->hp.tol2[b] = 0.0;
+      p->hp.cap[b] = 1;
+      if (done[b]) continue;
+      if (bnorm2[b] == 0.0) {
+        done[b] = 1;
+        p->pstats[b].rel_resid = 0.0;
+        continue;
+      }
+      const double rel = std::sqrt(rnorm2[b] / bnorm2[b]);
+      p->pstats[b].rel_resid = rel;
+      if (!(rel == rel)) {
+        done[b] = 1;
+        status[b] = FILL_ENOTSPD;
+        continue;
+      }
+      if (rel <= rtol) {
+        done[b] = 1;
+        continue;
+      }
+      if (total[b] >= p->max_iter || outer[b] >= kMaxOuter || (outer[b] >= 3 && rel > 0.5 * prev[b])) {
+        done[b] = 1;
+        status[b] = FILL_ENOCONV;
+        continue;
+      }
+      prev[b] = rel;
+      const double rn = std::sqrt(rnorm2[b]);
+      const double target = rtol / rel;  // inner relative reduction that reaches rtol
+      const double tol = p->prec == FILL_PREC_FP64 ? 0.5 * target : std::max(0.5 * target, p->inner_tol32);
+      p->hp.active[b] = 1;
+      p->hp.scale[b] = 1.0 / rn;
+      p->hp.unscale[b] = rn;
+      p->hp.tol2[b] = tol * tol;
+      p->hp.cap[b] = p->max_iter - total[b];
+      ++nactive;
     }
-    if (total >= p->max_iter || outer >= 60 || (outer > 0 && rel > 0.5 * prev_rel && outer >= 3)) {
-      status = fail(FILL_ENOCONV, "no convergence: true relative residual " + std::to_string(rel) +
-                                      " after " + std::to_string(total) + " CG iterations");
-      break;
-    }
-    prev_rel = rel;
-    const double rn = std::sqrt(rnorm2);
-    const double target = rtol / rel;  // inner relative reduction that reaches rtol
-    int it = 0, st = 0;
+    if (nactive == 0) break;
+    FILL_TRY(upload_params(p));
     if (p->prec == FILL_PREC_FP64) {
-      HIP_TRY(launch_scale_f64(p->v64.r, p->res, 1.0 / rn, n, p->stream));
-      FILL_TRY(inner_pcg<double>(p, 0.5 * target, p->max_iter - total, &it, &st));
-      HIP_TRY(launch_axpy_f64(p->u, p->v64.x, rn, n, p->stream));
+      HIP_TRY(launch_scale_f64(p->v64.r, p->res, p->dp.scale, p->comp_off, p->n_m_max, np, p->stream));
+      FILL_TRY(inner_pcg<double>(p, it, st));
+      HIP_TRY(launch_axpy_f64(p->u, p->v64.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
     } else {
-      HIP_TRY(launch_to_f32_scaled(p->v32.r, p->res, 1.0 / rn, n, p->stream));
-      const double tol = std::max(0.5 * target, p->inner_tol32);
-      FILL_TRY(inner_pcg<float>(p, tol, p->max_iter - total, &it, &st));
-      HIP_TRY(launch_axpy_f64_f32(p->u, p->v32.x, rn, n, p->stream));
+      HIP_TRY(launch_scale_to_f32(p->v32.r, p->res, p->dp.scale, p->comp_off, p->n_m_max, np, p->stream));
+      FILL_TRY(inner_pcg<float>(p, it, st));
+      HIP_TRY(launch_axpy_f32(p->u, p->v32.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
     }
-    total += it;
-    outer += 1;
-    p->stats.iters_inner = total;
-    p->stats.iters_outer = outer;
-    if (st == -6) return fail(FILL_ENOTSPD, "CG breakdown: p.Ap <= 0 or r.Mr <= 0");
-    // true FP64 residual res = b - A u
-    RowArgs<double> ai = row_base<double>(p), ao = row_base<double>(p);
+    for (int b = 0; b < np; ++b) {
+      if (!p->hp.active[b]) continue;
+      total[b] += it[b];
+      outer[b] += 1;
+      p->pstats[b].iters_inner = total[b];
+      p->pstats[b].iters_outer = outer[b];
+      if (st[b] == -6) {
+        done[b] = 1;
+        status[b] = FILL_ENOTSPD;
+      }
+    }
+    // true FP64 residual res = v - A u, every problem
+    RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
     ai.v0 = p->u;
     ao.v0 = p->res;
     ao.v1 = p->b;
     ao.part0 = p->part0;
     FILL_TRY(apply3<double>(p, R2C_COMPACT, ai, p->Dinv64, C2R_RESID, ao, nullptr));
-    FILL_TRY(read_sum(p, p->part0, p->nblk64, &rnorm2));
+    FILL_TRY(read_sums(p, p->part0, p->nblk64, rnorm2));
   }
-  p->stats.rel_resid = std::sqrt(rnorm2 / bnorm2);
-  return status;
+  int worst = FILL_OK;
+  for (int b = 0; b < np; ++b) {
+    if (bnorm2[b] > 0.0) p->pstats[b].rel_resid = std::sqrt(rnorm2[b] / bnorm2[b]);
+    p->pstats[b].status = status[b];
+    if (status[b] == FILL_ENOTSPD) worst = FILL_ENOTSPD;
+    else if (status[b] == FILL_ENOCONV && worst == FILL_OK) worst = FILL_ENOCONV;
+  }
+  if (worst == FILL_ENOTSPD) return fail(FILL_ENOTSPD, "CG breakdown (p.Ap <= 0 or r.Mr <= 0) or non-finite residual");
+  if (worst == FILL_ENOCONV) return fail(FILL_ENOCONV, "no convergence to the requested true residual");
+  return FILL_OK;
 }
 
 bool size_ok(int n) {
@@ -413,58 +499,71 @@ int twiddles(int n, std::vector<double2>& w64, std::vector<float2>& w32) {
   return fail(FILL_EUNSUPPORTED_SIZE, "no FFT plan for length " + std::to_string(n));
 }
 
-int upload_pk(fill_plan p, const double* Pk) {
+// Tables 1/(P N) and sqrt(P)/N, transposed (spectral column kx contiguous in ky).
+int upload_pk(fill_plan p, const double* Pk, int npk) {
   const int nx = p->nx, ny = p->ny, nc = p->ncol;
-  const size_t nt = (size_t)nc * ny;
+  const size_t nt = p->nt;
   std::vector<double> inv(nt), half(nt);
   std::vector<float> inv32(nt), half32(nt);
   const double scale = 1.0 / ((double)nx * (double)ny);
-  for (int iy = 0; iy < ny; ++iy) {
-    for (int ix = 0; ix < nc; ++ix) {
-      const double P = Pk[(size_t)iy * nc + ix];
-      if (!(P > 0.0) || !std::isfinite(P))
-        return fail(FILL_ENOTSPD, "Pk[" + std::to_string(iy) + "," + std::to_string(ix) + "] = " +
-                                      std::to_string(P) + " is not positive and finite");
-      const size_t o = (size_t)ix * ny + iy;  // transposed: spectral column kx contiguous in ky
-      inv[o] = scale / P;
-      half[o] = scale * std::sqrt(P);
-      inv32[o] = (float)inv[o];
-      half32[o] = (float)half[o];
+  for (int k = 0; k < npk; ++k) {
+    const double* P0 = Pk + (size_t)k * ny * nc;
+    for (int iy = 0; iy < ny; ++iy) {
+      for (int ix = 0; ix < nc; ++ix) {
+        const double P = P0[(size_t)iy * nc + ix];
+        if (!(P > 0.0) || !std::isfinite(P))
+          return fail(FILL_ENOTSPD, "Pk[" + std::to_string(k) + "][" + std::to_string(iy) + "," +
+                                        std::to_string(ix) + "] = " + std::to_string(P) +
+                                        " is not positive and finite");
+        const size_t o = (size_t)ix * ny + iy;
+        inv[o] = scale / P;
+        half[o] = scale * std::sqrt(P);
+        inv32[o] = (float)inv[o];
+        half32[o] = (float)half[o];
+      }
     }
+    HIP_TRY(hipMemcpy(p->Dinv64 + k * nt, inv.data(), nt * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->Dhalf64 + k * nt, half.data(), nt * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->Dinv32 + k * nt, inv32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->Dhalf32 + k * nt, half32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
   }
-  HIP_TRY(hipMemcpy(p->Dinv64, inv.data(), nt * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->Dhalf64, half.data(), nt * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->Dinv32, inv32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->Dhalf32, half32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
   return FILL_OK;
 }
 
 int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
-  const int nx = p->nx, ny = p->ny;
-  const size_t npix = p->npix, nt = (size_t)p->ncol * ny;
-  // mask -> compact index (row-major) and per-row offsets
-  std::vector<int> pos;
-  std::vector<int> row_off(ny + 1, 0);
-  std::vector<uint8_t> m01(npix);
-  for (int y = 0; y < ny; ++y) {
-    row_off[y] = (int)pos.size();
-    for (int x = 0; x < nx; ++x) {
-      const size_t i = (size_t)y * nx + x;
-      m01[i] = mask[i] ? 1 : 0;
-      if (m01[i]) pos.push_back((int)i);
+  const int nx = p->nx, ny = p->ny, np = p->nprob;
+  const size_t npix = p->npix, nt = p->nt;
+  // masks -> compact index (row-major per problem) and per-row offsets
+  std::vector<int> pos, row_off((size_t)np * (ny + 1), 0);
+  std::vector<uint8_t> m01(npix * np);
+  p->n_m.assign(np, 0);
+  p->coff.assign(np + 1, 0);
+  for (int b = 0; b < np; ++b) {
+    p->coff[b] = (int)pos.size();
+    for (int y = 0; y < ny; ++y) {
+      row_off[(size_t)b * (ny + 1) + y] = (int)pos.size() - p->coff[b];
+      for (int x = 0; x < nx; ++x) {
+        const size_t i = (size_t)y * nx + x;
+        const bool m = mask[(size_t)b * npix + i] != 0;
+        m01[(size_t)b * npix + i] = m ? 1 : 0;
+        if (m) pos.push_back((int)i);
+      }
     }
+    p->n_m[b] = (int)pos.size() - p->coff[b];
+    row_off[(size_t)b * (ny + 1) + ny] = p->n_m[b];
   }
-  row_off[ny] = (int)pos.size();
-  p->n_m = (int)pos.size();
-  p->stats.n_masked = p->n_m;
-  const int nm = std::max(p->n_m, 1);
-  FILL_TRY(dalloc(p, &p->mask, npix));
+  p->coff[np] = (int)pos.size();
+  p->n_m_total = (int)pos.size();
+  p->n_m_max = *std::max_element(p->n_m.begin(), p->n_m.end());
+  const int nm = std::max(p->n_m_total, 1);
+  FILL_TRY(dalloc(p, &p->mask, npix * np));
   FILL_TRY(dalloc(p, &p->pos, nm));
-  FILL_TRY(dalloc(p, &p->row_off, ny + 1));
-  FILL_TRY(dalloc(p, &p->Dinv64, nt));
-  FILL_TRY(dalloc(p, &p->Dhalf64, nt));
-  FILL_TRY(dalloc(p, &p->Dinv32, nt));
-  FILL_TRY(dalloc(p, &p->Dhalf32, nt));
+  FILL_TRY(dalloc(p, &p->row_off, (size_t)np * (ny + 1)));
+  FILL_TRY(dalloc(p, &p->comp_off, np + 1));
+  FILL_TRY(dalloc(p, &p->Dinv64, nt * p->npk));
+  FILL_TRY(dalloc(p, &p->Dhalf64, nt * p->npk));
+  FILL_TRY(dalloc(p, &p->Dinv32, nt * p->npk));
+  FILL_TRY(dalloc(p, &p->Dhalf32, nt * p->npk));
   std::vector<double2> twx64, twy64;
   std::vector<float2> twx32, twy32;
   FILL_TRY(twiddles(nx, twx64, twx32));
@@ -474,77 +573,158 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   FILL_TRY(dalloc(p, &p->twx32, twx32.size()));
   FILL_TRY(dalloc(p, &p->twy32, twy32.size()));
   double2* xt = nullptr;
-  FILL_TRY(dalloc(p, &xt, nt));
+  FILL_TRY(dalloc(p, &xt, nt * np));
   p->Xt = xt;
-  FILL_TRY(dalloc(p, &p->tfull, npix));
+  FILL_TRY(dalloc(p, &p->tfull, npix * np));
   FILL_TRY(dalloc(p, &p->b, nm));
   FILL_TRY(dalloc(p, &p->u, nm));
   FILL_TRY(dalloc(p, &p->res, nm));
   for (double** q : {&p->v64.x, &p->v64.r, &p->v64.z, &p->v64.p, &p->v64.q, &p->v64.t}) FILL_TRY(dalloc(p, q, nm));
   for (float** q : {&p->v32.x, &p->v32.r, &p->v32.z, &p->v32.p, &p->v32.q, &p->v32.t}) FILL_TRY(dalloc(p, q, nm));
-  FILL_TRY(dalloc(p, &p->part0, ny));
-  FILL_TRY(dalloc(p, &p->part1, ny));
-  FILL_TRY(dalloc(p, &p->part2, ny));
-  FILL_TRY(dalloc(p, &p->dsum, 4));
-  FILL_TRY(dalloc(p, &p->sc, 1));
-  HIP_TRY(hipHostMalloc((void**)&p->h_sc, sizeof(CGScalars), hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc((void**)&p->h_sum, 4 * sizeof(double), hipHostMallocDefault));
+  FILL_TRY(dalloc(p, &p->part0, (size_t)ny * np));
+  FILL_TRY(dalloc(p, &p->part1, (size_t)ny * np));
+  FILL_TRY(dalloc(p, &p->part2, (size_t)ny * np));
+  FILL_TRY(dalloc(p, &p->dsum, np));
+  FILL_TRY(dalloc(p, &p->sc, np));
+  // per-call parameter block: same layout on host (pinned) and device
+  const size_t n8 = (size_t)np * 8;
+  p->par_bytes = 8 * n8;
+  char* dpar = nullptr;
+  FILL_TRY(dalloc(p, &dpar, p->par_bytes));
+  p->par_dev = dpar;
+  HIP_TRY(hipHostMalloc(&p->par_host, p->par_bytes, hipHostMallocDefault));
+  std::memset(p->par_host, 0, p->par_bytes);
+  auto carve = [&](char* base, Params& q) {
+    q.scale = reinterpret_cast<double*>(base + 0 * n8);
+    q.unscale = reinterpret_cast<double*>(base + 1 * n8);
+    q.tol2 = reinterpret_cast<double*>(base + 2 * n8);
+    q.cap = reinterpret_cast<int*>(base + 3 * n8);
+    q.active = reinterpret_cast<int*>(base + 4 * n8);
+    q.in_tab = reinterpret_cast<const double**>(base + 5 * n8);
+    q.out_tab = reinterpret_cast<double**>(base + 6 * n8);
+    q.seeds = reinterpret_cast<uint64_t*>(base + 7 * n8);
+  };
+  carve(dpar, p->dp);
+  carve(static_cast<char*>(p->par_host), p->hp);
+  HIP_TRY(hipHostMalloc((void**)&p->h_sc, np * sizeof(CGScalars), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&p->h_sum, np * sizeof(double), hipHostMallocDefault));
+  p->pstats.assign(np, fill_stats{});
+  for (int b = 0; b < np; ++b) p->pstats[b].n_masked = p->n_m[b];
 
-  HIP_TRY(hipMemcpy(p->mask, m01.data(), npix, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->mask, m01.data(), npix * np, hipMemcpyHostToDevice));
   if (!pos.empty()) HIP_TRY(hipMemcpy(p->pos, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->row_off, row_off.data(), (ny + 1) * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->row_off, row_off.data(), row_off.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->comp_off, p->coff.data(), (np + 1) * sizeof(int), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->twx64, twx64.data(), twx64.size() * sizeof(double2), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->twx32, twx32.data(), twx32.size() * sizeof(float2), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->twy64, twy64.data(), twy64.size() * sizeof(double2), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->twy32, twy32.data(), twy32.size() * sizeof(float2), hipMemcpyHostToDevice));
-  return upload_pk(p, Pk);
+  return upload_pk(p, Pk, p->npk);
 }
 
-// Steps 2-4 of a solve, after x_out and t = Py(d - s) (or Py d) are in place.
-int rhs_solve_assemble(fill_plan p, double* x_out, double rtol) {
-  RowArgs<double> ai = row_base<double>(p), ao = row_base<double>(p);
+int check_maps(fill_plan p, const double* const* d, double* const* x) {
+  if (!d || !x) return fail(FILL_EINVAL, "NULL map array");
+  for (int b = 0; b < p->nprob; ++b) {
+    if (!d[b] || !x[b]) return fail(FILL_EINVAL, "NULL map for problem " + std::to_string(b));
+    if ((const void*)d[b] == (const void*)x[b]) return fail(FILL_EINVAL, "x_out aliases d_obs");
+  }
+  return FILL_OK;
+}
+
+// After x_out and t = Py (d - s) (or Py d) are in place: RHS, solve, assembly.
+int rhs_solve_assemble(fill_plan p, double rtol) {
+  const int np = p->nprob;
+  RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
   ai.full_in = p->tfull;
   ao.v0 = p->b;
   ao.scale = -1.0;
   ao.part0 = p->part0;
   FILL_TRY(apply3<double>(p, R2C_FULL, ai, p->Dinv64, C2R_COMPACT, ao, nullptr));
-  double bnorm2 = 0.0;
-  FILL_TRY(read_sum(p, p->part0, p->nblk64, &bnorm2));
+  std::vector<double> bnorm2;
+  FILL_TRY(read_sums(p, p->part0, p->nblk64, bnorm2));
   const int st = solve(p, bnorm2, rtol);
   if (st != FILL_OK && st != FILL_ENOCONV) return st;
-  HIP_TRY(launch_scatter_add(x_out, p->u, p->pos, p->n_m, p->stream));
+  HIP_TRY(launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, np, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return st;
 }
 
+void finish_stats(fill_plan p, int st, double ms) {
+  fill_stats agg{0, 0, p->n_m_total, st, 0.0, ms};
+  for (int b = 0; b < p->nprob; ++b) {
+    p->pstats[b].solve_ms = ms;
+    agg.iters_inner = std::max(agg.iters_inner, p->pstats[b].iters_inner);
+    agg.iters_outer = std::max(agg.iters_outer, p->pstats[b].iters_outer);
+    agg.rel_resid = std::max(agg.rel_resid, p->pstats[b].rel_resid);
+  }
+  p->stats = agg;
+}
+
 using clk = std::chrono::steady_clock;
 
-}  // namespace
+int realize_impl(fill_plan p, const double* const* d, const uint64_t* seeds, double* const* x, double rtol,
+                 bool mean) {
+  g_last_error.clear();
+  if (!p) return fail(FILL_EINVAL, "NULL plan");
+  if (!(rtol > 0.0)) return fail(FILL_EINVAL, "rtol must be > 0");
+  FILL_TRY(check_maps(p, d, x));
+  if (!mean && !seeds) return fail(FILL_EINVAL, "NULL seeds");
+  const auto t0 = clk::now();
+  const int np = p->nprob;
+  // the previous call's parameter upload must have completed before the
+  // pinned staging block is rewritten
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int b = 0; b < np; ++b) {
+    p->pstats[b] = fill_stats{0, 0, p->n_m[b], 0, 0.0, 0.0};
+    p->hp.in_tab[b] = d[b];
+    p->hp.out_tab[b] = x[b];
+    p->hp.seeds[b] = mean ? 0 : seeds[b];
+  }
+  if (p->n_m_total == 0) {
+    for (int b = 0; b < np; ++b)
+      HIP_TRY(hipMemcpyAsync(x[b], d[b], p->npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    finish_stats(p, FILL_OK, std::chrono::duration<double, std::milli>(clk::now() - t0).count());
+    return FILL_OK;
+  }
+  FILL_TRY(upload_params(p));
+  if (mean) {
+    HIP_TRY(launch_mean_prep(p->dp.out_tab, p->tfull, p->dp.in_tab, p->mask, p->npix, np, p->stream));
+  } else {
+    // s = C^{1/2} w; x_out = mask ? s : d; t = mask ? 0 : d - s
+    RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
+    ai.seeds = p->dp.seeds;
+    ai.stream = kRealizationStream;
+    ao.fin_tab = p->dp.in_tab;
+    ao.fout_tab = p->dp.out_tab;
+    ao.full_in = d[0];  // non-null: selects the observed-data branch
+    ao.full_out2 = p->tfull;
+    FILL_TRY(apply3<double>(p, R2C_NOISE, ai, p->Dhalf64, C2R_REALIZE, ao, nullptr));
+  }
+  const int st = rhs_solve_assemble(p, rtol);
+  finish_stats(p, st, std::chrono::duration<double, std::milli>(clk::now() - t0).count());
+  return st;
+}
 
-namespace {
 template <typename T>
 int time_kernel(fill_plan p, int kernel, int reps, double* avg_ms) {
   Vecs<T>& v = TypeSel<T>::vecs(p);
-  const size_t vb = (size_t)std::max(p->n_m, 1) * sizeof(T);
+  const size_t vb = (size_t)std::max(p->n_m_total, 1) * sizeof(T);
   HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
-  RowArgs<T> ai = row_base<T>(p), ao = row_base<T>(p);
+  RowArgs<T> ai = row_base<T>(p, 1), ao = row_base<T>(p, 1);
   ai.v0 = v.p;
   ao.v0 = v.q;
   ao.v1 = v.p;
   ao.part0 = p->part0;
-  ColArgs<T> ca;
-  ca.Xt = static_cast<cplx<T>*>(p->Xt);
-  ca.ldx = p->ny;
-  ca.ncol = p->nx / 2;
-  ca.D = TypeSel<T>::Dinv(p);
-  ca.tw = TypeSel<T>::twy(p);
-  ca.sc = nullptr;
+  const ColArgs<T> ca = col_base<T>(p, 1, TypeSel<T>::Dinv(p), nullptr);
+  RowArgs<T> am = row_base<T>(p, 1);
   auto launch = [&]() -> hipError_t {
     hipError_t e = hipSuccess;
     if (kernel == FILL_K_R2C || kernel == FILL_K_APPLY) e = launch_r2c<T>(R2C_COMPACT, ai, p->stream);
     if (e == hipSuccess && (kernel == FILL_K_COL || kernel == FILL_K_APPLY)) e = launch_col<T>(p->ny, ca, p->stream);
     if (e == hipSuccess && (kernel == FILL_K_C2R || kernel == FILL_K_APPLY))
       e = launch_c2r<T>(C2R_COMPACT, ao, p->stream);
+    if (e == hipSuccess && kernel == FILL_K_PROJ) e = launch_proj<T>(am, p->stream);
     return e;
   };
   HIP_TRY(launch());  // warm-up
@@ -562,6 +742,10 @@ int time_kernel(fill_plan p, int kernel, int reps, double* avg_ms) {
   *avg_ms = (double)ms / reps;
   return FILL_OK;
 }
+
+int plan_create_impl(int nx, int ny, int nprob, const uint8_t* masks, const double* Pk, int npk, int prec,
+                     void* stream, fill_plan* out);
+
 }  // namespace
 
 extern "C" {
@@ -570,43 +754,21 @@ int fill_supported_size(int n) { return size_ok(n) ? 1 : 0; }
 
 int fill_plan_create(int nx, int ny, const uint8_t* mask, const double* Pk, int prec, void* stream,
                      fill_plan* out) {
-  g_last_error.clear();
-  if (!out) return fail(FILL_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!mask || !Pk) return fail(FILL_EINVAL, "mask or Pk is NULL");
-  if (prec != FILL_PREC_FP64 && prec != FILL_PREC_FP32_OP) return fail(FILL_EINVAL, "unknown precision");
-  if (!size_ok(nx) || !size_ok(ny))
-    return fail(FILL_EUNSUPPORTED_SIZE, "grid " + std::to_string(nx) + "x" + std::to_string(ny) +
-                                            " is not a supported FFT size");
-  fill_plan p = new (std::nothrow) fill_plan_s();
-  if (!p) return fail(FILL_ENOMEM, "host allocation");
-  p->nx = nx;
-  p->ny = ny;
-  p->ncol = nx / 2 + 1;
-  p->prec = prec;
-  p->npix = (size_t)nx * ny;
-  p->stream = static_cast<hipStream_t>(stream);
-  const int r64 = row_block_rows<double>(nx), r32 = row_block_rows<float>(nx);
-  if (r64 <= 0 || r32 <= 0 || ny % r64 || ny % r32) {
-    delete p;
-    return fail(FILL_EUNSUPPORTED_SIZE, "ny not a multiple of the row block");
-  }
-  p->nblk64 = ny / r64;
-  p->nblk32 = ny / r32;
-  const int rc = plan_build(p, mask, Pk);
-  if (rc != FILL_OK) {
-    fill_plan_destroy(p);
-    return rc;
-  }
-  *out = p;
-  return FILL_OK;
+  return plan_create_impl(nx, ny, 1, mask, Pk, 1, prec, stream, out);
 }
+
+int fill_plan_create_batch(int nx, int ny, int nprob, const uint8_t* masks, const double* Pk, int n_pk, int prec,
+                           void* stream, fill_plan* out) {
+  return plan_create_impl(nx, ny, nprob, masks, Pk, n_pk, prec, stream, out);
+}
+
+int fill_plan_nprob(fill_plan p) { return p ? p->nprob : 0; }
 
 int fill_plan_set_pk(fill_plan p, const double* Pk) {
   g_last_error.clear();
   if (!p || !Pk) return fail(FILL_EINVAL, "NULL argument");
   HIP_TRY(hipStreamSynchronize(p->stream));
-  return upload_pk(p, Pk);
+  return upload_pk(p, Pk, p->npk);
 }
 
 int fill_plan_set_max_iter(fill_plan p, int max_iter) {
@@ -628,57 +790,62 @@ void fill_plan_destroy(fill_plan p) {
   for (void* a : p->allocs) (void)hipFree(a);
   if (p->h_sc) (void)hipHostFree(p->h_sc);
   if (p->h_sum) (void)hipHostFree(p->h_sum);
+  if (p->par_host) (void)hipHostFree(p->par_host);
   delete p;
 }
 
 int fill_realize(fill_plan p, const double* d_obs, uint64_t seed, double* x_out, double rtol) {
-  g_last_error.clear();
-  if (!p || !d_obs || !x_out) return fail(FILL_EINVAL, "NULL argument");
-  if (!(rtol > 0.0)) return fail(FILL_EINVAL, "rtol must be > 0");
-  if ((const void*)d_obs == (const void*)x_out) return fail(FILL_EINVAL, "x_out aliases d_obs");
-  const auto t0 = clk::now();
-  p->stats = fill_stats{0, 0, p->n_m, 0, 0.0, 0.0};
-  if (p->n_m == 0) {
-    HIP_TRY(hipMemcpyAsync(x_out, d_obs, p->npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    return FILL_OK;
-  }
-  // s = C^{1/2} w; x_out = mask ? s : d; t = mask ? 0 : d - s
-  RowArgs<double> ai = row_base<double>(p), ao = row_base<double>(p);
-  ai.seed = seed;
-  ai.stream = kRealizationStream;
-  ao.full_in = d_obs;
-  ao.full_out = x_out;
-  ao.full_out2 = p->tfull;
-  FILL_TRY(apply3<double>(p, R2C_NOISE, ai, p->Dhalf64, C2R_REALIZE, ao, nullptr));
-  const int st = rhs_solve_assemble(p, x_out, rtol);
-  p->stats.status = st;
-  p->stats.solve_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-  return st;
+  if (p && p->nprob != 1) return fail(FILL_EINVAL, "plan holds several problems: use fill_realize_batch");
+  return realize_impl(p, &d_obs, &seed, &x_out, rtol, false);
 }
 
 int fill_mean(fill_plan p, const double* d_obs, double* x_out, double rtol) {
+  if (p && p->nprob != 1) return fail(FILL_EINVAL, "plan holds several problems: use fill_mean_batch");
+  return realize_impl(p, &d_obs, nullptr, &x_out, rtol, true);
+}
+
+int fill_realize_batch(fill_plan p, const double* const* d_obs, const uint64_t* seeds, double* const* x_out,
+                       double rtol) {
+  return realize_impl(p, d_obs, seeds, x_out, rtol, false);
+}
+
+int fill_mean_batch(fill_plan p, const double* const* d_obs, double* const* x_out, double rtol) {
+  return realize_impl(p, d_obs, nullptr, x_out, rtol, true);
+}
+
+int fill_realize_multi(int nplans, const fill_plan* plans, const double* const* const* d_obs,
+                       const uint64_t* const* seeds, double* const* const* x_out, double rtol) {
   g_last_error.clear();
-  if (!p || !d_obs || !x_out) return fail(FILL_EINVAL, "NULL argument");
-  if (!(rtol > 0.0)) return fail(FILL_EINVAL, "rtol must be > 0");
-  if ((const void*)d_obs == (const void*)x_out) return fail(FILL_EINVAL, "x_out aliases d_obs");
-  const auto t0 = clk::now();
-  p->stats = fill_stats{0, 0, p->n_m, 0, 0.0, 0.0};
-  if (p->n_m == 0) {
-    HIP_TRY(hipMemcpyAsync(x_out, d_obs, p->npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    return FILL_OK;
+  if (nplans < 1 || !plans || !d_obs || !seeds || !x_out) return fail(FILL_EINVAL, "bad argument");
+  std::vector<int> rc(nplans, FILL_OK);
+  std::vector<std::string> err(nplans);
+  std::vector<std::thread> th;
+  for (int i = 0; i < nplans; ++i) {
+    th.emplace_back([&, i] {
+      rc[i] = realize_impl(plans[i], d_obs[i], seeds[i], x_out[i], rtol, false);
+      err[i] = g_last_error;
+    });
   }
-  HIP_TRY(launch_mean_prep(x_out, p->tfull, d_obs, p->mask, p->npix, p->stream));
-  const int st = rhs_solve_assemble(p, x_out, rtol);
-  p->stats.status = st;
-  p->stats.solve_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-  return st;
+  for (auto& t : th) t.join();
+  int worst = FILL_OK;
+  for (int i = 0; i < nplans; ++i) {
+    if (rc[i] != FILL_OK && (worst == FILL_OK || worst == FILL_ENOCONV)) {
+      worst = rc[i];
+      g_last_error = "plan " + std::to_string(i) + ": " + err[i];
+    }
+  }
+  return worst;
 }
 
 int fill_get_stats(fill_plan p, fill_stats* out) {
   if (!p || !out) return fail(FILL_EINVAL, "NULL argument");
   *out = p->stats;
+  return FILL_OK;
+}
+
+int fill_get_stats_batch(fill_plan p, fill_stats* out) {
+  if (!p || !out) return fail(FILL_EINVAL, "NULL argument");
+  for (int b = 0; b < p->nprob; ++b) out[b] = p->pstats[b];
   return FILL_OK;
 }
 
@@ -689,15 +856,16 @@ int fill_apply(fill_plan p, int op, int prec, const double* in, double* out) {
   if (op < FILL_OP_CINV || op > FILL_OP_E) return fail(FILL_EINVAL, "unknown operator");
   if (prec != FILL_PREC_FP64 && prec != FILL_PREC_FP32_OP) return fail(FILL_EINVAL, "unknown precision");
   const bool inv = (op == FILL_OP_CINV || op == FILL_OP_A);
-  const int n = p->n_m;
+  const int n = p->n_m[0];
+  HIP_TRY(hipStreamSynchronize(p->stream));
   if (op == FILL_OP_CINV || op == FILL_OP_CHALF) {
     if (prec == FILL_PREC_FP64) {
-      RowArgs<double> ai = row_base<double>(p), ao = row_base<double>(p);
+      RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
       ai.full_in = in;
       ao.full_out = out;
       FILL_TRY(apply3<double>(p, R2C_FULL, ai, inv ? p->Dinv64 : p->Dhalf64, C2R_FULL, ao, nullptr));
     } else {
-      RowArgs<float> ai = row_base<float>(p), ao = row_base<float>(p);
+      RowArgs<float> ai = row_base<float>(p, 1), ao = row_base<float>(p, 1);
       ai.full_in = in;
       ao.full_out = out;
       FILL_TRY(apply3<float>(p, R2C_FULL, ai, inv ? p->Dinv32 : p->Dhalf32, C2R_FULL, ao, nullptr));
@@ -707,14 +875,16 @@ int fill_apply(fill_plan p, int op, int prec, const double* in, double* out) {
     if (n > 0) {
       HIP_TRY(launch_gather(p->res, in, p->pos, n, p->stream));
       if (prec == FILL_PREC_FP64) {
-        RowArgs<double> ai = row_base<double>(p), ao = row_base<double>(p);
+        RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
         ai.v0 = p->res;
         ao.v0 = p->v64.q;
         FILL_TRY(apply3<double>(p, R2C_COMPACT, ai, inv ? p->Dinv64 : p->Dhalf64, C2R_COMPACT, ao, nullptr));
         HIP_TRY(launch_scatter(out, p->v64.q, p->pos, n, p->stream));
       } else {
-        HIP_TRY(launch_to_f32_scaled(p->v32.t, p->res, 1.0, n, p->stream));
-        RowArgs<float> ai = row_base<float>(p), ao = row_base<float>(p);
+        p->hp.scale[0] = 1.0;
+        FILL_TRY(upload_params(p));
+        HIP_TRY(launch_scale_to_f32(p->v32.t, p->res, p->dp.scale, p->comp_off, n, 1, p->stream));
+        RowArgs<float> ai = row_base<float>(p, 1), ao = row_base<float>(p, 1);
         ai.v0 = p->v32.t;
         ao.v0 = p->v32.q;
         FILL_TRY(apply3<float>(p, R2C_COMPACT, ai, inv ? p->Dinv32 : p->Dhalf32, C2R_COMPACT, ao, nullptr));
@@ -729,7 +899,7 @@ int fill_apply(fill_plan p, int op, int prec, const double* in, double* out) {
 int fill_realize_unconstrained(fill_plan p, uint64_t seed, double* out) {
   g_last_error.clear();
   if (!p || !out) return fail(FILL_EINVAL, "NULL argument");
-  RowArgs<double> ai = row_base<double>(p), ao = row_base<double>(p);
+  RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
   ai.seed = seed;
   ai.stream = kRealizationStream;
   ao.full_out = out;
@@ -749,7 +919,7 @@ int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t
 int fill_time_kernel(fill_plan p, int kernel, int prec, int reps, double* avg_ms) {
   g_last_error.clear();
   if (!p || !avg_ms || reps < 1) return fail(FILL_EINVAL, "bad argument");
-  if (kernel < FILL_K_R2C || kernel > FILL_K_APPLY) return fail(FILL_EINVAL, "unknown kernel");
+  if (kernel < FILL_K_R2C || kernel > FILL_K_PROJ) return fail(FILL_EINVAL, "unknown kernel");
   if (prec == FILL_PREC_FP64) return time_kernel<double>(p, kernel, reps, avg_ms);
   if (prec == FILL_PREC_FP32_OP) return time_kernel<float>(p, kernel, reps, avg_ms);
   return fail(FILL_EINVAL, "unknown precision");
@@ -795,3 +965,46 @@ const char* fill_strerror(int code) {
 const char* fill_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+namespace {
+
+int plan_create_impl(int nx, int ny, int nprob, const uint8_t* masks, const double* Pk, int npk, int prec,
+                     void* stream, fill_plan* out) {
+  g_last_error.clear();
+  if (!out) return fail(FILL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!masks || !Pk) return fail(FILL_EINVAL, "mask or Pk is NULL");
+  if (nprob < 1) return fail(FILL_EINVAL, "nprob must be >= 1");
+  if (npk != 1 && npk != nprob) return fail(FILL_EINVAL, "n_pk must be 1 or nprob");
+  if (prec != FILL_PREC_FP64 && prec != FILL_PREC_FP32_OP) return fail(FILL_EINVAL, "unknown precision");
+  if (!size_ok(nx) || !size_ok(ny))
+    return fail(FILL_EUNSUPPORTED_SIZE, "grid " + std::to_string(nx) + "x" + std::to_string(ny) +
+                                            " is not a supported FFT size");
+  fill_plan p = new (std::nothrow) fill_plan_s();
+  if (!p) return fail(FILL_ENOMEM, "host allocation");
+  p->nx = nx;
+  p->ny = ny;
+  p->ncol = nx / 2 + 1;
+  p->prec = prec;
+  p->nprob = nprob;
+  p->npk = npk;
+  p->npix = (size_t)nx * ny;
+  p->nt = (size_t)p->ncol * ny;
+  p->stream = static_cast<hipStream_t>(stream);
+  const int r64 = row_block_rows<double>(nx), r32 = row_block_rows<float>(nx);
+  if (r64 <= 0 || r32 <= 0 || ny % r64 || ny % r32) {
+    delete p;
+    return fail(FILL_EUNSUPPORTED_SIZE, "ny not a multiple of the row block");
+  }
+  p->nblk64 = ny / r64;
+  p->nblk32 = ny / r32;
+  const int rc = plan_build(p, masks, Pk);
+  if (rc != FILL_OK) {
+    fill_plan_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return FILL_OK;
+}
+
+}  // namespace

@@ -55,8 +55,20 @@ enum C2RMode {
   C2R_FULL = 4       // full_out = scale*val
 };
 
+// Arguments of the row passes.  A launch covers nprob problems of the same
+// grid (blockIdx.y = problem): pointers are problem 0's and bind_problem()
+// moves them to problem blockIdx.y (compact vectors by comp_off, the rest by
+// the strides).
 template <typename T> struct RowArgs {
   int nx, ny, ldx;
+  int nprob;
+  const int* comp_off;           // nprob+1 compact offsets (null: one problem)
+  size_t xt_stride;              // complex values between problems' spectra
+  size_t part_stride;            // partial-sum slots per problem
+  size_t pix_stride;             // pixels between problems' internal maps and masks
+  const double* const* fin_tab;  // caller input maps per problem (null: full_in + b*pix_stride)
+  double* const* fout_tab;       // caller output maps per problem (null: full_out + b*pix_stride)
+  const uint64_t* seeds;         // per-problem seeds (null: seed)
   const int* row_off;
   const int* pos;
   cplx<T>* Xt;
@@ -86,7 +98,40 @@ template <typename T> struct ColArgs {
   const T* D;
   const cplx<T>* tw;
   const CGScalars* sc;
+  int nprob;
+  size_t xt_stride;  // complex values between problems' spectra
+  size_t d_stride;   // table entries between problems' tables (0: one shared table)
 };
+
+template <typename T> __device__ __forceinline__ RowArgs<T> bind_problem(RowArgs<T> a) {
+  const int b = blockIdx.y;
+  if (b == 0) return a;
+  const int coff = a.comp_off ? a.comp_off[b] : 0;
+  a.row_off += (size_t)b * (a.ny + 1);
+  a.pos += coff;
+  if (a.v0) a.v0 += coff;
+  if (a.v1) a.v1 += coff;
+  if (a.v2) a.v2 += coff;
+  if (a.v3) a.v3 += coff;
+  a.Xt += (size_t)b * a.xt_stride;
+  if (a.sc) a.sc += b;
+  if (a.part0) a.part0 += (size_t)b * a.part_stride;
+  if (a.part1) a.part1 += (size_t)b * a.part_stride;
+  if (a.red0) a.red0 += (size_t)b * a.part_stride;
+  if (a.red1) a.red1 += (size_t)b * a.part_stride;
+  if (a.mask) a.mask += (size_t)b * a.pix_stride;
+  if (a.full_in) a.full_in += (size_t)b * a.pix_stride;
+  if (a.full_out) a.full_out += (size_t)b * a.pix_stride;
+  if (a.full_out2) a.full_out2 += (size_t)b * a.pix_stride;
+  return a;
+}
+// Per-problem caller maps and seeds (valid for every problem index, 0 included).
+template <typename T> __device__ __forceinline__ void bind_caller(RowArgs<T>& a) {
+  const int b = blockIdx.y;
+  if (a.fin_tab) a.full_in = a.fin_tab[b];
+  if (a.fout_tab) a.full_out = a.fout_tab[b];
+  if (a.seeds) a.seed = a.seeds[b];
+}
 
 // One CG scalar step, taken redundantly by every workgroup of the row pass
 // that needs it: the previous pass's per-workgroup partial sums are added in
@@ -159,8 +204,10 @@ template <int MODE> constexpr bool c2r_is_compact() { return MODE <= C2R_RESID; 
 // r2c
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T> a) {
+__global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T> a_in) {
   using C = cplx<T>;
+  RowArgs<T> a = bind_problem(a_in);
+  bind_caller(a);
   using CF = RowCfg<T, N>;
   constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS, H = CF::H;
   constexpr int LE = lds_line_elems<N>();
@@ -307,8 +354,10 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
 // c2r
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T> a) {
+__global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T> a_in) {
   using C = cplx<T>;
+  RowArgs<T> a = bind_problem(a_in);
+  bind_caller(a);
   using CF = RowCfg<T, N>;
   constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS, H = CF::H;
   constexpr int LE = lds_line_elems<N>();
@@ -478,8 +527,10 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
 // The projected map never leaves the chip.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
-__global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T> a) {
+__global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T> a_in) {
   using C = cplx<T>;
+  RowArgs<T> a = bind_problem(a_in);
+  bind_caller(a);
   using CF = RowCfg<T, N>;
   constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS;
   constexpr int LE = lds_line_elems<N>();
@@ -560,13 +611,17 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
 // column pass: forward FFT along y, multiply by D, inverse FFT along y
 // ---------------------------------------------------------------------------
 template <typename T, int N>
-__global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T> a) {
+__global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T> a_in) {
   using C = cplx<T>;
   using CF = ColCfg<T, N>;
   constexpr int E = CF::E, TPL = CF::TPL, W = CF::W;
   constexpr int LE = lds_line_elems<N>();
   __shared__ C lds[W * LE];
   __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
+  ColArgs<T> a = a_in;
+  a.Xt += (size_t)blockIdx.y * a.xt_stride;
+  a.D += (size_t)blockIdx.y * a.d_stride;
+  if (a.sc) a.sc += blockIdx.y;
   if (a.sc != nullptr && a.sc->done) return;
   const int l = threadIdx.x / TPL, tid = threadIdx.x % TPL;
   const int kx = blockIdx.x * W + l;
@@ -639,25 +694,25 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
 template <typename T, int N, int MODE>
 hipError_t launch_r2c_nm(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = RowCfg<T, N>;
-  FILL_LAUNCH((r2c_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), s, e0, e1, a);
+  FILL_LAUNCH((r2c_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 template <typename T, int N, int MODE>
 hipError_t launch_c2r_nm(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = RowCfg<T, N>;
-  FILL_LAUNCH((c2r_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), s, e0, e1, a);
+  FILL_LAUNCH((c2r_kernel<T, N, MODE>), dim3(a.ny / CF::ROWS, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 template <typename T, int N>
 hipError_t launch_proj_n(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = RowCfg<T, N>;
-  FILL_LAUNCH((proj_kernel<T, N>), dim3(a.ny / CF::ROWS), dim3(CF::THREADS), s, e0, e1, a);
+  FILL_LAUNCH((proj_kernel<T, N>), dim3(a.ny / CF::ROWS, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 template <typename T, int N>
 hipError_t launch_col_n(const ColArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = ColCfg<T, N>;
-  FILL_LAUNCH((col_kernel<T, N>), dim3((a.ncol + CF::W - 1) / CF::W), dim3(CF::THREADS), s, e0, e1, a);
+  FILL_LAUNCH((col_kernel<T, N>), dim3((a.ncol + CF::W - 1) / CF::W, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 

@@ -35,8 +35,9 @@ FILL_OP_E = 3
 
 # every symbol include/fill.h declares
 EXPORTS = (
-    "fill_supported_size", "fill_plan_create", "fill_plan_set_pk", "fill_plan_set_max_iter",
-    "fill_plan_set_inner_tol",
+    "fill_supported_size", "fill_plan_create", "fill_plan_create_batch", "fill_plan_nprob",
+    "fill_plan_set_pk", "fill_plan_set_max_iter", "fill_plan_set_inner_tol", "fill_realize_batch",
+    "fill_mean_batch", "fill_realize_multi", "fill_get_stats_batch",
     "fill_plan_destroy", "fill_realize", "fill_mean", "fill_get_stats", "fill_apply",
     "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_kernel_timing",
     "fill_kernel_timing_read", "fill_strerror",
@@ -69,6 +70,12 @@ def _load() -> C.CDLL:
     sig = {
         "fill_supported_size": (i32, [i32]),
         "fill_plan_create": (i32, [i32, i32, vp, vp, i32, vp, C.POINTER(vp)]),
+        "fill_plan_create_batch": (i32, [i32, i32, i32, vp, vp, i32, i32, vp, C.POINTER(vp)]),
+        "fill_plan_nprob": (i32, [vp]),
+        "fill_realize_batch": (i32, [vp, vp, vp, vp, dbl]),
+        "fill_mean_batch": (i32, [vp, vp, vp, dbl]),
+        "fill_realize_multi": (i32, [i32, vp, vp, vp, vp, dbl]),
+        "fill_get_stats_batch": (i32, [vp, C.POINTER(fill_stats)]),
         "fill_plan_set_pk": (i32, [vp, vp]),
         "fill_plan_set_max_iter": (i32, [vp, i32]),
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
@@ -121,6 +128,71 @@ def fill_plan_create(nx, ny, mask, Pk, prec, stream) -> int:
     _check(_lib.fill_plan_create(nx, ny, m.ctypes.data, p.ctypes.data, prec, stream or None, C.byref(h)),
            "fill_plan_create")
     return h.value
+
+
+def fill_plan_create_batch(nx, ny, masks, Pk, prec, stream) -> int:
+    """masks: host uint8 (nprob, ny, nx); Pk: host float64 (ny, nx//2+1) shared or (nprob, ny, nx//2+1)."""
+    m = np.ascontiguousarray(masks, dtype=np.uint8)
+    p = np.ascontiguousarray(Pk, dtype=np.float64)
+    if m.ndim != 3 or m.shape[1:] != (ny, nx):
+        raise ValueError(f"masks {m.shape} do not match grid {nx}x{ny}")
+    nprob = m.shape[0]
+    if p.shape == (ny, nx // 2 + 1):
+        npk = 1
+    elif p.shape == (nprob, ny, nx // 2 + 1):
+        npk = nprob
+    else:
+        raise ValueError(f"Pk {p.shape} is neither one table nor one per problem")
+    h = C.c_void_p()
+    _check(_lib.fill_plan_create_batch(nx, ny, nprob, m.ctypes.data, p.ctypes.data, npk, prec, stream or None,
+                                       C.byref(h)), "fill_plan_create_batch")
+    return h.value
+
+
+def fill_plan_nprob(plan) -> int:
+    return _lib.fill_plan_nprob(plan)
+
+
+def _ptr_array(ptrs):
+    return (C.c_void_p * len(ptrs))(*ptrs)
+
+
+def fill_realize_batch(plan, d_ptrs, seeds, x_ptrs, rtol, allow_noconv=False):
+    ok = (FILL_OK, FILL_ENOCONV) if allow_noconv else (FILL_OK,)
+    s = (C.c_uint64 * len(seeds))(*[int(v) for v in seeds])
+    return _check(_lib.fill_realize_batch(plan, _ptr_array(d_ptrs), s, _ptr_array(x_ptrs), float(rtol)),
+                  "fill_realize_batch", ok)
+
+
+def fill_mean_batch(plan, d_ptrs, x_ptrs, rtol, allow_noconv=False):
+    ok = (FILL_OK, FILL_ENOCONV) if allow_noconv else (FILL_OK,)
+    return _check(_lib.fill_mean_batch(plan, _ptr_array(d_ptrs), _ptr_array(x_ptrs), float(rtol)),
+                  "fill_mean_batch", ok)
+
+
+def fill_realize_multi(plans, d_ptrs, seeds, x_ptrs, rtol, allow_noconv=False):
+    """plans: list of handles; d_ptrs/x_ptrs/seeds: per plan, one entry per problem."""
+    ok = (FILL_OK, FILL_ENOCONV) if allow_noconv else (FILL_OK,)
+    n = len(plans)
+    keep = []
+    dd = (C.c_void_p * n)()
+    xx = (C.c_void_p * n)()
+    ss = (C.c_void_p * n)()
+    for i in range(n):
+        a, x = _ptr_array(d_ptrs[i]), _ptr_array(x_ptrs[i])
+        s = (C.c_uint64 * len(seeds[i]))(*[int(v) for v in seeds[i]])
+        keep += [a, x, s]
+        dd[i] = C.cast(a, C.c_void_p)
+        xx[i] = C.cast(x, C.c_void_p)
+        ss[i] = C.cast(s, C.c_void_p)
+    return _check(_lib.fill_realize_multi(n, _ptr_array(plans), dd, ss, xx, float(rtol)), "fill_realize_multi", ok)
+
+
+def fill_get_stats_batch(plan) -> list:
+    n = fill_plan_nprob(plan)
+    arr = (fill_stats * n)()
+    _check(_lib.fill_get_stats_batch(plan, arr), "fill_get_stats_batch")
+    return [{k: getattr(s, k) for k, _ in fill_stats._fields_} for s in arr]
 
 
 def fill_plan_set_pk(plan, Pk):
@@ -288,6 +360,80 @@ class Plan:
     def time_kernel(self, kernel, reps=50, prec=None) -> float:
         """Average milliseconds per launch of one kernel of the A apply."""
         return fill_time_kernel(self.handle, kernel, self.prec if prec is None else prec, reps)
+
+
+class BatchPlan:
+    """Owner of a batched fill_plan (nprob same-size problems) on a torch stream."""
+
+    def __init__(self, nx, ny, masks, Pk, prec=FILL_PREC_FP64, stream=None, device=None):
+        import torch
+        self.device = torch.device(device or "cuda")
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = s
+            if hasattr(masks, "cpu"):
+                masks = masks.cpu().numpy()
+            if hasattr(Pk, "cpu"):
+                Pk = Pk.cpu().numpy()
+            self.nx, self.ny, self.prec = nx, ny, prec
+            self.handle = fill_plan_create_batch(nx, ny, masks, Pk, prec, s.cuda_stream)
+            self.nprob = fill_plan_nprob(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fill_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def realize(self, d_obs, seeds, rtol, out=None, allow_noconv=False):
+        """d_obs: device float64 (nprob, ny, nx); returns x_out of the same shape."""
+        import torch
+        out = torch.empty_like(d_obs) if out is None else out
+        if d_obs.shape != (self.nprob, self.ny, self.nx) or out.shape != d_obs.shape:
+            raise ValueError("d_obs/out must be (nprob, ny, nx)")
+        _dev_ptr(d_obs, torch.float64)
+        _dev_ptr(out, torch.float64)
+        fill_realize_batch(self.handle, [d_obs[b].data_ptr() for b in range(self.nprob)], seeds,
+                           [out[b].data_ptr() for b in range(self.nprob)], rtol, allow_noconv)
+        return out
+
+    def mean(self, d_obs, rtol, out=None, allow_noconv=False):
+        import torch
+        out = torch.empty_like(d_obs) if out is None else out
+        _dev_ptr(d_obs, torch.float64)
+        _dev_ptr(out, torch.float64)
+        fill_mean_batch(self.handle, [d_obs[b].data_ptr() for b in range(self.nprob)],
+                        [out[b].data_ptr() for b in range(self.nprob)], rtol, allow_noconv)
+        return out
+
+    def stats(self) -> list:
+        return fill_get_stats_batch(self.handle)
+
+    def kernel_timing(self, kernel, prec=None):
+        fill_kernel_timing(self.handle, kernel, self.prec if prec is None else prec)
+
+    def kernel_timing_read(self):
+        return fill_kernel_timing_read(self.handle)
+
+    def set_inner_tol(self, tol):
+        fill_plan_set_inner_tol(self.handle, tol)
+
+
+def realize_multi(plans, d_obs_list, seeds_list, rtol, outs=None, allow_noconv=False):
+    """Run several BatchPlans concurrently (one host thread each)."""
+    import torch
+    outs = outs if outs is not None else [torch.empty_like(d) for d in d_obs_list]
+    fill_realize_multi([p.handle for p in plans],
+                       [[d[b].data_ptr() for b in range(p.nprob)] for p, d in zip(plans, d_obs_list)],
+                       seeds_list,
+                       [[o[b].data_ptr() for b in range(p.nprob)] for p, o in zip(plans, outs)],
+                       rtol, allow_noconv)
+    return outs
 
 
 def philox_words(seed, stream, n_blocks, device="cuda"):
