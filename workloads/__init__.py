@@ -44,6 +44,7 @@ __all__ = [
     "Problem",
     "make_problem",
     "CONFIGS",
+    "make_mixed_batch",
 ]
 
 
@@ -180,3 +181,22 @@ def make_problem(name: str = "grid2048", n: int | None = None, **over) -> Proble
     return Problem(name=f"{name}@{n}", nx=n, ny=n, P=P, mask=mask, d_obs=d, seed=cfg["seed"],
                    rtol=cfg["rtol"], meta=dict(band=band, n_holes=n_holes, damping=damping, **{
                        k: cfg[k] for k in ("k0sq", "floor", "rmin", "rmax", "mask_seed", "dobs_seed")}))
+
+
+def make_mixed_batch(nprob: int = 64, sizes=(256, 512, 768, 1024), seed: int = 2024) -> list[Problem]:
+    """Monte-Carlo batch of uneven grids: problem i has n ~ U{sizes}, a band of
+    U(5, 20)% of the rows plus U{20..100} holes of radius U(2, 10) px (mask
+    seed 1000 + i), P of the 2048^2 form with damping n/8, observed map seed
+    2 i and fill seed 2 i + 1; tolerance 1e-6."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(nprob):
+        n = int(rng.choice(sizes))
+        frac = float(rng.uniform(0.05, 0.20))
+        nh = int(rng.integers(20, 101))
+        P = damped_power_law(n, n, 4.0, n / 8.0, 1e-7)
+        mask = band_holes_mask(n, n, band_rows(n, frac), nh, 2.0, 10.0, 1000 + i)
+        d = observed_map(P, n, n, 2 * i, mask)
+        out.append(Problem(name=f"batch{i}@{n}", nx=n, ny=n, P=P, mask=mask, d_obs=d, seed=2 * i + 1,
+                           rtol=1e-6, meta=dict(band_frac=frac, n_holes=nh, damping=n / 8.0)))
+    return out
