@@ -209,6 +209,9 @@ def pcg_split(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
                 done = True
                 break
             rr_new = float(np.vdot(r, r))
+            if rr_new == 0.0:  # the split system is solved exactly: check the true residual
+                done = True
+                break
             p = r + (rr_new / rr) * p
             rr = rr_new
         res = v - apply_A(u, mask, P)
