@@ -206,6 +206,45 @@ int fill_realize_unconstrained(fill_plan plan, uint64_t seed, double* out);
  */
 int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t* out);
 
+/*
+ * Band-power spectrum: theta[b] = ln P at ln k = lnk_nodes[b] (nbands nodes,
+ * strictly increasing), ln P(k) piecewise linear in ln k between nodes and
+ * constant outside [lnk_nodes[0], lnk_nodes[nbands-1]] (k = 0 takes
+ * theta[0]).  Computes the tables of every problem of the plan from theta
+ * (host arrays; replaces any previous spectrum).  The model stands in for
+ * the paper's P = w C + N (Sec. 3) when the spectrum is to be differentiated.
+ */
+int fill_plan_set_bands(fill_plan plan, int nbands, const double* lnk_nodes, const double* theta);
+
+/*
+ * Gradient of a loss L on the filled map (the output of fill_realize with the
+ * same d_obs, seed and plan), given g = dL/dx_out (the derivative of the
+ * fill of Sec. 2.1 / 2.3; the paper does not give it).  One extra CG solve
+ * A lambda = g_x with the operators of Sec. 2.4, in the plan's precision
+ * with FP64 refinement to true relative residual rtol; then
+ *   grad_dobs = dL/dd_obs = g - C^-1 lambda on observed pixels, 0 on masked;
+ *   grad_logP[k] = dL/d ln P_k on the half spectrum (layout of Pk);
+ *   grad_theta[b] = sum_k phi_b(k) grad_logP[k] for the band model of
+ *   fill_plan_set_bands (required if grad_theta is not NULL).
+ *   d_obs, x_out, g   device, ny*nx doubles (x_out as returned by fill_realize).
+ *   grad_dobs         device, ny*nx doubles.
+ *   grad_theta        host, nbands doubles, or NULL.
+ *   grad_logP         host, ny*(nx/2+1) doubles, or NULL.
+ * Returns FILL_OK, FILL_ENOCONV (gradients from the best iterate) or an error.
+ */
+int fill_adjoint(fill_plan plan, const double* d_obs, uint64_t seed, const double* x_out, const double* g,
+                 double* grad_dobs, double* grad_theta, double* grad_logP, double rtol);
+
+/*
+ * fill_adjoint for every problem of a batched plan (host arrays of nprob
+ * device pointers); one batched adjoint solve.  grad_theta is the sum over
+ * problems (the band powers are shared); grad_logP (if not NULL) holds
+ * nprob per-problem blocks of ny*(nx/2+1).
+ */
+int fill_adjoint_batch(fill_plan plan, const double* const* d_obs, const uint64_t* seeds,
+                       const double* const* x_out, const double* const* g, double* const* grad_dobs,
+                       double* grad_theta, double* grad_logP, double rtol);
+
 /* Kernels that fill_time_kernel can time (one operator apply, Sec. 2.4). */
 enum fill_kernel {
   FILL_K_R2C = 0,    /* row pass: compact masked vector -> transposed half spectrum */

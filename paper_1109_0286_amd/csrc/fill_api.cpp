@@ -124,6 +124,17 @@ struct fill_plan_s {
   std::vector<fill_stats> pstats;
   fill_stats stats{};
   std::vector<void*> allocs;
+  // band-power spectrum model and adjoint workspaces (allocated on first use)
+  int nbands = 0;
+  double* lnk = nullptr;
+  double* adj_s = nullptr;
+  double* adj_cl = nullptr;
+  double* adj_h = nullptr;
+  double* adj_v = nullptr;
+  double2* adj_X[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* adj_G = nullptr;
+  double* adj_Gapi = nullptr;
+  double* adj_gth = nullptr;
   // optional HIP-event timing of every launch of one kernel during solves
   int timed_kernel = -1;
   int timed_prec = 0;
@@ -196,6 +207,16 @@ template <typename T> ColArgs<T> col_base(fill_plan p, int nprob, const T* D, co
   ca.xt_stride = p->nt;
   ca.d_stride = p->npk > 1 ? p->nt : 0;
   return ca;
+}
+
+// Arguments for problem b alone (one-problem launches).
+template <typename T> RowArgs<T> row_for(fill_plan p, int b) {
+  RowArgs<T> a = row_base<T>(p, 1);
+  a.row_off += (size_t)b * (p->ny + 1);
+  a.pos += p->coff[b];
+  a.mask += (size_t)b * p->npix;
+  a.Xt += (size_t)b * p->nt;
+  return a;
 }
 
 // Sum the elapsed times of the recorded event pairs (stream synchronised) and recycle them.
@@ -746,6 +767,119 @@ int time_kernel(fill_plan p, int kernel, int reps, double* avg_ms) {
 int plan_create_impl(int nx, int ny, int nprob, const uint8_t* masks, const double* Pk, int npk, int prec,
                      void* stream, fill_plan* out);
 
+// ln P(k) piecewise linear in ln k between the band nodes, constant outside;
+// k = 0 takes the first band.
+double band_lnP(double k, const double* lnk, const double* theta, int nb) {
+  if (k <= 0.0) return theta[0];
+  const double lk = std::log(k);
+  if (lk <= lnk[0]) return theta[0];
+  if (lk >= lnk[nb - 1]) return theta[nb - 1];
+  int j = int(std::upper_bound(lnk, lnk + nb, lk) - lnk) - 1;
+  const double t = (lk - lnk[j]) / (lnk[j + 1] - lnk[j]);
+  return (1.0 - t) * theta[j] + t * theta[j + 1];
+}
+
+int adjoint_workspace(fill_plan p) {
+  if (p->adj_s) return FILL_OK;
+  FILL_TRY(dalloc(p, &p->adj_s, p->npix));
+  FILL_TRY(dalloc(p, &p->adj_cl, p->npix));
+  FILL_TRY(dalloc(p, &p->adj_h, p->npix));
+  FILL_TRY(dalloc(p, &p->adj_v, p->npix));
+  for (int i = 0; i < 4; ++i) FILL_TRY(dalloc(p, &p->adj_X[i], p->nt));
+  FILL_TRY(dalloc(p, &p->adj_G, p->nt));
+  FILL_TRY(dalloc(p, &p->adj_Gapi, p->nt));
+  return FILL_OK;
+}
+
+// Forward 2D FFT of problem b's map, into adjoint spectrum slot `slot`:
+// r2c of (mode, args) then the forward-only column pass.
+int forward_spectrum(fill_plan p, int b, int mode, const RowArgs<double>& a, int slot) {
+  HIP_TRY(launch_r2c<double>(mode, a, p->stream));
+  HIP_TRY(launch_col_fwd(p->ny, static_cast<const double2*>(a.Xt), p->adj_X[slot], p->ny, p->nx / 2, p->twy64,
+                         p->stream));
+  (void)b;
+  return FILL_OK;
+}
+
+int adjoint_impl(fill_plan p, const double* const* d, const uint64_t* seeds, const double* const* x,
+                 const double* const* g, double* const* gy, double* grad_theta, double* grad_logP, double rtol) {
+  g_last_error.clear();
+  if (!p || !d || !seeds || !x || !g || !gy) return fail(FILL_EINVAL, "NULL argument");
+  if (!(rtol > 0.0)) return fail(FILL_EINVAL, "rtol must be > 0");
+  if (p->nbands < 1 && grad_theta) return fail(FILL_EINVAL, "grad_theta needs fill_plan_set_bands first");
+  const int np = p->nprob;
+  for (int b = 0; b < np; ++b)
+    if (!d[b] || !x[b] || !g[b] || !gy[b]) return fail(FILL_EINVAL, "NULL map for problem " + std::to_string(b));
+  FILL_TRY(adjoint_workspace(p));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int b = 0; b < np; ++b) p->hp.in_tab[b] = g[b];
+  FILL_TRY(upload_params(p));
+  // lambda = A^-1 g_x for every problem (the plan's precision, FP64 refinement)
+  HIP_TRY(launch_adj_gather(p->b, const_cast<double* const*>(p->dp.in_tab), p->pos, p->comp_off, p->n_m_max, np,
+                            p->stream));
+  HIP_TRY(launch_cnorm2(p->dsum, p->b, p->comp_off, np, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->h_sum, p->dsum, np * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  std::vector<double> bnorm2(p->h_sum, p->h_sum + np);
+  const int st = solve(p, bnorm2, rtol);
+  if (st != FILL_OK && st != FILL_ENOCONV) return st;
+  if (p->nbands > 0) HIP_TRY(hipMemsetAsync(p->adj_gth, 0, p->nbands * sizeof(double), p->stream));
+  for (int b = 0; b < np; ++b) {
+    const size_t doff = p->npk > 1 ? (size_t)b * p->nt : 0;
+    const double* Dinv = p->Dinv64 + doff;
+    const double* Dhalf = p->Dhalf64 + doff;
+    double* lam = p->u + p->coff[b];
+    // s = C^{1/2} w (problem b's seed)
+    RowArgs<double> ai = row_for<double>(p, b), ao = row_for<double>(p, b);
+    ai.seed = seeds[b];
+    ai.stream = kRealizationStream;
+    ao.full_out = p->adj_s;
+    ColArgs<double> ca = col_base<double>(p, 1, Dhalf, nullptr);
+    ca.Xt = ai.Xt;
+    HIP_TRY(launch_r2c<double>(R2C_NOISE, ai, p->stream));
+    HIP_TRY(launch_col<double>(p->ny, ca, p->stream));
+    HIP_TRY(launch_c2r<double>(C2R_REALIZE, ao, p->stream));
+    // cl = C^-1 lambda~ (full map)
+    ai = row_for<double>(p, b);
+    ai.v0 = lam;
+    ao = row_for<double>(p, b);
+    ao.full_out = p->adj_cl;
+    ca.D = Dinv;
+    HIP_TRY(launch_r2c<double>(R2C_COMPACT, ai, p->stream));
+    HIP_TRY(launch_col<double>(p->ny, ca, p->stream));
+    HIP_TRY(launch_c2r<double>(C2R_FULL, ao, p->stream));
+    // dL/dy, h, v
+    HIP_TRY(launch_adj_maps(p->mask + (size_t)b * p->npix, g[b], p->adj_cl, x[b], p->adj_s, d[b], gy[b], p->adj_h,
+                            p->adj_v, p->npix, p->stream));
+    if (!grad_theta && !grad_logP) continue;
+    // spectra of h, w, lambda~, v
+    RowArgs<double> a = row_for<double>(p, b);
+    a.full_in = p->adj_h;
+    FILL_TRY(forward_spectrum(p, b, R2C_FULL, a, 0));
+    a = row_for<double>(p, b);
+    a.seed = seeds[b];
+    a.stream = kRealizationStream;
+    FILL_TRY(forward_spectrum(p, b, R2C_NOISE, a, 1));
+    a = row_for<double>(p, b);
+    a.v0 = lam;
+    FILL_TRY(forward_spectrum(p, b, R2C_COMPACT, a, 2));
+    a = row_for<double>(p, b);
+    a.full_in = p->adj_v;
+    FILL_TRY(forward_spectrum(p, b, R2C_FULL, a, 3));
+    HIP_TRY(launch_spec_grad(p->adj_X[0], p->adj_X[1], p->adj_X[2], p->adj_X[3], Dhalf, Dinv, p->nx, p->ny,
+                             p->adj_G, grad_logP ? p->adj_Gapi : nullptr, p->stream));
+    if (grad_theta)
+      HIP_TRY(launch_band_reduce(p->adj_G, p->nx, p->ny, p->lnk, p->nbands, p->adj_gth, p->stream));
+    if (grad_logP)
+      HIP_TRY(hipMemcpyAsync(grad_logP + (size_t)b * p->nt, p->adj_Gapi, p->nt * sizeof(double),
+                             hipMemcpyDeviceToHost, p->stream));
+  }
+  if (grad_theta)
+    HIP_TRY(hipMemcpyAsync(grad_theta, p->adj_gth, p->nbands * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -835,6 +969,46 @@ int fill_realize_multi(int nplans, const fill_plan* plans, const double* const* 
     }
   }
   return worst;
+}
+
+int fill_plan_set_bands(fill_plan p, int nbands, const double* lnk_nodes, const double* theta) {
+  g_last_error.clear();
+  if (!p || !lnk_nodes || !theta || nbands < 1) return fail(FILL_EINVAL, "bad argument");
+  for (int b = 1; b < nbands; ++b)
+    if (!(lnk_nodes[b] > lnk_nodes[b - 1])) return fail(FILL_EINVAL, "band nodes must increase");
+  for (int b = 0; b < nbands; ++b)
+    if (!std::isfinite(theta[b]) || !std::isfinite(lnk_nodes[b])) return fail(FILL_ENOTSPD, "non-finite band power");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const int nx = p->nx, ny = p->ny, nc = p->ncol;
+  std::vector<double> Pk((size_t)p->npk * ny * nc);
+  for (int iy = 0; iy < ny; ++iy) {
+    const int ky = iy <= ny / 2 ? iy : iy - ny;
+    for (int ix = 0; ix < nc; ++ix) {
+      const double k = std::sqrt((double)ix * ix + (double)ky * ky);
+      const double P = std::exp(band_lnP(k, lnk_nodes, theta, nbands));
+      for (int t = 0; t < p->npk; ++t) Pk[((size_t)t * ny + iy) * nc + ix] = P;
+    }
+  }
+  (void)nx;
+  if (p->nbands != nbands) {
+    FILL_TRY(dalloc(p, &p->lnk, nbands));
+    FILL_TRY(dalloc(p, &p->adj_gth, nbands));
+    p->nbands = nbands;
+  }
+  HIP_TRY(hipMemcpy(p->lnk, lnk_nodes, nbands * sizeof(double), hipMemcpyHostToDevice));
+  return upload_pk(p, Pk.data(), p->npk);
+}
+
+int fill_adjoint(fill_plan p, const double* d_obs, uint64_t seed, const double* x_out, const double* g,
+                 double* grad_dobs, double* grad_theta, double* grad_logP, double rtol) {
+  if (p && p->nprob != 1) return fail(FILL_EINVAL, "plan holds several problems: use fill_adjoint_batch");
+  return adjoint_impl(p, &d_obs, &seed, &x_out, &g, &grad_dobs, grad_theta, grad_logP, rtol);
+}
+
+int fill_adjoint_batch(fill_plan p, const double* const* d_obs, const uint64_t* seeds, const double* const* x_out,
+                       const double* const* g, double* const* grad_dobs, double* grad_theta, double* grad_logP,
+                       double rtol) {
+  return adjoint_impl(p, d_obs, seeds, x_out, g, grad_dobs, grad_theta, grad_logP, rtol);
 }
 
 int fill_get_stats(fill_plan p, fill_stats* out) {

@@ -48,4 +48,18 @@ hipError_t launch_scatter_f32(double* full, const float* c, const int* pos, int 
 hipError_t launch_gather(double* c, const double* full, const int* pos, int n, hipStream_t s);
 hipError_t launch_philox_words(uint64_t* out, uint64_t seed, uint64_t stream, int64_t nblocks, hipStream_t s);
 
+// Adjoint (FP64).
+hipError_t launch_col_fwd(int ny, const double2* Xt, double2* Xs, int ldx, int nhalf, const double2* tw,
+                          hipStream_t s);
+hipError_t launch_adj_maps(const uint8_t* mask, const double* g, const double* cl, const double* x, const double* s,
+                           const double* d, double* grad_y, double* h, double* v, size_t npix, hipStream_t st);
+hipError_t launch_adj_gather(double* b, double* const* g_tab, const int* pos, const int* comp_off, int nmax, int nprob,
+                             hipStream_t st);
+hipError_t launch_spec_grad(const double2* Xh, const double2* Xw, const double2* Xl, const double2* Xv,
+                            const double* Dhalf, const double* Dinv, int nx, int ny, double* G, double* G_api,
+                            hipStream_t st);
+hipError_t launch_band_reduce(const double* G, int nx, int ny, const double* lnk, int nb, double* out,
+                              hipStream_t st);
+hipError_t launch_cnorm2(double* out, const double* v, const int* comp_off, int nprob, hipStream_t st);
+
 }  // namespace fillk

@@ -37,7 +37,8 @@ FILL_OP_E = 3
 EXPORTS = (
     "fill_supported_size", "fill_plan_create", "fill_plan_create_batch", "fill_plan_nprob",
     "fill_plan_set_pk", "fill_plan_set_max_iter", "fill_plan_set_inner_tol", "fill_realize_batch",
-    "fill_mean_batch", "fill_realize_multi", "fill_get_stats_batch",
+    "fill_mean_batch", "fill_realize_multi", "fill_get_stats_batch", "fill_plan_set_bands",
+    "fill_adjoint", "fill_adjoint_batch",
     "fill_plan_destroy", "fill_realize", "fill_mean", "fill_get_stats", "fill_apply",
     "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_kernel_timing",
     "fill_kernel_timing_read", "fill_strerror",
@@ -76,6 +77,9 @@ def _load() -> C.CDLL:
         "fill_mean_batch": (i32, [vp, vp, vp, dbl]),
         "fill_realize_multi": (i32, [i32, vp, vp, vp, vp, dbl]),
         "fill_get_stats_batch": (i32, [vp, C.POINTER(fill_stats)]),
+        "fill_plan_set_bands": (i32, [vp, i32, vp, vp]),
+        "fill_adjoint": (i32, [vp, vp, u64, vp, vp, vp, vp, vp, dbl]),
+        "fill_adjoint_batch": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, dbl]),
         "fill_plan_set_pk": (i32, [vp, vp]),
         "fill_plan_set_max_iter": (i32, [vp, i32]),
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
@@ -193,6 +197,28 @@ def fill_get_stats_batch(plan) -> list:
     arr = (fill_stats * n)()
     _check(_lib.fill_get_stats_batch(plan, arr), "fill_get_stats_batch")
     return [{k: getattr(s, k) for k, _ in fill_stats._fields_} for s in arr]
+
+
+def fill_plan_set_bands(plan, lnk_nodes, theta):
+    lnk = np.ascontiguousarray(lnk_nodes, dtype=np.float64)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if lnk.shape != th.shape or lnk.ndim != 1:
+        raise ValueError("lnk_nodes and theta must be 1-D of the same length")
+    return _check(_lib.fill_plan_set_bands(plan, len(lnk), lnk.ctypes.data, th.ctypes.data), "fill_plan_set_bands")
+
+
+def fill_adjoint_batch(plan, d_ptrs, seeds, x_ptrs, g_ptrs, gy_ptrs, nbands, nt=None, rtol=1e-10,
+                       want_logP=False, allow_noconv=False):
+    """Returns (grad_theta or None, grad_logP or None) as numpy arrays."""
+    ok = (FILL_OK, FILL_ENOCONV) if allow_noconv else (FILL_OK,)
+    s = (C.c_uint64 * len(seeds))(*[int(v) for v in seeds])
+    gth = np.zeros(nbands) if nbands else None
+    glp = np.zeros(len(d_ptrs) * nt) if want_logP else None
+    _check(_lib.fill_adjoint_batch(plan, _ptr_array(d_ptrs), s, _ptr_array(x_ptrs), _ptr_array(g_ptrs),
+                                   _ptr_array(gy_ptrs), gth.ctypes.data if gth is not None else None,
+                                   glp.ctypes.data if glp is not None else None, float(rtol)),
+           "fill_adjoint_batch", ok)
+    return gth, glp
 
 
 def fill_plan_set_pk(plan, Pk):
@@ -349,6 +375,24 @@ class Plan:
     def stats(self) -> dict:
         return fill_get_stats(self.handle)
 
+    def set_bands(self, lnk_nodes, theta):
+        fill_plan_set_bands(self.handle, lnk_nodes, theta)
+        self.nbands = len(lnk_nodes)
+
+    def adjoint(self, d_obs, seed, x_out, g, rtol=1e-10, want_logP=False, allow_noconv=False):
+        """(grad_dobs, grad_theta, grad_logP) of a loss with dL/dx_out = g."""
+        import torch
+        grad_d = torch.empty_like(d_obs)
+        for t in (d_obs, x_out, g, grad_d):
+            _dev_ptr(t, torch.float64)
+        gth, glp = fill_adjoint_batch(self.handle, [d_obs.data_ptr()], [seed], [x_out.data_ptr()], [g.data_ptr()],
+                                      [grad_d.data_ptr()], getattr(self, "nbands", 0),
+                                      nt=self.ny * (self.nx // 2 + 1), rtol=rtol, want_logP=want_logP,
+                                      allow_noconv=allow_noconv)
+        if glp is not None:
+            glp = glp.reshape(self.ny, self.nx // 2 + 1)
+        return grad_d, gth, glp
+
     def kernel_timing(self, kernel, prec=None):
         """Time every launch of `kernel` during later solves with HIP events (-1 = off)."""
         fill_kernel_timing(self.handle, kernel, self.prec if prec is None else prec)
@@ -422,6 +466,26 @@ class BatchPlan:
 
     def set_inner_tol(self, tol):
         fill_plan_set_inner_tol(self.handle, tol)
+
+    def set_bands(self, lnk_nodes, theta):
+        fill_plan_set_bands(self.handle, lnk_nodes, theta)
+        self.nbands = len(lnk_nodes)
+
+    def adjoint(self, d_obs, seeds, x_out, g, rtol=1e-10, want_logP=False, allow_noconv=False):
+        """(grad_dobs, grad_theta, grad_logP) of a loss with dL/dx_out = g (all (nprob, ny, nx))."""
+        import torch
+        grad_d = torch.empty_like(d_obs)
+        for t in (d_obs, x_out, g, grad_d):
+            _dev_ptr(t, torch.float64)
+        n = self.nprob
+        gth, glp = fill_adjoint_batch(self.handle, [d_obs[b].data_ptr() for b in range(n)], seeds,
+                                      [x_out[b].data_ptr() for b in range(n)], [g[b].data_ptr() for b in range(n)],
+                                      [grad_d[b].data_ptr() for b in range(n)], getattr(self, "nbands", 0),
+                                      nt=self.ny * (self.nx // 2 + 1), rtol=rtol, want_logP=want_logP,
+                                      allow_noconv=allow_noconv)
+        if glp is not None:
+            glp = glp.reshape(n, self.ny, self.nx // 2 + 1)
+        return grad_d, gth, glp
 
 
 def realize_multi(plans, d_obs_list, seeds_list, rtol, outs=None, allow_noconv=False):

@@ -1,0 +1,117 @@
+"""GPU: adjoint of the fill (gradients with respect to observed pixels and
+band powers) against the oracle's adjoint and against central differences.
+
+Bars: 1e-8 relative for the FP64 path; 1e-6 for FP32 operators with FP64
+refinement (both solves refined to a tight true residual so that the solve
+error stays below the bar).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as AD
+from pins import rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1109_0286_amd as F
+    return F
+
+
+def setup(n, nb=50, mseed=7, dseed=3, nholes=4):
+    lnk = AD.band_nodes(n, nb)
+    phi = AD.band_weights(n, n, lnk)
+    kb = np.exp(lnk)
+    theta = np.log(1.0 / (kb ** 2 + 4) * np.exp(-(kb / (n / 8)) ** 2) + 1e-7)
+    mask = W.band_holes_mask(n, n, W.band_rows(n, 0.1), nholes, 2, 5, mseed)
+    d = W.observed_map(AD.pk_from_bands(theta, phi), n, n, dseed, mask)
+    wts = np.random.default_rng(mseed + 100).uniform(0, 1, (n, n))
+    return lnk, phi, theta, mask, d, wts
+
+
+def gpu_grad(F, n, lnk, theta, mask, d, wts, seed, prec, rtol):
+    plan = F.Plan(n, n, mask, np.ones((n, n // 2 + 1)), prec)
+    plan.set_bands(lnk, theta)
+    dd = torch.from_numpy(d).cuda()
+    x = plan.realize(dd, seed, rtol, allow_noconv=True)
+    w = torch.from_numpy(wts).cuda()
+    L = float(torch.sum(w * x * x))
+    g = (2.0 * w * x).contiguous()
+    gd, gth, glp = plan.adjoint(dd, seed, x, g, rtol, want_logP=True, allow_noconv=True)
+    return L, gd.cpu().numpy(), gth, glp
+
+
+@pytest.mark.parametrize("prec,rtol,tol", [(0, 1e-12, 1e-8), (1, 1e-11, 1e-6)])
+def test_adjoint_matches_oracle(F, prec, rtol, tol):
+    n = 64
+    lnk, phi, theta, mask, d, wts = setup(n)
+    L, gd, gth, glp = gpu_grad(F, n, lnk, theta, mask, d, wts, 9, prec, rtol)
+    L0, gy0, gP0, gth0 = AD.adjoint_gradient(d, mask, theta, phi, 9, wts, 1e-13)
+    assert abs(L - L0) < tol * abs(L0)
+    assert rel(gth, gth0) < tol
+    assert rel(gd, gy0) < tol
+    assert rel(glp, gP0) < tol
+    assert np.all(gd[mask != 0] == 0.0)
+
+
+def test_adjoint_matches_gpu_central_differences(F):
+    n = 128
+    lnk, phi, theta, mask, d, wts = setup(n, nholes=12)
+    L, gd, gth, _ = gpu_grad(F, n, lnk, theta, mask, d, wts, 5, 1, 1e-11)
+    plan = F.Plan(n, n, mask, np.ones((n, n // 2 + 1)), 1)
+    w = torch.from_numpy(wts).cuda()
+
+    def loss(th, dd):
+        plan.set_bands(lnk, th)
+        x = plan.realize(torch.from_numpy(dd).cuda(), 5, 1e-11, allow_noconv=True)
+        return float(torch.sum(w * x * x))
+
+    h = 1e-4
+    scale = np.abs(gth).max()
+    for b in (0, 12, 25, 49):
+        e = np.zeros_like(theta)
+        e[b] = h
+        fd = (loss(theta + e, d) - loss(theta - e, d)) / (2 * h)
+        assert abs(fd - gth[b]) < 1e-6 * scale, (b, fd, gth[b])
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        dirn = np.where(mask != 0, 0.0, rng.standard_normal(d.shape))
+        fd = (loss(theta, d + h * dirn) - loss(theta, d - h * dirn)) / (2 * h)
+        an = float(np.sum(gd * dirn))
+        assert abs(fd - an) < 1e-6 * abs(an)
+
+
+def test_batch_adjoint_and_autograd_function(F):
+    n, nprob = 64, 3
+    lnk = AD.band_nodes(n, 50)
+    phi = AD.band_weights(n, n, lnk)
+    kb = np.exp(lnk)
+    theta = np.log(1.0 / (kb ** 2 + 4) * np.exp(-(kb / (n / 8)) ** 2) + 1e-7)
+    masks, ds, wl = [], [], []
+    for i in range(nprob):
+        m = W.band_holes_mask(n, n, W.band_rows(n, 0.1), 3 + i, 2, 5, 20 + i)
+        masks.append(m)
+        ds.append(W.observed_map(AD.pk_from_bands(theta, phi), n, n, 30 + i, m))
+        wl.append(np.random.default_rng(40 + i).uniform(0, 1, (n, n)))
+    seeds = [5, 6, 7]
+    bp = F.BatchPlan(n, n, np.stack(masks), np.ones((n, n // 2 + 1)), 0)
+    FillFn = F.autograd_fill()
+    dd = torch.from_numpy(np.stack(ds)).cuda().requires_grad_(True)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    x = FillFn.apply(dd, th, bp, seeds, lnk, 1e-11, 1e-11)
+    L = torch.sum(torch.from_numpy(np.stack(wl)).cuda() * x * x)
+    L.backward()
+    gth_ref = np.zeros_like(theta)
+    for i in range(nprob):
+        L0, gy0, _, gth0 = AD.adjoint_gradient(ds[i], masks[i], theta, phi, seeds[i], wl[i], 1e-13)
+        gth_ref += gth0
+        assert rel(dd.grad[i].cpu().numpy(), gy0) < 1e-8, i
+    assert rel(th.grad.numpy(), gth_ref) < 1e-8
