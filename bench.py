@@ -179,6 +179,84 @@ def bench_mixed64(args) -> int:
     return 0
 
 
+def bench_grid4096(args) -> int:
+    """The 4096^2 wide cut (30% band + 500 holes r~U(2,16), damping 512):
+    CG iterations and time for the FP64 path and for FP32 operators with
+    FP64 refinement, rtol 1e-8."""
+    import torch
+    import paper_1109_0286_amd as F
+    import workloads as W
+    prob = W.make_problem("grid4096")
+    d = torch.from_numpy(prob.d_obs).cuda()
+    res = {}
+    for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
+        plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
+        dt, st, col_ms, _ = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, F.FILL_K_COL)
+        res[name] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
+                     "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
+                     "rel_resid": st["rel_resid"], "col_kernel_ms": col_ms}
+        plan.close()
+    H = prob.ny * (prob.nx // 2 + 1)
+    achieved = 5.0 * 4 * H / (res["mixed"]["col_kernel_ms"] * 1e-3) / 1e9
+    out = {"metric": "PCG fill-in solves/s at 4096^2 (rel resid 1e-8)", "value": res["mixed"]["solves_per_s"],
+           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["mixed"]["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement", "data": "synthetic",
+           "config": {"workload": "4096x4096 torus, 30% band + 500 holes r~U(2,16), damping 512, floor 1e-7, "
+                                  "rtol 1e-8", "n_masked": prob.n_masked},
+           "paths": res,
+           "roofline": {"bound": "hbm", "kernel": "col_kernel<float,4096>", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_grad16(args) -> int:
+    """Forward fill + adjoint of a loss sum(w x^2), w ~ U(0,1), for 16 1024^2
+    maps (10% band + 100 holes r~U(2,10)) with P(k) from 50 log-spaced band
+    powers: one batched plan, FP32 operators with FP64 refinement."""
+    import torch
+    import paper_1109_0286_amd as F
+    import workloads as W
+    n, nprob, nb = 1024, 16, 50
+    lnk = np.linspace(0.0, np.log(np.sqrt(2.0) * n / 2), nb)
+    kb = np.exp(lnk)
+    theta = np.log(1.0 / (kb ** 2 + 4) * np.exp(-(kb / (n / 8)) ** 2) + 1e-7)
+    P = W.damped_power_law(n, n, 4.0, n / 8, 1e-7)
+    masks = np.stack([W.band_holes_mask(n, n, W.band_rows(n, 0.10), 100, 2.0, 10.0, 500 + i) for i in range(nprob)])
+    d = torch.from_numpy(np.stack([W.observed_map(P, n, n, 600 + i, masks[i]) for i in range(nprob)])).cuda()
+    w = torch.from_numpy(np.random.default_rng(7).uniform(0, 1, (nprob, n, n))).cuda()
+    seeds = list(range(1, nprob + 1))
+    bp = F.BatchPlan(n, n, masks, P, F.FILL_PREC_FP32_OP)
+    FillFn = F.autograd_fill()
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+
+    def step():
+        th.grad = None
+        dd = d.clone().requires_grad_(True)
+        x = FillFn.apply(dd, th, bp, seeds, lnk, 1e-8, 1e-10)
+        loss = torch.sum(w * x * x)
+        loss.backward()
+        return float(loss)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"metric": "forward + adjoint steps/s, 16 x 1024^2 maps, 50 band powers", "value": args.steps / dt,
+           "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement", "data": "synthetic",
+           "config": {"workload": "16 x 1024^2, 10% band + 100 holes r~U(2,10), 50 log-spaced band powers, "
+                                  "loss sum(w x^2) w~U(0,1), forward rtol 1e-8, adjoint rtol 1e-10"}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,8 +268,9 @@ def main() -> int:
     ap.add_argument("--reps", type=int, default=50, help="launches per isolated kernel timing")
     ap.add_argument("--batch", type=int, default=4,
                     help="realizations per launch in the batched 2048^2 leg (0: skip it)")
-    ap.add_argument("--workload", default="grid2048", choices=["grid2048", "mixed64"],
-                    help="grid2048: the headline line; mixed64: 64 problems of uneven sizes")
+    ap.add_argument("--workload", default="grid2048", choices=["grid2048", "mixed64", "grid4096", "grad16"],
+                    help="grid2048: the headline line; mixed64: 64 problems of uneven sizes; grid4096: the wide "
+                         "cut; grad16: forward + adjoint of 16 1024^2 maps with 50 band powers")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with three plain 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -206,6 +285,10 @@ def main() -> int:
 
     if args.workload == "mixed64":
         return bench_mixed64(args)
+    if args.workload == "grid4096":
+        return bench_grid4096(args)
+    if args.workload == "grad16":
+        return bench_grad16(args)
 
     prob = W.make_problem("grid2048")
     nx, ny, rtol, seed = prob.nx, prob.ny, prob.rtol, prob.seed

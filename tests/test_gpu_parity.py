@@ -228,6 +228,22 @@ def test_full_size_2048_workload_properties(F, prec):
     assert np.array_equal(x[~m].view(np.uint64), p.d_obs[~m].view(np.uint64))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_4096_wide_cut_properties(F, prec):
+    # 4096^2, 30% band + 500 holes: the oracle's FP64 residual of the GPU
+    # solution meets rtol; observed pixels untouched; finite everywhere.
+    p = W.make_problem("grid4096")
+    x, st, plan = run_fill(F, p.P, p.mask, p.d_obs, prec, p.seed, p.rtol)
+    m = p.mask != 0
+    s = host(plan.realize_unconstrained(p.seed))
+    v = O.rhs(np.where(m, 0.0, p.d_obs - s), p.mask, p.P)
+    u = np.where(m, x - s, 0.0)
+    res = np.linalg.norm(v - O.apply_A(u, p.mask, p.P)) / np.linalg.norm(v)
+    assert st["status"] == 0 and res < 1.5 * p.rtol
+    assert np.array_equal(x[~m].view(np.uint64), p.d_obs[~m].view(np.uint64))
+    assert np.all(np.isfinite(x))
+
+
 # ---------------------------------------------------------------------------
 # edge cases and errors
 # ---------------------------------------------------------------------------
