@@ -39,7 +39,7 @@ Readings of the paper used here (ambiguous or garbled passages):
 from __future__ import annotations
 
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 import scipy.fft as sfft
@@ -167,10 +167,15 @@ class PCGInfo:
     rel_residual: float
     converged: bool
     history: list
+    # CG step lengths alpha_j and direction coefficients beta_j of the first
+    # CG run (x0 = 0, before any restart): the Lanczos data of Sec. 6.4.
+    alphas: list = field(default_factory=list)
+    betas: list = field(default_factory=list)
 
 
 def pcg_split(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
-              max_iter: int = 20000, history: bool = False) -> tuple[np.ndarray, PCGInfo]:
+              max_iter: int = 20000, history: bool = False,
+              precond: bool = True) -> tuple[np.ndarray, PCGInfo]:
     """Solve A u = v with CG on the split system (E A E) u' = E v, u = E u' (Sec. 2.4).
 
     Plain Hestenes-Stiefel CG on the symmetric positive definite operator
@@ -179,25 +184,33 @@ def pcg_split(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
     CG updates), stops when that residual is below rtol * ||v||, and then
     recomputes it from scratch; if the recomputed residual is still too large
     it restarts CG from the current u.
+
+    precond=False replaces E by the plain projection Px: CG on A itself, as
+    Sec. 3 does for point-source masks.  The step lengths and direction
+    coefficients of the first CG run are kept in the returned info.
     """
+    E = apply_E if precond else (lambda a, m, _P: _Px(a, m))
     vnorm = float(np.linalg.norm(v))
     u = np.zeros_like(v)
     hist = []
+    alphas, betas = [], []
     total = 0
     if vnorm == 0.0:
         return u, PCGInfo(0, 0.0, True, hist)
     res = v.copy()
-    for _restart in range(20):
+    for restart in range(20):
         # CG on E A E d' = E res, accumulating d = E d' into u.
-        r = apply_E(res, mask, P)
+        r = E(res, mask, P)
         p = r.copy()
         rr = float(np.vdot(r, r))
         done = False
         while total < max_iter:
-            Ep = apply_E(p, mask, P)
+            Ep = E(p, mask, P)
             AEp = apply_A(Ep, mask, P)
-            q = apply_E(AEp, mask, P)
+            q = E(AEp, mask, P)
             alpha = rr / float(np.vdot(p, q))
+            if restart == 0:
+                alphas.append(alpha)
             u += alpha * Ep
             res -= alpha * AEp
             r -= alpha * q
@@ -212,13 +225,15 @@ def pcg_split(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
             if rr_new == 0.0:  # the split system is solved exactly: check the true residual
                 done = True
                 break
+            if restart == 0:
+                betas.append(rr_new / rr)
             p = r + (rr_new / rr) * p
             rr = rr_new
         res = v - apply_A(u, mask, P)
         rel = float(np.linalg.norm(res)) / vnorm
         if rel <= rtol or not done:
-            return u, PCGInfo(total, rel, rel <= rtol, hist)
-    return u, PCGInfo(total, rel, rel <= rtol, hist)
+            return u, PCGInfo(total, rel, rel <= rtol, hist, alphas, betas)
+    return u, PCGInfo(total, rel, rel <= rtol, hist, alphas, betas)
 
 
 @dataclass

@@ -129,3 +129,31 @@ def rel(a, b, m=None):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+
+
+def masked_circulant_block(P, mask, power):
+    """Dense block of C^power on the masked pixels, C the circulant with
+    eigenvalues P (rows/columns in row-major masked-pixel order).  Built from
+    the covariance function by numpy's inverse FFT and index arithmetic."""
+    ny, nx = mask.shape
+    xi = np.fft.irfft2(P ** power, s=(ny, nx))
+    iy, ix = np.divmod(np.flatnonzero(mask.ravel() != 0), nx)
+    return xi[(iy[:, None] - iy[None, :]) % ny, (ix[:, None] - ix[None, :]) % nx]
+
+
+def explicit_lanczos(M, q0, k):
+    """k steps of Lanczos with full reorthogonalisation on the dense symmetric
+    matrix M from q0: returns (diagonal, off-diagonal) of the tridiagonal."""
+    n = M.shape[0]
+    Q = np.zeros((n, k + 1))
+    Q[:, 0] = q0 / np.linalg.norm(q0)
+    a = np.zeros(k)
+    b = np.zeros(k)
+    for j in range(k):
+        w = M @ Q[:, j]
+        a[j] = Q[:, j] @ w
+        w -= Q[:, :j + 1] @ (Q[:, :j + 1].T @ w)
+        w -= Q[:, :j + 1] @ (Q[:, :j + 1].T @ w)
+        b[j] = np.linalg.norm(w)
+        Q[:, j + 1] = w / b[j]
+    return a, b[:k - 1]
