@@ -135,6 +135,47 @@ int fill_plan_set_max_iter(fill_plan plan, int max_iter);
  */
 int fill_plan_set_inner_tol(fill_plan plan, double tol);
 
+/*
+ * Preconditioner switch (default 1).  1: inner CG with M^-1 = E E,
+ * E = Px C^{1/2} Px, equivalent to the split system of Sec. 2.4.  0: CG on
+ * A = Px C^-1 Px itself, as Sec. 3 does for point-source masks (half the
+ * FFT passes per iteration, more iterations on wide cuts).  Applies to later
+ * solves; the result is the same solution to rtol either way.
+ */
+int fill_plan_set_precond(fill_plan plan, int on);
+
+/*
+ * Lanczos data of the solves (Sec. 6.4): record the CG step lengths alpha_j
+ * and direction coefficients beta_j of the first inner CG of each later solve
+ * (x0 = 0, the Krylov space of the right-hand side), at most cap steps per
+ * problem; cap = 0 stops recording.  Allocates 16*cap*nprob bytes of device
+ * memory on growth (cap <= 2^20).  Recording costs one store per coefficient.
+ */
+int fill_plan_set_lanczos(fill_plan plan, int cap);
+
+/*
+ * The recorded coefficients of problem `problem` of the last solve.
+ *   alpha, beta  host arrays of cap entries; alpha[0..k) and beta[0..k-1)
+ *                are written, k = min(n, cap).
+ *   n            out: number of CG steps recorded (0 if the problem needed
+ *                none).
+ * For the mixed path they are those of the FP32-operator inner CG.
+ * FILL_EINVAL without a record (fill_plan_set_lanczos) or for a bad index.
+ */
+int fill_get_lanczos(fill_plan plan, int problem, double* alpha, double* beta, int cap, int* n);
+
+/*
+ * Extreme eigenvalues of the Lanczos matrix of the recorded steps (diagonal
+ * 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j),
+ * found by Sturm-sequence bisection on the host: estimates of the smallest
+ * and largest eigenvalue of E A E (of A without the preconditioner); their
+ * ratio estimates the condition number that sets the iteration count
+ * (Sec. 2.4, Sec. 6.4).  The estimates lie inside the operator's spectrum and
+ * approach its ends as steps accumulate.  n: steps used.  FILL_EINVAL when
+ * nothing was recorded.
+ */
+int fill_lanczos_extremes(fill_plan plan, int problem, double* lam_min, double* lam_max, int* n);
+
 /* Release every resource of the plan (NULL is accepted). */
 void fill_plan_destroy(fill_plan plan);
 

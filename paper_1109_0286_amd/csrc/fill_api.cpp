@@ -89,6 +89,11 @@ struct fill_plan_s {
   int n_m_total = 0, n_m_max = 0;
   int max_iter = 20000;
   double inner_tol32 = 1e-4;
+  int precond = 1;  // 0: CG on A itself (z = r)
+  // CG coefficient record of the first inner solve of the last solve (Lanczos data)
+  int hist_cap = 0;
+  double* hist = nullptr;
+  std::vector<int> hist_n;
   int nblk64 = 0, nblk32 = 0;
 
   uint8_t* mask = nullptr;
@@ -299,22 +304,33 @@ int upload_params(fill_plan p) {
 // ||r|| = 1, d in v.x); tolerances, caps and the active set are in the device
 // parameters.  Returns per-problem iteration counts and statuses.
 template <typename T>
-int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status) {
+int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bool record) {
   Vecs<T>& v = TypeSel<T>::vecs(p);
   const int nb = TypeSel<T>::nblk(p), np = p->nprob;
   const T* Dinv = TypeSel<T>::Dinv(p);
+  const bool pre = p->precond != 0;
+  double* hist = record && p->hist_cap > 0 ? p->hist : nullptr;
   const size_t vb = (size_t)std::max(p->n_m_total, 1) * sizeof(T);
   HIP_TRY(hipMemsetAsync(v.x, 0, vb, p->stream));
   HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
 
-  // z = E (E r); its partial sums (r.z, r.r) feed the first iteration
-  RowArgs<T> a_in = row_base<T>(p, np), a_mid = row_base<T>(p, np), a_out = row_base<T>(p, np);
-  a_in.v0 = v.r;
-  a_out.v0 = v.z;
-  a_out.v1 = v.r;
-  a_out.part0 = p->part0;
-  a_out.part1 = p->part1;
-  FILL_TRY(apply_EE<T>(p, R2C_COMPACT, a_in, a_mid, a_out, nullptr));
+  // z = E (E r) (or z = r without the preconditioner); the partial sums
+  // (r.z, r.r) feed the first iteration
+  if (pre) {
+    RowArgs<T> a_in = row_base<T>(p, np), a_mid = row_base<T>(p, np), a_out = row_base<T>(p, np);
+    a_in.v0 = v.r;
+    a_out.v0 = v.z;
+    a_out.v1 = v.r;
+    a_out.part0 = p->part0;
+    a_out.part1 = p->part1;
+    FILL_TRY(apply_EE<T>(p, R2C_COMPACT, a_in, a_mid, a_out, nullptr));
+  } else {
+    RowArgs<T> a0 = row_base<T>(p, np);
+    a0.v1 = v.r;
+    a0.part0 = p->part0;
+    a0.part1 = p->part1;
+    HIP_TRY(launch_xr<T>(true, a0, nb, p->stream));
+  }
   HIP_TRY(launch_cg_init(p->sc, p->dp.tol2, p->dp.cap, p->dp.active, np, p->stream));
 
   // Iteration k (parity k % 2), all scalars on the device:
@@ -322,11 +338,13 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status) {
   //       (partials of r.z, r.r from the previous E E r pass), p.q behind;
   //   z = E E r, with alpha = rho/(p.q), x += alpha p, r -= alpha q fused in
   //       front, r.z and r.r behind.
-  RowArgs<T> pa_in[2], e_in[2];
+  //   Without the preconditioner the second half is one vector-update pass
+  //   (z = r: r.z = r.r).
+  RowArgs<T> pa_in[2], e_in[2], xr[2];
   RowArgs<T> pa_out = row_base<T>(p, np), e_mid = row_base<T>(p, np), e_out = row_base<T>(p, np);
   for (int par = 0; par < 2; ++par) {
     pa_in[par] = row_base<T>(p, np);
-    pa_in[par].v0 = v.z;
+    pa_in[par].v0 = pre ? v.z : v.r;
     pa_in[par].v1 = v.p;
     pa_in[par].sc = p->sc;
     pa_in[par].red0 = p->part0;
@@ -342,6 +360,11 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status) {
     e_in[par].red0 = p->part2;
     e_in[par].nred = nb;
     e_in[par].parity = par;
+    pa_in[par].hist = e_in[par].hist = hist;
+    pa_in[par].hist_cap = e_in[par].hist_cap = p->hist_cap;
+    xr[par] = e_in[par];
+    xr[par].part0 = p->part0;
+    xr[par].part1 = p->part1;
   }
   pa_out.v0 = v.q;
   pa_out.v1 = v.p;
@@ -358,7 +381,8 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status) {
     for (int k = 0; k < kChunk; ++k) {
       const int par = k & 1;
       FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc));
-      FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
+      if (pre) FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
+      else HIP_TRY(launch_xr<T>(false, xr[par], nb, p->stream));
     }
     HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -384,6 +408,8 @@ int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
   std::vector<double> rnorm2 = bnorm2, prev(np, 1.0);
   std::vector<int> total(np, 0), outer(np, 0), done(np, 0), status(np, FILL_OK);
   std::vector<int> it, st;
+  p->hist_n.assign(np, 0);
+  bool first = true;
   for (int b = 0; b < np; ++b) {
     p->pstats[b].iters_inner = 0;
     p->pstats[b].iters_outer = 0;
@@ -434,15 +460,16 @@ int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
     FILL_TRY(upload_params(p));
     if (p->prec == FILL_PREC_FP64) {
       HIP_TRY(launch_scale_f64(p->v64.r, p->res, p->dp.scale, p->comp_off, p->n_m_max, np, p->stream));
-      FILL_TRY(inner_pcg<double>(p, it, st));
+      FILL_TRY(inner_pcg<double>(p, it, st, first));
       HIP_TRY(launch_axpy_f64(p->u, p->v64.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
     } else {
       HIP_TRY(launch_scale_to_f32(p->v32.r, p->res, p->dp.scale, p->comp_off, p->n_m_max, np, p->stream));
-      FILL_TRY(inner_pcg<float>(p, it, st));
+      FILL_TRY(inner_pcg<float>(p, it, st, first));
       HIP_TRY(launch_axpy_f32(p->u, p->v32.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
     }
     for (int b = 0; b < np; ++b) {
       if (!p->hp.active[b]) continue;
+      if (first) p->hist_n[b] = std::min(it[b], p->hist_cap);
       total[b] += it[b];
       outer[b] += 1;
       p->pstats[b].iters_inner = total[b];
@@ -452,6 +479,7 @@ int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
         status[b] = FILL_ENOTSPD;
       }
     }
+    first = false;
     // true FP64 residual res = v - A u, every problem
     RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
     ai.v0 = p->u;
@@ -882,6 +910,71 @@ int adjoint_impl(fill_plan p, const double* const* d, const uint64_t* seeds, con
 
 }  // namespace
 
+namespace {
+
+// Lanczos matrix of k CG steps (Sec. 6.4; CG-Lanczos relation): diagonal
+// 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j.
+void lanczos_matrix(const double* al, const double* be, int k, std::vector<double>& d, std::vector<double>& e) {
+  d.assign(k, 0.0);
+  e.assign(k > 0 ? k - 1 : 0, 0.0);
+  for (int j = 0; j < k; ++j) {
+    d[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < k) e[j] = std::sqrt(be[j]) / al[j];
+  }
+}
+
+// Eigenvalues of the symmetric tridiagonal (d, e) below x: the number of
+// negative pivots of the LDL^T factorisation of T - x I (Sturm count); a
+// pivot smaller than pivmin in magnitude is taken as -pivmin.
+int sturm_below(const std::vector<double>& d, const std::vector<double>& e, double x, double pivmin) {
+  int c = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    q = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+    if (std::fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// The i-th smallest eigenvalue (0-based) by bisection inside the Gershgorin interval.
+double tridiag_eig(const std::vector<double>& d, const std::vector<double>& e, int i) {
+  const int n = (int)d.size();
+  double lo = d[0], hi = d[0], emax2 = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double r = (j > 0 ? std::fabs(e[j - 1]) : 0.0) + (j + 1 < n ? std::fabs(e[j]) : 0.0);
+    lo = std::min(lo, d[j] - r);
+    hi = std::max(hi, d[j] + r);
+    if (j + 1 < n) emax2 = std::max(emax2, e[j] * e[j]);
+  }
+  const double pivmin = 2.2250738585072014e-308 * std::max(1.0, emax2);
+  for (int it = 0; it < 400 && hi - lo > 4.0 * 2.220446049250313e-16 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(d, e, mid, pivmin) > i) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+int read_lanczos(fill_plan p, int problem, std::vector<double>& al, std::vector<double>& be) {
+  if (!p) return fail(FILL_EINVAL, "plan is NULL");
+  if (problem < 0 || problem >= p->nprob) return fail(FILL_EINVAL, "problem index out of range");
+  if (p->hist_cap <= 0 || !p->hist) return fail(FILL_EINVAL, "no coefficient record: call fill_plan_set_lanczos first");
+  const int n = (int)p->hist_n.size() > problem ? p->hist_n[problem] : 0;
+  std::vector<double> h((size_t)2 * std::max(n, 1));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (n > 0)
+    HIP_TRY(hipMemcpy(h.data(), p->hist + (size_t)problem * 2 * p->hist_cap, (size_t)2 * n * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  al.resize(n);
+  be.resize(n > 0 ? n - 1 : 0);
+  for (int j = 0; j < n; ++j) al[j] = h[2 * j];
+  for (int j = 0; j + 1 < n; ++j) be[j] = h[2 * j + 1];
+  return FILL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int fill_supported_size(int n) { return size_ok(n) ? 1 : 0; }
@@ -914,6 +1007,51 @@ int fill_plan_set_max_iter(fill_plan p, int max_iter) {
 int fill_plan_set_inner_tol(fill_plan p, double tol) {
   if (!p || !(tol > 0.0) || !(tol < 1.0)) return fail(FILL_EINVAL, "inner tolerance must be in (0, 1)");
   p->inner_tol32 = tol;
+  return FILL_OK;
+}
+
+int fill_plan_set_precond(fill_plan p, int on) {
+  if (!p || (on != 0 && on != 1)) return fail(FILL_EINVAL, "bad argument");
+  p->precond = on;
+  return FILL_OK;
+}
+
+int fill_plan_set_lanczos(fill_plan p, int cap) {
+  g_last_error.clear();
+  if (!p || cap < 0 || cap > (1 << 20)) return fail(FILL_EINVAL, "cap must be in [0, 2^20]");
+  if (cap > p->hist_cap) {
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    double* h = nullptr;
+    FILL_TRY(dalloc(p, &h, (size_t)p->nprob * 2 * cap));
+    p->hist = h;
+  }
+  p->hist_cap = cap;
+  p->hist_n.assign(p->nprob, 0);
+  return FILL_OK;
+}
+
+int fill_get_lanczos(fill_plan p, int problem, double* alpha, double* beta, int cap, int* n) {
+  g_last_error.clear();
+  if (!alpha || !beta || !n || cap < 0) return fail(FILL_EINVAL, "bad argument");
+  std::vector<double> al, be;
+  FILL_TRY(read_lanczos(p, problem, al, be));
+  const int k = std::min((int)al.size(), cap);
+  for (int j = 0; j < k; ++j) alpha[j] = al[j];
+  for (int j = 0; j + 1 < k; ++j) beta[j] = be[j];
+  *n = (int)al.size();
+  return FILL_OK;
+}
+
+int fill_lanczos_extremes(fill_plan p, int problem, double* lam_min, double* lam_max, int* n) {
+  g_last_error.clear();
+  if (!lam_min || !lam_max || !n) return fail(FILL_EINVAL, "NULL argument");
+  std::vector<double> al, be, d, e;
+  FILL_TRY(read_lanczos(p, problem, al, be));
+  *n = (int)al.size();
+  if (al.empty()) return fail(FILL_EINVAL, "no CG step recorded for this problem");
+  lanczos_matrix(al.data(), be.data(), (int)al.size(), d, e);
+  *lam_min = tridiag_eig(d, e, 0);
+  *lam_max = tridiag_eig(d, e, (int)d.size() - 1);
   return FILL_OK;
 }
 

@@ -85,6 +85,8 @@ template <typename T> struct RowArgs {
   const double* red1;
   int nred;
   int parity;          // iteration parity (selects the rho buffer)
+  double* hist;        // CG coefficient record (alpha_j at 2j, beta_j at 2j+1), or null
+  int hist_cap;        // coefficients recorded per problem
   const double* full_in;
   double* full_out;
   double* full_out2;
@@ -119,6 +121,7 @@ template <typename T> __device__ __forceinline__ RowArgs<T> bind_problem(RowArgs
   if (a.part1) a.part1 += (size_t)b * a.part_stride;
   if (a.red0) a.red0 += (size_t)b * a.part_stride;
   if (a.red1) a.red1 += (size_t)b * a.part_stride;
+  if (a.hist) a.hist += (size_t)b * 2 * a.hist_cap;
   if (a.mask) a.mask += (size_t)b * a.pix_stride;
   if (a.full_in) a.full_in += (size_t)b * a.pix_stride;
   if (a.full_out) a.full_out += (size_t)b * a.pix_stride;
@@ -143,6 +146,8 @@ template <typename T> __device__ __forceinline__ void bind_caller(RowArgs<T>& a)
 //     beta = rz / rho[parity]; rho[parity^1] = rz.
 //   XRUPDATE: pq = p.q from the A apply; stop if pq <= 0;
 //     alpha = rho[parity^1] / pq; iter += 1.
+// With a coefficient record (a.hist), workgroup 0 also stores alpha_j and
+// beta_j of iteration j: the data of the Lanczos matrix of the solve.
 template <int MODE, int NT, typename T>
 __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop) {
   __shared__ double s_coef;
@@ -172,6 +177,8 @@ __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop
         } else {
           sc->rho[a.parity ^ 1] = rz;
           sc->beta = coef;
+          const int j = sc->iter - 1;  // beta_j forms p_{j+1}
+          if (a.hist && j >= 0 && j < a.hist_cap) a.hist[2 * j + 1] = coef;
         }
       }
     } else {  // XRUPDATE
@@ -184,6 +191,7 @@ __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop
           sc->done = 1;
         } else {
           sc->alpha = coef;
+          if (a.hist && sc->iter < a.hist_cap) a.hist[2 * sc->iter] = coef;
           sc->iter += 1;
           if (sc->iter >= sc->max_iter) sc->cap = 1;
         }
@@ -690,6 +698,56 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
     if (ev0) hipExtLaunchKernelGGL(kern, grid, block, 0, s, ev0, ev1, 0, __VA_ARGS__);     \
     else hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);                         \
   } while (0)
+
+// ---------------------------------------------------------------------------
+// Vector update of CG without a preconditioner (z = r)
+// ---------------------------------------------------------------------------
+// alpha = rho / (p.q) (partials in red0), x += alpha p, r -= alpha q, then the
+// per-block partial sums of r.r into part0 and part1 (r.z = r.r), which the
+// next p = r + beta p pass reads.  INIT only sums the current r.  Block b of
+// grid.x covers the compact range of rows [b*rows, (b+1)*rows), the row
+// blocks of the row passes, so both passes see the same number of partials.
+constexpr int kXrThreads = 256;
+
+template <typename T, bool INIT>
+__global__ __launch_bounds__(kXrThreads) void xr_kernel(RowArgs<T> a_in, int rows) {
+  RowArgs<T> a = bind_problem(a_in);
+  if (a.sc != nullptr && a.sc->done) return;
+  T coef = T(0);
+  if constexpr (!INIT) {
+    bool stop = false;
+    coef = (T)cg_scalar_step<R2C_XRUPDATE, kXrThreads>(a, &stop);
+    if (stop) return;
+  }
+  const int blk = blockIdx.x;
+  const int c0 = a.row_off[blk * rows], c1 = a.row_off[(blk + 1) * rows];
+  double acc = 0.0, unused = 0.0;
+  for (int c = c0 + (int)threadIdx.x; c < c1; c += kXrThreads) {
+    T r;
+    if constexpr (INIT) {
+      r = a.v1[c];
+    } else {
+      r = a.v1[c] - coef * a.v3[c];
+      a.v0[c] = a.v0[c] + coef * a.v2[c];
+      a.v1[c] = r;
+    }
+    acc += (double)r * (double)r;
+  }
+  block_sum2<kXrThreads>(acc, unused);
+  if (threadIdx.x == 0) {
+    a.part0[blk] = acc;
+    a.part1[blk] = acc;
+  }
+}
+
+template <typename T>
+hipError_t launch_xr(bool init, const RowArgs<T>& a, int nblk, hipStream_t s) {
+  if (nblk <= 0 || a.ny % nblk != 0) return hipErrorInvalidValue;
+  const dim3 grid(nblk, a.nprob), block(kXrThreads);
+  if (init) hipLaunchKernelGGL((xr_kernel<T, true>), grid, block, 0, s, a, a.ny / nblk);
+  else hipLaunchKernelGGL((xr_kernel<T, false>), grid, block, 0, s, a, a.ny / nblk);
+  return hipGetLastError();
+}
 
 template <typename T, int N, int MODE>
 hipError_t launch_r2c_nm(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

@@ -21,6 +21,9 @@ hipError_t launch_col(int ny, const ColArgs<T>& a, hipStream_t s, hipEvent_t e0,
 template <typename T>
 hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> int row_block_rows(int nx);
+// CG vector update without a preconditioner (init: only the r.r partials),
+// nblk row blocks per problem.
+template <typename T> hipError_t launch_xr(bool init, const RowArgs<T>& a, int nblk, hipStream_t s);
 
 // Reset the device CG scalars of nprob problems at the start of an inner solve.
 hipError_t launch_cg_init(CGScalars* sc, const double* tol2, const int* cap, const int* active, int nprob,

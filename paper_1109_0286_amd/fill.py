@@ -42,7 +42,8 @@ EXPORTS = (
     "fill_plan_destroy", "fill_realize", "fill_mean", "fill_get_stats", "fill_apply",
     "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_kernel_timing",
     "fill_kernel_timing_read", "fill_strerror",
-    "fill_last_error",
+    "fill_last_error", "fill_plan_set_precond", "fill_plan_set_lanczos", "fill_get_lanczos",
+    "fill_lanczos_extremes",
 )
 
 FILL_K_R2C = 0
@@ -83,6 +84,10 @@ def _load() -> C.CDLL:
         "fill_plan_set_pk": (i32, [vp, vp]),
         "fill_plan_set_max_iter": (i32, [vp, i32]),
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
+        "fill_plan_set_precond": (i32, [vp, i32]),
+        "fill_plan_set_lanczos": (i32, [vp, i32]),
+        "fill_get_lanczos": (i32, [vp, i32, vp, vp, i32, C.POINTER(i32)]),
+        "fill_lanczos_extremes": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
         "fill_plan_destroy": (None, [vp]),
         "fill_realize": (i32, [vp, vp, u64, vp, dbl]),
         "fill_mean": (i32, [vp, vp, vp, dbl]),
@@ -234,6 +239,33 @@ def fill_plan_set_inner_tol(plan, tol):
     return _check(_lib.fill_plan_set_inner_tol(plan, float(tol)), "fill_plan_set_inner_tol")
 
 
+def fill_plan_set_precond(plan, on):
+    return _check(_lib.fill_plan_set_precond(plan, 1 if on else 0), "fill_plan_set_precond")
+
+
+def fill_plan_set_lanczos(plan, cap):
+    return _check(_lib.fill_plan_set_lanczos(plan, int(cap)), "fill_plan_set_lanczos")
+
+
+def fill_get_lanczos(plan, problem, cap):
+    """(alpha[k], beta[k-1]) recorded for one problem, k = min(steps, cap)."""
+    al = np.zeros(max(int(cap), 1))
+    be = np.zeros(max(int(cap), 1))
+    n = C.c_int(0)
+    _check(_lib.fill_get_lanczos(plan, int(problem), al.ctypes.data, be.ctypes.data, int(cap), C.byref(n)),
+           "fill_get_lanczos")
+    k = min(n.value, int(cap))
+    return al[:k].copy(), be[:max(k - 1, 0)].copy()
+
+
+def fill_lanczos_extremes(plan, problem):
+    """(lambda_min, lambda_max, steps) of the recorded Lanczos matrix."""
+    lo, hi, n = C.c_double(0.0), C.c_double(0.0), C.c_int(0)
+    _check(_lib.fill_lanczos_extremes(plan, int(problem), C.byref(lo), C.byref(hi), C.byref(n)),
+           "fill_lanczos_extremes")
+    return lo.value, hi.value, n.value
+
+
 def fill_plan_destroy(plan):
     _lib.fill_plan_destroy(plan)
 
@@ -341,6 +373,23 @@ class Plan:
 
     def set_inner_tol(self, tol):
         fill_plan_set_inner_tol(self.handle, tol)
+
+    def set_precond(self, on):
+        """Inner CG with (True, default) or without the E E preconditioner."""
+        fill_plan_set_precond(self.handle, on)
+
+    def set_lanczos(self, cap):
+        """Record up to cap CG coefficients of the first inner solve of later solves."""
+        fill_plan_set_lanczos(self.handle, cap)
+        self.lanczos_cap = int(cap)
+
+    def lanczos(self, problem=0):
+        """(alpha, beta) recorded by the last solve."""
+        return fill_get_lanczos(self.handle, problem, getattr(self, "lanczos_cap", 0))
+
+    def lanczos_extremes(self, problem=0):
+        """(lambda_min, lambda_max, steps): extreme Ritz values of the recorded Lanczos matrix."""
+        return fill_lanczos_extremes(self.handle, problem)
 
     def _new_map(self):
         import torch
@@ -470,6 +519,23 @@ class BatchPlan:
     def set_bands(self, lnk_nodes, theta):
         fill_plan_set_bands(self.handle, lnk_nodes, theta)
         self.nbands = len(lnk_nodes)
+
+    def set_precond(self, on):
+        """Inner CG with (True, default) or without the E E preconditioner."""
+        fill_plan_set_precond(self.handle, on)
+
+    def set_lanczos(self, cap):
+        """Record up to cap CG coefficients of the first inner solve of later solves."""
+        fill_plan_set_lanczos(self.handle, cap)
+        self.lanczos_cap = int(cap)
+
+    def lanczos(self, problem=0):
+        """(alpha, beta) recorded by the last solve."""
+        return fill_get_lanczos(self.handle, problem, getattr(self, "lanczos_cap", 0))
+
+    def lanczos_extremes(self, problem=0):
+        """(lambda_min, lambda_max, steps): extreme Ritz values of the recorded Lanczos matrix."""
+        return fill_lanczos_extremes(self.handle, problem)
 
     def adjoint(self, d_obs, seeds, x_out, g, rtol=1e-10, want_logP=False, allow_noconv=False):
         """(grad_dobs, grad_theta, grad_logP) of a loss with dL/dx_out = g (all (nprob, ny, nx))."""
