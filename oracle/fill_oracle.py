@@ -47,7 +47,7 @@ import scipy.fft as sfft
 __all__ = [
     "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1", "REALIZATION_STREAM",
     "philox4x64_10", "white_noise", "circulant_apply", "unconstrained_realization",
-    "rhs", "apply_A", "apply_E", "pcg_split", "fill_realize", "fill_mean", "FillResult",
+    "rhs", "apply_A", "apply_E", "pcg_split", "pcg_cxx", "fill_realize", "fill_mean", "FillResult",
 ]
 
 # FFT threads: ORACLE_WORKERS if set, else every core this process may run on.
@@ -231,6 +231,62 @@ def pcg_split(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
             rr = rr_new
         res = v - apply_A(u, mask, P)
         rel = float(np.linalg.norm(res)) / vnorm
+        if rel <= rtol or not done:
+            return u, PCGInfo(total, rel, rel <= rtol, hist, alphas, betas)
+    return u, PCGInfo(total, rel, rel <= rtol, hist, alphas, betas)
+
+
+def pcg_cxx(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
+            max_iter: int = 20000) -> tuple[np.ndarray, PCGInfo]:
+    """Solve A u = v by preconditioned CG with M^-1 = Px C Px.
+
+    The preconditioner is the covariance restricted to the masked pixels,
+    C_xx, an approximate inverse of A = (C^-1)_xx in the spirit of Sec. 2.4
+    (the powers of C cancel) with one operator apply instead of the two of
+    the split form.  Hestenes-Stiefel PCG from u = 0 on the unpreconditioned
+    residual; stop when ||v - A u|| <= rtol ||v|| (recursive residual, then
+    recomputed, restarting if the recomputed one is too large).  The step
+    lengths and direction coefficients of the first CG run are kept.
+    """
+    def Minv(a):
+        return _Px(circulant_apply(_Px(a, mask), P, 1.0), mask)
+
+    vnorm = float(np.linalg.norm(v))
+    u = np.zeros_like(v)
+    hist, alphas, betas = [], [], []
+    total = 0
+    if vnorm == 0.0:
+        return u, PCGInfo(0, 0.0, True, hist)
+    r = v.copy()
+    rel = 1.0
+    for restart in range(20):
+        z = Minv(r)
+        p = z.copy()
+        rz = float(np.vdot(r, z))
+        done = False
+        while total < max_iter:
+            q = apply_A(p, mask, P)
+            alpha = rz / float(np.vdot(p, q))
+            if restart == 0:
+                alphas.append(alpha)
+            u += alpha * p
+            r -= alpha * q
+            total += 1
+            rel = float(np.linalg.norm(r)) / vnorm
+            if rel <= rtol:
+                done = True
+                break
+            z = Minv(r)
+            rz_new = float(np.vdot(r, z))
+            if rz_new == 0.0:
+                done = True
+                break
+            if restart == 0:
+                betas.append(rz_new / rz)
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        r = v - apply_A(u, mask, P)
+        rel = float(np.linalg.norm(r)) / vnorm
         if rel <= rtol or not done:
             return u, PCGInfo(total, rel, rel <= rtol, hist, alphas, betas)
     return u, PCGInfo(total, rel, rel <= rtol, hist, alphas, betas)

@@ -91,3 +91,59 @@ def test_mutation_shifted_beta_index_fails(case64):
 
     d, o = wrong(info.alphas, info.betas)
     assert np.abs(d - a).max() > 1e-3 * np.abs(a).max()
+
+
+# --------------------------------------------------------------------------
+# PCG with M^-1 = Px C Px (covariance restricted to the masked pixels)
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def case_cxx():
+    p = W.make_problem("grid64")
+    m = p.mask
+    s = F.unconstrained_realization(p.P, p.seed)
+    v = F.rhs(np.where(m != 0, 0.0, p.d_obs - s), m, p.P)
+    Ci = masked_circulant_block(p.P, m, -1.0)
+    Cxx = masked_circulant_block(p.P, m, 1.0)
+    Lc = np.linalg.cholesky(Cxx)
+    u, info = F.pcg_cxx(v, m, p.P, 1e-12)
+    return p, v, u, info, Ci, Cxx, Lc
+
+
+def test_pcg_cxx_solves_the_dense_system(case_cxx):
+    # u* = A^-1 v with A the dense (C^-1)_xx block: direct solve
+    p, v, u, info, Ci, _, _ = case_cxx
+    m = p.mask.ravel() != 0
+    ref = np.linalg.solve(Ci, v.ravel()[m])
+    assert info.converged
+    assert np.linalg.norm(u.ravel()[m] - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert np.all(u.ravel()[~m] == 0.0)
+
+
+def test_pcg_cxx_tridiagonal_equals_explicit_lanczos(case_cxx):
+    # PCG with M^-1 = L L^T on A is CG on L^T A L from L^T r0
+    p, v, _, info, Ci, _, Lc = case_cxx
+    k = 10
+    vc = v.ravel()[p.mask.ravel() != 0]
+    a, b = explicit_lanczos(Lc.T @ Ci @ Lc, Lc.T @ vc, k)
+    d, o = L.lanczos_tridiagonal(info.alphas[:k], info.betas[:k - 1])
+    assert np.abs(d - a).max() <= 1e-9 * np.abs(a).max()
+    assert np.abs(o - b).max() <= 1e-9 * np.abs(b).max()
+
+
+def test_pcg_cxx_ritz_values_inside_spectrum(case_cxx):
+    _, _, _, info, Ci, _, Lc = case_cxx
+    ev = np.linalg.eigvalsh(Lc.T @ Ci @ Lc)
+    rv = L.ritz_values(info.alphas, info.betas)
+    assert rv[0] >= ev[0] * (1 - 1e-9) and rv[-1] <= ev[-1] * (1 + 1e-9)
+    assert abs(rv[-1] - ev[-1]) <= 1e-4 * ev[-1]
+    assert abs(rv[0] - ev[0]) <= 0.05 * ev[0]
+
+
+def test_pcg_cxx_matches_split_solution():
+    p = W.make_problem("grid2048", n=128)
+    v = F.rhs(np.where(p.mask != 0, 0.0, p.d_obs), p.mask, p.P)
+    u1, i1 = F.pcg_split(v, p.mask, p.P, 1e-11)
+    u2, i2 = F.pcg_cxx(v, p.mask, p.P, 1e-11)
+    assert i1.converged and i2.converged
+    assert np.linalg.norm(u2 - u1) <= 1e-6 * np.linalg.norm(u1)
