@@ -5,7 +5,9 @@ a band mask over 10% of the rows plus 200 holes of radius U(2, 12) px
 (mask seed 2), observed map drawn from P (seed 0), fill seed 1, true FP64
 relative residual 1e-8.  One step = one complete fill_realize: white-noise
 realization, right-hand side, preconditioned CG with FP64 refinement and
-assembly, inputs resident in device memory.
+assembly, inputs resident in device memory.  The inner CG is preconditioned
+with M^-1 = Px C Px by default (--precond); the 2048^2 line also times the
+split form E E of Sec. 2.4.
 
 `value` is solves/s of the FP32-operator path with FP64 refinement; the
 plain FP64 path is timed on the same inputs and reported beside it.  The
@@ -30,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PRECONDS = {"split": 1, "cxx": 2, "none": 0}  # fill_precond: E E (Sec. 2.4 split form), Px C Px, plain CG
 CALIB_BYTES = 256 << 20  # plain device copy used to scale the rocprofv3 byte counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "col_kernel_f32_2048_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1109_0286_amd", "csrc", f) for f in ("fft_device.hpp", "kernels.hpp")]
@@ -122,6 +125,7 @@ def bench_batch_2048(F, prob, args) -> dict:
     d = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(prob.d_obs, (B,) + prob.d_obs.shape))).cuda()
     seeds = list(range(1, B + 1))
     bp = F.BatchPlan(prob.nx, prob.ny, masks, prob.P, F.FILL_PREC_FP32_OP)
+    bp.set_precond(PRECONDS[args.precond])
     x = torch.empty_like(d)
     steps = max(1, args.steps // 4)
     for _ in range(max(1, args.warmup // 2)):
@@ -153,6 +157,7 @@ def bench_mixed64(args) -> int:
     for n, ps in sorted(groups.items()):
         plans.append(F.BatchPlan(n, n, np.stack([p.mask for p in ps]), ps[0].P, F.FILL_PREC_FP32_OP,
                                  stream=torch.cuda.Stream()))
+        plans[-1].set_precond(PRECONDS[args.precond])
         ds.append(torch.from_numpy(np.stack([p.d_obs for p in ps])).cuda())
         seeds.append([p.seed for p in ps])
     torch.cuda.synchronize()
@@ -174,7 +179,77 @@ def bench_mixed64(args) -> int:
            "config": {"workload": "64 problems, n ~ U{256,512,768,1024}, band U(5,20)% + U{20..100} holes "
                                   "r~U(2,10), damping n/8, rtol 1e-6; one batched plan per size, 4 streams",
                       "problems_per_size": {str(k): len(v) for k, v in sorted(groups.items())},
-                      "iters_inner_max": max(iters), "iters_inner_mean": float(np.mean(iters))}}
+                      "iters_inner_max": max(iters), "iters_inner_mean": float(np.mean(iters)),
+                      "preconditioner": args.precond}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def lanczos_report(plan, d, seed, rtol, cap=20000) -> dict:
+    """One extra (untimed) solve with the CG coefficient record on: the
+    extreme Ritz values of its Lanczos matrix, the condition number they
+    imply and the classical CG iteration bound for rtol."""
+    import math
+    plan.set_lanczos(cap)
+    plan.realize(d, seed, rtol)
+    lo, hi, n = plan.lanczos_extremes()
+    plan.set_lanczos(0)
+    kappa = hi / lo
+    return {"lambda_min": lo, "lambda_max": hi, "kappa": kappa, "steps": n,
+            "cg_bound_iters": math.ceil(0.5 * math.sqrt(kappa) * math.log(2.0 / rtol))}
+
+
+def compare_preconds(F, prob, d, args) -> dict:
+    """Solves/s and iterations of every preconditioner, FP64 and mixed (fewer steps)."""
+    res = {}
+    steps = max(2, args.steps // 4)
+    for pname, pc in PRECONDS.items():
+        if pname == "none" and prob.meta["band"][1] > 0:
+            continue  # thousands of iterations on a band: not a contender
+        for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
+            plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
+            plan.set_precond(pc)
+            dt, st, _, _ = time_solves(F, plan, d, prob.seed, prob.rtol, steps, 1, -1)
+            res[f"{name}_{pname}"] = {"solves_per_s": steps / dt, "iters_inner": st["iters_inner"],
+                                      "iters_outer": st["iters_outer"]}
+            plan.close()
+    return res
+
+
+def bench_holes2048(args) -> int:
+    """2048^2 point-source mask (the 200 holes of the 2048^2 workload, no
+    band): CG with each preconditioner and without one, FP64 and mixed,
+    with each system's Lanczos condition estimate."""
+    import torch
+    import paper_1109_0286_amd as F
+    import workloads as W
+    prob = W.make_problem("holes2048")
+    d = torch.from_numpy(prob.d_obs).cuda()
+    res = {}
+    for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
+        for pname, pc in PRECONDS.items():
+            plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
+            plan.set_precond(pc)
+            dt, st, _, _ = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, -1)
+            key = f"{name}_{pname}"
+            res[key] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
+                        "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
+                        "rel_resid": st["rel_resid"]}
+            if name == "fp64":
+                res[key]["lanczos"] = lanczos_report(plan, d, prob.seed, prob.rtol)
+            print(f"# {key}: {res[key]['solves_per_s']:.2f} solves/s, {st['iters_inner']} iterations",
+                  file=sys.stderr, flush=True)
+            plan.close()
+    best = max((k for k in res if k.startswith("mixed")), key=lambda k: res[k]["solves_per_s"])
+    out = {"metric": "PCG fill-in solves/s at 2048^2, point-source mask (rel resid 1e-8)",
+           "value": res[best]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res[best]["ms_per_solve"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement",
+           "data": "synthetic",
+           "config": {"workload": "2048x2048 torus, damped power law k0^2=4 damping 256 floor 1e-7, "
+                                  "200 holes r~U(2,12) and no band, rtol 1e-8", "n_masked": prob.n_masked,
+                      "value_path": best},
+           "paths": res}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -191,6 +266,7 @@ def bench_grid4096(args) -> int:
     res = {}
     for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
         plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
+        plan.set_precond(PRECONDS[args.precond])
         dt, st, col_ms, _ = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, F.FILL_K_COL)
         res[name] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
                      "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
@@ -203,7 +279,7 @@ def bench_grid4096(args) -> int:
            "ms_per_step": res["mixed"]["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement", "data": "synthetic",
            "config": {"workload": "4096x4096 torus, 30% band + 500 holes r~U(2,16), damping 512, floor 1e-7, "
-                                  "rtol 1e-8", "n_masked": prob.n_masked},
+                                  "rtol 1e-8", "n_masked": prob.n_masked, "preconditioner": args.precond},
            "paths": res,
            "roofline": {"bound": "hbm", "kernel": "col_kernel<float,4096>", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
@@ -228,6 +304,7 @@ def bench_grad16(args) -> int:
     w = torch.from_numpy(np.random.default_rng(7).uniform(0, 1, (nprob, n, n))).cuda()
     seeds = list(range(1, nprob + 1))
     bp = F.BatchPlan(n, n, masks, P, F.FILL_PREC_FP32_OP)
+    bp.set_precond(PRECONDS[args.precond])
     FillFn = F.autograd_fill()
     th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
 
@@ -252,7 +329,8 @@ def bench_grad16(args) -> int:
            "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement", "data": "synthetic",
            "config": {"workload": "16 x 1024^2, 10% band + 100 holes r~U(2,10), 50 log-spaced band powers, "
-                                  "loss sum(w x^2) w~U(0,1), forward rtol 1e-8, adjoint rtol 1e-10"}}
+                                  "loss sum(w x^2) w~U(0,1), forward rtol 1e-8, adjoint rtol 1e-10",
+                      "preconditioner": args.precond}}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -268,9 +346,14 @@ def main() -> int:
     ap.add_argument("--reps", type=int, default=50, help="launches per isolated kernel timing")
     ap.add_argument("--batch", type=int, default=4,
                     help="realizations per launch in the batched 2048^2 leg (0: skip it)")
-    ap.add_argument("--workload", default="grid2048", choices=["grid2048", "mixed64", "grid4096", "grad16"],
+    ap.add_argument("--workload", default="grid2048",
+                    choices=["grid2048", "mixed64", "grid4096", "grad16", "holes2048"],
                     help="grid2048: the headline line; mixed64: 64 problems of uneven sizes; grid4096: the wide "
-                         "cut; grad16: forward + adjoint of 16 1024^2 maps with 50 band powers")
+                         "cut; grad16: forward + adjoint of 16 1024^2 maps with 50 band powers; holes2048: "
+                         "point sources only, CG with and without the preconditioner")
+    ap.add_argument("--precond", default="cxx", choices=list(PRECONDS),
+                    help="inner-CG preconditioner (every workload): cxx (Px C Px, default), split (E E, the "
+                         "paper's split form) or none; the 2048^2 line also times the others")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with three plain 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -289,6 +372,8 @@ def main() -> int:
         return bench_grid4096(args)
     if args.workload == "grad16":
         return bench_grad16(args)
+    if args.workload == "holes2048":
+        return bench_holes2048(args)
 
     prob = W.make_problem("grid2048")
     nx, ny, rtol, seed = prob.nx, prob.ny, prob.rtol, prob.seed
@@ -296,6 +381,9 @@ def main() -> int:
     d = torch.from_numpy(prob.d_obs).cuda()
     plan32 = F.Plan(nx, ny, prob.mask, prob.P, F.FILL_PREC_FP32_OP)
     plan64 = F.Plan(nx, ny, prob.mask, prob.P, F.FILL_PREC_FP64)
+    pc = PRECONDS[args.precond]
+    plan32.set_precond(pc)
+    plan64.set_precond(pc)
     n_m = prob.n_masked
 
     dt64, st64, col64_ms, _ = time_solves(F, plan64, d, seed, rtol, args.steps, args.warmup, F.FILL_K_COL)
@@ -328,6 +416,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "2048x2048 torus, damped power law k0^2=4 damping 256 floor 1e-7, "
                                "10% band + 200 holes r~U(2,12), rtol 1e-8, 1 realization per step",
+                   "preconditioner": args.precond,
                    "n_masked": n_m, "iters_inner": st32["iters_inner"], "iters_outer": st32["iters_outer"],
                    "rel_resid": st32["rel_resid"]},
         "fp64_path": {"value": args.steps / dt64, "unit": "solves/s", "ms_per_step": dt64 / args.steps * 1e3,
@@ -339,6 +428,8 @@ def main() -> int:
                      "traffic": measured_traffic(), "bytes_per_launch": nbytes, "launches_timed": col32_n,
                      "kernel_source_hash": kernel_source_hash()},
     }
+    out["lanczos_fp64"] = lanczos_report(plan64, d, seed, rtol)
+    out["preconditioners"] = compare_preconds(F, prob, d, args)
     if args.batch > 0:
         out["batched_2048"] = bench_batch_2048(F, prob, args)
     if not args.no_cpu_baseline:

@@ -63,6 +63,13 @@ enum fill_precision {
                             scalars, true residual and refinement correction */
 };
 
+/* Preconditioners of the inner CG (fill_plan_set_precond). */
+enum fill_precond {
+  FILL_PRECOND_NONE = 0,   /* plain CG on A */
+  FILL_PRECOND_SPLIT = 1,  /* M^-1 = E E, the split form of Sec. 2.4 (default) */
+  FILL_PRECOND_CXX = 2     /* M^-1 = Px C Px */
+};
+
 /* Operators on full maps for fill_apply (Sec. 2.4 notation). */
 enum fill_op {
   FILL_OP_CINV = 0,   /* out = C^-1 in */
@@ -136,13 +143,20 @@ int fill_plan_set_max_iter(fill_plan plan, int max_iter);
 int fill_plan_set_inner_tol(fill_plan plan, double tol);
 
 /*
- * Preconditioner switch (default 1).  1: inner CG with M^-1 = E E,
- * E = Px C^{1/2} Px, equivalent to the split system of Sec. 2.4.  0: CG on
- * A = Px C^-1 Px itself, as Sec. 3 does for point-source masks (half the
- * FFT passes per iteration, more iterations on wide cuts).  Applies to later
- * solves; the result is the same solution to rtol either way.
+ * Preconditioner of the inner CG (enum fill_precond, default
+ * FILL_PRECOND_SPLIT), for later solves; every choice reaches the same
+ * solution to rtol.
+ *   FILL_PRECOND_SPLIT  M^-1 = E E, E = Px C^{1/2} Px: equivalent to the split
+ *                       system E A E u' = E v of Sec. 2.4 (two applies of E
+ *                       per iteration, fused into five passes).
+ *   FILL_PRECOND_CXX    M^-1 = Px C Px, the covariance block of the masked
+ *                       pixels: the same idea (the powers of C cancel) with
+ *                       one apply (three passes) per iteration.
+ *   FILL_PRECOND_NONE   CG on A itself, as Sec. 3 does for point-source masks
+ *                       (one vector pass per iteration; many more iterations
+ *                       on wide cuts).
  */
-int fill_plan_set_precond(fill_plan plan, int on);
+int fill_plan_set_precond(fill_plan plan, int mode);
 
 /*
  * Lanczos data of the solves (Sec. 6.4): record the CG step lengths alpha_j

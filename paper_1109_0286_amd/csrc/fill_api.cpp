@@ -89,7 +89,7 @@ struct fill_plan_s {
   int n_m_total = 0, n_m_max = 0;
   int max_iter = 20000;
   double inner_tol32 = 1e-4;
-  int precond = 1;  // 0: CG on A itself (z = r)
+  int precond = FILL_PRECOND_SPLIT;
   // CG coefficient record of the first inner solve of the last solve (Lanczos data)
   int hist_cap = 0;
   double* hist = nullptr;
@@ -102,8 +102,10 @@ struct fill_plan_s {
   int* comp_off = nullptr;
   double* Dinv64 = nullptr;
   double* Dhalf64 = nullptr;
+  double* Dfull64 = nullptr;  // P/N: the Px C Px preconditioner
   float* Dinv32 = nullptr;
   float* Dhalf32 = nullptr;
+  float* Dfull32 = nullptr;
   double2* twx64 = nullptr;
   double2* twy64 = nullptr;
   float2* twx32 = nullptr;
@@ -168,6 +170,7 @@ template <> struct TypeSel<double> {
   static const cplx<double>* twy(fill_plan p) { return p->twy64; }
   static const double* Dinv(fill_plan p) { return p->Dinv64; }
   static const double* Dhalf(fill_plan p) { return p->Dhalf64; }
+  static const double* Dfull(fill_plan p) { return p->Dfull64; }
   static int nblk(fill_plan p) { return p->nblk64; }
   static Vecs<double>& vecs(fill_plan p) { return p->v64; }
 };
@@ -176,6 +179,7 @@ template <> struct TypeSel<float> {
   static const cplx<float>* twy(fill_plan p) { return p->twy32; }
   static const float* Dinv(fill_plan p) { return p->Dinv32; }
   static const float* Dhalf(fill_plan p) { return p->Dhalf32; }
+  static const float* Dfull(fill_plan p) { return p->Dfull32; }
   static int nblk(fill_plan p) { return p->nblk32; }
   static Vecs<float>& vecs(fill_plan p) { return p->v32; }
 };
@@ -308,22 +312,23 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   Vecs<T>& v = TypeSel<T>::vecs(p);
   const int nb = TypeSel<T>::nblk(p), np = p->nprob;
   const T* Dinv = TypeSel<T>::Dinv(p);
-  const bool pre = p->precond != 0;
+  const int mode = p->precond;
   double* hist = record && p->hist_cap > 0 ? p->hist : nullptr;
   const size_t vb = (size_t)std::max(p->n_m_total, 1) * sizeof(T);
   HIP_TRY(hipMemsetAsync(v.x, 0, vb, p->stream));
   HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
 
-  // z = E (E r) (or z = r without the preconditioner); the partial sums
-  // (r.z, r.r) feed the first iteration
-  if (pre) {
+  // z = M^-1 r: E (E r), Px C Px r, or r without a preconditioner; the
+  // partial sums (r.z, r.r) feed the first iteration
+  if (mode != FILL_PRECOND_NONE) {
     RowArgs<T> a_in = row_base<T>(p, np), a_mid = row_base<T>(p, np), a_out = row_base<T>(p, np);
     a_in.v0 = v.r;
     a_out.v0 = v.z;
     a_out.v1 = v.r;
     a_out.part0 = p->part0;
     a_out.part1 = p->part1;
-    FILL_TRY(apply_EE<T>(p, R2C_COMPACT, a_in, a_mid, a_out, nullptr));
+    if (mode == FILL_PRECOND_SPLIT) FILL_TRY(apply_EE<T>(p, R2C_COMPACT, a_in, a_mid, a_out, nullptr));
+    else FILL_TRY(apply3<T>(p, R2C_COMPACT, a_in, TypeSel<T>::Dfull(p), C2R_DOT2, a_out, nullptr));
   } else {
     RowArgs<T> a0 = row_base<T>(p, np);
     a0.v1 = v.r;
@@ -338,13 +343,13 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   //       (partials of r.z, r.r from the previous E E r pass), p.q behind;
   //   z = E E r, with alpha = rho/(p.q), x += alpha p, r -= alpha q fused in
   //       front, r.z and r.r behind.
-  //   Without the preconditioner the second half is one vector-update pass
-  //   (z = r: r.z = r.r).
+  //   With M^-1 = Px C Px the second half is one apply (table P);
+  //   without a preconditioner it is one vector-update pass (z = r: r.z = r.r).
   RowArgs<T> pa_in[2], e_in[2], xr[2];
   RowArgs<T> pa_out = row_base<T>(p, np), e_mid = row_base<T>(p, np), e_out = row_base<T>(p, np);
   for (int par = 0; par < 2; ++par) {
     pa_in[par] = row_base<T>(p, np);
-    pa_in[par].v0 = pre ? v.z : v.r;
+    pa_in[par].v0 = mode != FILL_PRECOND_NONE ? v.z : v.r;
     pa_in[par].v1 = v.p;
     pa_in[par].sc = p->sc;
     pa_in[par].red0 = p->part0;
@@ -381,7 +386,9 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
     for (int k = 0; k < kChunk; ++k) {
       const int par = k & 1;
       FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc));
-      if (pre) FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
+      if (mode == FILL_PRECOND_SPLIT) FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
+      else if (mode == FILL_PRECOND_CXX)
+        FILL_TRY(apply3<T>(p, R2C_XRUPDATE, e_in[par], TypeSel<T>::Dfull(p), C2R_DOT2, e_out, p->sc));
       else HIP_TRY(launch_xr<T>(false, xr[par], nb, p->stream));
     }
     HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
@@ -552,8 +559,8 @@ int twiddles(int n, std::vector<double2>& w64, std::vector<float2>& w32) {
 int upload_pk(fill_plan p, const double* Pk, int npk) {
   const int nx = p->nx, ny = p->ny, nc = p->ncol;
   const size_t nt = p->nt;
-  std::vector<double> inv(nt), half(nt);
-  std::vector<float> inv32(nt), half32(nt);
+  std::vector<double> inv(nt), half(nt), full(nt);
+  std::vector<float> inv32(nt), half32(nt), full32(nt);
   const double scale = 1.0 / ((double)nx * (double)ny);
   for (int k = 0; k < npk; ++k) {
     const double* P0 = Pk + (size_t)k * ny * nc;
@@ -567,14 +574,18 @@ int upload_pk(fill_plan p, const double* Pk, int npk) {
         const size_t o = (size_t)ix * ny + iy;
         inv[o] = scale / P;
         half[o] = scale * std::sqrt(P);
+        full[o] = scale * P;
         inv32[o] = (float)inv[o];
         half32[o] = (float)half[o];
+        full32[o] = (float)full[o];
       }
     }
     HIP_TRY(hipMemcpy(p->Dinv64 + k * nt, inv.data(), nt * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->Dhalf64 + k * nt, half.data(), nt * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->Dinv32 + k * nt, inv32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->Dhalf32 + k * nt, half32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->Dfull64 + k * nt, full.data(), nt * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->Dfull32 + k * nt, full32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
   }
   return FILL_OK;
 }
@@ -613,6 +624,8 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   FILL_TRY(dalloc(p, &p->Dhalf64, nt * p->npk));
   FILL_TRY(dalloc(p, &p->Dinv32, nt * p->npk));
   FILL_TRY(dalloc(p, &p->Dhalf32, nt * p->npk));
+  FILL_TRY(dalloc(p, &p->Dfull64, nt * p->npk));
+  FILL_TRY(dalloc(p, &p->Dfull32, nt * p->npk));
   std::vector<double2> twx64, twy64;
   std::vector<float2> twx32, twy32;
   FILL_TRY(twiddles(nx, twx64, twx32));
@@ -1010,9 +1023,9 @@ int fill_plan_set_inner_tol(fill_plan p, double tol) {
   return FILL_OK;
 }
 
-int fill_plan_set_precond(fill_plan p, int on) {
-  if (!p || (on != 0 && on != 1)) return fail(FILL_EINVAL, "bad argument");
-  p->precond = on;
+int fill_plan_set_precond(fill_plan p, int mode) {
+  if (!p || mode < FILL_PRECOND_NONE || mode > FILL_PRECOND_CXX) return fail(FILL_EINVAL, "unknown preconditioner");
+  p->precond = mode;
   return FILL_OK;
 }
 

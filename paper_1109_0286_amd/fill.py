@@ -46,6 +46,10 @@ EXPORTS = (
     "fill_lanczos_extremes",
 )
 
+FILL_PRECOND_NONE = 0
+FILL_PRECOND_SPLIT = 1
+FILL_PRECOND_CXX = 2
+
 FILL_K_R2C = 0
 FILL_K_COL = 1
 FILL_K_C2R = 2
@@ -239,8 +243,11 @@ def fill_plan_set_inner_tol(plan, tol):
     return _check(_lib.fill_plan_set_inner_tol(plan, float(tol)), "fill_plan_set_inner_tol")
 
 
-def fill_plan_set_precond(plan, on):
-    return _check(_lib.fill_plan_set_precond(plan, 1 if on else 0), "fill_plan_set_precond")
+def fill_plan_set_precond(plan, mode):
+    """mode: FILL_PRECOND_NONE / _SPLIT / _CXX (True/False map to SPLIT/NONE)."""
+    if mode is True or mode is False:
+        mode = FILL_PRECOND_SPLIT if mode else FILL_PRECOND_NONE
+    return _check(_lib.fill_plan_set_precond(plan, int(mode)), "fill_plan_set_precond")
 
 
 def fill_plan_set_lanczos(plan, cap):
@@ -374,9 +381,9 @@ class Plan:
     def set_inner_tol(self, tol):
         fill_plan_set_inner_tol(self.handle, tol)
 
-    def set_precond(self, on):
-        """Inner CG with (True, default) or without the E E preconditioner."""
-        fill_plan_set_precond(self.handle, on)
+    def set_precond(self, mode):
+        """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
+        fill_plan_set_precond(self.handle, mode)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""
@@ -520,9 +527,9 @@ class BatchPlan:
         fill_plan_set_bands(self.handle, lnk_nodes, theta)
         self.nbands = len(lnk_nodes)
 
-    def set_precond(self, on):
-        """Inner CG with (True, default) or without the E E preconditioner."""
-        fill_plan_set_precond(self.handle, on)
+    def set_precond(self, mode):
+        """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
+        fill_plan_set_precond(self.handle, mode)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""

@@ -1,4 +1,5 @@
-"""GPU: the Lanczos record of the CG solves and CG without the preconditioner.
+"""GPU: the Lanczos record of the CG solves, CG without the preconditioner
+and CG with the Px C Px preconditioner.
 
 * CG coefficients (alpha_j, beta_j) of the first inner solve against the
   oracle's (same Krylov space: agreement to 1e-8 over the first steps, before
@@ -159,10 +160,76 @@ def test_lanczos_errors(F, grid64):
         plan.lanczos_extremes()  # nothing recorded
     with pytest.raises(F.FillError):
         F.fill_plan_set_lanczos(plan.handle, -1)
-    assert F.fill._lib.fill_plan_set_precond(plan.handle, 2) == F.FILL_EINVAL
+    assert F.fill._lib.fill_plan_set_precond(plan.handle, 3) == F.FILL_EINVAL
+    assert F.fill._lib.fill_plan_set_precond(plan.handle, -1) == F.FILL_EINVAL
     plan.set_lanczos(16)
     plan.realize(dev(p.d_obs), p.seed, 1e-10)
     al, be = plan.lanczos()
     assert len(al) == 16 and len(be) == 15  # capped record
     with pytest.raises(F.FillError):
         plan.lanczos_extremes(problem=1)
+
+
+# ---------------------------------------------------------------------------
+# M^-1 = Px C Px
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cxx64(grid64):
+    p, v, _ = grid64
+    _, info = OF.pcg_cxx(v, p.mask, p.P, 1e-12)
+    Ci = masked_circulant_block(p.P, p.mask, -1.0)
+    Lc = np.linalg.cholesky(masked_circulant_block(p.P, p.mask, 1.0))
+    return p, info, np.linalg.eigvalsh(Lc.T @ Ci @ Lc)
+
+
+def test_cxx_coefficients_and_ritz_values(F, cxx64):
+    p, info, ev = cxx64
+    plan = F.Plan(p.nx, p.ny, p.mask, p.P)
+    plan.set_precond(F.FILL_PRECOND_CXX)
+    plan.set_lanczos(4096)
+    plan.realize(dev(p.d_obs), p.seed, 1e-12)
+    al, be = plan.lanczos()
+    k = 10
+    assert np.abs(al[:k] - info.alphas[:k]).max() <= 1e-8 * np.abs(info.alphas[:k]).max()
+    assert np.abs(be[:k - 1] - info.betas[:k - 1]).max() <= 1e-8 * np.abs(info.betas[:k - 1]).max()
+    lo, hi, _ = plan.lanczos_extremes()
+    assert lo >= ev[0] * (1 - 1e-9) and hi <= ev[-1] * (1 + 1e-9)
+    assert abs(hi - ev[-1]) <= 1e-4 * ev[-1] and abs(lo - ev[0]) <= 0.05 * ev[0]
+
+
+@pytest.mark.parametrize("prec,tol,rtol", [(0, 1e-9, 1e-12), (1, 1e-5, 1e-11)])
+def test_cxx_fill_matches_oracle(F, grid64, prec, tol, rtol):
+    p, _, _ = grid64
+    ref = OF.fill_realize(p.d_obs, p.mask, p.P, p.seed, 1e-13)
+    plan = F.Plan(p.nx, p.ny, p.mask, p.P, prec=prec)
+    plan.set_precond(F.FILL_PRECOND_CXX)
+    x = host(plan.realize(dev(p.d_obs), p.seed, rtol))
+    m = p.mask != 0
+    assert rel(x, ref.x_out, m) < tol
+    assert np.array_equal(x[~m].view(np.uint64), p.d_obs[~m].view(np.uint64))
+
+
+def test_cxx_mixed_512_matches_oracle(F):
+    p = W.make_problem("grid2048", n=512)
+    ref = OF.fill_realize(p.d_obs, p.mask, p.P, p.seed, 1e-11)
+    plan = F.Plan(p.nx, p.ny, p.mask, p.P, prec=1)
+    plan.set_precond(F.FILL_PRECOND_CXX)
+    x = host(plan.realize(dev(p.d_obs), p.seed, 1e-10))
+    assert rel(x, ref.x_out, p.mask != 0) < 1e-5
+    assert plan.stats()["rel_resid"] <= 1e-10
+
+
+def test_cxx_batch_matches_single(F):
+    n = 256
+    probs = []
+    for i in range(2):
+        P = W.damped_power_law(n, n, 4.0, n / 8, 1e-7)
+        mask = W.band_holes_mask(n, n, W.band_rows(n, 0.1 + 0.05 * i), 20, 2.0, 8.0, 70 + i)
+        probs.append((P, mask, W.observed_map(P, n, n, 80 + i, mask)))
+    bp = F.BatchPlan(n, n, np.stack([m for _, m, _ in probs]), probs[0][0], prec=1)
+    bp.set_precond(F.FILL_PRECOND_CXX)
+    xb = host(bp.realize(dev(np.stack([d for _, _, d in probs])), [3, 4], 1e-9))
+    for i, (P, mask, d) in enumerate(probs):
+        ref = OF.fill_realize(d, mask, P, 3 + i, 1e-12)
+        assert rel(xb[i], ref.x_out, mask != 0) < 1e-5

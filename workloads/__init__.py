@@ -154,6 +154,9 @@ CONFIGS = {
     # 2048^2: 10% band + 200 holes r~U(2,12).
     "grid2048": dict(n=2048, k0sq=4.0, damping=256.0, floor=1e-7, band_frac=0.10, n_holes=200,
                      rmin=2.0, rmax=12.0, mask_seed=2, dobs_seed=0, seed=1, rtol=1e-8),
+    # 2048^2 point sources only: the 200 holes of the 2048^2 workload, no band.
+    "holes2048": dict(n=2048, k0sq=4.0, damping=256.0, floor=1e-7, band_frac=0.0, n_holes=200,
+                      rmin=2.0, rmax=12.0, mask_seed=2, dobs_seed=0, seed=1, rtol=1e-8),
     # 4096^2 wide cut: 30% band + 500 holes r~U(2,16).
     "grid4096": dict(n=4096, k0sq=4.0, damping=512.0, floor=1e-7, band_frac=0.30, n_holes=500,
                      rmin=2.0, rmax=16.0, mask_seed=4, dobs_seed=0, seed=1, rtol=1e-8),
