@@ -190,6 +190,17 @@ int fill_get_lanczos(fill_plan plan, int problem, double* alpha, double* beta, i
  */
 int fill_lanczos_extremes(fill_plan plan, int problem, double* lam_min, double* lam_max, int* n);
 
+/*
+ * Graph replay of the inner CG (default 1).  The inner CG runs in chunks of
+ * 16 iterations between host checks of the device convergence flags; with 1
+ * each chunk is captured once per plan (per precision, preconditioner and
+ * coefficient record) as a HIP graph on a private stream and replayed on the
+ * plan's stream by every later solve; with 0 the kernels are launched one by
+ * one.  Both give bitwise identical results.  Chunks are launched directly
+ * while fill_kernel_timing is on.
+ */
+int fill_plan_set_graph(fill_plan plan, int on);
+
 /* Release every resource of the plan (NULL is accepted). */
 void fill_plan_destroy(fill_plan plan);
 

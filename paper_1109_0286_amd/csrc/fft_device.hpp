@@ -147,39 +147,76 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C (&a)
 // radix plans: E elements per thread, radices dividing E, product = N
 // ---------------------------------------------------------------------------
 
-template <int... Rs> struct RadixList {
+// Radix plans.  A plan fixes the length N, the elements per thread E and the
+// radix of each Stockham pass (every radix divides E).  Two variants per
+// length: 0 holds E = 16 elements per thread where N allows (radix-16 passes,
+// fewest LDS exchanges, fewest threads), 1 holds E = 8 (radix <= 8: twice the
+// threads per line, so more waves per CU to hide memory latency, one more
+// exchange).  Which variant each kernel uses is chosen per precision, length
+// and pass kind by measurement (fft_tuned.hpp).
+template <int N_, int E_, int... Rs> struct RadixPlan {
+  static constexpr int N = N_;
+  static constexpr int E = E_;
   static constexpr int NP = sizeof...(Rs);
   static constexpr int radix(int p) {
     constexpr int r[] = {Rs...};
     return r[p];
   }
 };
-template <int N> struct FFTPlan;
-template <> struct FFTPlan<16> : RadixList<16> { static constexpr int E = 16; };
-template <> struct FFTPlan<32> : RadixList<8, 4> { static constexpr int E = 8; };
-template <> struct FFTPlan<64> : RadixList<8, 8> { static constexpr int E = 8; };
-template <> struct FFTPlan<128> : RadixList<16, 8> { static constexpr int E = 16; };
-template <> struct FFTPlan<256> : RadixList<16, 16> { static constexpr int E = 16; };
-template <> struct FFTPlan<512> : RadixList<16, 16, 2> { static constexpr int E = 16; };
-template <> struct FFTPlan<768> : RadixList<8, 8, 4, 3> { static constexpr int E = 24; };
-template <> struct FFTPlan<1024> : RadixList<16, 16, 4> { static constexpr int E = 16; };
-template <> struct FFTPlan<2048> : RadixList<16, 16, 8> { static constexpr int E = 16; };
-template <> struct FFTPlan<4096> : RadixList<16, 16, 16> { static constexpr int E = 16; };
+template <int N, int V> struct FFTPlanV;
+template <> struct FFTPlanV<16, 0> : RadixPlan<16, 16, 16> {};
+template <> struct FFTPlanV<32, 0> : RadixPlan<32, 8, 8, 4> {};
+template <> struct FFTPlanV<64, 0> : RadixPlan<64, 8, 8, 8> {};
+template <> struct FFTPlanV<128, 0> : RadixPlan<128, 16, 16, 8> {};
+template <> struct FFTPlanV<256, 0> : RadixPlan<256, 16, 16, 16> {};
+template <> struct FFTPlanV<512, 0> : RadixPlan<512, 16, 16, 16, 2> {};
+template <> struct FFTPlanV<768, 0> : RadixPlan<768, 24, 8, 8, 4, 3> {};
+template <> struct FFTPlanV<1024, 0> : RadixPlan<1024, 16, 16, 16, 4> {};
+template <> struct FFTPlanV<2048, 0> : RadixPlan<2048, 16, 16, 16, 8> {};
+template <> struct FFTPlanV<4096, 0> : RadixPlan<4096, 16, 16, 16, 16> {};
+template <> struct FFTPlanV<128, 1> : RadixPlan<128, 8, 8, 4, 4> {};
+template <> struct FFTPlanV<256, 1> : RadixPlan<256, 8, 8, 8, 4> {};
+template <> struct FFTPlanV<512, 1> : RadixPlan<512, 8, 8, 8, 8> {};
+template <> struct FFTPlanV<1024, 1> : RadixPlan<1024, 8, 8, 8, 4, 4> {};
+template <> struct FFTPlanV<2048, 1> : RadixPlan<2048, 8, 8, 8, 8, 4> {};
+template <> struct FFTPlanV<4096, 1> : RadixPlan<4096, 8, 8, 8, 8, 8> {};
+// Lengths with a single plan answer variant 1 with variant 0.
+template <> struct FFTPlanV<16, 1> : FFTPlanV<16, 0> {};
+template <> struct FFTPlanV<32, 1> : FFTPlanV<32, 0> {};
+template <> struct FFTPlanV<64, 1> : FFTPlanV<64, 0> {};
+template <> struct FFTPlanV<768, 1> : FFTPlanV<768, 0> {};
 
-template <int N, int P = 0> constexpr int plan_product() {
-  if constexpr (P == FFTPlan<N>::NP) return 1;
-  else return FFTPlan<N>::radix(P) * plan_product<N, P + 1>();
+enum FFTPass { kRowPass = 0, kColPass = 1 };
+
+}  // namespace fillk
+#include "fft_tuned.hpp"
+namespace fillk {
+
+// The plan of the row passes (length nx) or the column pass (length ny) in
+// precision T.  Building with FILL_FFT_FORCE_VARIANT=v gives every kernel
+// variant v (the autotuner's candidate builds).
+#ifdef FILL_FFT_FORCE_VARIANT
+constexpr int fft_variant(bool, int, int) { return FILL_FFT_FORCE_VARIANT; }
+#else
+constexpr int fft_variant(bool f32, int n, int pass) { return tuned_fft_variant(f32, n, pass); }
+#endif
+template <typename T, int N, int PASS>
+using FFTPlanFor = FFTPlanV<N, fft_variant(sizeof(T) == 4, N, PASS)>;
+
+template <typename PL, int P = 0> constexpr int plan_product() {
+  if constexpr (P == PL::NP) return 1;
+  else return PL::radix(P) * plan_product<PL, P + 1>();
 }
-template <int N, int P = 0> constexpr bool plan_divides_E() {
-  if constexpr (P == FFTPlan<N>::NP) return true;
-  else return (FFTPlan<N>::E % FFTPlan<N>::radix(P) == 0) && plan_divides_E<N, P + 1>();
+template <typename PL, int P = 0> constexpr bool plan_divides_E() {
+  if constexpr (P == PL::NP) return true;
+  else return (PL::E % PL::radix(P) == 0) && plan_divides_E<PL, P + 1>();
 }
 
 // LDS index padding: one spare element every R0 elements (R0 = the first
 // radix) turns the first pass's stride-R0 scatter into distinct banks.
-template <int N> constexpr int lds_pad_shift() { return FFTPlan<N>::radix(0) >= 16 ? 4 : 3; }
-template <int N> __device__ __forceinline__ int lpad(int i) { return i + (i >> lds_pad_shift<N>()); }
-template <int N> constexpr int lds_line_elems() { return N + (N >> lds_pad_shift<N>()); }
+template <typename PL> constexpr int lds_pad_shift() { return PL::radix(0) >= 16 ? 4 : 3; }
+template <typename PL> __device__ __forceinline__ int lpad(int i) { return i + (i >> lds_pad_shift<PL>()); }
+template <typename PL> constexpr int lds_line_elems() { return PL::N + (PL::N >> lds_pad_shift<PL>()); }
 
 // Twiddles.  Pass p (radix R, NS = product of the earlier radices, S =
 // N/(NS R)) needs w(i, k) = exp(-2 pi i * i k S / N) for k = j mod NS.  With
@@ -187,28 +224,28 @@ template <int N> constexpr int lds_line_elems() { return N + (N >> lds_pad_shift
 // HI[i][khi] = w(i, 16 khi), so w(i, k) = LO[i][klo] * HI[i][khi]: lanes with
 // consecutive j read consecutive LO entries and share HI entries, which keeps
 // the LDS reads free of bank conflicts.  Passes with NS = 1 need no table.
-template <int N> constexpr int pass_ns(int p) {
+template <typename PL> constexpr int pass_ns(int p) {
   int s = 1;
-  for (int q = 0; q < p; ++q) s *= FFTPlan<N>::radix(q);
+  for (int q = 0; q < p; ++q) s *= PL::radix(q);
   return s;
 }
-template <int N> constexpr int tw_pass_size(int p) {
-  const int R = FFTPlan<N>::radix(p), ns = pass_ns<N>(p);
+template <typename PL> constexpr int tw_pass_size(int p) {
+  const int R = PL::radix(p), ns = pass_ns<PL>(p);
   if (ns == 1) return 0;
   return R * 16 + (ns > 16 ? R * (ns / 16) : 0);
 }
-template <int N> constexpr int tw_pass_off(int p) {
+template <typename PL> constexpr int tw_pass_off(int p) {
   int o = 0;
-  for (int q = 0; q < p; ++q) o += tw_pass_size<N>(q);
+  for (int q = 0; q < p; ++q) o += tw_pass_size<PL>(q);
   return o;
 }
-template <int N> constexpr int tw_elems() { return tw_pass_off<N>(FFTPlan<N>::NP); }
+template <typename PL> constexpr int tw_elems() { return tw_pass_off<PL>(PL::NP); }
 
 // Copy the whole twiddle table from global memory into LDS; callers place a
 // barrier between this and the first use.
-template <int N, typename C>
+template <typename PL, typename C>
 __device__ __forceinline__ void tw_stage(C* q, const C* __restrict__ tw, int t, int nt) {
-  for (int i = t; i < tw_elems<N>(); i += nt) q[i] = tw[i];
+  for (int i = t; i < tw_elems<PL>(); i += nt) q[i] = tw[i];
 }
 
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
@@ -216,9 +253,10 @@ template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
 }
 
 // One Stockham pass in registers (butterflies j = tid + b*TPL, b < E/R).
-template <typename C, int N, int E, int P, int R, int NS, int DIR>
-__device__ __forceinline__ void stockham_pass(C (&v)[E], int tid, const C* tw) {
-  constexpr int TPL = N / E;
+template <typename C, typename PL, int P, int R, int NS, int DIR>
+__device__ __forceinline__ void stockham_pass(C (&v)[PL::E], int tid, const C* tw) {
+  constexpr int E = PL::E;
+  constexpr int TPL = PL::N / E;
   constexpr int B = E / R;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -228,11 +266,11 @@ __device__ __forceinline__ void stockham_pass(C (&v)[E], int tid, const C* tw) {
     if constexpr (NS > 1) {
       const int j = tid + b * TPL;
       const int k = j % NS;
-      const C* lo = tw + tw_pass_off<N>(P) + (k & 15);
+      const C* lo = tw + tw_pass_off<PL>(P) + (k & 15);
 #pragma unroll
       for (int i = 1; i < R; ++i) {
         C w = lo[16 * i];
-        if constexpr (NS > 16) w = cmul(w, tw[tw_pass_off<N>(P) + 16 * R + i * (NS / 16) + (k >> 4)]);
+        if constexpr (NS > 16) w = cmul(w, tw[tw_pass_off<PL>(P) + 16 * R + i * (NS / 16) + (k >> 4)]);
         a[i] = twmul<DIR>(a[i], w);
       }
     }
@@ -244,9 +282,10 @@ __device__ __forceinline__ void stockham_pass(C (&v)[E], int tid, const C* tw) {
 
 // Scatter the pass outputs y[(j/NS)*NS*R + j%NS + i*NS] to LDS, gather the
 // next pass's inputs x[tid + e*TPL].
-template <typename C, int N, int E, int R, int NS>
-__device__ __forceinline__ void stockham_exchange(C (&v)[E], int tid, C* lds) {
-  constexpr int TPL = N / E;
+template <typename C, typename PL, int R, int NS>
+__device__ __forceinline__ void stockham_exchange(C (&v)[PL::E], int tid, C* lds) {
+  constexpr int E = PL::E;
+  constexpr int TPL = PL::N / E;
   constexpr int B = E / R;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -254,27 +293,26 @@ __device__ __forceinline__ void stockham_exchange(C (&v)[E], int tid, C* lds) {
     const int k = j % NS;
     const int base = (j / NS) * NS * R + k;
 #pragma unroll
-    for (int i = 0; i < R; ++i) lds[lpad<N>(base + i * NS)] = v[b + i * B];
+    for (int i = 0; i < R; ++i) lds[lpad<PL>(base + i * NS)] = v[b + i * B];
   }
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = lds[lpad<N>(tid + e * TPL)];
+  for (int e = 0; e < E; ++e) v[e] = lds[lpad<PL>(tid + e * TPL)];
   __syncthreads();
 }
 
 // Full length-N transform of one line; v holds x[tid + e*TPL] on entry and
 // X[tid + e*TPL] on exit; tw is the LDS twiddle table.  Every thread of
 // the workgroup must call it (it contains workgroup barriers).
-template <typename C, int N, int DIR, int P = 0, int NS = 1>
-__device__ __forceinline__ void fft_line(C (&v)[FFTPlan<N>::E], int tid, C* lds, const C* tw) {
-  using PL = FFTPlan<N>;
-  static_assert(plan_product<N>() == N, "radix plan does not multiply to N");
-  static_assert(plan_divides_E<N>(), "every radix must divide E");
+template <typename C, typename PL, int DIR, int P = 0, int NS = 1>
+__device__ __forceinline__ void fft_line(C (&v)[PL::E], int tid, C* lds, const C* tw) {
+  static_assert(plan_product<PL>() == PL::N, "radix plan does not multiply to N");
+  static_assert(plan_divides_E<PL>(), "every radix must divide E");
   constexpr int R = PL::radix(P);
-  stockham_pass<C, N, PL::E, P, R, NS, DIR>(v, tid, tw);
+  stockham_pass<C, PL, P, R, NS, DIR>(v, tid, tw);
   if constexpr (P + 1 < PL::NP) {
-    stockham_exchange<C, N, PL::E, R, NS>(v, tid, lds);
-    fft_line<C, N, DIR, P + 1, NS * R>(v, tid, lds, tw);
+    stockham_exchange<C, PL, R, NS>(v, tid, lds);
+    fft_line<C, PL, DIR, P + 1, NS * R>(v, tid, lds, tw);
   }
 }
 
@@ -285,7 +323,8 @@ __device__ __forceinline__ void fft_line(C (&v)[FFTPlan<N>::E], int tid, C* lds,
 // Row kernels: ROWS image rows per workgroup (two rows per complex line), the
 // workgroup's LDS held near 64 KiB so two workgroups fit a CU.
 template <typename T, int N> struct RowCfg {
-  static constexpr int E = FFTPlan<N>::E;
+  using PL = FFTPlanFor<T, N, kRowPass>;
+  static constexpr int E = PL::E;
   static constexpr int TPL = N / E;
   static constexpr int RAW = (64 * 1024) / (N * 8);
   static constexpr int ROWS = RAW >= 16 ? 16 : RAW >= 8 ? 8 : RAW >= 4 ? 4 : 2;  // power of two
@@ -306,7 +345,8 @@ template <typename T, int N> struct RowCfg {
 
 // Column kernel: W spectral columns (lines of length N = ny) per workgroup.
 template <typename T, int N> struct ColCfg {
-  static constexpr int E = FFTPlan<N>::E;
+  using PL = FFTPlanFor<T, N, kColPass>;
+  static constexpr int E = PL::E;
   static constexpr int TPL = N / E;
   static constexpr int RAW = (64 * 1024) / (N * 16);
   static constexpr int W0 = RAW > 16 ? 16 : (RAW < 1 ? 1 : RAW);

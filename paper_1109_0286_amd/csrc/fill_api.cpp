@@ -94,6 +94,12 @@ struct fill_plan_s {
   int hist_cap = 0;
   double* hist = nullptr;
   std::vector<int> hist_n;
+  // the 16-iteration inner-CG chunk as a HIP graph, captured on first use per
+  // [FP32?][preconditioner][coefficient record] and replayed by every solve
+  int use_graph = 1;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2][3][2] = {};
+  hipGraphExec_t graph_exec[2][3][2] = {};
   int nblk64 = 0, nblk32 = 0;
 
   uint8_t* mask = nullptr;
@@ -304,6 +310,51 @@ int upload_params(fill_plan p) {
   return FILL_OK;
 }
 
+// The graph of one inner-CG chunk for (precision, preconditioner, record),
+// captured on a private stream on first use (launch helpers follow
+// p->stream, which is switched to that stream for the capture).
+template <typename F>
+int chunk_graph(fill_plan p, int f32, int mode, int rec, F&& chunk, hipGraphExec_t* out) {
+  hipGraphExec_t& ex = p->graph_exec[f32][mode][rec];
+  if (!ex) {
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    const hipStream_t saved = p->stream;
+    p->stream = p->cap_stream;
+    const hipError_t e0 = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    const int rc = e0 == hipSuccess ? chunk() : FILL_OK;
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = e0 == hipSuccess ? hipStreamEndCapture(p->cap_stream, &g) : hipSuccess;
+    p->stream = saved;
+    if (e0 != hipSuccess) return fail(FILL_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e0));
+    if (rc < 0 || e1 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (rc < 0) return rc;
+      return fail(FILL_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e1));
+    }
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+      ex = nullptr;
+      (void)hipGraphDestroy(g);
+      return fail(FILL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    }
+    p->graph[f32][mode][rec] = g;
+  }
+  *out = ex;
+  return FILL_OK;
+}
+
+// Drop captured chunk graphs (all, or only those that record coefficients).
+void drop_graphs(fill_plan p, bool record_only) {
+  for (int a = 0; a < 2; ++a)
+    for (int m = 0; m < 3; ++m)
+      for (int r = record_only ? 1 : 0; r < 2; ++r) {
+        if (p->graph_exec[a][m][r]) (void)hipGraphExecDestroy(p->graph_exec[a][m][r]);
+        if (p->graph[a][m][r]) (void)hipGraphDestroy(p->graph[a][m][r]);
+        p->graph_exec[a][m][r] = nullptr;
+        p->graph[a][m][r] = nullptr;
+      }
+}
+
 // Inner preconditioned CG for every active problem on A d = r (r in v.r with
 // ||r|| = 1, d in v.x); tolerances, caps and the active set are in the device
 // parameters.  Returns per-problem iteration counts and statuses.
@@ -382,7 +433,7 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   e_out.part1 = p->part1;
   e_out.sc = p->sc;
 
-  for (;;) {
+  auto chunk = [&]() -> int {
     for (int k = 0; k < kChunk; ++k) {
       const int par = k & 1;
       FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc));
@@ -391,6 +442,17 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
         FILL_TRY(apply3<T>(p, R2C_XRUPDATE, e_in[par], TypeSel<T>::Dfull(p), C2R_DOT2, e_out, p->sc));
       else HIP_TRY(launch_xr<T>(false, xr[par], nb, p->stream));
     }
+    return FILL_OK;
+  };
+  // Every argument of the chunk is a plan-owned pointer or a constant, so the
+  // chunk is captured once and replayed (not while a kernel is being timed:
+  // timed launches carry their own events).
+  hipGraphExec_t exec = nullptr;
+  if (p->use_graph && p->timed_kernel < 0) FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode, hist != nullptr, chunk, &exec));
+
+  for (;;) {
+    if (exec) HIP_TRY(hipGraphLaunch(exec, p->stream));
+    else FILL_TRY(chunk());
     HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
     bool all = true;
@@ -516,25 +578,23 @@ bool size_ok(int n) {
   return false;
 }
 
-// Twiddle table of the length-N transform in the per-pass LO/HI layout the
-// kernels read (see fft_device.hpp), each entry exp(-2 pi i t/N) evaluated in
-// long double and rounded to double (and to float for the FP32 kernels).
-template <int N> void make_twiddles(std::vector<double2>& w64, std::vector<float2>& w32) {
-  const int total = std::max(tw_elems<N>(), 1);
-  w64.assign(total, double2{1.0, 0.0});
-  w32.assign(total, float2{1.0f, 0.0f});
+// Twiddle table of the radix plan PL in the per-pass LO/HI layout the kernels
+// read (see fft_device.hpp), each entry exp(-2 pi i t/N) evaluated in long
+// double and rounded to the table's precision.
+template <typename PL, typename C> void make_twiddles(std::vector<C>& w) {
+  constexpr int N = PL::N;
+  w.assign(std::max(tw_elems<PL>(), 1), C{1, 0});
   const long double pi = 3.141592653589793238462643383279502884L;
   auto put = [&](int idx, long long t) {
     t %= N;
     const long double a = 2.0L * pi * (long double)t / (long double)N;
     const double c = (double)cosl(a), sn = (double)-sinl(a);
-    w64[idx] = double2{c, sn};
-    w32[idx] = float2{(float)c, (float)sn};
+    w[idx] = C{(decltype(C{}.x))c, (decltype(C{}.x))sn};
   };
-  for (int p = 0; p < FFTPlan<N>::NP; ++p) {
-    const int ns = pass_ns<N>(p);
+  for (int p = 0; p < PL::NP; ++p) {
+    const int ns = pass_ns<PL>(p);
     if (ns == 1) continue;
-    const int R = FFTPlan<N>::radix(p), S = N / (ns * R), off = tw_pass_off<N>(p);
+    const int R = PL::radix(p), S = N / (ns * R), off = tw_pass_off<PL>(p);
     for (int i = 0; i < R; ++i)
       for (int klo = 0; klo < 16; ++klo) put(off + 16 * i + klo, (long long)i * klo * S);
     if (ns > 16)
@@ -543,11 +603,19 @@ template <int N> void make_twiddles(std::vector<double2>& w64, std::vector<float
   }
 }
 
-int twiddles(int n, std::vector<double2>& w64, std::vector<float2>& w32) {
+// Twiddle tables of the plans that the pass kind `pass` uses at length n in
+// FP64 and in FP32 (the two precisions may use different plans).
+int twiddles(int n, int pass, std::vector<double2>& w64, std::vector<float2>& w32) {
   switch (n) {
-#define FILL_CASE(nn) \
-  case nn:            \
-    make_twiddles<nn>(w64, w32); \
+#define FILL_CASE(nn)                                                  \
+  case nn:                                                             \
+    if (pass == kRowPass) {                                            \
+      make_twiddles<FFTPlanFor<double, nn, kRowPass>>(w64);            \
+      make_twiddles<FFTPlanFor<float, nn, kRowPass>>(w32);             \
+    } else {                                                           \
+      make_twiddles<FFTPlanFor<double, nn, kColPass>>(w64);            \
+      make_twiddles<FFTPlanFor<float, nn, kColPass>>(w32);             \
+    }                                                                  \
     return FILL_OK;
     FILL_FOR_EACH_N(FILL_CASE)
 #undef FILL_CASE
@@ -628,8 +696,8 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   FILL_TRY(dalloc(p, &p->Dfull32, nt * p->npk));
   std::vector<double2> twx64, twy64;
   std::vector<float2> twx32, twy32;
-  FILL_TRY(twiddles(nx, twx64, twx32));
-  FILL_TRY(twiddles(ny, twy64, twy32));
+  FILL_TRY(twiddles(nx, kRowPass, twx64, twx32));
+  FILL_TRY(twiddles(ny, kColPass, twy64, twy32));
   FILL_TRY(dalloc(p, &p->twx64, twx64.size()));
   FILL_TRY(dalloc(p, &p->twy64, twy64.size()));
   FILL_TRY(dalloc(p, &p->twx32, twx32.size()));
@@ -1032,8 +1100,9 @@ int fill_plan_set_precond(fill_plan p, int mode) {
 int fill_plan_set_lanczos(fill_plan p, int cap) {
   g_last_error.clear();
   if (!p || cap < 0 || cap > (1 << 20)) return fail(FILL_EINVAL, "cap must be in [0, 2^20]");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  drop_graphs(p, true);  // recording graphs hold the record's address and size
   if (cap > p->hist_cap) {
-    HIP_TRY(hipStreamSynchronize(p->stream));
     double* h = nullptr;
     FILL_TRY(dalloc(p, &h, (size_t)p->nprob * 2 * cap));
     p->hist = h;
@@ -1068,9 +1137,17 @@ int fill_lanczos_extremes(fill_plan p, int problem, double* lam_min, double* lam
   return FILL_OK;
 }
 
+int fill_plan_set_graph(fill_plan p, int on) {
+  if (!p || (on != 0 && on != 1)) return fail(FILL_EINVAL, "bad argument");
+  p->use_graph = on;
+  return FILL_OK;
+}
+
 void fill_plan_destroy(fill_plan p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->stream);
+  drop_graphs(p, false);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   for (void* a : p->allocs) (void)hipFree(a);
   if (p->h_sc) (void)hipHostFree(p->h_sc);

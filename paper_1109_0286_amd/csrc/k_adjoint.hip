@@ -34,10 +34,11 @@ __global__ __launch_bounds__((ColCfg<double, N>::THREADS)) void col_fwd_kernel(c
                                                                                 const double2* tw) {
   using C = double2;
   using CF = ColCfg<double, N>;
+  using PL = typename CF::PL;
   constexpr int E = CF::E, TPL = CF::TPL, W = CF::W;
-  constexpr int LE = lds_line_elems<N>();
+  constexpr int LE = lds_line_elems<PL>();
   __shared__ C lds[W * LE];
-  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
+  __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   const int l = threadIdx.x / TPL, tid = threadIdx.x % TPL;
   const int kx = blockIdx.x * W + l;
   const bool valid = kx < nhalf;
@@ -45,12 +46,12 @@ __global__ __launch_bounds__((ColCfg<double, N>::THREADS)) void col_fwd_kernel(c
   C v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = valid ? g[tid + e * TPL] : C{0.0, 0.0};
-  tw_stage<N>(twq, tw, threadIdx.x, CF::THREADS);
+  tw_stage<PL>(twq, tw, threadIdx.x, CF::THREADS);
   C* line = lds + l * LE;
-  fft_line<C, N, -1>(v, tid, line, twq);
+  fft_line<C, PL, -1>(v, tid, line, twq);
   if (blockIdx.x == 0) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) line[lpad<N>(tid + e * TPL)] = v[e];
+    for (int e = 0; e < E; ++e) line[lpad<PL>(tid + e * TPL)] = v[e];
     __syncthreads();
   }
   if (!valid) return;
@@ -59,7 +60,7 @@ __global__ __launch_bounds__((ColCfg<double, N>::THREADS)) void col_fwd_kernel(c
   for (int e = 0; e < E; ++e) {
     const int ky = tid + e * TPL;
     if (blockIdx.x == 0 && l == 0) {
-      const C zk = v[e], zm = line[lpad<N>(ky == 0 ? 0 : N - ky)];
+      const C zk = v[e], zm = line[lpad<PL>(ky == 0 ? 0 : N - ky)];
       o[ky] = C{0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y)};                           // DC column
       Xs[(size_t)nhalf * ldx + ky] = C{0.5 * (zk.y + zm.y), 0.5 * (zm.x - zk.x)};    // Nyquist column
     } else {

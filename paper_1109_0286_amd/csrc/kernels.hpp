@@ -217,11 +217,12 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   RowArgs<T> a = bind_problem(a_in);
   bind_caller(a);
   using CF = RowCfg<T, N>;
+  using PL = typename CF::PL;
   constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS, H = CF::H;
-  constexpr int LE = lds_line_elems<N>();
+  constexpr int LE = lds_line_elems<PL>();
   constexpr int LDS_C = (CF::LINES * LE > (ROWS * N) / 2) ? CF::LINES * LE : (ROWS * N) / 2;
   __shared__ C lds[LDS_C];
-  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
+  __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   T* ldr = reinterpret_cast<T*>(lds);
   if (a.sc != nullptr && a.sc->done) return;
 
@@ -244,7 +245,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
       for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
       return;
     }
-    tw_stage<N>(twq, a.tw, t, NT);
+    tw_stage<PL>(twq, a.tw, t, NT);
     const int base = y0 * a.nx;
     if (c1 - c0 == ROWS * N) {
       // Every pixel of these rows is masked (a band): compact element c0 + i
@@ -321,7 +322,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     }
     __syncthreads();
   } else {
-    tw_stage<N>(twq, a.tw, t, NT);
+    tw_stage<PL>(twq, a.tw, t, NT);
     const size_t ra = (size_t)(y0 + 2 * l) * a.nx, rb = ra + a.nx;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -335,9 +336,9 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   }
 
   C* line = lds + l * LE;
-  fft_line<C, N, -1>(v, tid, line, twq);
+  fft_line<C, PL, -1>(v, tid, line, twq);
 #pragma unroll
-  for (int e = 0; e < E; ++e) line[lpad<N>(tid + e * TPL)] = v[e];
+  for (int e = 0; e < E; ++e) line[lpad<PL>(tid + e * TPL)] = v[e];
   __syncthreads();
   // Separate the two packed rows: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i).
   // The real DC and Nyquist bins of a row share column 0: (A_0, A_{N/2}).
@@ -346,11 +347,11 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     const C* ln = lds + (r >> 1) * LE;
     C out;
     if (kx == 0) {
-      const C z0 = ln[lpad<N>(0)], zh = ln[lpad<N>(N / 2)];
+      const C z0 = ln[lpad<PL>(0)], zh = ln[lpad<PL>(N / 2)];
       out = (r & 1) ? C{z0.y, zh.y} : C{z0.x, zh.x};
     } else {
-      const C zk = ln[lpad<N>(kx)];
-      const C zm = ln[lpad<N>(N - kx)];
+      const C zk = ln[lpad<PL>(kx)];
+      const C zm = ln[lpad<PL>(N - kx)];
       if (r & 1) out = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
       else out = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     }
@@ -367,12 +368,13 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
   RowArgs<T> a = bind_problem(a_in);
   bind_caller(a);
   using CF = RowCfg<T, N>;
+  using PL = typename CF::PL;
   constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS, H = CF::H;
-  constexpr int LE = lds_line_elems<N>();
+  constexpr int LE = lds_line_elems<PL>();
   constexpr int HS = CF::HS;
   constexpr int LDS_C = (CF::LINES * LE > ROWS * HS) ? CF::LINES * LE : ROWS * HS;
   __shared__ C lds[LDS_C];
-  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
+  __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   T* ldr = reinterpret_cast<T*>(lds);
   if (a.sc != nullptr && a.sc->done) return;
 
@@ -393,7 +395,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
       return;
     }
   }
-  tw_stage<N>(twq, a.tw, t, NT);
+  tw_stage<PL>(twq, a.tw, t, NT);
   for (int o = t; o < ROWS * (N / 2); o += NT) {
     const int kx = o / ROWS, r = o % ROWS;
     lds[r * HS + kx] = a.Xt[(size_t)kx * ldx + y0 + r];
@@ -420,7 +422,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
   }
   __syncthreads();
   C* line = lds + l * LE;
-  fft_line<C, N, +1>(v, tid, line, twq);
+  fft_line<C, PL, +1>(v, tid, line, twq);
 
   if constexpr (c2r_is_compact<MODE>()) {
 #pragma unroll
@@ -540,12 +542,13 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
   RowArgs<T> a = bind_problem(a_in);
   bind_caller(a);
   using CF = RowCfg<T, N>;
+  using PL = typename CF::PL;
   constexpr int E = CF::E, TPL = CF::TPL, ROWS = CF::ROWS, NT = CF::THREADS;
-  constexpr int LE = lds_line_elems<N>();
+  constexpr int LE = lds_line_elems<PL>();
   constexpr int HS = CF::HS;
   constexpr int LDS_C = (CF::LINES * LE > ROWS * HS) ? CF::LINES * LE : ROWS * HS;
   __shared__ C lds[LDS_C];
-  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
+  __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   if (a.sc != nullptr && a.sc->done) return;
 
   const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
@@ -564,7 +567,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
     ma[e] = a.mask[ra + tid + e * TPL];
     mb[e] = a.mask[rb + tid + e * TPL];
   }
-  tw_stage<N>(twq, a.tw, t, NT);
+  tw_stage<PL>(twq, a.tw, t, NT);
   for (int o = t; o < ROWS * (N / 2); o += NT) {
     const int kx = o / ROWS, r = o % ROWS;
     lds[r * HS + kx] = a.Xt[(size_t)kx * ldx + y0 + r];
@@ -591,23 +594,23 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
   }
   __syncthreads();
   C* line = lds + l * LE;
-  fft_line<C, N, +1>(v, tid, line, twq);
+  fft_line<C, PL, +1>(v, tid, line, twq);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = C{ma[e] ? v[e].x : T(0), mb[e] ? v[e].y : T(0)};
-  fft_line<C, N, -1>(v, tid, line, twq);
+  fft_line<C, PL, -1>(v, tid, line, twq);
 #pragma unroll
-  for (int e = 0; e < E; ++e) line[lpad<N>(tid + e * TPL)] = v[e];
+  for (int e = 0; e < E; ++e) line[lpad<PL>(tid + e * TPL)] = v[e];
   __syncthreads();
   for (int o = t; o < ROWS * (N / 2); o += NT) {
     const int kx = o / ROWS, r = o % ROWS;
     const C* ln = lds + (r >> 1) * LE;
     C out;
     if (kx == 0) {
-      const C z0 = ln[lpad<N>(0)], zh = ln[lpad<N>(N / 2)];
+      const C z0 = ln[lpad<PL>(0)], zh = ln[lpad<PL>(N / 2)];
       out = (r & 1) ? C{z0.y, zh.y} : C{z0.x, zh.x};
     } else {
-      const C zk = ln[lpad<N>(kx)];
-      const C zm = ln[lpad<N>(N - kx)];
+      const C zk = ln[lpad<PL>(kx)];
+      const C zm = ln[lpad<PL>(N - kx)];
       if (r & 1) out = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
       else out = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     }
@@ -622,10 +625,11 @@ template <typename T, int N>
 __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T> a_in) {
   using C = cplx<T>;
   using CF = ColCfg<T, N>;
+  using PL = typename CF::PL;
   constexpr int E = CF::E, TPL = CF::TPL, W = CF::W;
-  constexpr int LE = lds_line_elems<N>();
+  constexpr int LE = lds_line_elems<PL>();
   __shared__ C lds[W * LE];
-  __shared__ C twq[tw_elems<N>() > 0 ? tw_elems<N>() : 1];
+  __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   ColArgs<T> a = a_in;
   a.Xt += (size_t)blockIdx.y * a.xt_stride;
   a.D += (size_t)blockIdx.y * a.d_stride;
@@ -643,9 +647,9 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
     v[e] = valid ? g[tid + e * TPL] : C{T(0), T(0)};
     dv[e] = valid ? d[tid + e * TPL] : T(0);
   }
-  tw_stage<N>(twq, a.tw, threadIdx.x, CF::THREADS);
+  tw_stage<PL>(twq, a.tw, threadIdx.x, CF::THREADS);
   C* line = lds + l * LE;
-  fft_line<C, N, -1>(v, tid, line, twq);
+  fft_line<C, PL, -1>(v, tid, line, twq);
   if (blockIdx.x == 0) {
     // Column 0 carries two real sequences, DC (real part) and Nyquist
     // (imaginary part) of every row: Z = U + iV.  Separate them in frequency,
@@ -656,13 +660,13 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
 #pragma unroll
     for (int e = 0; e < E; ++e) dn[e] = (l == 0) ? dnyq[tid + e * TPL] : T(0);
 #pragma unroll
-    for (int e = 0; e < E; ++e) line[lpad<N>(tid + e * TPL)] = v[e];
+    for (int e = 0; e < E; ++e) line[lpad<PL>(tid + e * TPL)] = v[e];
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ky = tid + e * TPL;
       if (l == 0) {
-        const C zk = v[e], zm = line[lpad<N>(ky == 0 ? 0 : N - ky)];
+        const C zk = v[e], zm = line[lpad<PL>(ky == 0 ? 0 : N - ky)];
         const C u{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
         const C w{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
         const C u2{u.x * dv[e], u.y * dv[e]}, w2{w.x * dn[e], w.y * dn[e]};
@@ -680,7 +684,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
       v[e].y *= dv[e];
     }
   }
-  fft_line<C, N, +1>(v, tid, line, twq);
+  fft_line<C, PL, +1>(v, tid, line, twq);
   if (valid) {
 #pragma unroll
     for (int e = 0; e < E; ++e) g[tid + e * TPL] = v[e];

@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfill.so")
+# FILL_LIBRARY may name another build of the same library (the FFT autotuner
+# loads its candidate builds this way); by default the in-tree build.
+LIB_PATH = os.environ.get("FILL_LIBRARY") or os.path.join(HERE, "libfill.so")
 
 FILL_OK = 0
 FILL_EINVAL = -1
@@ -43,7 +45,7 @@ EXPORTS = (
     "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_kernel_timing",
     "fill_kernel_timing_read", "fill_strerror",
     "fill_last_error", "fill_plan_set_precond", "fill_plan_set_lanczos", "fill_get_lanczos",
-    "fill_lanczos_extremes",
+    "fill_lanczos_extremes", "fill_plan_set_graph",
 )
 
 FILL_PRECOND_NONE = 0
@@ -89,6 +91,7 @@ def _load() -> C.CDLL:
         "fill_plan_set_max_iter": (i32, [vp, i32]),
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
         "fill_plan_set_precond": (i32, [vp, i32]),
+        "fill_plan_set_graph": (i32, [vp, i32]),
         "fill_plan_set_lanczos": (i32, [vp, i32]),
         "fill_get_lanczos": (i32, [vp, i32, vp, vp, i32, C.POINTER(i32)]),
         "fill_lanczos_extremes": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
@@ -250,6 +253,10 @@ def fill_plan_set_precond(plan, mode):
     return _check(_lib.fill_plan_set_precond(plan, int(mode)), "fill_plan_set_precond")
 
 
+def fill_plan_set_graph(plan, on):
+    return _check(_lib.fill_plan_set_graph(plan, 1 if on else 0), "fill_plan_set_graph")
+
+
 def fill_plan_set_lanczos(plan, cap):
     return _check(_lib.fill_plan_set_lanczos(plan, int(cap)), "fill_plan_set_lanczos")
 
@@ -384,6 +391,10 @@ class Plan:
     def set_precond(self, mode):
         """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
         fill_plan_set_precond(self.handle, mode)
+
+    def set_graph(self, on):
+        """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
+        fill_plan_set_graph(self.handle, on)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""
@@ -530,6 +541,10 @@ class BatchPlan:
     def set_precond(self, mode):
         """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
         fill_plan_set_precond(self.handle, mode)
+
+    def set_graph(self, on):
+        """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
+        fill_plan_set_graph(self.handle, on)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""
