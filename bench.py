@@ -34,8 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 PRECONDS = {"split": 1, "cxx": 2, "none": 0}  # fill_precond: E E (Sec. 2.4 split form), Px C Px, plain CG
 CALIB_BYTES = 256 << 20  # plain device copy used to scale the rocprofv3 byte counters
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "col_kernel_f32_2048_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1109_0286_amd", "csrc", f) for f in ("fft_device.hpp", "kernels.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1109_0286_amd", "csrc", f)
+                  for f in ("fft_device.hpp", "fft_tuned.hpp", "kernels.hpp")]
 
 
 def kernel_source_hash() -> str:
@@ -45,14 +45,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    runs, or None if the kernel sources changed since they were taken."""
+def measured_traffic(n: int = 2048):
+    """HBM bytes per launch of the FP32 column pass at n x n from the committed
+    counter runs, or None if the kernel sources changed since they were taken."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(os.path.join(ROOT, "profiles", f"col_kernel_f32_{n}_traffic.json")))
     except (OSError, ValueError):
         return None
     return t["traffic_bytes"] if t.get("source_hash") == kernel_source_hash() else None
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """GB/s of a plain device-to-device copy (read + write bytes over time):
+    the attainable streaming rate to set the kernels' GB/s beside."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int) -> float:
@@ -282,7 +300,9 @@ def bench_grid4096(args) -> int:
                                   "rtol 1e-8", "n_masked": prob.n_masked, "preconditioner": args.precond},
            "paths": res,
            "roofline": {"bound": "hbm", "kernel": "col_kernel<float,4096>", "achieved": achieved,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": measured_traffic(4096), "bytes_per_launch": 5.0 * 4 * H,
+                        "copy_attainable_gbs": copy_bandwidth(), "kernel_source_hash": kernel_source_hash()}}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -362,10 +382,6 @@ def main() -> int:
               "draws would shard across GPUs by problem, which this build does not launch.", file=sys.stderr)
         return 2
 
-    import torch
-    import paper_1109_0286_amd as F
-    import workloads as W
-
     if args.workload == "mixed64":
         return bench_mixed64(args)
     if args.workload == "grid4096":
@@ -374,10 +390,16 @@ def main() -> int:
         return bench_grad16(args)
     if args.workload == "holes2048":
         return bench_holes2048(args)
+    return bench_grid2048(args)
 
+
+def bench_grid2048(args) -> int:
+    """The headline line: 2048^2 workload, mixed path, FP64 path beside it."""
+    import torch
+    import paper_1109_0286_amd as F
+    import workloads as W
     prob = W.make_problem("grid2048")
     nx, ny, rtol, seed = prob.nx, prob.ny, prob.rtol, prob.seed
-    torch.cuda.init()
     d = torch.from_numpy(prob.d_obs).cuda()
     plan32 = F.Plan(nx, ny, prob.mask, prob.P, F.FILL_PREC_FP32_OP)
     plan64 = F.Plan(nx, ny, prob.mask, prob.P, F.FILL_PREC_FP64)
@@ -425,7 +447,8 @@ def main() -> int:
         "kernel_ms_isolated": kernel_ms,
         "roofline": {"bound": "hbm", "kernel": "col_kernel<float,2048>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(), "bytes_per_launch": nbytes, "launches_timed": col32_n,
+                     "traffic": measured_traffic(2048), "bytes_per_launch": nbytes, "launches_timed": col32_n,
+                     "copy_attainable_gbs": copy_bandwidth(),
                      "kernel_source_hash": kernel_source_hash()},
     }
     out["lanczos_fp64"] = lanczos_report(plan64, d, seed, rtol)
@@ -435,14 +458,22 @@ def main() -> int:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, st64["iters_inner"])
     print(json.dumps(out), flush=True)
-    if args.calib_copy:
-        a = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
     return 0
 
 
+def calib_copies() -> None:
+    """Three plain copies of CALIB_BYTES: the reference dispatches that scale
+    the rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
 if __name__ == "__main__":
-    sys.exit(main())
+    rc = main()
+    if rc == 0 and "--calib-copy" in sys.argv[1:]:
+        calib_copies()
+    sys.exit(rc)
