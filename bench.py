@@ -203,6 +203,21 @@ def bench_mixed64(args) -> int:
     return 0
 
 
+def masked_errors(F, prob, d, plans: dict, rtol: float) -> dict:
+    """Relative L2 error on the masked pixels of each plan's result at the
+    workload's rtol against a tight FP64 solve (rtol 1e-11) of the same seed."""
+    import torch
+    ref_plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, F.FILL_PREC_FP64)
+    ref = ref_plan.realize(d, prob.seed, 1e-11, allow_noconv=True)
+    m = torch.from_numpy(prob.mask != 0).cuda()
+    out = {}
+    for name, plan in plans.items():
+        x = plan.realize(d, prob.seed, rtol)
+        out[name] = float(torch.linalg.norm((x - ref)[m]) / torch.linalg.norm(ref[m]))
+    ref_plan.close()
+    return out
+
+
 def lanczos_report(plan, d, seed, rtol, cap=20000) -> dict:
     """One extra (untimed) solve with the CG coefficient record on: the
     extreme Ritz values of its Lanczos matrix, the condition number they
@@ -281,7 +296,7 @@ def bench_grid4096(args) -> int:
     import workloads as W
     prob = W.make_problem("grid4096")
     d = torch.from_numpy(prob.d_obs).cuda()
-    res = {}
+    res, plans = {}, {}
     for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
         plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
         plan.set_precond(PRECONDS[args.precond])
@@ -289,6 +304,10 @@ def bench_grid4096(args) -> int:
         res[name] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
                      "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
                      "rel_resid": st["rel_resid"], "col_kernel_ms": col_ms}
+        plans[name] = plan
+    errs = masked_errors(F, prob, d, plans, prob.rtol)
+    for name, plan in plans.items():
+        res[name]["masked_rel_l2_error_vs_fp64_1e-11"] = errs[name]
         plan.close()
     H = prob.ny * (prob.nx // 2 + 1)
     achieved = 5.0 * 4 * H / (res["mixed"]["col_kernel_ms"] * 1e-3) / 1e9
@@ -334,7 +353,7 @@ def bench_grad16(args) -> int:
         x = FillFn.apply(dd, th, bp, seeds, lnk, 1e-8, 1e-10)
         loss = torch.sum(w * x * x)
         loss.backward()
-        return float(loss)
+        return float(loss.detach())
 
     for _ in range(args.warmup):
         step()
@@ -451,6 +470,7 @@ def bench_grid2048(args) -> int:
                      "copy_attainable_gbs": copy_bandwidth(),
                      "kernel_source_hash": kernel_source_hash()},
     }
+    out["masked_rel_l2_error_vs_fp64_1e-11"] = masked_errors(F, prob, d, {"mixed": plan32, "fp64": plan64}, rtol)
     out["lanczos_fp64"] = lanczos_report(plan64, d, seed, rtol)
     out["preconditioners"] = compare_preconds(F, prob, d, args)
     if args.batch > 0:
