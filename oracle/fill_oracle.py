@@ -47,7 +47,8 @@ import scipy.fft as sfft
 __all__ = [
     "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1", "REALIZATION_STREAM",
     "philox4x64_10", "white_noise", "circulant_apply", "unconstrained_realization",
-    "rhs", "apply_A", "apply_E", "pcg_split", "pcg_cxx", "fill_realize", "fill_mean", "FillResult",
+    "rhs", "apply_A", "apply_A_skew", "apply_E", "cg_residual_history", "pcg_split", "pcg_cxx",
+    "fill_realize", "fill_mean", "FillResult",
 ]
 
 # FFT threads: ORACLE_WORKERS if set, else every core this process may run on.
@@ -149,6 +150,46 @@ def _Py(v: np.ndarray, mask: np.ndarray) -> np.ndarray:
 def apply_A(v: np.ndarray, mask: np.ndarray, P: np.ndarray) -> np.ndarray:
     """A v = Px C^-1 Px v, the operator of eq. ModEq."""
     return _Px(circulant_apply(_Px(v, mask), P, -1.0), mask)
+
+
+def apply_A_skew(v: np.ndarray, mask: np.ndarray, P: np.ndarray, eps: float) -> np.ndarray:
+    """A deliberately non-Hermitian variant of A for the Hermiticity study of Sec. 3.
+
+    Each spectral mode of C^-1 Px v is multiplied by 1 + i eps sin(2 pi kx / nx):
+    A_eps = Px C^-1 (I + eps K) Px with K the circulant of eigenvalues
+    i sin(2 pi kx / nx), a real antisymmetric operator (the central
+    difference along x).  eps = 0 gives A.
+    """
+    ny, nx = v.shape
+    kx = np.arange(nx // 2 + 1)
+    f = 1.0 + 1j * eps * np.sin(2.0 * np.pi * kx / nx)
+    w = sfft.irfft2(sfft.rfft2(_Px(v, mask), workers=_workers(v.size)) / P * f[None, :], s=v.shape,
+                    workers=_workers(v.size))
+    return _Px(w, mask)
+
+
+def cg_residual_history(op, b: np.ndarray, iters: int) -> np.ndarray:
+    """Plain Hestenes-Stiefel CG (x0 = 0) on op x = b for a fixed number of
+    steps: the recursive residual norms ||r_0||, ..., ||r_iters|| (the
+    quantity whose per-step ratio Sec. 3 tracks on non-Hermitian operators)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(np.vdot(r, r))
+    hist = [np.sqrt(rr)]
+    for _ in range(iters):
+        q = op(p)
+        pq = float(np.vdot(p, q))
+        if pq == 0.0 or rr == 0.0:
+            break
+        alpha = rr / pq
+        x += alpha * p
+        r -= alpha * q
+        rr_new = float(np.vdot(r, r))
+        hist.append(np.sqrt(rr_new))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return np.asarray(hist)
 
 
 def apply_E(v: np.ndarray, mask: np.ndarray, P: np.ndarray) -> np.ndarray:
