@@ -287,6 +287,88 @@ def bench_holes2048(args) -> int:
     return 0
 
 
+def operator_asymmetry(F, plan, n, prec, trials=4) -> float:
+    """max over random pairs of |<u, A v> - <A u, v>| / (||u|| ||A v||) for the
+    plan's A apply in precision prec (FP64 reference norm)."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(11)
+    worst = 0.0
+    for _ in range(trials):
+        u = torch.randn((n, n), generator=g, dtype=torch.float64).cuda()
+        v = torch.randn((n, n), generator=g, dtype=torch.float64).cuda()
+        Av = plan.apply(F.FILL_OP_A, v, prec=prec)
+        Au = plan.apply(F.FILL_OP_A, u, prec=prec)
+        Av64 = plan.apply(F.FILL_OP_A, v, prec=F.FILL_PREC_FP64)
+        d = float(torch.sum(u * Av) - torch.sum(Au * v))
+        worst = max(worst, abs(d) / float(torch.linalg.norm(u) * torch.linalg.norm(Av64)))
+    return worst
+
+
+def bench_hermiticity(args) -> int:
+    """Hermiticity study (Sec. 3): plain CG on the deliberately non-Hermitian
+    A_eps = Px C^-1 (I + eps K) Px at 512^2 (the 2048^2 workload's mask and
+    spectrum form) for a range of condition numbers (noise floors) and eps:
+    iterations of the first CG to 1e-8, the smallest residual reached, and the
+    convergence rate -ln(||r_n+1|| / ||r_n||) over the first and last fifth of
+    the iterations, from the device record of the CG coefficients.  `value` is
+    the measured asymmetry of the FP32 operator, on the same scale as eps's."""
+    import math
+    import torch
+    import paper_1109_0286_amd as F
+    import workloads as W
+    n, cap = 512, 3000
+    eps_list = (0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1)
+    t0 = time.perf_counter()
+    rows = []
+    asym = {}
+    for floor in (1e-2, 1e-3, 1e-4, 1e-5, 1e-7):
+        prob = W.make_problem("grid2048", n=n, floor=floor)
+        d = torch.from_numpy(prob.d_obs).cuda()
+        plan = F.Plan(n, n, prob.mask, prob.P, F.FILL_PREC_FP64)
+        plan.set_precond(F.FILL_PRECOND_NONE)
+        plan.set_lanczos(cap)
+        plan.set_max_iter(cap)
+        for eps in eps_list:
+            plan.set_skew(eps)
+            plan.realize(d, prob.seed, 1e-10, allow_noconv=True)
+            al, be = plan.lanczos()
+            if eps == 0.0:
+                lo, hi, _ = plan.lanczos_extremes()
+                kappa = hi / lo
+                asym[f"floor {floor:g}"] = {"fp32": operator_asymmetry(F, plan, n, F.FILL_PREC_FP32_OP),
+                                            "fp64": operator_asymmetry(F, plan, n, F.FILL_PREC_FP64)}
+            lr = np.concatenate([[0.0], np.cumsum(0.5 * np.log(be))])  # ln ||r_j|| / ||r_0||
+            hit = np.nonzero(lr <= math.log(1e-8))[0]
+            q = max(1, len(be) // 5)
+            rows.append({"floor": floor, "kappa_A": kappa, "eps": eps, "steps": len(al),
+                         "iters_to_1e-8": int(hit[0]) if len(hit) else None,
+                         "min_rel_resid": float(math.exp(lr.min())),
+                         "rate_first": float(-0.5 * np.mean(np.log(be[:q]))),
+                         "rate_last": float(-0.5 * np.mean(np.log(be[-q:])))})
+            print(f"# floor {floor:g} kappa {kappa:.3g} eps {eps:g}: {rows[-1]['iters_to_1e-8']} iterations, "
+                  f"min {rows[-1]['min_rel_resid']:.2e}", file=sys.stderr, flush=True)
+        plan.close()
+    eps_asym = {}
+    prob = W.make_problem("grid2048", n=n)
+    plan = F.Plan(n, n, prob.mask, prob.P, F.FILL_PREC_FP64)
+    for eps in (1e-5, 1e-3):
+        plan.set_skew(eps)
+        eps_asym[f"eps {eps:g}"] = operator_asymmetry(F, plan, n, F.FILL_PREC_FP64)
+    plan.close()
+    dt = time.perf_counter() - t0
+    fp32 = max(v["fp32"] for v in asym.values())
+    out = {"metric": "Hermiticity study: measured asymmetry of the FP32 operator (and plain-CG behaviour vs eps, "
+                     "kappa)", "value": fp32, "unit": "relative asymmetry |<u,Av>-<Au,v>|/(|u||Av|)",
+           "n_gpus": 1, "steps": len(rows), "warmup": 0, "ms_per_step": dt / len(rows) * 1e3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64 (sweep), f32 (value)",
+           "data": "synthetic",
+           "config": {"workload": "512x512, 2048^2-form spectrum with floors 1e-2..1e-7 and mask, plain CG, "
+                                  f"cap {cap} iterations, A_eps = Px C^-1 (I + eps K) Px"},
+           "asymmetry_of_operators": asym, "asymmetry_of_skewed_fp64": eps_asym, "sweep": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_grid4096(args) -> int:
     """The 4096^2 wide cut (30% band + 500 holes r~U(2,16), damping 512):
     CG iterations and time for the FP64 path and for FP32 operators with
@@ -386,10 +468,11 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=4,
                     help="realizations per launch in the batched 2048^2 leg (0: skip it)")
     ap.add_argument("--workload", default="grid2048",
-                    choices=["grid2048", "mixed64", "grid4096", "grad16", "holes2048"],
+                    choices=["grid2048", "mixed64", "grid4096", "grad16", "holes2048", "hermiticity"],
                     help="grid2048: the headline line; mixed64: 64 problems of uneven sizes; grid4096: the wide "
                          "cut; grad16: forward + adjoint of 16 1024^2 maps with 50 band powers; holes2048: "
-                         "point sources only, CG with and without the preconditioner")
+                         "point sources only, CG with and without the preconditioner; hermiticity: plain CG on a "
+                         "deliberately non-Hermitian operator vs eps and kappa")
     ap.add_argument("--precond", default="cxx", choices=list(PRECONDS),
                     help="inner-CG preconditioner (every workload): cxx (Px C Px, default), split (E E, the "
                          "paper's split form) or none; the 2048^2 line also times the others")
@@ -409,6 +492,8 @@ def main() -> int:
         return bench_grad16(args)
     if args.workload == "holes2048":
         return bench_holes2048(args)
+    if args.workload == "hermiticity":
+        return bench_hermiticity(args)
     return bench_grid2048(args)
 
 

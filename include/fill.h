@@ -191,6 +191,19 @@ int fill_get_lanczos(fill_plan plan, int problem, double* alpha, double* beta, i
 int fill_lanczos_extremes(fill_plan plan, int problem, double* lam_min, double* lam_max, int* n);
 
 /*
+ * Non-Hermitian study (Sec. 3 reports that CG stalls on operators that are
+ * not exactly Hermitian, the more so the larger the condition number): with
+ * eps != 0 the A applies inside the inner CG, and fill_apply(FILL_OP_A), use
+ *   A_eps = Px C^-1 (I + eps K) Px,
+ * K the real antisymmetric circulant with eigenvalues i sin(2 pi kx / nx)
+ * (the central difference along x), i.e. each spectral mode of C^-1 is
+ * multiplied by 1 + i eps sin(2 pi kx / nx).  The FP64 true residual of the
+ * refinement loop keeps the exact A.  eps = 0 (default) restores A; |eps| < 1,
+ * else FILL_EINVAL.  For experiments only.
+ */
+int fill_plan_set_skew(fill_plan plan, double eps);
+
+/*
  * Graph replay of the inner CG (default 1).  The inner CG runs in chunks of
  * 16 iterations between host checks of the device convergence flags; with 1
  * each chunk is captured once per plan (per precision, preconditioner and

@@ -90,6 +90,7 @@ struct fill_plan_s {
   int max_iter = 20000;
   double inner_tol32 = 1e-4;
   int precond = FILL_PRECOND_SPLIT;
+  double skew = 0.0;  // non-Hermitian study: eps of the perturbed A inside the inner CG
   // CG coefficient record of the first inner solve of the last solve (Lanczos data)
   int hist_cap = 0;
   double* hist = nullptr;
@@ -221,6 +222,7 @@ template <typename T> ColArgs<T> col_base(fill_plan p, int nprob, const T* D, co
   ca.nprob = nprob;
   ca.xt_stride = p->nt;
   ca.d_stride = p->npk > 1 ? p->nt : 0;
+  ca.skew = 0.0;
   return ca;
 }
 
@@ -274,9 +276,10 @@ int timed_launch(fill_plan p, int kernel, F&& launch) {
 // One operator apply: r2c (mode rm, args ai) -> column pass with table D -> c2r (mode cm, args ao).
 template <typename T>
 int apply3(fill_plan p, int rm, const RowArgs<T>& ai, const T* D, int cm, const RowArgs<T>& ao,
-           const CGScalars* sc) {
+           const CGScalars* sc, double skew = 0.0) {
   FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(rm, ai, p->stream, a, b); }));
-  const ColArgs<T> ca = col_base<T>(p, ai.nprob, D, sc);
+  ColArgs<T> ca = col_base<T>(p, ai.nprob, D, sc);
+  ca.skew = skew;
   FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
   FILL_TRY(timed_launch<T>(p, FILL_K_C2R, [&](hipEvent_t a, hipEvent_t b) { return launch_c2r<T>(cm, ao, p->stream, a, b); }));
   return FILL_OK;
@@ -436,7 +439,7 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   auto chunk = [&]() -> int {
     for (int k = 0; k < kChunk; ++k) {
       const int par = k & 1;
-      FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc));
+      FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc, p->skew));
       if (mode == FILL_PRECOND_SPLIT) FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
       else if (mode == FILL_PRECOND_CXX)
         FILL_TRY(apply3<T>(p, R2C_XRUPDATE, e_in[par], TypeSel<T>::Dfull(p), C2R_DOT2, e_out, p->sc));
@@ -1137,6 +1140,15 @@ int fill_lanczos_extremes(fill_plan p, int problem, double* lam_min, double* lam
   return FILL_OK;
 }
 
+int fill_plan_set_skew(fill_plan p, double eps) {
+  g_last_error.clear();
+  if (!p || !(std::fabs(eps) < 1.0)) return fail(FILL_EINVAL, "eps must lie in (-1, 1)");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  drop_graphs(p, false);  // captured chunks hold the old value
+  p->skew = eps;
+  return FILL_OK;
+}
+
 int fill_plan_set_graph(fill_plan p, int on) {
   if (!p || (on != 0 && on != 1)) return fail(FILL_EINVAL, "bad argument");
   p->use_graph = on;
@@ -1280,7 +1292,8 @@ int fill_apply(fill_plan p, int op, int prec, const double* in, double* out) {
         RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
         ai.v0 = p->res;
         ao.v0 = p->v64.q;
-        FILL_TRY(apply3<double>(p, R2C_COMPACT, ai, inv ? p->Dinv64 : p->Dhalf64, C2R_COMPACT, ao, nullptr));
+        FILL_TRY(apply3<double>(p, R2C_COMPACT, ai, inv ? p->Dinv64 : p->Dhalf64, C2R_COMPACT, ao, nullptr,
+                                inv ? p->skew : 0.0));
         HIP_TRY(launch_scatter(out, p->v64.q, p->pos, n, p->stream));
       } else {
         p->hp.scale[0] = 1.0;
@@ -1289,7 +1302,8 @@ int fill_apply(fill_plan p, int op, int prec, const double* in, double* out) {
         RowArgs<float> ai = row_base<float>(p, 1), ao = row_base<float>(p, 1);
         ai.v0 = p->v32.t;
         ao.v0 = p->v32.q;
-        FILL_TRY(apply3<float>(p, R2C_COMPACT, ai, inv ? p->Dinv32 : p->Dhalf32, C2R_COMPACT, ao, nullptr));
+        FILL_TRY(apply3<float>(p, R2C_COMPACT, ai, inv ? p->Dinv32 : p->Dhalf32, C2R_COMPACT, ao, nullptr,
+                               inv ? p->skew : 0.0));
         HIP_TRY(launch_scatter_f32(out, p->v32.q, p->pos, n, p->stream));
       }
     }

@@ -103,6 +103,7 @@ template <typename T> struct ColArgs {
   int nprob;
   size_t xt_stride;  // complex values between problems' spectra
   size_t d_stride;   // table entries between problems' tables (0: one shared table)
+  double skew;       // 0, or eps of the non-Hermitian study: D(k) (1 + i eps sin(2 pi kx / nx))
 };
 
 template <typename T> __device__ __forceinline__ RowArgs<T> bind_problem(RowArgs<T> a) {
@@ -683,6 +684,13 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
       v[e].x *= dv[e];
       v[e].y *= dv[e];
     }
+  }
+  if (a.skew != 0.0 && kx > 0) {
+    // column kx > 0: multiply by 1 + i f, f = eps sin(pi kx / ncol) (f = 0 on
+    // the packed DC/Nyquist column), an antisymmetric real-space perturbation
+    const T f = (T)(a.skew * sin(3.14159265358979323846 * (double)kx / (double)a.ncol));
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = C{v[e].x - f * v[e].y, v[e].y + f * v[e].x};
   }
   fft_line<C, PL, +1>(v, tid, line, twq);
   if (valid) {

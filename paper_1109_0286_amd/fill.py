@@ -45,7 +45,7 @@ EXPORTS = (
     "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_kernel_timing",
     "fill_kernel_timing_read", "fill_strerror",
     "fill_last_error", "fill_plan_set_precond", "fill_plan_set_lanczos", "fill_get_lanczos",
-    "fill_lanczos_extremes", "fill_plan_set_graph",
+    "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew",
 )
 
 FILL_PRECOND_NONE = 0
@@ -92,6 +92,7 @@ def _load() -> C.CDLL:
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
         "fill_plan_set_precond": (i32, [vp, i32]),
         "fill_plan_set_graph": (i32, [vp, i32]),
+        "fill_plan_set_skew": (i32, [vp, dbl]),
         "fill_plan_set_lanczos": (i32, [vp, i32]),
         "fill_get_lanczos": (i32, [vp, i32, vp, vp, i32, C.POINTER(i32)]),
         "fill_lanczos_extremes": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
@@ -253,6 +254,10 @@ def fill_plan_set_precond(plan, mode):
     return _check(_lib.fill_plan_set_precond(plan, int(mode)), "fill_plan_set_precond")
 
 
+def fill_plan_set_skew(plan, eps):
+    return _check(_lib.fill_plan_set_skew(plan, float(eps)), "fill_plan_set_skew")
+
+
 def fill_plan_set_graph(plan, on):
     return _check(_lib.fill_plan_set_graph(plan, 1 if on else 0), "fill_plan_set_graph")
 
@@ -395,6 +400,10 @@ class Plan:
     def set_graph(self, on):
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
         fill_plan_set_graph(self.handle, on)
+
+    def set_skew(self, eps):
+        """Non-Hermitian study: inner-CG A applies use Px C^-1 (I + eps K) Px (0 restores A)."""
+        fill_plan_set_skew(self.handle, eps)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""
@@ -545,6 +554,10 @@ class BatchPlan:
     def set_graph(self, on):
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
         fill_plan_set_graph(self.handle, on)
+
+    def set_skew(self, eps):
+        """Non-Hermitian study: inner-CG A applies use Px C^-1 (I + eps K) Px (0 restores A)."""
+        fill_plan_set_skew(self.handle, eps)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""
