@@ -7,3 +7,4 @@ this package.  It shares no code with the GPU path.
 from .fill_oracle import *  # noqa: F401,F403
 from . import dense  # noqa: F401
 from . import lanczos  # noqa: F401
+from . import strips  # noqa: F401
