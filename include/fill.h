@@ -214,6 +214,52 @@ int fill_plan_set_skew(fill_plan plan, double eps);
  */
 int fill_plan_set_graph(fill_plan plan, int on);
 
+/*
+ * Noise-boosted strip refinement (Sec. 6.2 subdivision, Sec. 6.4 refinement):
+ * an approximate maximum-likelihood fill by a few CG iterations on nested
+ * strips along the boundary of the masked region.
+ *
+ * fill_strips_create: subdivision and one plan per strip.
+ *   mask       host uint8 ny*nx, 1 = masked (copied).
+ *   P_signal   host FP64 ny*(nx/2+1), the signal part of the spectrum (layout
+ *              as fill_plan_create); noise: the white-noise level N >= 0.
+ *   nstrips    strips 1..64 with noise boosts betas[i] > 0 and widths
+ *              widths[i] >= 1 (host arrays; widths decreasing for nested
+ *              strips); 2 floor(w) + 1 must not exceed min(nx, ny).
+ *   threshold  in [0, 1): strip i holds the masked pixels whose periodic disk
+ *              {dx^2 + dy^2 <= w_i^2} contains more than threshold * (pixels
+ *              in the disk) observed pixels (the paper uses 0.03).
+ *   iters      CG iterations per strip (>= 1; the paper uses 20).
+ *   prec       enum fill_precision of the strip solves.
+ * Strip i is solved with spectrum P_signal + betas[i] * noise (FILL_ENOTSPD
+ * if not positive).  Empty strips are skipped.  Owned by the library.
+ */
+typedef struct fill_strips_s* fill_strips;
+int fill_strips_create(int nx, int ny, const uint8_t* mask, const double* P_signal, double noise, int nstrips,
+                       const double* betas, const double* widths, double threshold, int iters, int prec,
+                       void* hip_stream, fill_strips* out);
+
+/*
+ * The refined fill: x_out (device ny*nx, may not alias d_obs) = d_obs on
+ * observed pixels; masked pixels start at 0 and each strip in order replaces
+ * its pixels by `iters` CG iterations of the maximum-likelihood fill given
+ * every other pixel of the current map.  Masked values of d_obs are ignored.
+ */
+int fill_strips_mean(fill_strips strips, const double* d_obs, double* x_out);
+
+/* Strip i as a host uint8 ny*nx mask (out must hold ny*nx bytes). */
+int fill_strips_mask(fill_strips strips, int i, uint8_t* out);
+
+/* The plan of strip i (owned by the strips object; NULL for an empty strip),
+ * e.g. to record its CG coefficients with fill_plan_set_lanczos. */
+int fill_strips_plan(fill_strips strips, int i, fill_plan* out);
+
+/* Message of the last failed fill_strips_* call on this thread. */
+const char* fill_strips_last_error(void);
+
+/* Release the strips object and its plans (NULL is accepted). */
+void fill_strips_destroy(fill_strips strips);
+
 /* Release every resource of the plan (NULL is accepted). */
 void fill_plan_destroy(fill_plan plan);
 

@@ -38,8 +38,10 @@ def disk_offsets(w: float) -> np.ndarray:
 def observed_counts(mask: np.ndarray, w: float) -> np.ndarray:
     """Number of observed pixels in the periodic disk of radius w around each
     pixel: the top-hat convolution of the observed indicator, by FFT, rounded
-    to the integer it is."""
+    to the integer it is.  The disk must fit the torus: 2 floor(w) + 1 <= min(nx, ny)."""
     ny, nx = mask.shape
+    if 2 * int(np.floor(w)) + 1 > min(nx, ny):
+        raise ValueError(f"disk of radius {w} does not fit a {nx}x{ny} torus")
     obs = (mask == 0).astype(np.float64)
     ker = np.zeros((ny, nx))
     off = disk_offsets(w)

@@ -65,4 +65,9 @@ hipError_t launch_band_reduce(const double* G, int nx, int ny, const double* lnk
                               hipStream_t st);
 hipError_t launch_cnorm2(double* out, const double* v, const int* comp_off, int nprob, hipStream_t st);
 
+// Strip subdivision (exact periodic-disk counts of observed pixels) and map selection.
+hipError_t launch_strip_flags(const uint8_t* mask, int* pre, const int* hw, int r, int nx, int ny, double thr_count,
+                              uint8_t* out, hipStream_t s);
+hipError_t launch_select_observed(double* x, const double* d, const uint8_t* mask, size_t npix, hipStream_t s);
+
 }  // namespace fillk

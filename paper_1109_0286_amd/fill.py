@@ -45,7 +45,8 @@ EXPORTS = (
     "fill_realize_unconstrained", "fill_philox_words", "fill_time_kernel", "fill_kernel_timing",
     "fill_kernel_timing_read", "fill_strerror",
     "fill_last_error", "fill_plan_set_precond", "fill_plan_set_lanczos", "fill_get_lanczos",
-    "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew",
+    "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew", "fill_strips_create",
+    "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
 )
 
 FILL_PRECOND_NONE = 0
@@ -93,6 +94,12 @@ def _load() -> C.CDLL:
         "fill_plan_set_precond": (i32, [vp, i32]),
         "fill_plan_set_graph": (i32, [vp, i32]),
         "fill_plan_set_skew": (i32, [vp, dbl]),
+        "fill_strips_create": (i32, [i32, i32, vp, vp, dbl, i32, vp, vp, dbl, i32, i32, vp, C.POINTER(vp)]),
+        "fill_strips_mean": (i32, [vp, vp, vp]),
+        "fill_strips_mask": (i32, [vp, i32, vp]),
+        "fill_strips_plan": (i32, [vp, i32, C.POINTER(vp)]),
+        "fill_strips_last_error": (C.c_char_p, []),
+        "fill_strips_destroy": (None, [vp]),
         "fill_plan_set_lanczos": (i32, [vp, i32]),
         "fill_get_lanczos": (i32, [vp, i32, vp, vp, i32, C.POINTER(i32)]),
         "fill_lanczos_extremes": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
@@ -599,6 +606,66 @@ def realize_multi(plans, d_obs_list, seeds_list, rtol, outs=None, allow_noconv=F
                        [[o[b].data_ptr() for b in range(p.nprob)] for p, o in zip(plans, outs)],
                        rtol, allow_noconv)
     return outs
+
+
+def _check_strips(code: int, where: str, ok=(FILL_OK,)) -> int:
+    if code not in ok:
+        raise FillError(code, where, _lib.fill_strips_last_error().decode())
+    return code
+
+
+class Strips:
+    """Owner of a fill_strips object (noise-boosted strip refinement) on a torch stream."""
+
+    def __init__(self, nx, ny, mask, P_signal, noise, betas, widths, threshold=0.03, iters=20,
+                 prec=FILL_PREC_FP64, stream=None, device=None):
+        import torch
+        self.device = torch.device(device or "cuda")
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            P = np.ascontiguousarray(P_signal, dtype=np.float64)
+            if m.shape != (ny, nx) or P.shape != (ny, nx // 2 + 1):
+                raise ValueError("mask / P_signal do not match the grid")
+            b = np.ascontiguousarray(betas, dtype=np.float64)
+            w = np.ascontiguousarray(widths, dtype=np.float64)
+            if b.shape != w.shape or b.ndim != 1:
+                raise ValueError("betas and widths must be 1-D of equal length")
+            h = C.c_void_p()
+            _check_strips(_lib.fill_strips_create(nx, ny, m.ctypes.data, P.ctypes.data, float(noise), len(b),
+                                                  b.ctypes.data, w.ctypes.data, float(threshold), int(iters),
+                                                  int(prec), C.c_void_p(s.cuda_stream), C.byref(h)),
+                          "fill_strips_create")
+            self.handle, self.nx, self.ny, self.nstrips = h.value, nx, ny, len(b)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.fill_strips_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mean(self, d_obs, out=None):
+        import torch
+        out = torch.empty_like(d_obs) if out is None else out
+        _check_strips(_lib.fill_strips_mean(self.handle, _dev_ptr(d_obs, torch.float64),
+                                            _dev_ptr(out, torch.float64)), "fill_strips_mean")
+        return out
+
+    def mask(self, i):
+        out = np.zeros((self.ny, self.nx), np.uint8)
+        _check_strips(_lib.fill_strips_mask(self.handle, int(i), out.ctypes.data), "fill_strips_mask")
+        return out
+
+    def plan(self, i):
+        """The raw fill_plan handle of strip i (None for an empty strip); owned by this object."""
+        h = C.c_void_p()
+        _check_strips(_lib.fill_strips_plan(self.handle, int(i), C.byref(h)), "fill_strips_plan")
+        return h.value
 
 
 def philox_words(seed, stream, n_blocks, device="cuda"):

@@ -66,3 +66,30 @@ def test_build_sources_are_gfx950_only():
     for f in os.listdir(src):
         txt = open(os.path.join(src, f)).read()
         assert "__CUDA" not in txt and "__HIP_PLATFORM" not in txt, f
+
+
+def test_strips_create_rejects_bad_arguments_before_touching_the_gpu():
+    import numpy as np
+    import paper_1109_0286_amd as F
+    lib = F.fill._lib
+    m = np.zeros((64, 64), np.uint8)
+    P = np.ones((64, 33))
+    h = ctypes.c_void_p()
+
+    def create(nstrips, betas, widths, threshold=0.03, iters=20, prec=0, noise=1e-3):
+        b = np.asarray(betas, dtype=np.float64)
+        w = np.asarray(widths, dtype=np.float64)
+        return lib.fill_strips_create(64, 64, m.ctypes.data, P.ctypes.data, noise, nstrips, b.ctypes.data,
+                                      w.ctypes.data, threshold, iters, prec, None, ctypes.byref(h))
+
+    assert create(0, [1.0], [4.0]) == F.FILL_EINVAL
+    assert create(1, [1.0], [32.0]) == F.FILL_EINVAL      # disk of 65 px does not fit 64
+    assert create(1, [1.0], [0.5]) == F.FILL_EINVAL
+    assert create(1, [0.0], [4.0]) == F.FILL_EINVAL
+    assert create(1, [1.0], [4.0], threshold=1.0) == F.FILL_EINVAL
+    assert create(1, [1.0], [4.0], iters=0) == F.FILL_EINVAL
+    assert create(1, [1.0], [4.0], prec=5) == F.FILL_EINVAL
+    assert create(1, [1.0], [4.0], noise=-1.0) == F.FILL_EINVAL
+    assert create(1, [1.0], [40.0]) == F.FILL_EINVAL
+    assert b"disk" in lib.fill_strips_last_error()
+    assert h.value is None

@@ -29,6 +29,12 @@ def test_observed_counts_brute_force(w):
     assert np.array_equal(S.observed_counts(mask, w), _brute_counts(mask, w))
 
 
+def test_disk_must_fit_the_torus():
+    with pytest.raises(ValueError):
+        S.observed_counts(np.zeros((16, 32), np.uint8), 8.0)
+    S.observed_counts(np.zeros((16, 32), np.uint8), 7.9)
+
+
 def test_strip_nesting_and_adjacency():
     mask = W.band_holes_mask(64, 64, (20, 24), 6, 2.0, 6.0, 8)
     prev = None
@@ -84,7 +90,7 @@ def test_one_strip_step_is_the_conditional_mean():
 def test_whole_mask_strip_with_beta_one_is_the_exact_fill():
     p = W.make_problem("grid64")
     floor = 1e-6
-    x, strips = S.strip_fill(p.d_obs, p.mask, p.P - floor, floor, [1.0], [100.0], iters=600)
+    x, strips = S.strip_fill(p.d_obs, p.mask, p.P - floor, floor, [1.0], [31.0], iters=600)
     assert np.array_equal(strips[0], p.mask)
     ref = F.fill_mean(p.d_obs, p.mask, p.P, 1e-12)
     m = p.mask != 0
