@@ -622,7 +622,9 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
 // ---------------------------------------------------------------------------
 // column pass: forward FFT along y, multiply by D, inverse FFT along y
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+// SKEW: the non-Hermitian study's variant (a.skew != 0); the solver's
+// kernel is instantiated without it.
+template <typename T, int N, bool SKEW>
 __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T> a_in) {
   using C = cplx<T>;
   using CF = ColCfg<T, N>;
@@ -685,7 +687,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
       v[e].y *= dv[e];
     }
   }
-  if (a.skew != 0.0 && kx > 0) {
+  if (SKEW && kx > 0) {
     // column kx > 0: multiply by 1 + i f, f = eps sin(pi kx / ncol) (f = 0 on
     // the packed DC/Nyquist column), an antisymmetric real-space perturbation
     const T f = (T)(a.skew * sin(3.14159265358979323846 * (double)kx / (double)a.ncol));
@@ -782,7 +784,12 @@ hipError_t launch_proj_n(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipE
 template <typename T, int N>
 hipError_t launch_col_n(const ColArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = ColCfg<T, N>;
-  FILL_LAUNCH((col_kernel<T, N>), dim3((a.ncol + CF::W - 1) / CF::W, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
+  if (a.skew != 0.0)
+    FILL_LAUNCH((col_kernel<T, N, true>), dim3((a.ncol + CF::W - 1) / CF::W, a.nprob), dim3(CF::THREADS), s, e0, e1,
+                a);
+  else
+    FILL_LAUNCH((col_kernel<T, N, false>), dim3((a.ncol + CF::W - 1) / CF::W, a.nprob), dim3(CF::THREADS), s, e0,
+                e1, a);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def main(run: str, n: int) -> None:
     ta, pa = BENCH_ARGS[n]
     rows = list(csv.DictReader(open(os.path.join(run, "trace", "trace_kernel_stats.csv"))))
     clean = json.loads(open(os.path.join(run, "bench.json")).read().strip().splitlines()[-1])
-    name = f"col_kernel<float, {n}>"
+    name = f"col_kernel<float, {n}, false>"
     col_rocprof = next(float(r["AverageNs"]) / 1e3 for r in rows if name in r["Name"])
     live, line = bench_numbers(clean, n)
     roof = clean["roofline"]
