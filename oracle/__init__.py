@@ -8,3 +8,4 @@ from .fill_oracle import *  # noqa: F401,F403
 from . import dense  # noqa: F401
 from . import lanczos  # noqa: F401
 from . import strips  # noqa: F401
+from . import laplace  # noqa: F401
