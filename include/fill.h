@@ -215,6 +215,23 @@ int fill_plan_set_skew(fill_plan plan, double eps);
 int fill_plan_set_graph(fill_plan plan, int on);
 
 /*
+ * Kernel-based Laplace relaxation of the masked pixels (Sec. 6.1, 6.3): in the
+ * far interior of a wide cut the fill nearly solves the Laplace equation, and
+ * a harmonic function equals its average over an annulus around any point.
+ * Kernel j (0 <= j < nkernels) is the annulus r_{j-1}^2 < dx^2 + dy^2 <= r_j^2
+ * (r_{-1} = 0), r_j = r0 ratio^j, normalised to sum 1; a masked pixel uses the
+ * largest j >= 1 whose disk of radius r_j holds no observed pixel, else 0 (the
+ * boundary layer, whose small kernel reaches the data).  x_out (device ny*nx,
+ * may not alias d_obs) = d_obs on observed pixels; masked pixels start at 0
+ * and take `iters` Jacobi sweeps (each: one FFT convolution per kernel in use,
+ * FP64, problem 0's mask; one-problem plans only).  1 <= nkernels <= 16,
+ * r0 >= 1, ratio > 1, 2 floor(r_max) + 1 <= min(nx, ny), else FILL_EINVAL.
+ * The kernel spectra and classes are kept in the plan while the parameters
+ * repeat.  An approximation: it is the start of fill_strips_refine.
+ */
+int fill_laplace(fill_plan plan, const double* d_obs, double* x_out, int nkernels, double r0, double ratio, int iters);
+
+/*
  * Noise-boosted strip refinement (Sec. 6.2 subdivision, Sec. 6.4 refinement):
  * an approximate maximum-likelihood fill by a few CG iterations on nested
  * strips along the boundary of the masked region.
@@ -246,6 +263,13 @@ int fill_strips_create(int nx, int ny, const uint8_t* mask, const double* P_sign
  * every other pixel of the current map.  Masked values of d_obs are ignored.
  */
 int fill_strips_mean(fill_strips strips, const double* d_obs, double* x_out);
+
+/*
+ * The strip sequence on an already filled map, in place: x (device ny*nx)
+ * holds the data on observed pixels and a start on masked ones (for example
+ * the output of fill_laplace, as the paper starts from its Laplace fill).
+ */
+int fill_strips_refine(fill_strips strips, double* x);
 
 /* Strip i as a host uint8 ny*nx mask (out must hold ny*nx bytes). */
 int fill_strips_mask(fill_strips strips, int i, uint8_t* out);

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/fill.h"
@@ -149,6 +150,16 @@ struct fill_plan_s {
   double* adj_G = nullptr;
   double* adj_Gapi = nullptr;
   double* adj_gth = nullptr;
+  // kernel-based Laplace relaxation (Sec. 6.3): kernel spectra and classes
+  int lap_k = 0;
+  double lap_r0 = 0.0, lap_ratio = 0.0;
+  std::vector<double*> lap_tab;
+  std::vector<int> lap_used;
+  uint8_t* lap_cls = nullptr;
+  double* lap_x[3] = {nullptr, nullptr, nullptr};
+  int* lap_pre = nullptr;
+  int* lap_hw = nullptr;
+  uint8_t* lap_touch = nullptr;
   // optional HIP-event timing of every launch of one kernel during solves
   int timed_kernel = -1;
   int timed_prec = 0;
@@ -996,6 +1007,88 @@ int adjoint_impl(fill_plan p, const double* const* d, const uint64_t* seeds, con
 
 namespace {
 
+// Kernel j of the Laplace relaxation: offsets with r_in^2 < dy^2 + dx^2 <= r_out^2.
+std::vector<std::pair<int, int>> annulus(double r_in, double r_out) {
+  std::vector<std::pair<int, int>> off;
+  const int r = (int)std::floor(r_out);
+  for (int dy = -r; dy <= r; ++dy)
+    for (int dx = -r; dx <= r; ++dx) {
+      const double d2 = (double)dy * dy + (double)dx * dx;
+      if (d2 > r_in * r_in && d2 <= r_out * r_out) off.emplace_back(dy, dx);
+    }
+  return off;
+}
+
+// Kernel spectra (as D tables: real spectrum / N) and per-pixel kernel
+// classes for (nkernels, r0, ratio); kept while the parameters repeat.
+int laplace_setup(fill_plan p, int nk, double r0, double ratio) {
+  if (p->lap_k == nk && p->lap_r0 == r0 && p->lap_ratio == ratio) return FILL_OK;
+  const int nx = p->nx, ny = p->ny;
+  const size_t npix = p->npix, nt = p->nt;
+  FILL_TRY(adjoint_workspace(p));
+  if (!p->lap_cls) {
+    FILL_TRY(dalloc(p, &p->lap_cls, npix));
+    for (int i = 0; i < 3; ++i) FILL_TRY(dalloc(p, &p->lap_x[i], npix));
+    FILL_TRY(dalloc(p, &p->lap_pre, (size_t)ny * (nx + 1)));
+    FILL_TRY(dalloc(p, &p->lap_hw, (size_t)std::min(nx, ny)));
+    FILL_TRY(dalloc(p, &p->lap_touch, npix));
+  }
+  while ((int)p->lap_tab.size() < nk) {
+    double* t = nullptr;
+    FILL_TRY(dalloc(p, &t, nt));
+    p->lap_tab.push_back(t);
+  }
+  p->lap_k = 0;  // invalid until complete
+  std::vector<double> radii(nk);
+  for (int j = 0; j < nk; ++j) radii[j] = r0 * std::pow(ratio, (double)j);
+  // spectra: forward FFT of the normalised kernel image
+  std::vector<double> img(npix);
+  for (int j = 0; j < nk; ++j) {
+    const auto off = annulus(j == 0 ? 0.0 : radii[j - 1], radii[j]);
+    if (off.empty()) return fail(FILL_EINVAL, "empty Laplace kernel " + std::to_string(j));
+    std::fill(img.begin(), img.end(), 0.0);
+    const double w = 1.0 / (double)off.size();
+    for (const auto& o : off) img[(size_t)((o.first % ny + ny) % ny) * nx + (size_t)((o.second % nx + nx) % nx)] = w;
+    HIP_TRY(hipMemcpyAsync(p->adj_h, img.data(), npix * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    RowArgs<double> a = row_for<double>(p, 0);
+    a.full_in = p->adj_h;
+    FILL_TRY(forward_spectrum(p, 0, R2C_FULL, a, 0));
+    HIP_TRY(launch_real_scale(p->lap_tab[j], p->adj_X[0], 1.0 / (double)npix, nt, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));  // img is reused
+  }
+  // classes: the largest j >= 1 whose disk of radius r_j touches no observed pixel, else 0
+  int* pre = p->lap_pre;
+  int* dhw = p->lap_hw;
+  uint8_t* touch = p->lap_touch;
+  HIP_TRY(launch_class_init(p->lap_cls, p->mask, npix, p->stream));
+  for (int j = 1; j < nk; ++j) {
+    const int r = (int)std::floor(radii[j]);
+    std::vector<int> hw(2 * r + 1);
+    for (int dy = -r; dy <= r; ++dy) {
+      int h = (int)std::floor(std::sqrt(std::max(0.0, radii[j] * radii[j] - (double)dy * dy)));
+      while ((double)(h + 1) * (h + 1) + (double)dy * dy <= radii[j] * radii[j]) ++h;
+      while (h > 0 && (double)h * h + (double)dy * dy > radii[j] * radii[j]) --h;
+      hw[dy + r] = h;
+    }
+    HIP_TRY(hipMemcpyAsync(dhw, hw.data(), hw.size() * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(launch_strip_flags(p->mask, pre, dhw, r, nx, ny, 0.0, touch, p->stream));
+    HIP_TRY(launch_class_raise(p->lap_cls, touch, p->mask, j, npix, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));  // hw is reused
+  }
+  std::vector<uint8_t> cls(npix);
+  HIP_TRY(hipMemcpy(cls.data(), p->lap_cls, npix, hipMemcpyDeviceToHost));
+  std::vector<char> seen(nk, 0);
+  for (uint8_t c : cls)
+    if (c < nk) seen[c] = 1;
+  p->lap_used.clear();
+  for (int j = 0; j < nk; ++j)
+    if (seen[j]) p->lap_used.push_back(j);
+  p->lap_k = nk;
+  p->lap_r0 = r0;
+  p->lap_ratio = ratio;
+  return FILL_OK;
+}
+
 // Lanczos matrix of k CG steps (Sec. 6.4; CG-Lanczos relation): diagonal
 // 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j.
 void lanczos_matrix(const double* al, const double* be, int k, std::vector<double>& d, std::vector<double>& e) {
@@ -1209,6 +1302,38 @@ int fill_realize_multi(int nplans, const fill_plan* plans, const double* const* 
     }
   }
   return worst;
+}
+
+int fill_laplace(fill_plan p, const double* d_obs, double* x_out, int nkernels, double r0, double ratio, int iters) {
+  g_last_error.clear();
+  if (!p || !d_obs || !x_out) return fail(FILL_EINVAL, "NULL argument");
+  if (p->nprob != 1) return fail(FILL_EINVAL, "fill_laplace needs a one-problem plan");
+  if (d_obs == x_out) return fail(FILL_EINVAL, "x_out may not alias d_obs");
+  if (nkernels < 1 || nkernels > 16 || !(r0 >= 1.0) || !(ratio > 1.0) || iters < 1)
+    return fail(FILL_EINVAL, "need 1 <= nkernels <= 16, r0 >= 1, ratio > 1, iters >= 1");
+  const double rmax = r0 * std::pow(ratio, (double)(nkernels - 1));
+  if (!(2.0 * std::floor(rmax) + 1.0 <= (double)std::min(p->nx, p->ny)))
+    return fail(FILL_EINVAL, "the largest Laplace kernel does not fit the grid");
+  FILL_TRY(laplace_setup(p, nkernels, r0, ratio));
+  const size_t npix = p->npix;
+  double* a = p->lap_x[0];
+  double* b = p->lap_x[1];
+  double* avg = p->lap_x[2];
+  HIP_TRY(launch_select_observed(a, d_obs, p->mask, npix, p->stream));
+  HIP_TRY(hipMemcpyAsync(b, a, npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  // Jacobi sweeps: every used kernel's average of the current map, written to its class
+  for (int it = 0; it < iters; ++it) {
+    for (int j : p->lap_used) {
+      RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
+      ai.full_in = a;
+      ao.full_out = avg;
+      FILL_TRY(apply3<double>(p, R2C_FULL, ai, p->lap_tab[j], C2R_FULL, ao, nullptr));
+      HIP_TRY(launch_take_class(b, avg, p->lap_cls, j, npix, p->stream));
+    }
+    std::swap(a, b);
+  }
+  HIP_TRY(hipMemcpyAsync(x_out, a, npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  return FILL_OK;
 }
 
 int fill_plan_set_bands(fill_plan p, int nbands, const double* lnk_nodes, const double* theta) {

@@ -1,7 +1,8 @@
 // Strip subdivision of the masked region (Sec. 6.2): the top-hat convolution
 // of the observed indicator with a periodic disk, as exact integer counts from
 // per-row prefix sums, and the threshold test that puts a masked pixel into
-// the strip of width w.
+// the strip of width w.  Also the per-pixel kernel classes and the
+// class-wise update of the kernel-based Laplace relaxation (Sec. 6.3).
 #include "launch.hpp"
 
 namespace fillk {
@@ -55,6 +56,59 @@ __global__ __launch_bounds__(ST) void k_disk_strip(const uint8_t* mask, const in
 __global__ __launch_bounds__(ST) void k_select_observed(double* x, const double* d, const uint8_t* mask, size_t npix) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npix; i += (size_t)gridDim.x * blockDim.x)
     x[i] = mask[i] != 0 ? 0.0 : d[i];
+}
+
+// cls[i] = j for masked pixels whose disk touches no observed pixel (flag 0).
+__global__ __launch_bounds__(ST) void k_class_raise(uint8_t* cls, const uint8_t* touch, const uint8_t* mask, int j,
+                                                    size_t npix) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npix; i += (size_t)gridDim.x * blockDim.x)
+    if (mask[i] != 0 && touch[i] == 0) cls[i] = (uint8_t)j;
+}
+
+// cls[i] = mask ? 0 : 255
+__global__ __launch_bounds__(ST) void k_class_init(uint8_t* cls, const uint8_t* mask, size_t npix) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npix; i += (size_t)gridDim.x * blockDim.x)
+    cls[i] = mask[i] != 0 ? 0 : 255;
+}
+
+// x[i] = avg[i] on the pixels of class j
+__global__ __launch_bounds__(ST) void k_take_class(double* x, const double* avg, const uint8_t* cls, int j,
+                                                   size_t npix) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npix; i += (size_t)gridDim.x * blockDim.x)
+    if (cls[i] == (uint8_t)j) x[i] = avg[i];
+}
+
+// tab[i] = X[i].x * scale (real part of a real even kernel's spectrum)
+__global__ __launch_bounds__(ST) void k_real_scale(double* tab, const double2* X, double scale, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    tab[i] = X[i].x * scale;
+}
+
+namespace {
+dim3 sgrid(size_t n) {
+  size_t g = (n + ST - 1) / ST;
+  if (g > 4096) g = 4096;
+  if (g == 0) g = 1;
+  return dim3((unsigned)g);
+}
+}  // namespace
+
+hipError_t launch_class_init(uint8_t* cls, const uint8_t* mask, size_t npix, hipStream_t s) {
+  hipLaunchKernelGGL(k_class_init, sgrid(npix), dim3(ST), 0, s, cls, mask, npix);
+  return hipGetLastError();
+}
+hipError_t launch_class_raise(uint8_t* cls, const uint8_t* touch, const uint8_t* mask, int j, size_t npix,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_class_raise, sgrid(npix), dim3(ST), 0, s, cls, touch, mask, j, npix);
+  return hipGetLastError();
+}
+hipError_t launch_take_class(double* x, const double* avg, const uint8_t* cls, int j, size_t npix, hipStream_t s) {
+  hipLaunchKernelGGL(k_take_class, sgrid(npix), dim3(ST), 0, s, x, avg, cls, j, npix);
+  return hipGetLastError();
+}
+hipError_t launch_real_scale(double* tab, const double2* X, double scale, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_real_scale, sgrid(n), dim3(ST), 0, s, tab, X, scale, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_strip_flags(const uint8_t* mask, int* pre, const int* hw, int r, int nx, int ny, double thr_count,

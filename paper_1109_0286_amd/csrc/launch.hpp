@@ -69,5 +69,11 @@ hipError_t launch_cnorm2(double* out, const double* v, const int* comp_off, int 
 hipError_t launch_strip_flags(const uint8_t* mask, int* pre, const int* hw, int r, int nx, int ny, double thr_count,
                               uint8_t* out, hipStream_t s);
 hipError_t launch_select_observed(double* x, const double* d, const uint8_t* mask, size_t npix, hipStream_t s);
+// Laplace relaxation helpers: kernel classes, class-wise update, kernel spectra.
+hipError_t launch_class_init(uint8_t* cls, const uint8_t* mask, size_t npix, hipStream_t s);
+hipError_t launch_class_raise(uint8_t* cls, const uint8_t* touch, const uint8_t* mask, int j, size_t npix,
+                              hipStream_t s);
+hipError_t launch_take_class(double* x, const double* avg, const uint8_t* cls, int j, size_t npix, hipStream_t s);
+hipError_t launch_real_scale(double* tab, const double2* X, double scale, size_t n, hipStream_t s);
 
 }  // namespace fillk

@@ -146,22 +146,28 @@ int fill_strips_create(int nx, int ny, const uint8_t* mask, const double* P_sign
   return FILL_OK;
 }
 
-int fill_strips_mean(fill_strips s, const double* d_obs, double* x_out) {
+int fill_strips_refine(fill_strips s, double* x) {
   g_strip_error.clear();
-  if (!s || !d_obs || !x_out) return sfail(FILL_EINVAL, "NULL argument");
-  if (d_obs == x_out) return sfail(FILL_EINVAL, "x_out may not alias d_obs");
+  if (!s || !x) return sfail(FILL_EINVAL, "NULL argument");
   const size_t npix = (size_t)s->nx * s->ny;
-  S_HIP(fillk::launch_select_observed(x_out, d_obs, s->dmask, npix, s->stream));
   for (int i = 0; i < s->nstrips; ++i) {
     if (!s->plans[i]) continue;
     // every pixel outside strip i is data; rtol 1e-300 makes the solve run its
     // iteration cap, which it reports as FILL_ENOCONV
-    const int rc = fill_mean(s->plans[i], x_out, s->tmp, 1e-300);
+    const int rc = fill_mean(s->plans[i], x, s->tmp, 1e-300);
     if (rc != FILL_OK && rc != FILL_ENOCONV)
       return sfail(rc, std::string("strip ") + std::to_string(i) + ": " + fill_last_error());
-    S_HIP(hipMemcpyAsync(x_out, s->tmp, npix * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    S_HIP(hipMemcpyAsync(x, s->tmp, npix * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
   }
   return FILL_OK;
+}
+
+int fill_strips_mean(fill_strips s, const double* d_obs, double* x_out) {
+  g_strip_error.clear();
+  if (!s || !d_obs || !x_out) return sfail(FILL_EINVAL, "NULL argument");
+  if (d_obs == x_out) return sfail(FILL_EINVAL, "x_out may not alias d_obs");
+  S_HIP(fillk::launch_select_observed(x_out, d_obs, s->dmask, (size_t)s->nx * s->ny, s->stream));
+  return fill_strips_refine(s, x_out);
 }
 
 int fill_strips_mask(fill_strips s, int i, uint8_t* out) {

@@ -47,6 +47,7 @@ EXPORTS = (
     "fill_last_error", "fill_plan_set_precond", "fill_plan_set_lanczos", "fill_get_lanczos",
     "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew", "fill_strips_create",
     "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
+    "fill_strips_refine", "fill_laplace",
 )
 
 FILL_PRECOND_NONE = 0
@@ -96,6 +97,8 @@ def _load() -> C.CDLL:
         "fill_plan_set_skew": (i32, [vp, dbl]),
         "fill_strips_create": (i32, [i32, i32, vp, vp, dbl, i32, vp, vp, dbl, i32, i32, vp, C.POINTER(vp)]),
         "fill_strips_mean": (i32, [vp, vp, vp]),
+        "fill_strips_refine": (i32, [vp, vp]),
+        "fill_laplace": (i32, [vp, vp, vp, i32, dbl, dbl, i32]),
         "fill_strips_mask": (i32, [vp, i32, vp]),
         "fill_strips_plan": (i32, [vp, i32, C.POINTER(vp)]),
         "fill_strips_last_error": (C.c_char_p, []),
@@ -408,6 +411,14 @@ class Plan:
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
         fill_plan_set_graph(self.handle, on)
 
+    def laplace(self, d_obs, nkernels=8, r0=1.5, ratio=2.0, iters=100, out=None):
+        """Kernel-based Laplace relaxation of the masked pixels (an approximate fill)."""
+        import torch
+        out = self._new_map() if out is None else out
+        _check(_lib.fill_laplace(self.handle, _dev_ptr(d_obs, torch.float64), _dev_ptr(out, torch.float64),
+                                 int(nkernels), float(r0), float(ratio), int(iters)), "fill_laplace")
+        return out
+
     def set_skew(self, eps):
         """Non-Hermitian study: inner-CG A applies use Px C^-1 (I + eps K) Px (0 restores A)."""
         fill_plan_set_skew(self.handle, eps)
@@ -562,6 +573,14 @@ class BatchPlan:
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
         fill_plan_set_graph(self.handle, on)
 
+    def laplace(self, d_obs, nkernels=8, r0=1.5, ratio=2.0, iters=100, out=None):
+        """Kernel-based Laplace relaxation of the masked pixels (an approximate fill)."""
+        import torch
+        out = self._new_map() if out is None else out
+        _check(_lib.fill_laplace(self.handle, _dev_ptr(d_obs, torch.float64), _dev_ptr(out, torch.float64),
+                                 int(nkernels), float(r0), float(ratio), int(iters)), "fill_laplace")
+        return out
+
     def set_skew(self, eps):
         """Non-Hermitian study: inner-CG A applies use Px C^-1 (I + eps K) Px (0 restores A)."""
         fill_plan_set_skew(self.handle, eps)
@@ -655,6 +674,12 @@ class Strips:
         _check_strips(_lib.fill_strips_mean(self.handle, _dev_ptr(d_obs, torch.float64),
                                             _dev_ptr(out, torch.float64)), "fill_strips_mean")
         return out
+
+    def refine(self, x):
+        """The strip sequence on a filled map (data on observed pixels, a start on masked ones), in place."""
+        import torch
+        _check_strips(_lib.fill_strips_refine(self.handle, _dev_ptr(x, torch.float64)), "fill_strips_refine")
+        return x
 
     def mask(self, i):
         out = np.zeros((self.ny, self.nx), np.uint8)
