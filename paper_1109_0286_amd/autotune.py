@@ -1,11 +1,13 @@
-"""Autotuner of the FFT radix plans: elements per thread (plan variant) per
-precision, transform length and pass kind (row passes or column pass).
+"""Autotuner of the FFT kernels' shapes: elements per thread (radix-plan
+variant) per precision, transform length and pass kind (row passes or column
+pass), and rows per row-pass workgroup per precision and length.
 
 Three steps, the middle one on the GPU:
 
   python paper_1109_0286_amd/autotune.py build
-      builds one candidate library per plan variant (every kernel on that
-      variant) under paper_1109_0286_amd/_tune/;
+      builds one candidate library per (plan variant, row scale) pair
+      (every kernel on that variant, every row pass on that row scale) under
+      paper_1109_0286_amd/_tune/;
   python paper_1109_0286_amd/autotune.py measure OUT.json
       for each candidate (a child process loading it through FILL_LIBRARY)
       and each length n with two variants, times the kernels inside a short
@@ -13,9 +15,10 @@ Three steps, the middle one on the GPU:
       plans, M^-1 = Px C Px): the average launch duration of the r2c, c2r and
       col kernels from HIP events around every launch;
   python paper_1109_0286_amd/autotune.py apply OUT.json
-      picks per (precision, n, pass) the faster variant (row passes: mean r2c
-      + mean c2r; column pass: mean col), writes csrc/fft_tuned.hpp and the
-      summary profiles/fft_autotune.md.  Rebuild with build.py afterwards.
+      picks per (precision, n) the fastest (variant, row scale) for the row
+      passes (mean r2c + mean c2r) and the fastest variant for the column pass
+      (mean col, averaged over the row scales), writes csrc/fft_tuned.hpp and
+      the summary profiles/fft_autotune.md.  Rebuild with build.py afterwards.
 """
 
 from __future__ import annotations
@@ -29,6 +32,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 TUNE = os.path.join(HERE, "_tune")
 VARIANTS = (0, 1)
+ROW_SCALES = (1, 2)
+CANDIDATES = tuple((v, r) for v in VARIANTS for r in ROW_SCALES)
 LENGTHS = (128, 256, 512, 1024, 2048, 4096)  # lengths with two plan variants
 KERNELS = ("r2c", "c2r", "col")
 HEADER = os.path.join(HERE, "csrc", "fft_tuned.hpp")
@@ -36,18 +41,22 @@ SUMMARY = os.path.join(ROOT, "profiles", "fft_autotune.md")
 VARIANT_NAMES = {0: "E=16 (radix 16 passes)", 1: "E=8 (radix <= 8 passes)"}
 
 
-def lib_path(v: int) -> str:
-    return os.path.join(TUNE, f"variant{v}", "libfill.so")
+def cand_name(c) -> str:
+    return f"v{c[0]}r{c[1]}"
+
+
+def lib_path(c) -> str:
+    return os.path.join(TUNE, cand_name(c), "libfill.so")
 
 
 def cmd_build() -> None:
     sys.path.insert(0, HERE)
     import build as B
-    for v in VARIANTS:
-        B.build(variant=v, lib=lib_path(v))
+    for c in CANDIDATES:
+        B.build(variant=c[0], rows=c[1], lib=lib_path(c))
 
 
-def _child(v: int, out: str) -> None:
+def _child(v: str, out: str) -> None:
     """Runs with FILL_LIBRARY = candidate v: in-solve kernel timings."""
     sys.path.insert(0, ROOT)
     import numpy as np
@@ -69,7 +78,7 @@ def _child(v: int, out: str) -> None:
                 ms, cnt = plan.kernel_timing_read()
                 plan.kernel_timing(-1)
                 res[f"{pname}/{n}/{k}"] = ms / max(cnt, 1)
-            print(f"variant {v} n {n} {pname}: " +
+            print(f"candidate {v} n {n} {pname}: " +
                   " ".join(f"{k} {res[f'{pname}/{n}/{k}'] * 1e3:.2f} us" for k in KERNELS), flush=True)
             plan.close()
     json.dump(res, open(out, "w"))
@@ -77,19 +86,19 @@ def _child(v: int, out: str) -> None:
 
 def cmd_measure(out: str) -> int:
     import tempfile
-    result = {"variants": {}}
-    for v in VARIANTS:
-        lib = lib_path(v)
+    result = {"candidates": {}}
+    for c in CANDIDATES:
+        lib = lib_path(c)
         if not os.path.exists(lib):
             print(f"{lib} is missing: run `autotune.py build` first", file=sys.stderr)
             return 1
         with tempfile.NamedTemporaryFile(suffix=".json", delete=False) as tf:
             part = tf.name
         env = dict(os.environ, FILL_LIBRARY=lib)
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "_child", str(v), part], env=env)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "_child", cand_name(c), part], env=env)
         if r.returncode != 0:
             return r.returncode
-        result["variants"][str(v)] = json.load(open(part))
+        result["candidates"][cand_name(c)] = json.load(open(part))
         os.unlink(part)
     try:
         import torch
@@ -102,12 +111,13 @@ def cmd_measure(out: str) -> int:
 
 
 def choose(result: dict) -> dict:
-    t = result["variants"]
+    t = result["candidates"]
     pick = {}
     for prec in ("f32", "f64"):
         for n in LENGTHS:
-            row = {v: t[str(v)][f"{prec}/{n}/r2c"] + t[str(v)][f"{prec}/{n}/c2r"] for v in VARIANTS}
-            col = {v: t[str(v)][f"{prec}/{n}/col"] for v in VARIANTS}
+            row = {c: t[cand_name(c)][f"{prec}/{n}/r2c"] + t[cand_name(c)][f"{prec}/{n}/c2r"] for c in CANDIDATES}
+            col = {v: sum(t[cand_name((v, r))][f"{prec}/{n}/col"] for r in ROW_SCALES) / len(ROW_SCALES)
+                   for v in VARIANTS}
             pick[(prec, n, "row")] = (min(row, key=row.get), row)
             pick[(prec, n, "col")] = (min(col, key=col.get), col)
     return pick
@@ -118,8 +128,9 @@ def cmd_apply(path: str) -> None:
     pick = choose(result)
     lines = [
         "// FFT plan variant per (precision, length, pass kind): 0 = E 16, 1 = E 8",
-        "// elements per thread (fft_device.hpp).  Written by autotune.py from in-solve",
-        "// kernel timings on " + str(result.get("device")) + "; lengths not listed use variant 0.",
+        "// elements per thread (fft_device.hpp); rows per row-pass workgroup relative",
+        "// to the 64 KiB default.  Written by autotune.py from in-solve kernel timings",
+        "// on " + str(result.get("device")) + "; lengths not listed use variant 0, scale 1.",
         "#pragma once",
         "",
         "namespace fillk {",
@@ -128,10 +139,16 @@ def cmd_apply(path: str) -> None:
     ]
     lines.append("  switch (n) {")
     for n in LENGTHS:
-        v = {(pr, ps): pick[(pr, n, ps)][0] for pr in ("f32", "f64") for ps in ("row", "col")}
-        lines.append(f"    case {n}: return f32 ? (pass == 0 ? {v[('f32', 'row')]} : {v[('f32', 'col')]})")
-        lines.append(f"                 : (pass == 0 ? {v[('f64', 'row')]} : {v[('f64', 'col')]});")
-    lines += ["    default: return 0;", "  }", "}", "", "}  // namespace fillk", ""]
+        rv = {pr: pick[(pr, n, "row")][0][0] for pr in ("f32", "f64")}
+        cv = {pr: pick[(pr, n, "col")][0] for pr in ("f32", "f64")}
+        lines.append(f"    case {n}: return f32 ? (pass == 0 ? {rv['f32']} : {cv['f32']})")
+        lines.append(f"                 : (pass == 0 ? {rv['f64']} : {cv['f64']});")
+    lines += ["    default: return 0;", "  }", "}", "", "constexpr int tuned_row_scale(bool f32, int n) {",
+              "  switch (n) {"]
+    for n in LENGTHS:
+        rs = {pr: pick[(pr, n, "row")][0][1] for pr in ("f32", "f64")}
+        lines.append(f"    case {n}: return f32 ? {rs['f32']} : {rs['f64']};")
+    lines += ["    default: return 1;", "  }", "}", "", "}  // namespace fillk", ""]
     open(HEADER, "w").write("\n".join(lines))
     md = ["# FFT plan autotuning (in-solve kernel durations, HIP events)", "",
           "Commands (R = repository root; `build` and `apply` on the host, `measure` on the GPU):", "", "```",
@@ -139,14 +156,19 @@ def cmd_apply(path: str) -> None:
           "python $R/paper_1109_0286_amd/autotune.py measure $R/gpurun_out/tune.json",
           "python $R/paper_1109_0286_amd/autotune.py apply $R/gpurun_out/tune.json", "```", "",
           f"Device: {result.get('device')}.  Variants: " +
-          "; ".join(f"{v} = {VARIANT_NAMES[v]}" for v in VARIANTS) + ".", "",
-          "Row passes: mean r2c + mean c2r launch (us); column pass: mean col launch (us).", "",
-          "| precision | n | pass | variant 0 | variant 1 | chosen |", "|---|---:|---|---:|---:|---:|"]
+          "; ".join(f"{v} = {VARIANT_NAMES[v]}" for v in VARIANTS) + "; row scale s = s x 64 KiB of LDS per "
+          "row-pass workgroup.", "",
+          "Row passes: mean r2c + mean c2r launch (us) per candidate vNrS (variant N, row scale S); column "
+          "pass: mean col launch (us) per variant, averaged over the row scales.", "",
+          "| precision | n | " + " | ".join(f"row {cand_name(c)}" for c in CANDIDATES) +
+          " | row chosen | col v0 | col v1 | col chosen |",
+          "|---|---:|" + "---:|" * len(CANDIDATES) + "---|---:|---:|---:|"]
     for prec in ("f32", "f64"):
         for n in LENGTHS:
-            for ps in ("row", "col"):
-                v, t = pick[(prec, n, ps)]
-                md.append(f"| {prec} | {n} | {ps} | {t[0] * 1e3:.2f} | {t[1] * 1e3:.2f} | {v} |")
+            rc, rt = pick[(prec, n, "row")]
+            cc, ct = pick[(prec, n, "col")]
+            md.append(f"| {prec} | {n} | " + " | ".join(f"{rt[c] * 1e3:.2f}" for c in CANDIDATES) +
+                      f" | {cand_name(rc)} | {ct[0] * 1e3:.2f} | {ct[1] * 1e3:.2f} | {cc} |")
     open(SUMMARY, "w").write("\n".join(md) + "\n")
     print(f"wrote {HEADER} and {SUMMARY}; rebuild with python paper_1109_0286_amd/build.py")
 
@@ -161,7 +183,7 @@ def main(argv) -> int:
         cmd_apply(argv[1])
         return 0
     if len(argv) >= 3 and argv[0] == "_child":
-        _child(int(argv[1]), argv[2])
+        _child(argv[1], argv[2])
         return 0
     print(__doc__, file=sys.stderr)
     return 2

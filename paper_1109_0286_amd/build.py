@@ -4,9 +4,9 @@ Every source under csrc/ is compiled with hipcc for gfx950 into
 _build/*.o (in parallel) and linked into libfill.so next to this file.
 Usage: python paper_1109_0286_amd/build.py  (runs without importing the package).
 
-build(variant=v, lib=path) builds a candidate library in which every FFT
-kernel uses radix-plan variant v (the autotuner's candidates) instead of the
-tuned table.
+build(variant=v, rows=r, lib=path) builds a candidate library in which every
+FFT kernel uses radix-plan variant v and every row pass r times the default
+rows per workgroup (the autotuner's candidates) instead of the tuned table.
 """
 
 from __future__ import annotations
@@ -44,9 +44,12 @@ def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
     return obj
 
 
-def build(verbose: bool = True, variant: int | None = None, lib: str = LIB) -> str:
-    build_dir = BUILD if variant is None else os.path.join(BUILD, f"variant{variant}")
+def build(verbose: bool = True, variant: int | None = None, lib: str = LIB, rows: int | None = None) -> str:
+    tag = "" if variant is None else f"variant{variant}" + ("" if rows is None else f"_rows{rows}")
+    build_dir = BUILD if variant is None else os.path.join(BUILD, tag)
     extra = () if variant is None else (f"-DFILL_FFT_FORCE_VARIANT={int(variant)}",)
+    if rows is not None:
+        extra = extra + (f"-DFILL_FFT_FORCE_ROWS={int(rows)}",)
     os.makedirs(build_dir, exist_ok=True)
     os.makedirs(os.path.dirname(lib), exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))

@@ -200,6 +200,13 @@ constexpr int fft_variant(bool, int, int) { return FILL_FFT_FORCE_VARIANT; }
 #else
 constexpr int fft_variant(bool f32, int n, int pass) { return tuned_fft_variant(f32, n, pass); }
 #endif
+// Rows per row-pass workgroup relative to the 64 KiB default (1 or 2); the
+// autotuner's candidate builds force it with FILL_FFT_FORCE_ROWS=s.
+#ifdef FILL_FFT_FORCE_ROWS
+constexpr int row_scale(bool, int) { return FILL_FFT_FORCE_ROWS; }
+#else
+constexpr int row_scale(bool f32, int n) { return tuned_row_scale(f32, n); }
+#endif
 template <typename T, int N, int PASS>
 using FFTPlanFor = FFTPlanV<N, fft_variant(sizeof(T) == 4, N, PASS)>;
 
@@ -321,12 +328,13 @@ __device__ __forceinline__ void fft_line(C (&v)[PL::E], int tid, C* lds, const C
 // ---------------------------------------------------------------------------
 
 // Row kernels: ROWS image rows per workgroup (two rows per complex line), the
-// workgroup's LDS held near 64 KiB so two workgroups fit a CU.
+// workgroup's LDS held near 64 KiB (or twice that, by tuning: longer
+// contiguous pieces of the transposed spectrum, fewer workgroups).
 template <typename T, int N> struct RowCfg {
   using PL = FFTPlanFor<T, N, kRowPass>;
   static constexpr int E = PL::E;
   static constexpr int TPL = N / E;
-  static constexpr int RAW = (64 * 1024) / (N * 8);
+  static constexpr int RAW = row_scale(sizeof(T) == 4, N) * (64 * 1024) / (N * 8);
   static constexpr int ROWS = RAW >= 16 ? 16 : RAW >= 8 ? 8 : RAW >= 4 ? 4 : 2;  // power of two
   // consecutive row blocks that share a 128-byte line of the transposed spectrum
   static constexpr int XG0 = 128 / (ROWS * 2 * (int)sizeof(T));
