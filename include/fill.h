@@ -247,7 +247,9 @@ int fill_laplace(fill_plan plan, const double* d_obs, double* x_out, int nkernel
  *              {dx^2 + dy^2 <= w_i^2} contains more than threshold * (pixels
  *              in the disk) observed pixels (the paper uses 0.03).
  *   iters      CG iterations per strip (>= 1; the paper uses 20).
- *   prec       enum fill_precision of the strip solves.
+ *   prec       enum fill_precision of the strip solves (with FILL_PREC_FP32_OP
+ *              the iterations are counted over the FP32 inner solves and
+ *              their FP64 refinement restarts together).
  * Strip i is solved with spectrum P_signal + betas[i] * noise (FILL_ENOTSPD
  * if not positive).  Empty strips are skipped.  Owned by the library.
  */
