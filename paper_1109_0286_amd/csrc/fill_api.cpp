@@ -680,6 +680,11 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   std::vector<uint8_t> m01(npix * np);
   p->n_m.assign(np, 0);
   p->coff.assign(np + 1, 0);
+  // compact vectors are indexed with 32-bit ints in the kernels
+  size_t total = 0;
+  for (size_t i = 0; i < npix * np; ++i) total += mask[i] != 0;
+  if (total > (size_t)INT32_MAX - 1) return fail(FILL_EINVAL, "more than 2^31 masked pixels in one plan");
+  pos.reserve(total);
   for (int b = 0; b < np; ++b) {
     p->coff[b] = (int)pos.size();
     for (int y = 0; y < ny; ++y) {
