@@ -206,6 +206,72 @@ __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop
   return s_coef;
 }
 
+// Twiddle table of plan PL held in registers between its loads and its LDS
+// stores, so that the loads share a round trip with the data loads issued
+// after them (the counter of outstanding loads is in order).
+template <typename PL, typename C, int NT> struct TwPrefetch {
+  static constexpr int TW = tw_elems<PL>();
+  static constexpr int TWP = (TW + NT - 1) / NT;
+  C wv[TWP > 0 ? TWP : 1];
+  __device__ __forceinline__ void load(const C* tw, int t) {
+#pragma unroll
+    for (int u = 0; u < TWP; ++u) {
+      const int i = t + u * NT;
+      if (i < TW) wv[u] = tw[i];
+    }
+  }
+  __device__ __forceinline__ void store(C* twq, int t) const {
+#pragma unroll
+    for (int u = 0; u < TWP; ++u) {
+      const int i = t + u * NT;
+      if (i < TW) twq[i] = wv[u];
+    }
+  }
+};
+
+// The ROWS x NH block of the transposed spectrum that one row block owns
+// (rows y0.., columns 0..NH-1: column kx at Xt[kx*ldx + y0 .. + ROWS-1]) into
+// LDS rows of stride HS.  Every thread holds exactly ROWS*NH/NT loads in
+// flight before any LDS store, instead of one round trip per element.
+// The twiddle table of plan PL is staged into twq in the same batch of loads.
+// Largest divisor of n that is at most m (m >= 1).
+constexpr int divisor_at_most(int n, int m) {
+  for (int c = m < n ? m : n; c > 1; --c)
+    if (n % c == 0) return c;
+  return 1;
+}
+
+// At most MAXB bytes of loads in flight per thread (a budget on the staging
+// registers; more would spill in the register-heavy FP64 kernels).
+template <typename C, typename PL, int ROWS, int NH, int NT, int HS, int MAXB = 128>
+__device__ __forceinline__ void transposed_read(C* lds, const C* Xt, size_t ldx, int y0, int t, C* twq,
+                                                const C* tw) {
+  static_assert((ROWS * NH) % NT == 0, "transposed tiling");
+  constexpr int PER = ROWS * NH / NT;
+  constexpr int CH = divisor_at_most(PER, MAXB / (int)sizeof(C) > 0 ? MAXB / (int)sizeof(C) : 1);
+  // FP32: the twiddle loads join the first batch; FP64: staged before it
+  // (no registers to spare)
+  constexpr bool PRE = sizeof(C) == 8;
+  TwPrefetch<PL, C, NT> twp;
+  if constexpr (PRE) twp.load(tw, t);
+  else tw_stage<PL>(twq, tw, t, NT);
+#pragma unroll
+  for (int ch = 0; ch < PER; ch += CH) {
+    C tv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int o = t + (ch + u) * NT;
+      tv[u] = Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int o = t + (ch + u) * NT;
+      lds[(o % ROWS) * HS + o / ROWS] = tv[u];
+    }
+  }
+  if constexpr (PRE) twp.store(twq, t);
+}
+
 template <int MODE> constexpr bool r2c_is_compact() { return MODE <= R2C_XRUPDATE; }
 template <int MODE> constexpr bool c2r_is_compact() { return MODE <= C2R_RESID; }
 
@@ -246,7 +312,11 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
       for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
       return;
     }
-    tw_stage<PL>(twq, a.tw, t, NT);
+    // FP32: twiddle loads share the data loads' round trip; FP64 has no
+    // registers to spare for them
+    TwPrefetch<PL, C, NT> twp;
+    if constexpr (sizeof(T) == 4) twp.load(a.tw, t);
+    else tw_stage<PL>(twq, a.tw, t, NT);
     const int base = y0 * a.nx;
     if (c1 - c0 == ROWS * N) {
       // Every pixel of these rows is masked (a band): compact element c0 + i
@@ -316,6 +386,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     }
     __syncthreads();
     }
+    if constexpr (sizeof(T) == 4) twp.store(twq, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int x = tid + e * TPL;
@@ -323,7 +394,6 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     }
     __syncthreads();
   } else {
-    tw_stage<PL>(twq, a.tw, t, NT);
     const size_t ra = (size_t)(y0 + 2 * l) * a.nx, rb = ra + a.nx;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -334,6 +404,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
         v[e] = C{(T)white_noise_at(ra + x, a.seed, a.stream), (T)white_noise_at(rb + x, a.seed, a.stream)};
       }
     }
+    tw_stage<PL>(twq, a.tw, t, NT);  // after the row loads: one round trip for both
   }
 
   C* line = lds + l * LE;
@@ -343,7 +414,11 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   __syncthreads();
   // Separate the two packed rows: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i).
   // The real DC and Nyquist bins of a row share column 0: (A_0, A_{N/2}).
-  for (int o = t; o < ROWS * (N / 2); o += NT) {
+  static_assert((ROWS * (N / 2)) % NT == 0, "transposed tiling");
+  constexpr int WU = sizeof(T) == 4 ? ROWS * (N / 2) / NT : 1;  // FP64: registers are short
+#pragma unroll WU
+  for (int u = 0; u < ROWS * (N / 2) / NT; ++u) {
+    const int o = t + u * NT;
     const int kx = o / ROWS, r = o % ROWS;
     const C* ln = lds + (r >> 1) * LE;
     C out;
@@ -396,11 +471,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
       return;
     }
   }
-  tw_stage<PL>(twq, a.tw, t, NT);
-  for (int o = t; o < ROWS * (N / 2); o += NT) {
-    const int kx = o / ROWS, r = o % ROWS;
-    lds[r * HS + kx] = a.Xt[(size_t)kx * ldx + y0 + r];
-  }
+  transposed_read<C, PL, ROWS, N / 2, NT, HS>(lds, a.Xt, ldx, y0, t, twq, a.tw);
   __syncthreads();
   C v[E];
 #pragma unroll
@@ -568,11 +639,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
     ma[e] = a.mask[ra + tid + e * TPL];
     mb[e] = a.mask[rb + tid + e * TPL];
   }
-  tw_stage<PL>(twq, a.tw, t, NT);
-  for (int o = t; o < ROWS * (N / 2); o += NT) {
-    const int kx = o / ROWS, r = o % ROWS;
-    lds[r * HS + kx] = a.Xt[(size_t)kx * ldx + y0 + r];
-  }
+  transposed_read<C, PL, ROWS, N / 2, NT, HS, (sizeof(T) == 8 ? 32 : 128)>(lds, a.Xt, ldx, y0, t, twq, a.tw);
   __syncthreads();
   C v[E];
 #pragma unroll
@@ -602,7 +669,11 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
 #pragma unroll
   for (int e = 0; e < E; ++e) line[lpad<PL>(tid + e * TPL)] = v[e];
   __syncthreads();
-  for (int o = t; o < ROWS * (N / 2); o += NT) {
+  static_assert((ROWS * (N / 2)) % NT == 0, "transposed tiling");
+  constexpr int WU = sizeof(T) == 4 ? ROWS * (N / 2) / NT : 1;  // FP64: registers are short
+#pragma unroll WU
+  for (int u = 0; u < ROWS * (N / 2) / NT; ++u) {
+    const int o = t + u * NT;
     const int kx = o / ROWS, r = o % ROWS;
     const C* ln = lds + (r >> 1) * LE;
     C out;
