@@ -8,11 +8,11 @@ namespace fillk {
 
 constexpr int tuned_fft_variant(bool f32, int n, int pass) {
   switch (n) {
-    case 128: return f32 ? (pass == 0 ? 1 : 1)
-                 : (pass == 0 ? 1 : 1);
-    case 256: return f32 ? (pass == 0 ? 1 : 1)
-                 : (pass == 0 ? 1 : 1);
-    case 512: return f32 ? (pass == 0 ? 1 : 1)
+    case 128: return f32 ? (pass == 0 ? 1 : 0)
+                 : (pass == 0 ? 1 : 0);
+    case 256: return f32 ? (pass == 0 ? 0 : 0)
+                 : (pass == 0 ? 1 : 0);
+    case 512: return f32 ? (pass == 0 ? 1 : 0)
                  : (pass == 0 ? 1 : 1);
     case 1024: return f32 ? (pass == 0 ? 1 : 1)
                  : (pass == 0 ? 1 : 1);
@@ -26,7 +26,7 @@ constexpr int tuned_fft_variant(bool f32, int n, int pass) {
 
 constexpr int tuned_row_scale(bool f32, int n) {
   switch (n) {
-    case 128: return f32 ? 1 : 2;
+    case 128: return f32 ? 2 : 2;
     case 256: return f32 ? 2 : 1;
     case 512: return f32 ? 1 : 1;
     case 1024: return f32 ? 1 : 1;
