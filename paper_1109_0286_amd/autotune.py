@@ -155,10 +155,11 @@ def cmd_apply(path: str) -> None:
     lines += ["    default: return 1;", "  }", "}", "", "}  // namespace fillk", ""]
     open(HEADER, "w").write("\n".join(lines))
     md = ["# FFT plan autotuning (in-solve kernel durations, HIP events)", "",
-          "Commands (R = repository root; `build` and `apply` on the host, `measure` on the GPU):", "", "```",
+          "Commands (R = repository root, OUT = an output directory; `build` and `apply` on the host, `measure` "
+          "on the GPU):", "", "```",
           "python $R/paper_1109_0286_amd/autotune.py build",
-          "python $R/paper_1109_0286_amd/autotune.py measure $R/gpurun_out/tune.json",
-          "python $R/paper_1109_0286_amd/autotune.py apply $R/gpurun_out/tune.json", "```", "",
+          "python $R/paper_1109_0286_amd/autotune.py measure $OUT/tune.json",
+          "python $R/paper_1109_0286_amd/autotune.py apply $OUT/tune.json", "```", "",
           f"Device: {result.get('device')}.  Variants: " +
           "; ".join(f"{v} = {VARIANT_NAMES[v]}" for v in VARIANTS) + "; row scale s = s x 64 KiB of LDS per "
           "row-pass workgroup.", "",

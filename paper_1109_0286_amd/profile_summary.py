@@ -24,10 +24,10 @@ BENCH_ARGS = {
     2048: ("--steps 5 --warmup 1 --no-cpu-baseline --batch 0", "--steps 1 --warmup 0 --no-cpu-baseline --batch 0"),
     4096: ("--workload grid4096 --steps 2 --warmup 1", "--workload grid4096 --steps 1 --warmup 0"),
 }
-TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $R/gpurun_out/p{n}/trace -o trace "
+TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $OUT/p{n}/trace -o trace "
              "--output-format csv -- python $R/bench.py {a}")
 PMC_CMD = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --kernel-include-regex "
-           "\"col_kernel<float|copyBuffer\" -d $R/gpurun_out/p{n}/{d} -o {d} --output-format csv -- "
+           "\"col_kernel<float|copyBuffer\" -d $OUT/p{n}/{d} -o {d} --output-format csv -- "
            "python $R/bench.py {a} --calib-copy")
 CALIB = 256 << 20
 MODES = ("Modes: r2c 0 compact, 1 p = z + beta p, 2 x += alpha p / r -= alpha q, 3 full map, 4 white noise; "
@@ -61,7 +61,8 @@ def main(run: str, n: int) -> None:
     roof = clean["roofline"]
     with open(os.path.join(ROOT, "profiles", f"fill_{n}_kernel_stats.md"), "w") as f:
         f.write(f"# Kernel statistics: {n}x{n} fill, FP64 and FP32-operator paths (rocprofv3)\n\n")
-        f.write("Command (R = repository root):\n\n```\n" + TRACE_CMD.format(n=n, a=ta) + "\n```\n\n")
+        f.write("Command (R = repository root, OUT = an output directory):\n\n```\n" + TRACE_CMD.format(n=n, a=ta) +
+                "\n```\n\n")
         f.write(f"- `col_kernel<float,{n}>` average under rocprofv3 (every launch of the run): {col_rocprof:.2f} us; "
                 f"bench.py without the profiler (HIP events timestamped by each dispatch, timed region of the "
                 f"mixed path): {live:.2f} us.\n")
@@ -98,7 +99,8 @@ def main(run: str, n: int) -> None:
     json.dump(out, open(os.path.join(ROOT, "profiles", f"col_kernel_f32_{n}_traffic.json"), "w"), indent=1)
     with open(os.path.join(ROOT, "profiles", f"col_kernel_f32_{n}_traffic.md"), "w") as f:
         f.write(f"# HBM traffic of col_kernel<float,{n}> ({n}x{n} workload), rocprofv3 counters\n\n")
-        f.write("Commands (R = repository root):\n\n```\n" + "\n".join(out["commands"]) + "\n```\n\n")
+        f.write("Commands (R = repository root, OUT = an output directory):\n\n```\n" + "\n".join(out["commands"]) +
+                "\n```\n\n")
         f.write(f"- FETCH_SIZE median {fk:.1f} KiB per dispatch over {cnt} dispatches; "
                 f"WRITE_SIZE median {wk:.1f} KiB.\n")
         f.write(f"- Calibration: a plain 256 MiB device copy (`__amd_rocclr_copyBuffer`, the run's last three "
