@@ -104,9 +104,10 @@ int fill_supported_size(int n);
  *   prec      enum fill_precision.
  *   stream    hipStream_t to run on (NULL = the null stream).
  *   out       receives the plan; *out is NULL on error.
- * The plan holds the device copies of the mask, the spectral tables 1/P and
- * sqrt(P) in FP64 and FP32, and all workspaces; it is used from one host
- * thread at a time.
+ * The plan holds the device copies of the mask, the spectral tables 1/P,
+ * sqrt(P) and P in FP64 and FP32, and all workspaces; it is used from one
+ * host thread at a time (separate plans on separate streams may run
+ * concurrently).
  */
 int fill_plan_create(int nx, int ny, const uint8_t* mask, const double* Pk, int prec,
                      void* stream, fill_plan* out);

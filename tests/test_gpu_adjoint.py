@@ -117,3 +117,22 @@ def test_batch_adjoint_and_autograd_function(F):
         gth_ref += gth0
         assert rel(dd.grad[i].cpu().numpy(), gy0) < 1e-8, i
     assert rel(th.grad.numpy(), gth_ref) < 1e-8
+
+
+@pytest.mark.parametrize("pc,prec,tol", [(2, 0, 1e-8), (2, 1, 1e-6), (0, 1, 1e-6)])
+def test_adjoint_with_other_preconditioners(F, pc, prec, tol):
+    # the adjoint solve uses the plan's preconditioner (Px C Px or none):
+    # same gradient as the oracle's
+    n = 64
+    lnk, phi, theta, mask, d, wts = setup(n)
+    plan = F.Plan(n, n, mask, np.ones((n, n // 2 + 1)), prec)
+    plan.set_precond(pc)
+    plan.set_bands(lnk, theta)
+    dd = torch.from_numpy(d).cuda()
+    rtol = 1e-12 if prec == 0 else 1e-11
+    x = plan.realize(dd, 9, rtol, allow_noconv=True)
+    g = (2.0 * torch.from_numpy(wts).cuda() * x).contiguous()
+    gd, gth, _ = plan.adjoint(dd, 9, x, g, rtol, allow_noconv=True)
+    _, gy0, _, gth0 = AD.adjoint_gradient(d, mask, theta, phi, 9, wts, 1e-13)
+    assert rel(gth, gth0) < tol
+    assert rel(gd.cpu().numpy(), gy0) < tol
