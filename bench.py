@@ -126,8 +126,18 @@ def cpu_baseline(prob, iters_fp64: int, budget_s: float = 20.0) -> dict:
         n_it += chunk
     per_it = t_it / n_it
     per_solve = t_fixed + per_it * iters_fp64 + 2 * per_it / 3  # + final residual apply
+    # one chunk of the same iterations on one thread
+    workers = OF._WORKERS
+    OF._WORKERS = 1
+    try:
+        t1 = time.perf_counter()
+        O.pcg_split(v, m, prob.P, rtol=1e-300, max_iter=chunk)
+        per_it_1 = (time.perf_counter() - t1) / chunk
+    finally:
+        OF._WORKERS = workers
     return {
         "value": 1.0 / per_solve, "unit": "solves/s", "cores": OF._WORKERS, "kind": "oracle",
+        "ms_per_iteration": per_it * 1e3, "single_thread_ms_per_iteration": per_it_1 * 1e3,
         "sample": (f"2048^2 workload: 1 realization + RHS ({t_fixed:.2f} s) and {n_it} PCG iterations "
                    f"({per_it * 1e3:.0f} ms/iteration, scipy.fft FP64, {OF._WORKERS} threads), "
                    f"extrapolated to the {iters_fp64} iterations the FP64 solve needs"),
