@@ -9,3 +9,4 @@ from . import dense  # noqa: F401
 from . import lanczos  # noqa: F401
 from . import strips  # noqa: F401
 from . import laplace  # noqa: F401
+from . import block_precond  # noqa: F401
