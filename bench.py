@@ -33,9 +33,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 PRECONDS = {"split": 1, "cxx": 2, "none": 0}  # fill_precond: E E (Sec. 2.4 split form), Px C Px, plain CG
+CGS = {"standard": 0, "single": 1}  # fill_cg_variant: Hestenes-Stiefel, single-reduction (Chronopoulos-Gear)
 CALIB_BYTES = 256 << 20  # plain device copy used to scale the rocprofv3 byte counters
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1109_0286_amd", "csrc", f)
                   for f in ("fft_device.hpp", "fft_tuned.hpp", "kernels.hpp")]
+
+
+def configure(plan, args) -> None:
+    """The inner CG of every timed plan: --precond and --cg."""
+    plan.set_precond(PRECONDS[args.precond])
+    plan.set_cg(CGS[args.cg])
 
 
 def kernel_source_hash() -> str:
@@ -153,7 +160,7 @@ def bench_batch_2048(F, prob, args) -> dict:
     d = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(prob.d_obs, (B,) + prob.d_obs.shape))).cuda()
     seeds = list(range(1, B + 1))
     bp = F.BatchPlan(prob.nx, prob.ny, masks, prob.P, F.FILL_PREC_FP32_OP)
-    bp.set_precond(PRECONDS[args.precond])
+    configure(bp, args)
     x = torch.empty_like(d)
     steps = max(1, args.steps // 4)
     for _ in range(max(1, args.warmup // 2)):
@@ -185,7 +192,7 @@ def bench_mixed64(args) -> int:
     for n, ps in sorted(groups.items()):
         plans.append(F.BatchPlan(n, n, np.stack([p.mask for p in ps]), ps[0].P, F.FILL_PREC_FP32_OP,
                                  stream=torch.cuda.Stream()))
-        plans[-1].set_precond(PRECONDS[args.precond])
+        configure(plans[-1], args)
         ds.append(torch.from_numpy(np.stack([p.d_obs for p in ps])).cuda())
         seeds.append([p.seed for p in ps])
     torch.cuda.synchronize()
@@ -208,7 +215,7 @@ def bench_mixed64(args) -> int:
                                   "r~U(2,10), damping n/8, rtol 1e-6; one batched plan per size, 4 streams",
                       "problems_per_size": {str(k): len(v) for k, v in sorted(groups.items())},
                       "iters_inner_max": max(iters), "iters_inner_mean": float(np.mean(iters)),
-                      "preconditioner": args.precond}}
+                      "preconditioner": args.precond, "cg": args.cg}}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -249,13 +256,15 @@ def compare_preconds(F, prob, d, args) -> dict:
     for pname, pc in PRECONDS.items():
         if pname == "none" and prob.meta["band"][1] > 0:
             continue  # thousands of iterations on a band: not a contender
-        for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
-            plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
-            plan.set_precond(pc)
-            dt, st, _, _ = time_solves(F, plan, d, prob.seed, prob.rtol, steps, 1, -1)
-            res[f"{name}_{pname}"] = {"solves_per_s": steps / dt, "iters_inner": st["iters_inner"],
-                                      "iters_outer": st["iters_outer"]}
-            plan.close()
+        for cname, cg in CGS.items():
+            for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
+                plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
+                plan.set_precond(pc)
+                plan.set_cg(cg)
+                dt, st, _, _ = time_solves(F, plan, d, prob.seed, prob.rtol, steps, 1, -1)
+                res[f"{name}_{pname}_{cname}"] = {"solves_per_s": steps / dt, "iters_inner": st["iters_inner"],
+                                                  "iters_outer": st["iters_outer"]}
+                plan.close()
     return res
 
 
@@ -271,18 +280,20 @@ def bench_holes2048(args) -> int:
     res = {}
     for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
         for pname, pc in PRECONDS.items():
-            plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
-            plan.set_precond(pc)
-            dt, st, _, _ = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, -1)
-            key = f"{name}_{pname}"
-            res[key] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
-                        "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
-                        "rel_resid": st["rel_resid"]}
-            if name == "fp64":
-                res[key]["lanczos"] = lanczos_report(plan, d, prob.seed, prob.rtol)
-            print(f"# {key}: {res[key]['solves_per_s']:.2f} solves/s, {st['iters_inner']} iterations",
-                  file=sys.stderr, flush=True)
-            plan.close()
+            for cname, cg in CGS.items():
+                plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
+                plan.set_precond(pc)
+                plan.set_cg(cg)
+                dt, st, _, _ = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, -1)
+                key = f"{name}_{pname}_{cname}"
+                res[key] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
+                            "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
+                            "rel_resid": st["rel_resid"]}
+                if name == "fp64":
+                    res[key]["lanczos"] = lanczos_report(plan, d, prob.seed, prob.rtol)
+                print(f"# {key}: {res[key]['solves_per_s']:.2f} solves/s, {st['iters_inner']} iterations",
+                      file=sys.stderr, flush=True)
+                plan.close()
     best = max((k for k in res if k.startswith("mixed")), key=lambda k: res[k]["solves_per_s"])
     out = {"metric": "PCG fill-in solves/s at 2048^2, point-source mask (rel resid 1e-8)",
            "value": res[best]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -336,6 +347,7 @@ def bench_hermiticity(args) -> int:
         d = torch.from_numpy(prob.d_obs).cuda()
         plan = F.Plan(n, n, prob.mask, prob.P, F.FILL_PREC_FP64)
         plan.set_precond(F.FILL_PRECOND_NONE)
+        plan.set_cg(F.FILL_CG_STANDARD)  # the study is defined on the standard recurrence
         plan.set_lanczos(cap)
         plan.set_max_iter(cap)
         for eps in eps_list:
@@ -403,7 +415,7 @@ def bench_strips2048(args) -> int:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     exact = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, F.FILL_PREC_FP32_OP)
-    exact.set_precond(PRECONDS[args.precond])
+    configure(exact, args)
     xe = torch.empty_like(d)
     exact.mean(d, prob.rtol, out=xe)
     torch.cuda.synchronize()
@@ -449,7 +461,7 @@ def bench_strips2048(args) -> int:
                                   "(2000,100),(400,35),(40,15),(1,7), threshold 0.03, 20 iterations each",
                       "n_masked": prob.n_masked},
            "exact_ml_fill": {"fills_per_s": 1.0 / dte, "ms": dte * 1e3, "rtol": prob.rtol,
-                             "preconditioner": args.precond, "iters": exact.stats()["iters_inner"]},
+                             "preconditioner": args.precond, "cg": args.cg, "iters": exact.stats()["iters_inner"]},
            "masked_rel_l2_vs_exact": err, "strips": kappa, "laplace_then_strips": lap_res}
     print(json.dumps(out), flush=True)
     return 0
@@ -467,7 +479,7 @@ def bench_grid4096(args) -> int:
     res, plans = {}, {}
     for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
         plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
-        plan.set_precond(PRECONDS[args.precond])
+        configure(plan, args)
         dt, st, col_ms, _ = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, F.FILL_K_COL)
         res[name] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
                      "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
@@ -484,7 +496,8 @@ def bench_grid4096(args) -> int:
            "ms_per_step": res["mixed"]["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement", "data": "synthetic",
            "config": {"workload": "4096x4096 torus, 30% band + 500 holes r~U(2,16), damping 512, floor 1e-7, "
-                                  "rtol 1e-8", "n_masked": prob.n_masked, "preconditioner": args.precond},
+                                  "rtol 1e-8", "n_masked": prob.n_masked, "preconditioner": args.precond,
+                      "cg": args.cg},
            "paths": res,
            "roofline": {"bound": "hbm", "kernel": "col_kernel<float,4096>", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -511,7 +524,7 @@ def bench_grad16(args) -> int:
     w = torch.from_numpy(np.random.default_rng(7).uniform(0, 1, (nprob, n, n))).cuda()
     seeds = list(range(1, nprob + 1))
     bp = F.BatchPlan(n, n, masks, P, F.FILL_PREC_FP32_OP)
-    bp.set_precond(PRECONDS[args.precond])
+    configure(bp, args)
     FillFn = F.autograd_fill()
     th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
 
@@ -537,7 +550,7 @@ def bench_grad16(args) -> int:
            "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement", "data": "synthetic",
            "config": {"workload": "16 x 1024^2, 10% band + 100 holes r~U(2,10), 50 log-spaced band powers, "
                                   "loss sum(w x^2) w~U(0,1), forward rtol 1e-8, adjoint rtol 1e-10",
-                      "preconditioner": args.precond}}
+                      "preconditioner": args.precond, "cg": args.cg}}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -563,6 +576,9 @@ def main() -> int:
     ap.add_argument("--precond", default="cxx", choices=list(PRECONDS),
                     help="inner-CG preconditioner (every workload): cxx (Px C Px, default), split (E E, the "
                          "paper's split form) or none; the 2048^2 line also times the others")
+    ap.add_argument("--cg", default="standard", choices=list(CGS),
+                    help="inner-CG recurrence (every workload): standard (Hestenes-Stiefel) or single "
+                         "(single-reduction, one launch fewer per iteration); the 2048^2 line times both")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with three plain 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -596,9 +612,8 @@ def bench_grid2048(args) -> int:
     d = torch.from_numpy(prob.d_obs).cuda()
     plan32 = F.Plan(nx, ny, prob.mask, prob.P, F.FILL_PREC_FP32_OP)
     plan64 = F.Plan(nx, ny, prob.mask, prob.P, F.FILL_PREC_FP64)
-    pc = PRECONDS[args.precond]
-    plan32.set_precond(pc)
-    plan64.set_precond(pc)
+    configure(plan32, args)
+    configure(plan64, args)
     n_m = prob.n_masked
 
     dt64, st64, col64_ms, _ = time_solves(F, plan64, d, seed, rtol, args.steps, args.warmup, F.FILL_K_COL)
@@ -631,7 +646,7 @@ def bench_grid2048(args) -> int:
         "data": "synthetic",
         "config": {"workload": "2048x2048 torus, damped power law k0^2=4 damping 256 floor 1e-7, "
                                "10% band + 200 holes r~U(2,12), rtol 1e-8, 1 realization per step",
-                   "preconditioner": args.precond,
+                   "preconditioner": args.precond, "cg": args.cg,
                    "n_masked": n_m, "iters_inner": st32["iters_inner"], "iters_outer": st32["iters_outer"],
                    "rel_resid": st32["rel_resid"]},
         "fp64_path": {"value": args.steps / dt64, "unit": "solves/s", "ms_per_step": dt64 / args.steps * 1e3,

@@ -70,6 +70,12 @@ enum fill_precond {
   FILL_PRECOND_CXX = 2     /* M^-1 = Px C Px */
 };
 
+/* Recurrences of the inner CG (fill_plan_set_cg). */
+enum fill_cg_variant {
+  FILL_CG_STANDARD = 0,         /* Hestenes-Stiefel: two reduction points per iteration (default) */
+  FILL_CG_SINGLE_REDUCTION = 1  /* Chronopoulos-Gear: one reduction point per iteration */
+};
+
 /* Operators on full maps for fill_apply (Sec. 2.4 notation). */
 enum fill_op {
   FILL_OP_CINV = 0,   /* out = C^-1 in */
@@ -158,6 +164,25 @@ int fill_plan_set_inner_tol(fill_plan plan, double tol);
  *                       on wide cuts).
  */
 int fill_plan_set_precond(fill_plan plan, int mode);
+
+/*
+ * Recurrence of the inner CG (enum fill_cg_variant), for later solves.  Both
+ * compute the conjugate-gradient iterates of Sec. 2.4 (the same alpha_j and
+ * beta_j in exact arithmetic) and reach the same solution to rtol.
+ *   FILL_CG_STANDARD          alpha = r.z / p.Ap, then beta = r'.z' / r.z: two
+ *                             reduction points, so the operator apply and the
+ *                             preconditioner apply are separate pass chains.
+ *   FILL_CG_SINGLE_REDUCTION  z = M^-1 r and w = A z are formed back to back
+ *                             and r.z, r.r, w.z are summed together; alpha and
+ *                             beta follow from them (p.Ap = w.z - beta r.z /
+ *                             alpha_prev), with s = A p carried by recurrence.
+ *                             The preconditioner's last row pass and the
+ *                             operator's first are fused: one launch fewer per
+ *                             iteration with every preconditioner.
+ * The non-Hermitian study (fill_plan_set_skew) is defined on the standard
+ * recurrence.  Returns FILL_EINVAL for an unknown variant.
+ */
+int fill_plan_set_cg(fill_plan plan, int variant);
 
 /*
  * Lanczos data of the solves (Sec. 6.4): record the CG step lengths alpha_j

@@ -64,8 +64,9 @@ template <typename T> struct Vecs {
   T* r = nullptr;
   T* z = nullptr;
   T* p = nullptr;
-  T* q = nullptr;
+  T* q = nullptr;  // A p (s of single-reduction CG)
   T* t = nullptr;
+  T* w = nullptr;  // A z (single-reduction CG)
 };
 
 // Per-call parameters, mirrored host (pinned) -> device in one copy.
@@ -91,17 +92,19 @@ struct fill_plan_s {
   int max_iter = 20000;
   double inner_tol32 = 1e-4;
   int precond = FILL_PRECOND_SPLIT;
+  int cg_variant = FILL_CG_STANDARD;
   double skew = 0.0;  // non-Hermitian study: eps of the perturbed A inside the inner CG
   // CG coefficient record of the first inner solve of the last solve (Lanczos data)
   int hist_cap = 0;
   double* hist = nullptr;
   std::vector<int> hist_n;
   // the 16-iteration inner-CG chunk as a HIP graph, captured on first use per
-  // [FP32?][preconditioner][coefficient record] and replayed by every solve
+  // [FP32?][preconditioner + 3 * CG variant][coefficient record] and replayed
+  // by every solve
   int use_graph = 1;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph[2][3][2] = {};
-  hipGraphExec_t graph_exec[2][3][2] = {};
+  hipGraph_t graph[2][6][2] = {};
+  hipGraphExec_t graph_exec[2][6][2] = {};
   int nblk64 = 0, nblk32 = 0;
 
   uint8_t* mask = nullptr;
@@ -128,6 +131,7 @@ struct fill_plan_s {
   double* part0 = nullptr;
   double* part1 = nullptr;
   double* part2 = nullptr;
+  double* part3 = nullptr;
   double* dsum = nullptr;
   CGScalars* sc = nullptr;
   void* par_dev = nullptr;
@@ -304,7 +308,7 @@ int apply_EE(fill_plan p, int rm, const RowArgs<T>& ai, const RowArgs<T>& amid, 
   FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(rm, ai, p->stream, a, b); }));
   const ColArgs<T> ca = col_base<T>(p, ai.nprob, TypeSel<T>::Dhalf(p), sc);
   FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
-  FILL_TRY(timed_launch<T>(p, FILL_K_PROJ, [&](hipEvent_t a, hipEvent_t b) { return launch_proj<T>(amid, p->stream, a, b); }));
+  FILL_TRY(timed_launch<T>(p, FILL_K_PROJ, [&](hipEvent_t a, hipEvent_t b) { return launch_proj<T>(false, amid, p->stream, a, b); }));
   FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
   FILL_TRY(timed_launch<T>(p, FILL_K_C2R, [&](hipEvent_t a, hipEvent_t b) { return launch_c2r<T>(C2R_DOT2, ao, p->stream, a, b); }));
   return FILL_OK;
@@ -360,7 +364,7 @@ int chunk_graph(fill_plan p, int f32, int mode, int rec, F&& chunk, hipGraphExec
 // Drop captured chunk graphs (all, or only those that record coefficients).
 void drop_graphs(fill_plan p, bool record_only) {
   for (int a = 0; a < 2; ++a)
-    for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < 6; ++m)
       for (int r = record_only ? 1 : 0; r < 2; ++r) {
         if (p->graph_exec[a][m][r]) (void)hipGraphExecDestroy(p->graph_exec[a][m][r]);
         if (p->graph[a][m][r]) (void)hipGraphDestroy(p->graph[a][m][r]);
@@ -369,11 +373,142 @@ void drop_graphs(fill_plan p, bool record_only) {
       }
 }
 
+// Run inner-CG chunks (graph replays, or direct launches) until every problem
+// is done; per-problem iteration counts and statuses.
+template <typename F>
+int run_chunks(fill_plan p, hipGraphExec_t exec, F&& chunk, std::vector<int>& iters, std::vector<int>& status) {
+  const int np = p->nprob;
+  for (;;) {
+    if (exec) HIP_TRY(hipGraphLaunch(exec, p->stream));
+    else FILL_TRY(chunk());
+    HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    bool all = true;
+    for (int b = 0; b < np; ++b) all = all && p->h_sc[b].done;
+    if (all) break;
+  }
+  iters.resize(np);
+  status.resize(np);
+  for (int b = 0; b < np; ++b) {
+    iters[b] = p->h_sc[b].iter;
+    status[b] = p->h_sc[b].status;
+  }
+  return FILL_OK;
+}
+
+// Inner CG in single-reduction form (Chronopoulos and Gear), same contract as
+// inner_pcg.  Iteration j: one r2c pass takes the scalar step from the
+// partials of r.z, r.r and w.z, applies p = z + beta p, s = w + beta s,
+// x += alpha p, r -= alpha s and transforms the new r; z = M^-1 r and w = A z
+// follow with no scalar in between, so the preconditioner's closing row pass
+// and the operator's opening one are a single projection pass:
+//   Px C Px: r2c -> col(P) -> proj(z; r.z, r.r) -> col(1/P) -> c2r(w; w.z)
+//   E E:     r2c -> col(sqrt P) -> proj -> col(sqrt P) -> proj(z; r.z, r.r) -> col(1/P) -> c2r(w; w.z)
+//   none:    r2c (with r.r of the new r) -> col(1/P) -> c2r(w; w.r)
+// (one launch fewer per iteration than the standard form).
+template <typename T>
+int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bool record) {
+  Vecs<T>& v = TypeSel<T>::vecs(p);
+  const int nb = TypeSel<T>::nblk(p), np = p->nprob;
+  const int mode = p->precond;
+  const bool pre = mode != FILL_PRECOND_NONE;
+  double* hist = record && p->hist_cap > 0 ? p->hist : nullptr;
+  const size_t vb = (size_t)std::max(p->n_m_total, 1) * sizeof(T);
+  HIP_TRY(hipMemsetAsync(v.x, 0, vb, p->stream));
+  HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
+  HIP_TRY(hipMemsetAsync(v.q, 0, vb, p->stream));
+  // without a preconditioner the r.r partials of the r2c pass alternate
+  // between two buffers by iteration parity
+  double* const rrb[2] = {p->part0, p->part3};
+
+  // z = M^-1 r and w = A z from the transformed r (every kernel returns at
+  // once for a finished problem when sc is set)
+  auto tail = [&](CGScalars* sc) -> int {
+    const ColArgs<T> cm = col_base<T>(p, np, mode == FILL_PRECOND_SPLIT ? TypeSel<T>::Dhalf(p) : TypeSel<T>::Dfull(p), sc);
+    ColArgs<T> ca = col_base<T>(p, np, TypeSel<T>::Dinv(p), sc);
+    ca.skew = p->skew;
+    if (pre) {
+      FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, cm, p->stream, a, b); }));
+      if (mode == FILL_PRECOND_SPLIT) {
+        RowArgs<T> mid = row_base<T>(p, np);
+        mid.sc = sc;
+        FILL_TRY(timed_launch<T>(p, FILL_K_PROJ, [&](hipEvent_t a, hipEvent_t b) { return launch_proj<T>(false, mid, p->stream, a, b); }));
+        FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, cm, p->stream, a, b); }));
+      }
+      RowArgs<T> zp = row_base<T>(p, np);
+      zp.sc = sc;
+      zp.v0 = v.z;
+      zp.v1 = v.r;
+      zp.part0 = p->part0;
+      zp.part1 = p->part1;
+      FILL_TRY(timed_launch<T>(p, FILL_K_PROJ, [&](hipEvent_t a, hipEvent_t b) { return launch_proj<T>(true, zp, p->stream, a, b); }));
+    }
+    FILL_TRY(timed_launch<T>(p, FILL_K_COL, [&](hipEvent_t a, hipEvent_t b) { return launch_col<T>(p->ny, ca, p->stream, a, b); }));
+    RowArgs<T> wo = row_base<T>(p, np);
+    wo.sc = sc;
+    wo.v0 = v.w;
+    wo.v1 = pre ? v.z : v.r;
+    wo.part0 = p->part2;
+    FILL_TRY(timed_launch<T>(p, FILL_K_C2R, [&](hipEvent_t a, hipEvent_t b) { return launch_c2r<T>(C2R_DOT2, wo, p->stream, a, b); }));
+    return FILL_OK;
+  };
+
+  // z_0, w_0 and the partials of the first scalar step
+  if (!pre) {
+    RowArgs<T> a0 = row_base<T>(p, np);
+    a0.v1 = v.r;
+    a0.part0 = rrb[0];
+    a0.part1 = p->part1;
+    HIP_TRY(launch_xr<T>(true, a0, nb, p->stream));
+  }
+  {
+    RowArgs<T> ai = row_base<T>(p, np);
+    ai.v0 = v.r;
+    FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(R2C_COMPACT, ai, p->stream, a, b); }));
+    FILL_TRY(tail(nullptr));
+  }
+  HIP_TRY(launch_cg_init(p->sc, p->dp.tol2, p->dp.cap, p->dp.active, np, p->stream));
+
+  RowArgs<T> up[2];
+  for (int par = 0; par < 2; ++par) {
+    RowArgs<T>& u = up[par];
+    u = row_base<T>(p, np);
+    u.v0 = v.x;
+    u.v1 = v.r;
+    u.v2 = v.p;
+    u.v3 = v.q;
+    u.v4 = pre ? v.z : nullptr;
+    u.v5 = v.w;
+    u.sc = p->sc;
+    u.nred = nb;
+    u.parity = par;
+    u.red0 = pre ? p->part0 : rrb[par];
+    u.red1 = pre ? p->part1 : rrb[par];
+    u.red2 = p->part2;
+    u.part0 = pre ? nullptr : rrb[par ^ 1];
+    u.hist = hist;
+    u.hist_cap = p->hist_cap;
+  }
+  auto chunk = [&]() -> int {
+    for (int k = 0; k < kChunk; ++k) {
+      const RowArgs<T>& u = up[k & 1];
+      FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(R2C_CG1UPDATE, u, p->stream, a, b); }));
+      FILL_TRY(tail(p->sc));
+    }
+    return FILL_OK;
+  };
+  hipGraphExec_t exec = nullptr;
+  if (p->use_graph && p->timed_kernel < 0)
+    FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode + 3, hist != nullptr, chunk, &exec));
+  return run_chunks(p, exec, chunk, iters, status);
+}
+
 // Inner preconditioned CG for every active problem on A d = r (r in v.r with
 // ||r|| = 1, d in v.x); tolerances, caps and the active set are in the device
 // parameters.  Returns per-problem iteration counts and statuses.
 template <typename T>
 int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bool record) {
+  if (p->cg_variant == FILL_CG_SINGLE_REDUCTION) return inner_pcg_cg1<T>(p, iters, status, record);
   Vecs<T>& v = TypeSel<T>::vecs(p);
   const int nb = TypeSel<T>::nblk(p), np = p->nprob;
   const T* Dinv = TypeSel<T>::Dinv(p);
@@ -463,23 +598,7 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   // timed launches carry their own events).
   hipGraphExec_t exec = nullptr;
   if (p->use_graph && p->timed_kernel < 0) FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode, hist != nullptr, chunk, &exec));
-
-  for (;;) {
-    if (exec) HIP_TRY(hipGraphLaunch(exec, p->stream));
-    else FILL_TRY(chunk());
-    HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    bool all = true;
-    for (int b = 0; b < np; ++b) all = all && p->h_sc[b].done;
-    if (all) break;
-  }
-  iters.resize(np);
-  status.resize(np);
-  for (int b = 0; b < np; ++b) {
-    iters[b] = p->h_sc[b].iter;
-    status[b] = p->h_sc[b].status;
-  }
-  return FILL_OK;
+  return run_chunks(p, exec, chunk, iters, status);
 }
 
 // Solve A u = v for every problem (v, u compact FP64), each to true relative residual rtol.
@@ -728,11 +847,14 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   FILL_TRY(dalloc(p, &p->b, nm));
   FILL_TRY(dalloc(p, &p->u, nm));
   FILL_TRY(dalloc(p, &p->res, nm));
-  for (double** q : {&p->v64.x, &p->v64.r, &p->v64.z, &p->v64.p, &p->v64.q, &p->v64.t}) FILL_TRY(dalloc(p, q, nm));
-  for (float** q : {&p->v32.x, &p->v32.r, &p->v32.z, &p->v32.p, &p->v32.q, &p->v32.t}) FILL_TRY(dalloc(p, q, nm));
+  for (double** q : {&p->v64.x, &p->v64.r, &p->v64.z, &p->v64.p, &p->v64.q, &p->v64.t, &p->v64.w})
+    FILL_TRY(dalloc(p, q, nm));
+  for (float** q : {&p->v32.x, &p->v32.r, &p->v32.z, &p->v32.p, &p->v32.q, &p->v32.t, &p->v32.w})
+    FILL_TRY(dalloc(p, q, nm));
   FILL_TRY(dalloc(p, &p->part0, (size_t)ny * np));
   FILL_TRY(dalloc(p, &p->part1, (size_t)ny * np));
   FILL_TRY(dalloc(p, &p->part2, (size_t)ny * np));
+  FILL_TRY(dalloc(p, &p->part3, (size_t)ny * np));
   FILL_TRY(dalloc(p, &p->dsum, np));
   FILL_TRY(dalloc(p, &p->sc, np));
   // per-call parameter block: same layout on host (pinned) and device
@@ -873,7 +995,7 @@ int time_kernel(fill_plan p, int kernel, int reps, double* avg_ms) {
     if (e == hipSuccess && (kernel == FILL_K_COL || kernel == FILL_K_APPLY)) e = launch_col<T>(p->ny, ca, p->stream);
     if (e == hipSuccess && (kernel == FILL_K_C2R || kernel == FILL_K_APPLY))
       e = launch_c2r<T>(C2R_COMPACT, ao, p->stream);
-    if (e == hipSuccess && kernel == FILL_K_PROJ) e = launch_proj<T>(am, p->stream);
+    if (e == hipSuccess && kernel == FILL_K_PROJ) e = launch_proj<T>(false, am, p->stream);
     return e;
   };
   HIP_TRY(launch());  // warm-up
@@ -1195,6 +1317,14 @@ int fill_plan_set_inner_tol(fill_plan p, double tol) {
 int fill_plan_set_precond(fill_plan p, int mode) {
   if (!p || mode < FILL_PRECOND_NONE || mode > FILL_PRECOND_CXX) return fail(FILL_EINVAL, "unknown preconditioner");
   p->precond = mode;
+  return FILL_OK;
+}
+
+int fill_plan_set_cg(fill_plan p, int variant) {
+  g_last_error.clear();
+  if (!p || (variant != FILL_CG_STANDARD && variant != FILL_CG_SINGLE_REDUCTION))
+    return fail(FILL_EINVAL, "unknown CG variant");
+  p->cg_variant = variant;
   return FILL_OK;
 }
 

@@ -29,6 +29,8 @@ __global__ void k_cg_init(CGScalars* sc, const double* tol2, const int* cap, con
   s.rho[1] = 1.0;
   s.alpha = 0.0;
   s.beta = 0.0;
+  s.alph[0] = __builtin_huge_val();  // single-reduction CG: the first alpha is rho / mu
+  s.alph[1] = __builtin_huge_val();
   s.rr = 0.0;
   s.tol2 = tol2[b];
   s.done = active[b] ? 0 : 1;

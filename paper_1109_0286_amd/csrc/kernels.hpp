@@ -29,6 +29,7 @@ struct CGScalars {
   double rho[2];  // r.z
   double alpha;   // rho / (p.q)
   double beta;    // rho_new / rho_old
+  double alph[2]; // single-reduction CG: alpha by iteration parity, as rho
   double rr;      // r.r of the recursive residual
   double tol2;    // stop when rr <= tol2
   int done;       // set when converged, failed or capped: every kernel then returns at once
@@ -44,7 +45,11 @@ enum R2CMode {
   R2C_PUPDATE = 1,   // p = z + beta p   (v0 = z, v1 = p), input p
   R2C_XRUPDATE = 2,  // x += alpha p, r -= alpha q (v0 = x, v1 = r, v2 = p, v3 = q), input r
   R2C_FULL = 3,      // input full map full_in (double)
-  R2C_NOISE = 4      // input white noise of (seed, stream)
+  R2C_NOISE = 4,     // input white noise of (seed, stream)
+  // single-reduction CG step: p = z + beta p, s = w + beta s, x += alpha p,
+  // r -= alpha s (v0 = x, v1 = r, v2 = p, v3 = s, v4 = z or null for z = r,
+  // v5 = w), input r; with part0, the r.r partials of the new r
+  R2C_CG1UPDATE = 5
 };
 
 enum C2RMode {
@@ -77,12 +82,15 @@ template <typename T> struct RowArgs {
   T* v1;
   T* v2;
   T* v3;
+  T* v4;
+  T* v5;
   T scale;
   CGScalars* sc;
   double* part0;
   double* part1;
   const double* red0;  // partial sums of the previous row pass (CG scalar inputs)
   const double* red1;
+  const double* red2;
   int nred;
   int parity;          // iteration parity (selects the rho buffer)
   double* hist;        // CG coefficient record (alpha_j at 2j, beta_j at 2j+1), or null
@@ -116,12 +124,15 @@ template <typename T> __device__ __forceinline__ RowArgs<T> bind_problem(RowArgs
   if (a.v1) a.v1 += coff;
   if (a.v2) a.v2 += coff;
   if (a.v3) a.v3 += coff;
+  if (a.v4) a.v4 += coff;
+  if (a.v5) a.v5 += coff;
   a.Xt += (size_t)b * a.xt_stride;
   if (a.sc) a.sc += b;
   if (a.part0) a.part0 += (size_t)b * a.part_stride;
   if (a.part1) a.part1 += (size_t)b * a.part_stride;
   if (a.red0) a.red0 += (size_t)b * a.part_stride;
   if (a.red1) a.red1 += (size_t)b * a.part_stride;
+  if (a.red2) a.red2 += (size_t)b * a.part_stride;
   if (a.hist) a.hist += (size_t)b * 2 * a.hist_cap;
   if (a.mask) a.mask += (size_t)b * a.pix_stride;
   if (a.full_in) a.full_in += (size_t)b * a.pix_stride;
@@ -206,6 +217,65 @@ __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop
   return s_coef;
 }
 
+// The scalar step of single-reduction CG (Chronopoulos and Gear): one pass of
+// partial sums per iteration gives rho = r.z (red0), r.r (red1) and
+// mu = w.z (red2), w = A z.  With p = z + beta p_{j-1}, A p_{j-1} =
+// (r_{j-1} - r_j) / alpha_{j-1} and z.r_{j-1} = 0, p.Ap = mu - beta rho / alpha_{j-1}:
+//   beta = rho / rho_{j-1},  alpha = rho / (mu - beta rho / alpha_{j-1}),
+// the coefficients of the standard recurrence in exact arithmetic.  The first
+// step sees rho_{-1} = 1, alpha_{-1} = inf (so alpha = rho / mu) and p = s = 0.
+// Stops as the standard step does (rr <= tol2, the cap, rho or p.Ap not > 0);
+// workgroup 0 persists rho and alpha by parity, the record and the count.
+template <int NT, typename T>
+__device__ __forceinline__ void cg1_scalar_step(const RowArgs<T>& a, bool* stop, double* beta, double* alpha) {
+  __shared__ double s_ab[2];
+  __shared__ int s_stop;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, unused = 0.0;
+  for (int i = threadIdx.x; i < a.nred; i += NT) {
+    s0 += a.red0[i];
+    s1 += a.red1[i];
+    s2 += a.red2[i];
+  }
+  block_sum2<NT>(s0, s1);
+  __syncthreads();
+  block_sum2<NT>(s2, unused);
+  if (threadIdx.x == 0) {
+    CGScalars* sc = a.sc;
+    const double rz = s0, rr = s1, mu = s2;
+    int st = 0, stat = 0;
+    const double b = rz / sc->rho[a.parity];
+    const double pap = mu - b * rz / sc->alph[a.parity];
+    if (rr <= sc->tol2) st = 1;
+    else if (sc->cap) { st = 1; stat = -4; }
+    else if (!(rz > 0.0) || !(pap > 0.0)) { st = 1; stat = -6; }
+    const double al = rz / pap;
+    if (blockIdx.x == 0) {
+      sc->rr = rr;
+      if (st) {
+        sc->status = stat;
+        sc->done = 1;
+      } else {
+        const int j = sc->iter;
+        sc->rho[a.parity ^ 1] = rz;
+        sc->alph[a.parity ^ 1] = al;
+        sc->beta = b;
+        sc->alpha = al;
+        if (a.hist && j < a.hist_cap) a.hist[2 * j] = al;
+        if (a.hist && j >= 1 && j - 1 < a.hist_cap) a.hist[2 * (j - 1) + 1] = b;  // beta_{j-1} forms p_j
+        sc->iter = j + 1;
+        if (j + 1 >= sc->max_iter) sc->cap = 1;
+      }
+    }
+    s_ab[0] = b;
+    s_ab[1] = al;
+    s_stop = st;
+  }
+  __syncthreads();
+  *stop = s_stop != 0;
+  *beta = s_ab[0];
+  *alpha = s_ab[1];
+}
+
 // Twiddle table of plan PL held in registers between its loads and its LDS
 // stores, so that the loads share a round trip with the data loads issued
 // after them (the counter of outstanding loads is in order).
@@ -272,7 +342,7 @@ __device__ __forceinline__ void transposed_read(C* lds, const C* Xt, size_t ldx,
   if constexpr (PRE) twp.store(twq, t);
 }
 
-template <int MODE> constexpr bool r2c_is_compact() { return MODE <= R2C_XRUPDATE; }
+template <int MODE> constexpr bool r2c_is_compact() { return MODE <= R2C_XRUPDATE || MODE == R2C_CG1UPDATE; }
 template <int MODE> constexpr bool c2r_is_compact() { return MODE <= C2R_RESID; }
 
 // ---------------------------------------------------------------------------
@@ -300,16 +370,26 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   const size_t ldx = (size_t)a.ldx;
   C v[E];
 
+  constexpr bool CG1 = MODE == R2C_CG1UPDATE;
+  double acc = 0.0;  // CG1: r.r of the new r
   if constexpr (r2c_is_compact<MODE>()) {
-    T coef = T(0);
+    T coef = T(0), coef2 = T(0);  // beta (PUPDATE, CG1) or alpha (XRUPDATE); CG1: alpha
     if constexpr (MODE == R2C_PUPDATE || MODE == R2C_XRUPDATE) {
       bool stop = false;
       coef = (T)cg_scalar_step<MODE, NT>(a, &stop);
       if (stop) return;
+    } else if constexpr (CG1) {
+      bool stop = false;
+      double b = 0.0, al = 0.0;
+      cg1_scalar_step<NT>(a, &stop, &b, &al);
+      if (stop) return;
+      coef = (T)b;
+      coef2 = (T)al;
     }
     const int c0 = a.row_off[y0], c1 = a.row_off[y0 + ROWS];
     if (c0 == c1) {  // no masked pixel in these rows: the spectrum is zero
       for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
+      if (CG1 && t == 0 && a.part0) a.part0[blk] = 0.0;
       return;
     }
     // FP32: twiddle loads share the data loads' round trip; FP64 has no
@@ -321,11 +401,12 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     if (c1 - c0 == ROWS * N) {
       // Every pixel of these rows is masked (a band): compact element c0 + i
       // is pixel i of the block, so no index loads and no zero fill.
-      constexpr int PER = ROWS * N / NT, FB = sizeof(T) == 4 ? 16 : 8;
+      constexpr int PER = ROWS * N / NT;
+      constexpr int FB = CG1 ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8);
       static_assert(PER % FB == 0, "chunking");
 #pragma unroll 1
       for (int ch = 0; ch < PER; ch += FB) {
-        T val[FB], xv[FB];
+        T val[FB], xv[FB], pv[FB], sv[FB];
 #pragma unroll
         for (int u = 0; u < FB; ++u) {
           const int c = c0 + t + (ch + u) * NT;
@@ -333,6 +414,12 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
             val[u] = a.v0[c];
           } else if constexpr (MODE == R2C_PUPDATE) {
             val[u] = a.v0[c] + coef * a.v1[c];
+          } else if constexpr (CG1) {
+            const T r = a.v1[c];
+            pv[u] = (a.v4 ? a.v4[c] : r) + coef * a.v2[c];
+            sv[u] = a.v5[c] + coef * a.v3[c];
+            xv[u] = a.v0[c] + coef2 * pv[u];
+            val[u] = r - coef2 * sv[u];
           } else {
             val[u] = a.v1[c] - coef * a.v3[c];
             xv[u] = a.v0[c] + coef * a.v2[c];
@@ -342,9 +429,14 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
         for (int u = 0; u < FB; ++u) {
           const int i = t + (ch + u) * NT, c = c0 + i;
           if constexpr (MODE == R2C_PUPDATE) a.v1[c] = val[u];
-          if constexpr (MODE == R2C_XRUPDATE) {
+          if constexpr (MODE == R2C_XRUPDATE || CG1) {
             a.v1[c] = val[u];
             a.v0[c] = xv[u];
+          }
+          if constexpr (CG1) {
+            a.v2[c] = pv[u];
+            a.v3[c] = sv[u];
+            acc += (double)val[u] * (double)val[u];
           }
           ldr[i] = val[u];
         }
@@ -353,11 +445,12 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     } else {
     for (int i = t; i < ROWS * N; i += NT) ldr[i] = T(0);
     __syncthreads();
-    for (int cb = c0 + t; cb < c1; cb += NT * kBatch) {
-      int pp[kBatch];
-      T val[kBatch], xv[kBatch];
+    constexpr int KB = CG1 ? 4 : kBatch;
+    for (int cb = c0 + t; cb < c1; cb += NT * KB) {
+      int pp[KB];
+      T val[KB], xv[KB], pv[KB], sv[KB];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
+      for (int u = 0; u < KB; ++u) {
         const int c = cb + u * NT;
         if (c < c1) {
           pp[u] = a.pos[c];
@@ -365,6 +458,12 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
             val[u] = a.v0[c];
           } else if constexpr (MODE == R2C_PUPDATE) {
             val[u] = a.v0[c] + coef * a.v1[c];
+          } else if constexpr (CG1) {
+            const T r = a.v1[c];
+            pv[u] = (a.v4 ? a.v4[c] : r) + coef * a.v2[c];
+            sv[u] = a.v5[c] + coef * a.v3[c];
+            xv[u] = a.v0[c] + coef2 * pv[u];
+            val[u] = r - coef2 * sv[u];
           } else {
             val[u] = a.v1[c] - coef * a.v3[c];
             xv[u] = a.v0[c] + coef * a.v2[c];
@@ -372,13 +471,18 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
         }
       }
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
+      for (int u = 0; u < KB; ++u) {
         const int c = cb + u * NT;
         if (c < c1) {
           if constexpr (MODE == R2C_PUPDATE) a.v1[c] = val[u];
-          if constexpr (MODE == R2C_XRUPDATE) {
+          if constexpr (MODE == R2C_XRUPDATE || CG1) {
             a.v1[c] = val[u];
             a.v0[c] = xv[u];
+          }
+          if constexpr (CG1) {
+            a.v2[c] = pv[u];
+            a.v3[c] = sv[u];
+            acc += (double)val[u] * (double)val[u];
           }
           ldr[pp[u] - base] = val[u];
         }
@@ -432,6 +536,94 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
       else out = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     }
     a.Xt[(size_t)kx * ldx + y0 + r] = out;
+  }
+  if constexpr (CG1) {
+    if (a.part0) {
+      double unused = 0.0;
+      block_sum2<NT>(acc, unused);
+      if (t == 0) a.part0[blk] = acc;
+    }
+  }
+}
+
+// The compact output of a c2r-type pass (modes C2R_COMPACT, C2R_DOT2,
+// C2R_RESID): the ROWS x N block of real rows is in LDS (ldr); compact
+// elements c0..c1-1 (pixels pos[c]) are written to v0 with the mode's FP64
+// partial sums into part0/part1 at slot blk.
+template <int MODE, int N, int ROWS, int NT, typename T>
+__device__ __forceinline__ void compact_out(const RowArgs<T>& a, const T* ldr, int y0, int c0, int c1, int t,
+                                            int blk) {
+  const int base = y0 * a.nx;
+  double acc0 = 0.0, acc1 = 0.0;
+  const bool dot_self = (a.v1 == nullptr);
+  if (c1 - c0 == ROWS * N) {
+    // fully masked rows: compact element c0 + i is pixel i of the block
+    constexpr int PER = ROWS * N / NT, FB = sizeof(T) == 4 ? 16 : 8;
+#pragma unroll 1
+    for (int ch = 0; ch < PER; ch += FB) {
+      T w[FB];
+#pragma unroll
+      for (int u = 0; u < FB; ++u) w[u] = dot_self ? T(0) : a.v1[c0 + t + (ch + u) * NT];
+#pragma unroll
+      for (int u = 0; u < FB; ++u) {
+        const int i = t + (ch + u) * NT, c = c0 + i;
+        const T val = ldr[i];
+        if constexpr (MODE == C2R_COMPACT) {
+          const T o = a.scale * val;
+          a.v0[c] = o;
+          acc0 += (double)o * (double)(dot_self ? o : w[u]);
+        } else if constexpr (MODE == C2R_DOT2) {
+          a.v0[c] = val;
+          const double r = (double)w[u];
+          acc0 += r * (double)val;
+          acc1 += r * r;
+        } else {
+          const T r = w[u] - val;
+          a.v0[c] = r;
+          acc0 += (double)r * (double)r;
+        }
+      }
+    }
+  } else
+  for (int cb = c0 + t; cb < c1; cb += NT * kBatch) {
+    int pp[kBatch];
+    T w[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int c = cb + u * NT;
+      if (c < c1) {
+        pp[u] = a.pos[c];
+        w[u] = dot_self ? T(0) : a.v1[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int c = cb + u * NT;
+      if (c < c1) {
+        const T val = ldr[pp[u] - base];
+        if constexpr (MODE == C2R_COMPACT) {
+          const T o = a.scale * val;
+          a.v0[c] = o;
+          acc0 += (double)o * (double)(dot_self ? o : w[u]);
+        } else if constexpr (MODE == C2R_DOT2) {
+          a.v0[c] = val;
+          const double r = (double)w[u];
+          acc0 += r * (double)val;
+          acc1 += r * r;
+        } else {
+          const T r = w[u] - val;
+          a.v0[c] = r;
+          acc0 += (double)r * (double)r;
+        }
+      }
+    }
+  }
+  if (a.part0) {
+    block_sum2<NT>(acc0, acc1);
+    if (t == 0) {
+      a.part0[blk] = acc0;
+      if (a.part1) a.part1[blk] = acc1;
+    }
   }
 }
 
@@ -504,78 +696,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
       ldr[(2 * l + 1) * N + x] = v[e].y;
     }
     __syncthreads();
-    const int base = y0 * a.nx;
-    double acc0 = 0.0, acc1 = 0.0;
-    const bool dot_self = (a.v1 == nullptr);
-    if (c1 - c0 == ROWS * N) {
-      // fully masked rows: compact element c0 + i is pixel i of the block
-      constexpr int PER = ROWS * N / NT, FB = sizeof(T) == 4 ? 16 : 8;
-#pragma unroll 1
-      for (int ch = 0; ch < PER; ch += FB) {
-        T w[FB];
-#pragma unroll
-        for (int u = 0; u < FB; ++u) w[u] = dot_self ? T(0) : a.v1[c0 + t + (ch + u) * NT];
-#pragma unroll
-        for (int u = 0; u < FB; ++u) {
-          const int i = t + (ch + u) * NT, c = c0 + i;
-          const T val = ldr[i];
-          if constexpr (MODE == C2R_COMPACT) {
-            const T o = a.scale * val;
-            a.v0[c] = o;
-            acc0 += (double)o * (double)(dot_self ? o : w[u]);
-          } else if constexpr (MODE == C2R_DOT2) {
-            a.v0[c] = val;
-            const double r = (double)w[u];
-            acc0 += r * (double)val;
-            acc1 += r * r;
-          } else {
-            const T r = w[u] - val;
-            a.v0[c] = r;
-            acc0 += (double)r * (double)r;
-          }
-        }
-      }
-    } else
-    for (int cb = c0 + t; cb < c1; cb += NT * kBatch) {
-      int pp[kBatch];
-      T w[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int c = cb + u * NT;
-        if (c < c1) {
-          pp[u] = a.pos[c];
-          w[u] = dot_self ? T(0) : a.v1[c];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int c = cb + u * NT;
-        if (c < c1) {
-          const T val = ldr[pp[u] - base];
-          if constexpr (MODE == C2R_COMPACT) {
-            const T o = a.scale * val;
-            a.v0[c] = o;
-            acc0 += (double)o * (double)(dot_self ? o : w[u]);
-          } else if constexpr (MODE == C2R_DOT2) {
-            a.v0[c] = val;
-            const double r = (double)w[u];
-            acc0 += r * (double)val;
-            acc1 += r * r;
-          } else {
-            const T r = w[u] - val;
-            a.v0[c] = r;
-            acc0 += (double)r * (double)r;
-          }
-        }
-      }
-    }
-    if (a.part0) {
-      block_sum2<NT>(acc0, acc1);
-      if (t == 0) {
-        a.part0[blk] = acc0;
-        if (a.part1) a.part1[blk] = acc1;
-      }
-    }
+    compact_out<MODE, N, ROWS, NT>(a, ldr, y0, c0, c1, t, blk);
   } else {
     const size_t ra = (size_t)(y0 + 2 * l) * a.nx, rb = ra + a.nx;
 #pragma unroll
@@ -603,12 +724,15 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
 }
 
 // ---------------------------------------------------------------------------
-// proj: the row pass between two applies of C^{1/2} in E E r (Sec. 2.4):
-// inverse real FFT along x, projection Px (masked pixels kept, observed ones
-// zeroed), forward real FFT along x, transposed half spectrum written back.
-// The projected map never leaves the chip.
+// proj: the row pass between two column passes: inverse real FFT along x,
+// projection Px (masked pixels kept, observed ones zeroed), forward real FFT
+// along x, transposed half spectrum written back.  The projected map never
+// leaves the chip.  Between the two applies of C^{1/2} in E E r (Sec. 2.4)
+// it is the whole row pass; with DOT it also writes the masked values to v0
+// in compact order with the partials of v1.v0 and v1.v1 (C2R_DOT2): in
+// single-reduction CG it ends z = M^-1 r and starts w = A z in one pass.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, bool DOT>
 __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T> a_in) {
   using C = cplx<T>;
   RowArgs<T> a = bind_problem(a_in);
@@ -621,6 +745,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
   constexpr int LDS_C = (CF::LINES * LE > ROWS * HS) ? CF::LINES * LE : ROWS * HS;
   __shared__ C lds[LDS_C];
   __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
+  T* ldr = reinterpret_cast<T*>(lds);
   if (a.sc != nullptr && a.sc->done) return;
 
   const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
@@ -628,8 +753,13 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
   const int t = threadIdx.x;
   const int l = t / TPL, tid = t % TPL;
   const size_t ldx = (size_t)a.ldx;
-  if (a.row_off[y0] == a.row_off[y0 + ROWS]) {  // no masked pixel: the projection is zero
+  const int c0 = a.row_off[y0], c1 = a.row_off[y0 + ROWS];
+  if (c0 == c1) {  // no masked pixel: the projection is zero
     for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
+    if (DOT && t == 0) {
+      if (a.part0) a.part0[blk] = 0.0;
+      if (a.part1) a.part1[blk] = 0.0;
+    }
     return;
   }
   const size_t ra = (size_t)(y0 + 2 * l) * a.nx, rb = ra + a.nx;
@@ -665,6 +795,18 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
   fft_line<C, PL, +1>(v, tid, line, twq);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = C{ma[e] ? v[e].x : T(0), mb[e] ? v[e].y : T(0)};
+  if constexpr (DOT) {
+    __syncthreads();  // every line's FFT is done with LDS
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = tid + e * TPL;
+      ldr[(2 * l) * N + x] = v[e].x;
+      ldr[(2 * l + 1) * N + x] = v[e].y;
+    }
+    __syncthreads();
+    compact_out<C2R_DOT2, N, ROWS, NT>(a, ldr, y0, c0, c1, t, blk);
+    __syncthreads();  // the gather is done with LDS before the forward FFT
+  }
   fft_line<C, PL, -1>(v, tid, line, twq);
 #pragma unroll
   for (int e = 0; e < E; ++e) line[lpad<PL>(tid + e * TPL)] = v[e];
@@ -847,9 +989,10 @@ hipError_t launch_c2r_nm(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipE
   return hipGetLastError();
 }
 template <typename T, int N>
-hipError_t launch_proj_n(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_proj_n(bool dot, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using CF = RowCfg<T, N>;
-  FILL_LAUNCH((proj_kernel<T, N>), dim3(a.ny / CF::ROWS, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
+  if (dot) FILL_LAUNCH((proj_kernel<T, N, true>), dim3(a.ny / CF::ROWS, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
+  else FILL_LAUNCH((proj_kernel<T, N, false>), dim3(a.ny / CF::ROWS, a.nprob), dim3(CF::THREADS), s, e0, e1, a);
   return hipGetLastError();
 }
 template <typename T, int N>
@@ -872,6 +1015,7 @@ hipError_t launch_r2c_n(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t
     case R2C_XRUPDATE: return launch_r2c_nm<T, N, R2C_XRUPDATE>(a, s, e0, e1);
     case R2C_FULL: return launch_r2c_nm<T, N, R2C_FULL>(a, s, e0, e1);
     case R2C_NOISE: return launch_r2c_nm<T, N, R2C_NOISE>(a, s, e0, e1);
+    case R2C_CG1UPDATE: return launch_r2c_nm<T, N, R2C_CG1UPDATE>(a, s, e0, e1);
   }
   return hipErrorInvalidValue;
 }
@@ -908,9 +1052,10 @@ hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e
   return hipErrorInvalidValue;
 }
 template <typename T>
-hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+hipError_t launch_proj(bool dot, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr) {
   switch (a.nx) {
-#define FILL_CASE(n) case n: return launch_proj_n<T, n>(a, s, e0, e1);
+#define FILL_CASE(n) case n: return launch_proj_n<T, n>(dot, a, s, e0, e1);
     FILL_FOR_EACH_N(FILL_CASE)
 #undef FILL_CASE
   }

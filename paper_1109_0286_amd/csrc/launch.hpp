@@ -18,8 +18,9 @@ template <typename T>
 hipError_t launch_c2r(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T>
 hipError_t launch_col(int ny, const ColArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// dot: also write the projected values in compact order with DOT2 partials
 template <typename T>
-hipError_t launch_proj(const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_proj(bool dot, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> int row_block_rows(int nx);
 // CG vector update without a preconditioner (init: only the r.r partials),
 // nblk row blocks per problem.

@@ -47,12 +47,15 @@ EXPORTS = (
     "fill_last_error", "fill_plan_set_precond", "fill_plan_set_lanczos", "fill_get_lanczos",
     "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew", "fill_strips_create",
     "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
-    "fill_strips_refine", "fill_laplace",
+    "fill_strips_refine", "fill_laplace", "fill_plan_set_cg",
 )
 
 FILL_PRECOND_NONE = 0
 FILL_PRECOND_SPLIT = 1
 FILL_PRECOND_CXX = 2
+
+FILL_CG_STANDARD = 0
+FILL_CG_SINGLE_REDUCTION = 1
 
 FILL_K_R2C = 0
 FILL_K_COL = 1
@@ -93,6 +96,7 @@ def _load() -> C.CDLL:
         "fill_plan_set_max_iter": (i32, [vp, i32]),
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
         "fill_plan_set_precond": (i32, [vp, i32]),
+        "fill_plan_set_cg": (i32, [vp, i32]),
         "fill_plan_set_graph": (i32, [vp, i32]),
         "fill_plan_set_skew": (i32, [vp, dbl]),
         "fill_strips_create": (i32, [i32, i32, vp, vp, dbl, i32, vp, vp, dbl, i32, i32, vp, C.POINTER(vp)]),
@@ -264,6 +268,11 @@ def fill_plan_set_precond(plan, mode):
     return _check(_lib.fill_plan_set_precond(plan, int(mode)), "fill_plan_set_precond")
 
 
+def fill_plan_set_cg(plan, variant):
+    """variant: FILL_CG_STANDARD or FILL_CG_SINGLE_REDUCTION."""
+    return _check(_lib.fill_plan_set_cg(plan, int(variant)), "fill_plan_set_cg")
+
+
 def fill_plan_set_skew(plan, eps):
     return _check(_lib.fill_plan_set_skew(plan, float(eps)), "fill_plan_set_skew")
 
@@ -406,6 +415,10 @@ class Plan:
     def set_precond(self, mode):
         """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
         fill_plan_set_precond(self.handle, mode)
+
+    def set_cg(self, variant):
+        """Inner-CG recurrence: FILL_CG_STANDARD (default) or FILL_CG_SINGLE_REDUCTION."""
+        fill_plan_set_cg(self.handle, variant)
 
     def set_graph(self, on):
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
@@ -568,6 +581,10 @@ class BatchPlan:
     def set_precond(self, mode):
         """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
         fill_plan_set_precond(self.handle, mode)
+
+    def set_cg(self, variant):
+        """Inner-CG recurrence: FILL_CG_STANDARD (default) or FILL_CG_SINGLE_REDUCTION."""
+        fill_plan_set_cg(self.handle, variant)
 
     def set_graph(self, on):
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
