@@ -13,18 +13,22 @@ symmetric Toeplitz system per frequency kx.  The solution it leads to is the
 same (it only changes the CG path); the definition below fixes the operator so
 that the GPU's application of it can be checked element by element.
 
-Definition (parameters BW = 32, HALO = 4, TILE = 16, CMAX = 1024):
+Definition (parameters BW = 32, HALO = 4, TILE = 16, CMAX = 1024, NBMAX = 2048):
 
 1. Band runs: maximal runs of consecutive rows y0..y0+h-1 (not wrapping)
    whose every pixel is masked, with h <= ny - 2 BW.
 2. Band part, per run and per kx = 0..nx/2:
    t_kx(d) = sum_dx k(d mod ny, dx) cos(2 pi kx dx / nx)   (real: k is even
    in dx and, for spectra symmetric under ky -> -ky, in dy), T_kx[i, j] =
-   t_kx(i - j) for |i - j| < BW and 0 beyond; the band rows' part of M^-1 r is
+   t_kx(i - j) for |i - j| < BW and 0 beyond, plus sigma_kx on the diagonal,
+   sigma_kx = 2 sum_{d = BW}^{h-1} |t_kx(d)|: a bound (Gershgorin) on the norm
+   of the discarded part, so that T_kx stays positive definite however slowly
+   t_kx decays (sigma_kx = 0 when h <= BW); the band rows' part of M^-1 r is
    IDFT_x(T_kx^-1 DFT_x(r on the run)).
 3. The other masked pixels (outside band runs) split into connected components
-   (4-neighbours, periodic); a component of more than CMAX pixels is cut into
-   cells by the absolute TILE x TILE grid, otherwise it is one cell.
+   (4-neighbours, periodic); a component of more than CMAX pixels, or whose
+   grown block (step 4) would hold more than NBMAX pixels, is cut into cells by
+   the absolute TILE x TILE grid, otherwise it is one cell.
 4. Each cell grows into a block: every masked pixel (band rows included)
    within Chebyshev distance HALO (periodic) of the cell.  The block's part of
    M^-1 r is A_b^-1 r_b, A_b = A restricted to the block's pixels.
@@ -40,10 +44,10 @@ import numpy as np
 import scipy.fft as sfft
 import scipy.ndimage as ndi
 
-__all__ = ["BW", "HALO", "TILE", "CMAX", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
+__all__ = ["BW", "HALO", "TILE", "CMAX", "NBMAX", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
            "BlockPrecond", "pcg_block"]
 
-BW, HALO, TILE, CMAX = 32, 4, 16, 1024
+BW, HALO, TILE, CMAX, NBMAX = 32, 4, 16, 1024, 2048
 
 
 def kernel_cinv(P: np.ndarray) -> np.ndarray:
@@ -70,13 +74,13 @@ def band_runs(mask: np.ndarray, bw: int = BW) -> list:
     return runs
 
 
-def band_symbols(k: np.ndarray, bw: int = BW) -> np.ndarray:
-    """t[d, kx] = sum_dx k(d, dx) cos(2 pi kx dx / nx) for d = 0..bw-1."""
+def band_symbols(k: np.ndarray, nd: int = BW) -> np.ndarray:
+    """t[d, kx] = sum_dx k(d, dx) cos(2 pi kx dx / nx) for d = 0..nd-1."""
     nx = k.shape[1]
     dx = np.arange(nx)
     kx = np.arange(nx // 2 + 1)
     cos = np.cos(2.0 * np.pi * np.outer(dx, kx) / nx)
-    return k[:bw] @ cos
+    return k[:nd] @ cos
 
 
 def _components(sel: np.ndarray) -> list:
@@ -113,7 +117,7 @@ def cells(mask: np.ndarray, runs: list) -> list:
         sel[y0:y0 + h] = False
     out = []
     for c in _components(sel):
-        if len(c) <= CMAX:
+        if len(c) <= CMAX and len(blocks(mask, [c])[0]) <= NBMAX:
             out.append(c)
             continue
         key = (c[:, 0] // TILE) * (mask.shape[1] // TILE + 1) + c[:, 1] // TILE
@@ -147,13 +151,14 @@ class BlockPrecond:
         self.shape = (ny, nx)
         k = kernel_cinv(P)
         self.runs = band_runs(mask, bw)
-        t = band_symbols(k, bw)
+        t = band_symbols(k, max([h for _, h in self.runs], default=1))
         self.band_T = []
         for y0, h in self.runs:
             d = np.abs(np.arange(h)[:, None] - np.arange(h)[None, :])
             Ts = np.zeros((nx // 2 + 1, h, h))
             for kx in range(nx // 2 + 1):
-                Ts[kx] = np.where(d < bw, t[np.minimum(d, bw - 1), kx], 0.0)
+                sigma = 2.0 * np.abs(t[bw:h, kx]).sum()
+                Ts[kx] = np.where(d < bw, t[d, kx], 0.0) + sigma * np.eye(h)
             self.band_T.append(Ts)
         self.cells = cells(mask, self.runs)
         self.blocks = blocks(mask, self.cells)

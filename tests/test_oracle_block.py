@@ -5,7 +5,9 @@
   here from a dense covariance block (numpy irfft2 + index arithmetic) and
   parts found by brute-force flood fill and dilation;
 * on a band taller than the bandwidth, each x-frequency goes through the
-  truncated Toeplitz matrix formed from the dense covariance;
+  truncated Toeplitz matrix formed from the dense covariance, shifted by the
+  Gershgorin bound of the discarded part; with a slowly decaying kernel the
+  plain truncation is indefinite and the shifted one is not;
 * exactness: band-only and single-hole masks give M^-1 A = I;
 * M^-1 is symmetric positive definite;
 * structure: periodic components, tiling above CMAX, band-run rules;
@@ -132,7 +134,8 @@ def test_tall_band_uses_truncated_toeplitz_per_frequency():
         t = np.array([sum(Ab[0, d * nx + x] * np.cos(2 * np.pi * kx * x / nx) for x in range(nx))
                       for d in range(h)])
         d = np.abs(np.arange(h)[:, None] - np.arange(h)[None, :])
-        T = np.where(d < B.BW, t[d], 0.0)
+        sigma = 2.0 * np.abs(t[B.BW:]).sum()   # Gershgorin bound of the discarded part
+        T = np.where(d < B.BW, t[d], 0.0) + sigma * np.eye(h)
         a = rng.standard_normal(h)
         u = np.zeros((ny, nx))
         u[y0:y0 + h] = a[:, None] * np.cos(2 * np.pi * kx * np.arange(nx) / nx)[None, :]
@@ -140,6 +143,23 @@ def test_tall_band_uses_truncated_toeplitz_per_frequency():
         b = np.linalg.solve(T, a)
         expect = b[:, None] * np.cos(2 * np.pi * kx * np.arange(nx) / nx)[None, :]
         assert rel(z[y0:y0 + h], expect) < 1e-10
+
+
+def test_slow_decay_truncation_needs_the_shift():
+    ny, nx, h, y0 = 256, 128, 51, 90   # sharp spectral knee: t_kx(d) decays slowly in d
+    P = W.damped_power_law(nx, ny, 2.0, 12.0, 1e-6)
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[y0:y0 + h] = 1
+    t = B.band_symbols(B.kernel_cinv(P), h)
+    d = np.abs(np.arange(h)[:, None] - np.arange(h)[None, :])
+    plain_min = min(np.linalg.eigvalsh(np.where(d < B.BW, t[d, kx], 0.0)).min() for kx in range(nx // 2 + 1))
+    assert plain_min < 0.0
+    M = B.BlockPrecond(mask, P)
+    assert min(np.linalg.eigvalsh(T).min() for T in M.band_T[0]) > 0.0
+    # the shifted factor still approximates the band well: M^-1 A close to I
+    rng = np.random.default_rng(4)
+    v = np.where(mask != 0, rng.standard_normal((ny, nx)), 0.0)
+    assert rel(M.apply(OF.apply_A(v, mask, P)), v, mask != 0) < 0.5
 
 
 def test_band_only_and_single_hole_are_exact():
