@@ -32,7 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-PRECONDS = {"split": 1, "cxx": 2, "none": 0}  # fill_precond: E E (Sec. 2.4 split form), Px C Px, plain CG
+# fill_precond: E E (Sec. 2.4 split form), Px C Px, plain CG, block (additive-Schwarz inverse of A)
+PRECONDS = {"split": 1, "cxx": 2, "none": 0, "block": 3}
 CGS = {"standard": 0, "single": 1}  # fill_cg_variant: Hestenes-Stiefel, single-reduction (Chronopoulos-Gear)
 CALIB_BYTES = 256 << 20  # plain device copy used to scale the rocprofv3 byte counters
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1109_0286_amd", "csrc", f)
@@ -257,6 +258,8 @@ def compare_preconds(F, prob, d, args) -> dict:
         if pname == "none" and prob.meta["band"][1] > 0:
             continue  # thousands of iterations on a band: not a contender
         for cname, cg in CGS.items():
+            if pname == "block" and cname != "standard":
+                continue  # the block preconditioner runs with the standard recurrence
             for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
                 plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
                 plan.set_precond(pc)

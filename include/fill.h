@@ -67,7 +67,8 @@ enum fill_precision {
 enum fill_precond {
   FILL_PRECOND_NONE = 0,   /* plain CG on A */
   FILL_PRECOND_SPLIT = 1,  /* M^-1 = E E, the split form of Sec. 2.4 (default) */
-  FILL_PRECOND_CXX = 2     /* M^-1 = Px C Px */
+  FILL_PRECOND_CXX = 2,    /* M^-1 = Px C Px */
+  FILL_PRECOND_BLOCK = 3   /* M^-1 = block (additive Schwarz) inverse of A: see fill_plan_set_precond */
 };
 
 /* Recurrences of the inner CG (fill_plan_set_cg). */
@@ -81,7 +82,8 @@ enum fill_op {
   FILL_OP_CINV = 0,   /* out = C^-1 in */
   FILL_OP_CHALF = 1,  /* out = C^{1/2} in */
   FILL_OP_A = 2,      /* out = Px C^-1 Px in   (zero on observed pixels) */
-  FILL_OP_E = 3       /* out = Px C^{1/2} Px in (zero on observed pixels) */
+  FILL_OP_E = 3,      /* out = Px C^{1/2} Px in (zero on observed pixels) */
+  FILL_OP_MINV = 4    /* out = M^-1 in, the block preconditioner (zero on observed pixels) */
 };
 
 typedef struct fill_stats {
@@ -162,6 +164,24 @@ int fill_plan_set_inner_tol(fill_plan plan, double tol);
  *   FILL_PRECOND_NONE   CG on A itself, as Sec. 3 does for point-source masks
  *                       (one vector pass per iteration; many more iterations
  *                       on wide cuts).
+ *   FILL_PRECOND_BLOCK  not from the paper: an additive-Schwarz inverse of A
+ *                       built on the short range of C^-1.  Runs of fully
+ *                       masked rows (bands, at most ny - 64 rows) are solved
+ *                       exactly per x-frequency kx (their part of A is one
+ *                       symmetric Toeplitz matrix per kx, kept to bandwidth 32
+ *                       and factored by banded Cholesky); every other
+ *                       connected piece of the mask (4-neighbours, periodic;
+ *                       pieces over 1024 pixels are cut into 16 x 16 cells),
+ *                       grown by 4 pixels into the mask, is solved exactly by a
+ *                       dense inverse (at most 2048 pixels).  Selecting it
+ *                       builds these on the host from the kernel of C^-1 (one
+ *                       GPU apply), in the plan's precision; the time and
+ *                       memory grow with the band height times nx and with
+ *                       the sum of squared piece sizes.  It is rebuilt by
+ *                       fill_plan_set_pk / fill_plan_set_bands.  One-problem
+ *                       plans only, spectra with P(kx, ky) = P(kx, -ky); else
+ *                       FILL_EINVAL (FILL_ENOTSPD if a factor is not positive
+ *                       definite).  Used with the standard CG recurrence.
  */
 int fill_plan_set_precond(fill_plan plan, int mode);
 
@@ -370,6 +390,8 @@ int fill_get_stats_batch(fill_plan plan, fill_stats* out);
  * a full map (device in/out, ny*nx doubles, may not alias) in precision prec (enum fill_precision; FP32
  * rounds the input to float and returns the float result widened).  The
  * operators are the ones every CG iteration applies (Sec. 2.4).
+ * FILL_OP_MINV applies the block preconditioner; it needs FILL_PRECOND_BLOCK
+ * selected and prec equal to the plan's precision, else FILL_EINVAL.
  */
 int fill_apply(fill_plan plan, int op, int prec, const double* in, double* out);
 

@@ -22,7 +22,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfill.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["k_f64.hip", "k_f32.hip", "k_misc.hip", "k_adjoint.hip", "k_strips.hip", "fill_api.cpp", "strips.cpp"]
+SOURCES = ["k_f64.hip", "k_f32.hip", "k_misc.hip", "k_adjoint.hip", "k_strips.hip", "k_block.hip", "fill_api.cpp",
+           "strips.cpp", "block.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,298 @@
+// Host construction of the block preconditioner (see block.hpp).
+#include "block.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <thread>
+
+namespace fillb {
+namespace {
+
+// Work items 0..n-1 over the host's cores.
+template <typename F> void parallel_for(int n, F&& f) {
+  const int nt = std::max(1, std::min<int>(n, (int)std::thread::hardware_concurrency()));
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    for (int i = next++; i < n; i = next++) f(i);
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+}
+
+// Dense SPD inverse in place (row-major n x n): Cholesky A = L L^T, then
+// A^-1 = L^-T L^-1.  Returns false if a pivot is not positive.
+bool spd_inverse(std::vector<double>& A, int n) {
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  for (int j = 0; j < n; ++j) {
+    double d = a(j, j);
+    for (int m = 0; m < j; ++m) d -= a(j, m) * a(j, m);
+    if (!(d > 0.0)) return false;
+    const double l = std::sqrt(d);
+    a(j, j) = l;
+    for (int i = j + 1; i < n; ++i) {
+      double s = a(i, j);
+      for (int m = 0; m < j; ++m) s -= a(i, m) * a(j, m);
+      a(i, j) = s / l;
+    }
+  }
+  // W = L^-1 (lower), column by column: L w = e_j
+  std::vector<double> W((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    for (int i = j; i < n; ++i) {
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int m = j; m < i; ++m) s -= a(i, m) * W[(size_t)m * n + j];
+      W[(size_t)i * n + j] = s / a(i, i);
+    }
+  }
+  // A^-1 = W^T W: (i, j) = sum_{m >= max(i, j)} W[m][i] W[m][j]
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int m = i; m < n; ++m) s += W[(size_t)m * n + i] * W[(size_t)m * n + j];
+      a(i, j) = s;
+      a(j, i) = s;
+    }
+  return true;
+}
+
+}  // namespace
+
+int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, Layout* L,
+                 std::string* err) {
+  L->nx = nx;
+  L->ny = ny;
+  const size_t npix = (size_t)nx * ny;
+  std::vector<int> comp_of(npix, -1);  // compact index of each masked pixel
+  int n_m = 0;
+  for (size_t q = 0; q < npix; ++q)
+    if (mask[q]) comp_of[q] = n_m++;
+  L->n_m = n_m;
+
+  // ---- band runs
+  std::vector<uint8_t> in_run(ny, 0);
+  for (int y = 0; y < ny;) {
+    bool full = true;
+    for (int x = 0; x < nx && full; ++x) full = mask[(size_t)y * nx + x] != 0;
+    if (!full) {
+      ++y;
+      continue;
+    }
+    const int y0 = y;
+    while (y < ny) {
+      bool f = true;
+      for (int x = 0; x < nx && f; ++x) f = mask[(size_t)y * nx + x] != 0;
+      if (!f) break;
+      ++y;
+    }
+    const int h = y - y0;
+    if (h <= ny - 2 * BW) {
+      Run r;
+      r.y0 = y0;
+      r.h = h;
+      r.hp = (h + 31) / 32 * 32;
+      r.cb0 = comp_of[(size_t)y0 * nx];
+      L->runs.push_back(r);
+      for (int j = y0; j < y; ++j) in_run[j] = 1;
+    }
+  }
+  const int ncol = nx / 2, nk = nx / 2 + 1;
+  for (Run& r : L->runs) {
+    r.bt_off = L->bt_total;
+    L->bt_total += (size_t)ncol * r.hp;
+    r.fs_off = L->fs_total;
+    L->fs_total += (size_t)nk * 32 * r.hp;
+    for (int j = 0; j <= r.hp; ++j) L->brow_off.push_back(r.cb0 + std::min(j, r.h) * nx);
+    L->max_run_pixels = std::max(L->max_run_pixels, r.h * nx);
+  }
+  L->fwd.assign(L->fs_total, 0.0);
+  L->bwd.assign(L->fs_total, 0.0);
+  if (!L->runs.empty()) {
+    const double* t = tsym;
+    std::atomic<int> bad{-1};
+    for (const Run& r : L->runs) {
+      const int h = r.h, hp = r.hp;
+      parallel_for(nk, [&](int kx) {
+        double sigma = 0.0;  // Gershgorin bound of the part beyond the bandwidth
+        for (int d = BW; d < h; ++d) sigma += 2.0 * std::fabs(t[(size_t)d * nk + kx]);
+        // banded Cholesky of nx T_kx: Lb[i*BW + d] = L(i, i-d)
+        std::vector<double> Lb((size_t)h * BW, 0.0);
+        auto l = [&](int i, int j) -> double& { return Lb[(size_t)i * BW + (i - j)]; };
+        for (int i = 0; i < h; ++i) {
+          for (int j = std::max(0, i - BW + 1); j <= i; ++j) {
+            double s = (double)nx * (t[(size_t)(i - j) * nk + kx] + (i == j ? sigma : 0.0));
+            for (int m = std::max(0, i - BW + 1); m < j; ++m) s -= l(i, m) * l(j, m);
+            if (i == j) {
+              if (!(s > 0.0)) {
+                bad = kx;
+                return;
+              }
+              l(i, i) = std::sqrt(s);
+            } else {
+              l(i, j) = s / l(j, j);
+            }
+          }
+        }
+        // streams, lane k, position i (forward, i ascending) or s (backward,
+        // i = hp-1-s descending); the head lane of step i is i mod 32 and
+        // reads 1/L(i,i); lane k != head holds window element i + d (forward,
+        // d = (k - i) mod 32) or i - d (backward, d = (i - k) mod 32) and reads
+        // its coupling L(i+d, i) or L(i, i-d).  Padded rows are the identity.
+        for (int k = 0; k < 32; ++k) {
+          double* f = L->fwd.data() + r.fs_off + ((size_t)kx * 32 + k) * hp;
+          double* g = L->bwd.data() + r.fs_off + ((size_t)kx * 32 + k) * hp;
+          for (int i = 0; i < hp; ++i) {
+            const int d = ((k - i) % 32 + 32) % 32;
+            if (d == 0) f[i] = i < h ? 1.0 / l(i, i) : 1.0;
+            else f[i] = (i + d < h && d < BW) ? l(i + d, i) : 0.0;
+          }
+          for (int s = 0; s < hp; ++s) {
+            const int i = hp - 1 - s;
+            const int d = ((i - k) % 32 + 32) % 32;
+            if (d == 0) g[s] = i < h ? 1.0 / l(i, i) : 1.0;
+            else g[s] = (i < h && i - d >= 0 && d < BW) ? l(i, i - d) : 0.0;
+          }
+        }
+      });
+      if (bad >= 0) {
+        *err = "block preconditioner: the band factor of kx = " + std::to_string(bad.load()) +
+               " is not positive definite";
+        return -1;
+      }
+    }
+  }
+
+  // ---- cells: pieces of the masked pixels outside the runs
+  auto other = [&](size_t q) { return mask[q] && !in_run[q / nx]; };
+  std::vector<int> piece(npix, -1);
+  std::vector<std::vector<int>> cells;  // flat pixel indices
+  std::vector<int> stamp(npix, -1);
+  int stamp_id = 0;
+  auto grow = [&](const std::vector<int>& cell, std::vector<int>* out) {
+    const int id = stamp_id++;
+    out->clear();
+    for (int q : cell) {
+      const int y = q / nx, x = q % nx;
+      for (int dy = -HALO; dy <= HALO; ++dy)
+        for (int dx = -HALO; dx <= HALO; ++dx) {
+          const int yy = ((y + dy) % ny + ny) % ny, xx = ((x + dx) % nx + nx) % nx;
+          const int qq = yy * nx + xx;
+          if (mask[qq] && stamp[qq] != id) {
+            stamp[qq] = id;
+            out->push_back(qq);
+          }
+        }
+    }
+    std::sort(out->begin(), out->end());
+  };
+  std::vector<std::vector<int>> blocks;
+  std::vector<int> grown;
+  int npieces = 0;
+  for (size_t q0 = 0; q0 < npix; ++q0) {
+    if (!other(q0) || piece[q0] >= 0) continue;
+    std::vector<int> comp, stack{(int)q0};
+    piece[q0] = npieces;
+    while (!stack.empty()) {
+      const int q = stack.back();
+      stack.pop_back();
+      comp.push_back(q);
+      const int y = q / nx, x = q % nx;
+      const int nb[4] = {((y + 1) % ny) * nx + x, ((y + ny - 1) % ny) * nx + x, y * nx + (x + 1) % nx,
+                         y * nx + (x + nx - 1) % nx};
+      for (int qq : nb)
+        if (other(qq) && piece[qq] < 0) {
+          piece[qq] = npieces;
+          stack.push_back(qq);
+        }
+    }
+    ++npieces;
+    bool whole = (int)comp.size() <= CMAX;
+    if (whole) {
+      grow(comp, &grown);
+      whole = (int)grown.size() <= NBMAX;
+    }
+    if (whole) {
+      blocks.push_back(grown);
+      continue;
+    }
+    // cut along the absolute TILE grid
+    std::sort(comp.begin(), comp.end(), [&](int a, int b) {
+      const long ka = (long)(a / nx / TILE) * (nx / TILE + 1) + (a % nx) / TILE;
+      const long kb = (long)(b / nx / TILE) * (nx / TILE + 1) + (b % nx) / TILE;
+      return ka != kb ? ka < kb : a < b;
+    });
+    size_t s = 0;
+    while (s < comp.size()) {
+      const long key = (long)(comp[s] / nx / TILE) * (nx / TILE + 1) + (comp[s] % nx) / TILE;
+      size_t e = s;
+      std::vector<int> cell;
+      while (e < comp.size() &&
+             (long)(comp[e] / nx / TILE) * (nx / TILE + 1) + (comp[e] % nx) / TILE == key)
+        cell.push_back(comp[e++]);
+      grow(cell, &grown);
+      if ((int)grown.size() > NBMAX) {
+        *err = "block preconditioner: a grown cell exceeds the block size limit";
+        return -1;
+      }
+      blocks.push_back(grown);
+      s = e;
+    }
+  }
+
+  // ---- dense inverses
+  const int nb = (int)blocks.size();
+  L->boff.assign(nb + 1, 0);
+  L->moff.assign(nb, 0);
+  size_t mt = 0;
+  for (int b = 0; b < nb; ++b) {
+    L->boff[b + 1] = L->boff[b] + (int)blocks[b].size();
+    L->moff[b] = mt;
+    mt += blocks[b].size() * (size_t)block_ld((int)blocks[b].size());
+  }
+  L->bidx.resize(L->boff[nb]);
+  L->binv.assign(mt, 0.0);
+  std::atomic<int> badb{-1};
+  parallel_for(nb, [&](int b) {
+    const std::vector<int>& px = blocks[b];
+    const int n = (int)px.size();
+    std::vector<double> A((size_t)n * n);
+    for (int i = 0; i < n; ++i) {
+      const int yi = px[i] / nx, xi = px[i] % nx;
+      L->bidx[L->boff[b] + i] = comp_of[px[i]];
+      for (int j = 0; j < n; ++j) {
+        const int yj = px[j] / nx, xj = px[j] % nx;
+        const int dy = ((yi - yj) % ny + ny) % ny, dx = ((xi - xj) % nx + nx) % nx;
+        A[(size_t)i * n + j] = kmap[(size_t)dy * nx + dx];
+      }
+    }
+    if (!spd_inverse(A, n)) {
+      badb = b;
+      return;
+    }
+    const int ld = block_ld(n);
+    for (int j = 0; j < n; ++j)
+      std::copy(A.begin() + (size_t)j * n, A.begin() + (size_t)(j + 1) * n, L->binv.begin() + L->moff[b] + (size_t)j * ld);
+  });
+  if (badb >= 0) {
+    *err = "block preconditioner: a block of C^-1 is not positive definite";
+    return -1;
+  }
+
+  // ---- combine tables
+  L->cst.assign(n_m + 1, 0);
+  for (int b = 0; b < nb; ++b)
+    for (int i = L->boff[b]; i < L->boff[b + 1]; ++i) L->cst[L->bidx[i] + 1] += 1;
+  for (int c = 0; c < n_m; ++c) L->cst[c + 1] += L->cst[c];
+  L->cix.assign(L->cst[n_m], 0);
+  std::vector<int> fill(L->cst.begin(), L->cst.end() - 1);
+  for (int b = 0; b < nb; ++b)
+    for (int i = L->boff[b]; i < L->boff[b + 1]; ++i) L->cix[fill[L->bidx[i]]++] = i;
+  L->inb.assign(n_m, 0);
+  for (const Run& r : L->runs)
+    for (int c = r.cb0; c < r.cb0 + r.h * nx; ++c) L->inb[c] = 1;
+  return 0;
+}
+
+}  // namespace fillb

@@ -1,0 +1,73 @@
+// Host construction of the block preconditioner M^-1 ~ (Px C^-1 Px)^-1:
+// per-frequency banded factors for the runs of fully masked rows and dense
+// inverses of the grown pieces of the rest of the mask (additive Schwarz).
+//
+//   band runs   maximal runs y0..y0+h-1 of fully masked rows, h <= ny - 2 BW;
+//               per kx = 0..nx/2 the matrix nx T_kx, T_kx[i][j] = t_kx(i - j)
+//               for |i - j| < BW plus sigma_kx on the diagonal, where
+//               t_kx(d) = sum_dx k(d, dx) cos(2 pi kx dx/nx) (k the kernel of
+//               C^-1) and sigma_kx = 2 sum_{BW <= d < h} |t_kx(d)| bounds the
+//               discarded part (keeps T_kx positive definite), factored as
+//               L L^T (banded Cholesky);
+//   cells       connected pieces (4-neighbours, periodic) of the masked pixels
+//               outside the runs; a piece of more than CMAX pixels, or whose
+//               grown block would exceed NBMAX, is cut by the TILE x TILE grid;
+//   blocks      each cell grown by HALO (Chebyshev, periodic) within the mask,
+//               with the dense inverse of C^-1 restricted to its pixels.
+//
+// The applies of the band factors run as two sequential substitutions, one
+// wave per (run, kx): lanes 0..31 carry the real parts, 32..63 the imaginary
+// parts, lane k holding the window element j = k (mod 32).  The factor is
+// stored as one stream per (kx, lane) in the order the substitution uses it
+// (see block.cpp), so each lane reads its own contiguous stream.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fillb {
+
+constexpr int BW = 32;       // band bandwidth (one window lane per coupled row)
+constexpr int HALO = 4;      // Chebyshev growth of each cell into the mask
+constexpr int TILE = 16;     // cell grid for large pieces
+constexpr int CMAX = 1024;   // largest piece kept whole
+constexpr int NBMAX = 2048;  // largest block (dense inverse)
+
+// Column stride of a block inverse of n pixels (16-byte aligned columns in FP32).
+inline int block_ld(int n) { return (n + 3) / 4 * 4; }
+
+struct Run {
+  int y0 = 0, h = 0, hp = 0;  // first row, rows, rows padded to a multiple of 32
+  int cb0 = 0;                // compact index of the run's first pixel
+  size_t bt_off = 0;          // complex offset of the run's spectrum [nx/2][hp]
+  size_t fs_off = 0;          // offset of the run's streams [(nx/2+1)*32][hp]
+};
+
+struct Layout {
+  int nx = 0, ny = 0, n_m = 0;
+  std::vector<Run> runs;
+  std::vector<int> brow_off;   // per run: hp+1 compact offsets of the virtual rows
+  size_t bt_total = 0;         // complex values of all runs' spectra
+  size_t fs_total = 0;         // values of all runs' streams (each of fwd and bwd)
+  std::vector<double> fwd, bwd;
+  // blocks
+  std::vector<int> boff;       // nblocks+1 offsets into bidx / seg
+  std::vector<int> bidx;       // compact indices of each block's pixels
+  std::vector<size_t> moff;    // offsets of each block's inverse: n columns of stride block_ld(n)
+  std::vector<double> binv;
+  // combine: contributions of block entries to compact elements (CSR), band flags
+  std::vector<int> cst;        // n_m+1
+  std::vector<int> cix;        // entries: positions in seg
+  std::vector<uint8_t> inb;    // 1 if the element lies in a band run
+  int max_run_pixels = 0;
+};
+
+// mask: ny*nx (1 = masked); kmap: ny*nx FP64 kernel of C^-1 (C^-1 v = k (*) v);
+// tsym: ny*(nx/2+1), tsym[d*(nx/2+1) + kx] = t_kx(d).
+// Returns 0, or -1 with *err set (a band factor or a block is not positive
+// definite, or a block is too large).
+int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, Layout* out,
+                 std::string* err);
+
+}  // namespace fillb

@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "../../include/fill.h"
+#include "block.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -57,6 +58,7 @@ int fail(int code, const std::string& msg) {
 
 constexpr uint64_t kRealizationStream = 0x52;
 constexpr int kChunk = 16;  // CG iterations between host polls (even: keeps the rho parity)
+constexpr int kChunkBlock = 4;  // the same with the block preconditioner (few iterations per solve)
 constexpr int kMaxOuter = 60;
 
 template <typename T> struct Vecs {
@@ -81,6 +83,32 @@ struct Params {
   uint64_t* seeds;
 };
 
+// Device side of the block preconditioner (FILL_PRECOND_BLOCK), built for the
+// plan's precision from its mask and spectrum.
+struct BlockDev {
+  bool built = false;
+  std::vector<void*> allocs;
+  std::vector<fillb::Run> runs;
+  std::vector<size_t> run_brow;  // offset of each run's virtual row offsets in brow_off
+  int max_hp = 0, nblocks = 0;
+  int* brow_off = nullptr;
+  int* bpos = nullptr;           // 0, 1, 2, ...: a run's pixel index relative to its first pixel
+  void* Bt = nullptr;
+  void* fwd = nullptr;
+  void* bwd = nullptr;
+  int* run_hp = nullptr;
+  size_t* run_bt = nullptr;
+  size_t* run_fs = nullptr;
+  int* boff = nullptr;
+  int* bidx = nullptr;
+  size_t* moff = nullptr;
+  void* binv = nullptr;
+  void* seg = nullptr;
+  int* cst = nullptr;
+  int* cix = nullptr;
+  uint8_t* inb = nullptr;
+};
+
 }  // namespace
 
 struct fill_plan_s {
@@ -93,18 +121,21 @@ struct fill_plan_s {
   double inner_tol32 = 1e-4;
   int precond = FILL_PRECOND_SPLIT;
   int cg_variant = FILL_CG_STANDARD;
+  BlockDev blk;
+  std::vector<uint8_t> hmask;  // host copies: masks (0/1) and spectrum tables
+  std::vector<double> hpk;
   double skew = 0.0;  // non-Hermitian study: eps of the perturbed A inside the inner CG
   // CG coefficient record of the first inner solve of the last solve (Lanczos data)
   int hist_cap = 0;
   double* hist = nullptr;
   std::vector<int> hist_n;
   // the 16-iteration inner-CG chunk as a HIP graph, captured on first use per
-  // [FP32?][preconditioner + 3 * CG variant][coefficient record] and replayed
+  // [FP32?][preconditioner + 4 * CG variant][coefficient record] and replayed
   // by every solve
   int use_graph = 1;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph[2][6][2] = {};
-  hipGraphExec_t graph_exec[2][6][2] = {};
+  hipGraph_t graph[2][8][2] = {};
+  hipGraphExec_t graph_exec[2][8][2] = {};
   int nblk64 = 0, nblk32 = 0;
 
   uint8_t* mask = nullptr;
@@ -364,13 +395,223 @@ int chunk_graph(fill_plan p, int f32, int mode, int rec, F&& chunk, hipGraphExec
 // Drop captured chunk graphs (all, or only those that record coefficients).
 void drop_graphs(fill_plan p, bool record_only) {
   for (int a = 0; a < 2; ++a)
-    for (int m = 0; m < 6; ++m)
+    for (int m = 0; m < 8; ++m)
       for (int r = record_only ? 1 : 0; r < 2; ++r) {
         if (p->graph_exec[a][m][r]) (void)hipGraphExecDestroy(p->graph_exec[a][m][r]);
         if (p->graph[a][m][r]) (void)hipGraphDestroy(p->graph[a][m][r]);
         p->graph_exec[a][m][r] = nullptr;
         p->graph[a][m][r] = nullptr;
       }
+}
+
+// ---------------------------------------------------------------------------
+// Block preconditioner (FILL_PRECOND_BLOCK): host set-up and apply
+// ---------------------------------------------------------------------------
+template <typename P> int balloc(fill_plan p, P** out, size_t count) {
+  void* ptr = nullptr;
+  const size_t bytes = std::max<size_t>(count * sizeof(P), 256);
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) return fail(FILL_ENOMEM, std::string("hipMalloc ") + std::to_string(bytes) + " bytes: " +
+                                                    hipGetErrorString(e));
+  p->blk.allocs.push_back(ptr);
+  *out = static_cast<P*>(ptr);
+  return FILL_OK;
+}
+template <typename P> int bupload(fill_plan p, P** out, const std::vector<P>& v) {
+  FILL_TRY(balloc(p, out, v.size()));
+  if (!v.empty()) HIP_TRY(hipMemcpy(*out, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice));
+  return FILL_OK;
+}
+template <typename T> int bupload_as(fill_plan p, void** out, const std::vector<double>& v) {
+  std::vector<T> c(v.begin(), v.end());
+  T* d = nullptr;
+  FILL_TRY(bupload(p, &d, c));
+  *out = d;
+  return FILL_OK;
+}
+
+void block_free(fill_plan p) {
+  for (void* a : p->blk.allocs) (void)hipFree(a);
+  p->blk = BlockDev();
+}
+
+// Build the block preconditioner for the plan's mask, spectrum and precision.
+int block_setup(fill_plan p) {
+  static_assert(fillb::NBMAX == kBlockMax, "block size limit");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  drop_graphs(p, false);  // captured chunks hold the old tables
+  block_free(p);
+  if (p->nprob != 1) return fail(FILL_EINVAL, "the block preconditioner takes one-problem plans");
+  const int nx = p->nx, ny = p->ny, nc = p->ncol;
+  const size_t npix = p->npix;
+  for (int iy = 1; iy < ny; ++iy)
+    for (int ix = 0; ix < nc; ++ix) {
+      const double a = p->hpk[(size_t)iy * nc + ix], b = p->hpk[(size_t)((ny - iy) % ny) * nc + ix];
+      if (std::fabs(a - b) > 1e-12 * std::max(a, b))
+        return fail(FILL_EINVAL, "block preconditioner: the spectrum must satisfy P(kx, ky) = P(kx, -ky)");
+    }
+  // kernel of C^-1: C^-1 applied to a unit impulse at pixel 0, in FP64
+  std::vector<double> kmap(npix, 0.0), tsym;
+  {
+    double* din = nullptr;
+    double* dout = nullptr;
+    FILL_TRY(balloc(p, &din, npix));
+    FILL_TRY(balloc(p, &dout, npix));
+    kmap[0] = 1.0;
+    HIP_TRY(hipMemcpy(din, kmap.data(), npix * sizeof(double), hipMemcpyHostToDevice));
+    RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
+    ai.full_in = din;
+    ao.full_out = dout;
+    FILL_TRY(apply3<double>(p, R2C_FULL, ai, p->Dinv64, C2R_FULL, ao, nullptr));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipMemcpy(kmap.data(), dout, npix * sizeof(double), hipMemcpyDeviceToHost));
+    // band symbols t_kx(d): the row transform of the kernel (real: k is even in x)
+    RowArgs<double> at = row_base<double>(p, 1);
+    at.full_in = dout;
+    HIP_TRY(launch_r2c<double>(R2C_FULL, at, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    const int ncx = nx / 2;
+    std::vector<double2> xt((size_t)ncx * ny);
+    HIP_TRY(hipMemcpy(xt.data(), p->Xt, xt.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    tsym.assign((size_t)ny * nc, 0.0);
+    for (int d = 0; d < ny; ++d) {
+      tsym[(size_t)d * nc] = xt[d].x;        // DC: column 0, real part
+      tsym[(size_t)d * nc + ncx] = xt[d].y;  // Nyquist: column 0, imaginary part
+      for (int kx = 1; kx < ncx; ++kx) tsym[(size_t)d * nc + kx] = xt[(size_t)kx * ny + d].x;
+    }
+    block_free(p);
+  }
+  fillb::Layout L;
+  std::string err;
+  if (fillb::build_layout(nx, ny, p->hmask.data(), kmap.data(), tsym.data(), &L, &err) != 0)
+    return fail(FILL_ENOTSPD, err);
+  BlockDev& B = p->blk;
+  const bool f32 = p->prec == FILL_PREC_FP32_OP;
+  const size_t ts = f32 ? sizeof(float) : sizeof(double);
+  B.runs = L.runs;
+  size_t ro = 0;
+  std::vector<int> hp, bpos(std::max(L.max_run_pixels, 1));
+  std::vector<size_t> bt, fs;
+  for (const fillb::Run& r : L.runs) {
+    B.run_brow.push_back(ro);
+    ro += (size_t)r.hp + 1;
+    B.max_hp = std::max(B.max_hp, r.hp);
+    hp.push_back(r.hp);
+    bt.push_back(r.bt_off);
+    fs.push_back(r.fs_off);
+  }
+  for (size_t i = 0; i < bpos.size(); ++i) bpos[i] = (int)i;
+  B.nblocks = (int)L.boff.size() - 1;
+  FILL_TRY(bupload(p, &B.brow_off, L.brow_off));
+  FILL_TRY(bupload(p, &B.bpos, bpos));
+  FILL_TRY(bupload(p, &B.run_hp, hp));
+  FILL_TRY(bupload(p, &B.run_bt, bt));
+  FILL_TRY(bupload(p, &B.run_fs, fs));
+  FILL_TRY(bupload(p, &B.boff, L.boff));
+  FILL_TRY(bupload(p, &B.bidx, L.bidx));
+  FILL_TRY(bupload(p, &B.moff, L.moff));
+  FILL_TRY(bupload(p, &B.cst, L.cst));
+  FILL_TRY(bupload(p, &B.cix, L.cix));
+  FILL_TRY(bupload(p, &B.inb, L.inb));
+  {
+    uint8_t* bt_raw = nullptr;
+    FILL_TRY(balloc(p, &bt_raw, std::max<size_t>(L.bt_total, 1) * 2 * ts));
+    B.Bt = bt_raw;
+    uint8_t* seg_raw = nullptr;
+    FILL_TRY(balloc(p, &seg_raw, std::max<size_t>(L.bidx.size(), 1) * ts));
+    B.seg = seg_raw;
+  }
+  if (f32) {
+    FILL_TRY(bupload_as<float>(p, &B.fwd, L.fwd));
+    FILL_TRY(bupload_as<float>(p, &B.bwd, L.bwd));
+    FILL_TRY(bupload_as<float>(p, &B.binv, L.binv));
+  } else {
+    FILL_TRY(bupload_as<double>(p, &B.fwd, L.fwd));
+    FILL_TRY(bupload_as<double>(p, &B.bwd, L.bwd));
+    FILL_TRY(bupload_as<double>(p, &B.binv, L.binv));
+  }
+  B.built = true;
+  return FILL_OK;
+}
+
+// After a change of spectrum: rebuild a built block preconditioner (if that
+// fails, the plan falls back to M^-1 = Px C Px and the error is returned).
+int block_follow_pk(fill_plan p) {
+  if (!p->blk.built) return FILL_OK;
+  const int rc = block_setup(p);
+  if (rc != FILL_OK && p->precond == FILL_PRECOND_BLOCK) p->precond = FILL_PRECOND_CXX;
+  return rc;
+}
+
+// z = M^-1 r (compact vectors of the plan's precision), with the partials of
+// r.z and r.r over the row blocks (part0/part1 may be null).  Launches: per
+// band run a forward row transform of its rows, the banded solves of every
+// (run, kx), per run the inverse row transform into z, the dense block
+// products and the combination.
+template <typename T>
+int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGScalars* sc) {
+  BlockDev& B = p->blk;
+  if (!B.built || (sizeof(T) == 4) != (p->prec == FILL_PREC_FP32_OP))
+    return fail(FILL_EINVAL, "block preconditioner not built for this precision");
+  const int nruns = (int)B.runs.size();
+  auto run_args = [&](int q) {
+    const fillb::Run& run = B.runs[q];
+    RowArgs<T> a = row_base<T>(p, 1);
+    a.ny = run.hp;
+    a.ldx = run.hp;
+    a.comp_off = nullptr;
+    a.row_off = B.brow_off + B.run_brow[q];
+    a.pos = B.bpos - run.cb0;  // pos[c] = c - cb0: the pixel index within the run's rows
+    a.Xt = static_cast<cplx<T>*>(B.Bt) + run.bt_off;
+    a.sc = sc;
+    return a;
+  };
+  for (int q = 0; q < nruns; ++q) {
+    RowArgs<T> a = run_args(q);
+    a.v0 = const_cast<T*>(r);
+    HIP_TRY(launch_r2c<T>(R2C_COMPACT, a, p->stream));
+  }
+  if (nruns > 0) {
+    BandArgs<T> ba;
+    ba.Bt = static_cast<cplx<T>*>(B.Bt);
+    ba.fwd = static_cast<const T*>(B.fwd);
+    ba.bwd = static_cast<const T*>(B.bwd);
+    ba.run_hp = B.run_hp;
+    ba.run_bt = B.run_bt;
+    ba.run_fs = B.run_fs;
+    ba.ncol = p->nx / 2;
+    ba.sc = sc;
+    HIP_TRY(launch_band_solve<T>(ba, nruns, B.max_hp, p->stream));
+  }
+  for (int q = 0; q < nruns; ++q) {
+    RowArgs<T> a = run_args(q);
+    a.v0 = z;
+    HIP_TRY(launch_c2r<T>(C2R_COMPACT, a, p->stream));
+  }
+  BlockArgs<T> bk;
+  bk.r = r;
+  bk.seg = static_cast<T*>(B.seg);
+  bk.boff = B.boff;
+  bk.bidx = B.bidx;
+  bk.moff = B.moff;
+  bk.binv = static_cast<const T*>(B.binv);
+  bk.sc = sc;
+  HIP_TRY(launch_block_mv<T>(bk, B.nblocks, p->stream));
+  const int nb = TypeSel<T>::nblk(p);
+  CombArgs<T> cb;
+  cb.z = z;
+  cb.r = r;
+  cb.seg = static_cast<const T*>(B.seg);
+  cb.cst = B.cst;
+  cb.cix = B.cix;
+  cb.inb = B.inb;
+  cb.row_off = p->row_off;
+  cb.rows = p->ny / nb;
+  cb.part0 = part0;
+  cb.part1 = part1;
+  cb.sc = sc;
+  HIP_TRY(launch_combine<T>(cb, nb, p->stream));
+  return FILL_OK;
 }
 
 // Run inner-CG chunks (graph replays, or direct launches) until every problem
@@ -499,7 +740,7 @@ int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status
   };
   hipGraphExec_t exec = nullptr;
   if (p->use_graph && p->timed_kernel < 0)
-    FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode + 3, hist != nullptr, chunk, &exec));
+    FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode + 4, hist != nullptr, chunk, &exec));
   return run_chunks(p, exec, chunk, iters, status);
 }
 
@@ -508,7 +749,8 @@ int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status
 // parameters.  Returns per-problem iteration counts and statuses.
 template <typename T>
 int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bool record) {
-  if (p->cg_variant == FILL_CG_SINGLE_REDUCTION) return inner_pcg_cg1<T>(p, iters, status, record);
+  if (p->cg_variant == FILL_CG_SINGLE_REDUCTION && p->precond != FILL_PRECOND_BLOCK)
+    return inner_pcg_cg1<T>(p, iters, status, record);
   Vecs<T>& v = TypeSel<T>::vecs(p);
   const int nb = TypeSel<T>::nblk(p), np = p->nprob;
   const T* Dinv = TypeSel<T>::Dinv(p);
@@ -528,6 +770,7 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
     a_out.part0 = p->part0;
     a_out.part1 = p->part1;
     if (mode == FILL_PRECOND_SPLIT) FILL_TRY(apply_EE<T>(p, R2C_COMPACT, a_in, a_mid, a_out, nullptr));
+    else if (mode == FILL_PRECOND_BLOCK) FILL_TRY(block_apply<T>(p, v.r, v.z, p->part0, p->part1, nullptr));
     else FILL_TRY(apply3<T>(p, R2C_COMPACT, a_in, TypeSel<T>::Dfull(p), C2R_DOT2, a_out, nullptr));
   } else {
     RowArgs<T> a0 = row_base<T>(p, np);
@@ -583,13 +826,17 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   e_out.sc = p->sc;
 
   auto chunk = [&]() -> int {
-    for (int k = 0; k < kChunk; ++k) {
+    for (int k = 0; k < (mode == FILL_PRECOND_BLOCK ? kChunkBlock : kChunk); ++k) {
       const int par = k & 1;
       FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc, p->skew));
       if (mode == FILL_PRECOND_SPLIT) FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
       else if (mode == FILL_PRECOND_CXX)
         FILL_TRY(apply3<T>(p, R2C_XRUPDATE, e_in[par], TypeSel<T>::Dfull(p), C2R_DOT2, e_out, p->sc));
-      else HIP_TRY(launch_xr<T>(false, xr[par], nb, p->stream));
+      else if (mode == FILL_PRECOND_BLOCK) {
+        RowArgs<T> u = e_in[par];  // x += alpha p, r -= alpha q; the r.z, r.r partials come after M^-1
+        HIP_TRY(launch_xr<T>(false, u, nb, p->stream));
+        FILL_TRY(block_apply<T>(p, v.r, v.z, p->part0, p->part1, p->sc));
+      } else HIP_TRY(launch_xr<T>(false, xr[par], nb, p->stream));
     }
     return FILL_OK;
   };
@@ -760,6 +1007,7 @@ int twiddles(int n, int pass, std::vector<double2>& w64, std::vector<float2>& w3
 int upload_pk(fill_plan p, const double* Pk, int npk) {
   const int nx = p->nx, ny = p->ny, nc = p->ncol;
   const size_t nt = p->nt;
+  p->hpk.assign(Pk, Pk + (size_t)npk * nt);
   std::vector<double> inv(nt), half(nt), full(nt);
   std::vector<float> inv32(nt), half32(nt), full32(nt);
   const double scale = 1.0 / ((double)nx * (double)ny);
@@ -883,6 +1131,7 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   for (int b = 0; b < np; ++b) p->pstats[b].n_masked = p->n_m[b];
 
   HIP_TRY(hipMemcpy(p->mask, m01.data(), npix * np, hipMemcpyHostToDevice));
+  p->hmask = m01;
   if (!pos.empty()) HIP_TRY(hipMemcpy(p->pos, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->row_off, row_off.data(), row_off.size() * sizeof(int), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->comp_off, p->coff.data(), (np + 1) * sizeof(int), hipMemcpyHostToDevice));
@@ -1299,7 +1548,8 @@ int fill_plan_set_pk(fill_plan p, const double* Pk) {
   g_last_error.clear();
   if (!p || !Pk) return fail(FILL_EINVAL, "NULL argument");
   HIP_TRY(hipStreamSynchronize(p->stream));
-  return upload_pk(p, Pk, p->npk);
+  FILL_TRY(upload_pk(p, Pk, p->npk));
+  return block_follow_pk(p);
 }
 
 int fill_plan_set_max_iter(fill_plan p, int max_iter) {
@@ -1315,7 +1565,9 @@ int fill_plan_set_inner_tol(fill_plan p, double tol) {
 }
 
 int fill_plan_set_precond(fill_plan p, int mode) {
-  if (!p || mode < FILL_PRECOND_NONE || mode > FILL_PRECOND_CXX) return fail(FILL_EINVAL, "unknown preconditioner");
+  g_last_error.clear();
+  if (!p || mode < FILL_PRECOND_NONE || mode > FILL_PRECOND_BLOCK) return fail(FILL_EINVAL, "unknown preconditioner");
+  if (mode == FILL_PRECOND_BLOCK && !p->blk.built) FILL_TRY(block_setup(p));
   p->precond = mode;
   return FILL_OK;
 }
@@ -1390,6 +1642,7 @@ void fill_plan_destroy(fill_plan p) {
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   for (void* a : p->allocs) (void)hipFree(a);
+  for (void* a : p->blk.allocs) (void)hipFree(a);
   if (p->h_sc) (void)hipHostFree(p->h_sc);
   if (p->h_sum) (void)hipHostFree(p->h_sum);
   if (p->par_host) (void)hipHostFree(p->par_host);
@@ -1496,7 +1749,8 @@ int fill_plan_set_bands(fill_plan p, int nbands, const double* lnk_nodes, const 
     p->nbands = nbands;
   }
   HIP_TRY(hipMemcpy(p->lnk, lnk_nodes, nbands * sizeof(double), hipMemcpyHostToDevice));
-  return upload_pk(p, Pk.data(), p->npk);
+  FILL_TRY(upload_pk(p, Pk.data(), p->npk));
+  return block_follow_pk(p);
 }
 
 int fill_adjoint(fill_plan p, const double* d_obs, uint64_t seed, const double* x_out, const double* g,
@@ -1527,8 +1781,31 @@ int fill_apply(fill_plan p, int op, int prec, const double* in, double* out) {
   g_last_error.clear();
   if (!p || !in || !out) return fail(FILL_EINVAL, "NULL argument");
   if (in == out) return fail(FILL_EINVAL, "out aliases in");
-  if (op < FILL_OP_CINV || op > FILL_OP_E) return fail(FILL_EINVAL, "unknown operator");
+  if (op < FILL_OP_CINV || op > FILL_OP_MINV) return fail(FILL_EINVAL, "unknown operator");
   if (prec != FILL_PREC_FP64 && prec != FILL_PREC_FP32_OP) return fail(FILL_EINVAL, "unknown precision");
+  if (op == FILL_OP_MINV) {
+    if (p->precond != FILL_PRECOND_BLOCK || !p->blk.built)
+      return fail(FILL_EINVAL, "FILL_OP_MINV applies the block preconditioner: select FILL_PRECOND_BLOCK first");
+    if (prec != p->prec) return fail(FILL_EINVAL, "FILL_OP_MINV runs in the plan's precision");
+    const int nm = p->n_m[0];
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipMemsetAsync(out, 0, p->npix * sizeof(double), p->stream));
+    if (nm > 0) {
+      HIP_TRY(launch_gather(p->res, in, p->pos, nm, p->stream));
+      if (prec == FILL_PREC_FP64) {
+        FILL_TRY(block_apply<double>(p, p->res, p->v64.q, nullptr, nullptr, nullptr));
+        HIP_TRY(launch_scatter(out, p->v64.q, p->pos, nm, p->stream));
+      } else {
+        p->hp.scale[0] = 1.0;
+        FILL_TRY(upload_params(p));
+        HIP_TRY(launch_scale_to_f32(p->v32.t, p->res, p->dp.scale, p->comp_off, nm, 1, p->stream));
+        FILL_TRY(block_apply<float>(p, p->v32.t, p->v32.q, nullptr, nullptr, nullptr));
+        HIP_TRY(launch_scatter_f32(out, p->v32.q, p->pos, nm, p->stream));
+      }
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return FILL_OK;
+  }
   const bool inv = (op == FILL_OP_CINV || op == FILL_OP_A);
   const int n = p->n_m[0];
   HIP_TRY(hipStreamSynchronize(p->stream));

@@ -1,0 +1,271 @@
+// Kernels of the block preconditioner M^-1 r (additive Schwarz; the host side
+// is block.cpp):
+//   band_solve_kernel  per (run, kx): solve (nx T_kx) u = rhat by the banded
+//                      factor L L^T, forward then backward substitution, in
+//                      place on the run's transposed row spectrum;
+//   block_mv_kernel    per (block, 256-row chunk): seg = A_b^-1 r_b (dense
+//                      inverse, FP32/FP64);
+//   combine_kernel     per row block: z = band part (already in z on band
+//                      pixels) + the block entries covering each element, and
+//                      the FP64 partials of r.z and r.r.
+// The row transforms of the band runs are the r2c / c2r kernels of the
+// operator, launched on each run's rows as a grid of its own.
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace fillk {
+
+namespace {
+
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// 32 consecutive values of one lane's stream (aligned to 32 elements).
+__device__ __forceinline__ void load32(float (&f)[32], const float* p) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const float4 v = q[u];
+    f[4 * u] = v.x;
+    f[4 * u + 1] = v.y;
+    f[4 * u + 2] = v.z;
+    f[4 * u + 3] = v.w;
+  }
+}
+__device__ __forceinline__ void load32(double (&f)[32], const double* p) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const double2 v = q[u];
+    f[2 * u] = v.x;
+    f[2 * u + 1] = v.y;
+  }
+}
+
+// One wave per (column kx of the run's spectrum, run).  Column 0 carries the
+// DC values in its real parts and the Nyquist values in its imaginary parts,
+// which use the factors of kx = 0 and kx = nx/2.  Window: lane k (mod 32) of
+// each half holds the element i + ((k - i) mod 32) (forward) or
+// i - ((i - k) mod 32) (backward) of the running right-hand side; the head
+// lane of step i (k = i mod 32) finishes element i, which every lane takes
+// with a lane read; the others subtract their coupling times it.
+template <typename T>
+__global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
+  extern __shared__ unsigned char band_smem[];
+  if (a.sc != nullptr && a.sc->done) return;
+  const int col = blockIdx.x, run = blockIdx.y;
+  const int hp = a.run_hp[run];
+  cplx<T>* X = a.Bt + a.run_bt[run] + (size_t)col * hp;
+  T* sre = reinterpret_cast<T*>(band_smem);
+  T* sim = sre + hp;
+  const int lane = threadIdx.x, k = lane & 31, half = lane >> 5;
+  for (int i = lane; i < hp; i += 64) {
+    const cplx<T> c = X[i];
+    sre[i] = c.x;
+    sim[i] = c.y;
+  }
+  __syncthreads();
+  T* s = half ? sim : sre;
+  const int kx = (col == 0 && half) ? a.ncol : col;
+  const size_t so = a.run_fs[run] + ((size_t)kx * 32 + k) * hp;
+  const T* F = a.fwd + so;
+  const T* G = a.bwd + so;
+
+  // forward: L y = rhat.  The element that enters lane k's slot during a
+  // chunk (c0 + 32 + k) is read from LDS at the chunk's start.
+  T w = s[k];
+  T f[32], fn[32];
+  load32(f, F);
+  for (int c0 = 0; c0 < hp; c0 += 32) {
+    if (c0 + 32 < hp) load32(fn, F + c0 + 32);
+    const T nxt = (c0 + 32 < hp) ? s[c0 + 32 + k] : T(0);
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const T tv = w * f[u];
+      const T ylo = lane_value(tv, u), yhi = lane_value(tv, 32 + u);
+      const T y = half ? yhi : ylo;
+      if (k == u) {
+        s[c0 + u] = y;
+        w = nxt;
+      } else {
+        w -= f[u] * y;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) f[u] = fn[u];
+  }
+  __syncthreads();
+
+  // backward: L^T x = y (the element entering lane k's slot during a chunk
+  // is hp - 64 - c0 + k)
+  w = s[hp - 32 + k];
+  load32(f, G);
+  for (int c0 = 0; c0 < hp; c0 += 32) {
+    if (c0 + 32 < hp) load32(fn, G + c0 + 32);
+    const T nxt = (c0 + 64 <= hp) ? s[hp - 64 - c0 + k] : T(0);
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int hl = 31 - u;  // head lane of step i = hp - 1 - (c0 + u)
+      const T tv = w * f[u];
+      const T xlo = lane_value(tv, hl), xhi = lane_value(tv, 32 + hl);
+      const T x = half ? xhi : xlo;
+      if (k == hl) {
+        s[hp - 1 - (c0 + u)] = x;
+        w = nxt;
+      } else {
+        w -= f[u] * x;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) f[u] = fn[u];
+  }
+  __syncthreads();
+  for (int i = lane; i < hp; i += 64) X[i] = cplx<T>{sre[i], sim[i]};
+}
+
+constexpr int kBlkThreads = 512;           // 8 waves
+constexpr int kBlkWaves = kBlkThreads / 64;
+constexpr int kBlkRows = 256;              // rows per workgroup: 4 per lane
+constexpr int kBlkUnroll = 4;              // columns in flight per wave
+
+// 4 consecutive entries of a column (16-byte aligned in FP32).
+__device__ __forceinline__ void load4(float (&v)[4], const float* p) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+__device__ __forceinline__ void load4(double (&v)[4], const double* p) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+
+// seg[o + i] = sum_j Ainv[j][i] r[bidx[o + j]] (the inverse is symmetric;
+// column j is contiguous with stride ld = 4 ceil(n / 4)).  Workgroup (chunk,
+// block) takes rows chunk*256 .. +255, lane l four consecutive rows, wave w
+// the columns j = w (mod 8), kBlkUnroll of them in flight; the waves' sums
+// are added in a fixed order (deterministic).
+template <typename T>
+__global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
+  __shared__ T rv[kBlockMax];
+  __shared__ T red[kBlkWaves][kBlkRows];
+  if (a.sc != nullptr && a.sc->done) return;
+  const int b = blockIdx.y, t = threadIdx.x;
+  const int o = a.boff[b], n = a.boff[b + 1] - o;
+  const int r0 = blockIdx.x * kBlkRows;
+  if (r0 >= n) return;
+  for (int j = t; j < n; j += kBlkThreads) rv[j] = a.r[a.bidx[o + j]];
+  __syncthreads();
+  const int ld = (n + 3) / 4 * 4;
+  const int w = t >> 6, lane = t & 63;
+  const int row = r0 + 4 * lane;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  if (row < n) {
+    const T* M = a.binv + a.moff[b] + row;
+    int j = w;
+    for (; j + (kBlkUnroll - 1) * kBlkWaves < n; j += kBlkUnroll * kBlkWaves) {
+      T v[kBlkUnroll][4];
+#pragma unroll
+      for (int u = 0; u < kBlkUnroll; ++u) load4(v[u], M + (size_t)(j + u * kBlkWaves) * ld);
+#pragma unroll
+      for (int u = 0; u < kBlkUnroll; ++u) {
+        const T rj = rv[j + u * kBlkWaves];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += v[u][e] * rj;
+      }
+    }
+    for (; j < n; j += kBlkWaves) {
+      T v[4];
+      load4(v, M + (size_t)j * ld);
+      const T rj = rv[j];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += v[e] * rj;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[w][4 * lane + e] = acc[e];
+  __syncthreads();
+  if (t < kBlkRows && r0 + t < n) {
+    T s = red[0][t];
+#pragma unroll
+    for (int q = 1; q < kBlkWaves; ++q) s += red[q][t];
+    a.seg[o + r0 + t] = s;
+  }
+}
+
+constexpr int kCombThreads = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
+  if (a.sc != nullptr && a.sc->done) return;
+  const int blk = blockIdx.x;
+  const int c0 = a.row_off[blk * a.rows], c1 = a.row_off[(blk + 1) * a.rows];
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int c = c0 + (int)threadIdx.x; c < c1; c += kCombThreads) {
+    T zc = a.inb[c] ? a.z[c] : T(0);
+    const int e1 = a.cst[c + 1];
+    for (int e = a.cst[c]; e < e1; ++e) zc += a.seg[a.cix[e]];
+    a.z[c] = zc;
+    const double rc = (double)a.r[c];
+    acc0 += rc * (double)zc;
+    acc1 += rc * rc;
+  }
+  if (a.part0) {
+    block_sum2<kCombThreads>(acc0, acc1);
+    if (threadIdx.x == 0) {
+      a.part0[blk] = acc0;
+      if (a.part1) a.part1[blk] = acc1;
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s) {
+  if (nruns <= 0) return hipSuccess;
+  const size_t lds = (size_t)2 * max_hp * sizeof(T);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_kernel<T>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(band_solve_kernel<T>, dim3(a.ncol, nruns), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_mv_kernel<T>, dim3((kBlockMax + kBlkRows - 1) / kBlkRows, nblocks), dim3(kBlkThreads), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_combine(const CombArgs<T>& a, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(combine_kernel<T>, dim3(nblk), dim3(kCombThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_band_solve<float>(const BandArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_band_solve<double>(const BandArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_block_mv<float>(const BlockArgs<float>&, int, hipStream_t);
+template hipError_t launch_block_mv<double>(const BlockArgs<double>&, int, hipStream_t);
+template hipError_t launch_combine<float>(const CombArgs<float>&, int, hipStream_t);
+template hipError_t launch_combine<double>(const CombArgs<double>&, int, hipStream_t);
+
+}  // namespace fillk

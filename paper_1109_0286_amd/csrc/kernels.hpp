@@ -114,6 +114,42 @@ template <typename T> struct ColArgs {
   double skew;       // 0, or eps of the non-Hermitian study: D(k) (1 + i eps sin(2 pi kx / nx))
 };
 
+// Block preconditioner (k_block.hip): the banded per-frequency solves of the
+// band runs, the dense block products and their combination.
+constexpr int kBlockMax = 2048;  // largest block (dense inverse)
+template <typename T> struct BandArgs {
+  cplx<T>* Bt;            // the runs' transposed row spectra, run r at run_bt[r]: [nx/2][hp]
+  const T* fwd;           // factor streams, run r at run_fs[r]: [(nx/2+1)*32][hp]
+  const T* bwd;
+  const int* run_hp;      // padded rows of each run (multiple of 32)
+  const size_t* run_bt;
+  const size_t* run_fs;
+  int ncol;               // nx/2
+  const CGScalars* sc;
+};
+template <typename T> struct BlockArgs {
+  const T* r;             // compact input
+  T* seg;                 // per-block outputs
+  const int* boff;        // nblocks+1 offsets into bidx / seg
+  const int* bidx;        // compact indices of the blocks' pixels
+  const size_t* moff;     // offsets of the n x n inverses
+  const T* binv;
+  const CGScalars* sc;
+};
+template <typename T> struct CombArgs {
+  T* z;                   // in: band part on band pixels; out: M^-1 r
+  const T* r;
+  const T* seg;
+  const int* cst;         // n_m+1: block entries covering each element (CSR)
+  const int* cix;
+  const uint8_t* inb;     // element lies in a band run
+  const int* row_off;
+  int rows;               // rows per workgroup (partials per row block)
+  double* part0;          // r.z partials (or null)
+  double* part1;          // r.r partials (or null)
+  const CGScalars* sc;
+};
+
 template <typename T> __device__ __forceinline__ RowArgs<T> bind_problem(RowArgs<T> a) {
   const int b = blockIdx.y;
   if (b == 0) return a;
@@ -960,10 +996,12 @@ __global__ __launch_bounds__(kXrThreads) void xr_kernel(RowArgs<T> a_in, int row
     }
     acc += (double)r * (double)r;
   }
-  block_sum2<kXrThreads>(acc, unused);
-  if (threadIdx.x == 0) {
-    a.part0[blk] = acc;
-    a.part1[blk] = acc;
+  if (a.part0) {
+    block_sum2<kXrThreads>(acc, unused);
+    if (threadIdx.x == 0) {
+      a.part0[blk] = acc;
+      a.part1[blk] = acc;
+    }
   }
 }
 

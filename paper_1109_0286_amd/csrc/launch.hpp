@@ -10,6 +10,9 @@ namespace fillk {
 struct CGScalars;
 template <typename T> struct RowArgs;
 template <typename T> struct ColArgs;
+template <typename T> struct BandArgs;
+template <typename T> struct BlockArgs;
+template <typename T> struct CombArgs;
 
 // e0/e1 (may be null): events timestamped at the start and end of the dispatch.
 template <typename T>
@@ -25,6 +28,13 @@ template <typename T> int row_block_rows(int nx);
 // CG vector update without a preconditioner (init: only the r.r partials),
 // nblk row blocks per problem.
 template <typename T> hipError_t launch_xr(bool init, const RowArgs<T>& a, int nblk, hipStream_t s);
+
+// Block preconditioner: banded per-frequency solves of nruns band runs (the
+// largest padded to max_hp rows), dense block products, combination with the
+// r.z / r.r partials over nblk row blocks.
+template <typename T> hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s);
+template <typename T> hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s);
+template <typename T> hipError_t launch_combine(const CombArgs<T>& a, int nblk, hipStream_t s);
 
 // Reset the device CG scalars of nprob problems at the start of an inner solve.
 hipError_t launch_cg_init(CGScalars* sc, const double* tol2, const int* cap, const int* active, int nprob,

@@ -34,6 +34,7 @@ FILL_OP_CINV = 0
 FILL_OP_CHALF = 1
 FILL_OP_A = 2
 FILL_OP_E = 3
+FILL_OP_MINV = 4
 
 # every symbol include/fill.h declares
 EXPORTS = (
@@ -53,6 +54,7 @@ EXPORTS = (
 FILL_PRECOND_NONE = 0
 FILL_PRECOND_SPLIT = 1
 FILL_PRECOND_CXX = 2
+FILL_PRECOND_BLOCK = 3
 
 FILL_CG_STANDARD = 0
 FILL_CG_SINGLE_REDUCTION = 1
@@ -262,7 +264,7 @@ def fill_plan_set_inner_tol(plan, tol):
 
 
 def fill_plan_set_precond(plan, mode):
-    """mode: FILL_PRECOND_NONE / _SPLIT / _CXX (True/False map to SPLIT/NONE)."""
+    """mode: FILL_PRECOND_NONE / _SPLIT / _CXX / _BLOCK (True/False map to SPLIT/NONE)."""
     if mode is True or mode is False:
         mode = FILL_PRECOND_SPLIT if mode else FILL_PRECOND_NONE
     return _check(_lib.fill_plan_set_precond(plan, int(mode)), "fill_plan_set_precond")
@@ -413,7 +415,7 @@ class Plan:
         fill_plan_set_inner_tol(self.handle, tol)
 
     def set_precond(self, mode):
-        """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
+        """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, _BLOCK or _NONE (False)."""
         fill_plan_set_precond(self.handle, mode)
 
     def set_cg(self, variant):
@@ -579,7 +581,7 @@ class BatchPlan:
         self.nbands = len(lnk_nodes)
 
     def set_precond(self, mode):
-        """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, or _NONE (False)."""
+        """Inner-CG preconditioner: FILL_PRECOND_SPLIT (default, or True), _CXX, _BLOCK or _NONE (False)."""
         fill_plan_set_precond(self.handle, mode)
 
     def set_cg(self, variant):
