@@ -37,7 +37,13 @@ PRECONDS = {"split": 1, "cxx": 2, "none": 0, "block": 3}
 CGS = {"standard": 0, "single": 1}  # fill_cg_variant: Hestenes-Stiefel, single-reduction (Chronopoulos-Gear)
 CALIB_BYTES = 256 << 20  # plain device copy used to scale the rocprofv3 byte counters
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1109_0286_amd", "csrc", f)
-                  for f in ("fft_device.hpp", "fft_tuned.hpp", "kernels.hpp")]
+                  for f in ("fft_device.hpp", "fft_tuned.hpp", "kernels.hpp", "k_block.hip")]
+# kernels that can be timed inside solves (fill_kernel_timing ids) per preconditioner
+TIMED = {"r2c": 0, "col": 1, "c2r": 2, "proj": 4, "band": 5, "blockmv": 6, "combine": 7}
+KERNELS_OF = {"block": ("r2c", "col", "c2r", "band", "blockmv", "combine"), "cxx": ("r2c", "col", "c2r"),
+              "split": ("r2c", "col", "c2r", "proj"), "none": ("r2c", "col", "c2r")}
+KERNEL_NAMES = {"r2c": "r2c_kernel", "col": "col_kernel", "c2r": "c2r_kernel", "proj": "proj_kernel",
+                "band": "band_solve_kernel", "blockmv": "block_mv_kernel", "combine": "combine_kernel"}
 
 
 def configure(plan, args) -> None:
@@ -53,12 +59,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n: int = 2048):
-    """HBM bytes per launch of the FP32 column pass at n x n from the committed
+def measured_traffic(kernel: str, n: int = 2048):
+    """HBM bytes per launch of one FP32 kernel at n x n from the committed
     counter runs, or None if the kernel sources changed since they were taken."""
     try:
-        t = json.load(open(os.path.join(ROOT, "profiles", f"col_kernel_f32_{n}_traffic.json")))
-    except (OSError, ValueError):
+        t = json.load(open(os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[kernel]}_f32_{n}_traffic.json")))
+    except (OSError, ValueError, KeyError):
         return None
     return t["traffic_bytes"] if t.get("source_hash") == kernel_source_hash() else None
 
@@ -81,19 +87,50 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int) -> float:
-    """Algorithmic bytes per launch of one kernel of the A apply.
+def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int, info=None) -> float:
+    """Algorithmic bytes per launch of one kernel of a CG iteration.
 
-    H = ny (nx/2+1) half-spectrum complex values, s = bytes per real.
-    col: read + write H complex, read the H-entry real table  -> 5 s H
-    r2c: read n_m values and their n_m int32 pixel indices, write H complex -> 2 s H + (s + 4) n_m
-    c2r: read H complex, read the n_m indices, write n_m values             -> 2 s H + (s + 4) n_m
+    H = ny (nx/2+1) half-spectrum complex values, s = bytes per real, n_m
+    masked pixels; info: the block preconditioner's sizes (runs' padded rows
+    R, block pixels Nb, stored inverse entries Eb).
+    col:     read + write H complex, read the H-entry real table       -> 5 s H
+    r2c:     p = z + beta p: read z, p, write p, write H complex        -> 2 s H + 3 s n_m
+    c2r:     read H complex, write q, read p                            -> 2 s H + 2 s n_m
+    proj:    read + write H complex, read the mask                      -> 4 s H + nx ny
+    band:    read both factor streams and the runs' spectra, write them -> 64 (nx/2+1) R s + 4 (nx/2) R s
+    blockmv: read the inverses, gather r (value + index), write outputs -> Eb s + Nb (2 s + 4)
+    combine: read z, r, the band flag and the CSR start, write z, read
+             the covering entries (index + value)                     -> n_m (3 s + 5) + Nb (4 + s)
     """
     H = ny * (nx // 2 + 1)
     s = prec_bytes
     if kernel == "col":
         return 5.0 * s * H
-    return 2.0 * s * H + (s + 4.0) * n_m
+    if kernel == "r2c":
+        return 2.0 * s * H + 3.0 * s * n_m
+    if kernel == "c2r":
+        return 2.0 * s * H + 2.0 * s * n_m
+    if kernel == "proj":
+        return 4.0 * s * H + nx * ny
+    R = info["band_rows"] if info else 0
+    Nb = info["block_pixels"] if info else 0
+    if kernel == "band":
+        return 64.0 * (nx // 2 + 1) * R * s + 4.0 * (nx // 2) * R * s
+    if kernel == "blockmv":
+        return float(info["block_entries"]) * s + Nb * (2.0 * s + 4.0)
+    if kernel == "combine":
+        return n_m * (3.0 * s + 5.0) + Nb * (4.0 + s)
+    raise ValueError(kernel)
+
+
+def kernel_breakdown(F, plan, d, seed, rtol, names, steps=3) -> dict:
+    """Per kernel: average launch time (HIP events on the plan's stream),
+    launches and ms per solve, from `steps` solves per kernel."""
+    out = {}
+    for k in names:
+        _, st, avg_ms, n = time_solves(F, plan, d, seed, rtol, steps, 1, TIMED[k])
+        out[k] = {"ms_per_launch": avg_ms, "launches_per_solve": n / steps, "ms_per_solve": avg_ms * n / steps}
+    return out
 
 
 def time_solves(F, plan, d, seed, rtol, steps, warmup, timed_kernel):
@@ -116,8 +153,9 @@ def time_solves(F, plan, d, seed, rtol, steps, warmup, timed_kernel):
 
 
 def cpu_baseline(prob, iters_fp64: int, budget_s: float = 20.0) -> dict:
-    """Oracle on the host: one realization + RHS, then PCG iterations for a
-    bounded time; the solve rate is extrapolated to the FP64 iteration count."""
+    """Oracle on the host: one realization + RHS, then iterations of its
+    split-form PCG for a bounded time; the solve rate is extrapolated to the
+    iteration count that PCG needs (iters_fp64)."""
     import oracle as O
     from oracle import fill_oracle as OF
     m = prob.mask
@@ -148,7 +186,8 @@ def cpu_baseline(prob, iters_fp64: int, budget_s: float = 20.0) -> dict:
         "ms_per_iteration": per_it * 1e3, "single_thread_ms_per_iteration": per_it_1 * 1e3,
         "sample": (f"2048^2 workload: 1 realization + RHS ({t_fixed:.2f} s) and {n_it} PCG iterations "
                    f"({per_it * 1e3:.0f} ms/iteration, scipy.fft FP64, {OF._WORKERS} threads), "
-                   f"extrapolated to the {iters_fp64} iterations the FP64 solve needs"),
+                   f"extrapolated to the {iters_fp64} iterations of the oracle's split-form PCG (its own solver) at "
+                   f"the workload's rtol"),
     }
 
 
@@ -480,20 +519,26 @@ def bench_grid4096(args) -> int:
     prob = W.make_problem("grid4096")
     d = torch.from_numpy(prob.d_obs).cuda()
     res, plans = {}, {}
-    for name, prec in (("fp64", F.FILL_PREC_FP64), ("mixed", F.FILL_PREC_FP32_OP)):
+    names = KERNELS_OF[args.precond]
+    dom, breakdown, info = None, None, None
+    for name, prec in (("mixed", F.FILL_PREC_FP32_OP), ("fp64", F.FILL_PREC_FP64)):
         plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
         configure(plan, args)
-        dt, st, col_ms, _ = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, F.FILL_K_COL)
+        if name == "mixed":
+            info = plan.block_info() if args.precond == "block" else None
+            breakdown = kernel_breakdown(F, plan, d, prob.seed, prob.rtol, names, steps=2)
+            dom = max(breakdown, key=lambda k: breakdown[k]["ms_per_solve"])
+        dt, st, dom_ms, dom_n = time_solves(F, plan, d, prob.seed, prob.rtol, args.steps, args.warmup, TIMED[dom])
         res[name] = {"solves_per_s": args.steps / dt, "ms_per_solve": dt / args.steps * 1e3,
                      "iters_inner": st["iters_inner"], "iters_outer": st["iters_outer"],
-                     "rel_resid": st["rel_resid"], "col_kernel_ms": col_ms}
+                     "rel_resid": st["rel_resid"], "dominant_kernel_ms": dom_ms, "dominant_launches": dom_n}
         plans[name] = plan
     errs = masked_errors(F, prob, d, plans, prob.rtol)
     for name, plan in plans.items():
         res[name]["masked_rel_l2_error_vs_fp64_1e-11"] = errs[name]
         plan.close()
-    H = prob.ny * (prob.nx // 2 + 1)
-    achieved = 5.0 * 4 * H / (res["mixed"]["col_kernel_ms"] * 1e-3) / 1e9
+    nbytes = kernel_bytes(dom, 4, prob.nx, prob.ny, prob.n_masked, info)
+    achieved = nbytes / (res["mixed"]["dominant_kernel_ms"] * 1e-3) / 1e9
     out = {"metric": "PCG fill-in solves/s at 4096^2 (rel resid 1e-8)", "value": res["mixed"]["solves_per_s"],
            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": res["mixed"]["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
@@ -502,9 +547,11 @@ def bench_grid4096(args) -> int:
                                   "rtol 1e-8", "n_masked": prob.n_masked, "preconditioner": args.precond,
                       "cg": args.cg},
            "paths": res,
-           "roofline": {"bound": "hbm", "kernel": "col_kernel<float,4096>", "achieved": achieved,
+           "kernels_per_mixed_solve": breakdown,
+           "block_preconditioner": info,
+           "roofline": {"bound": "hbm", "kernel": f"{KERNEL_NAMES[dom]}<float> (4096^2)", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": measured_traffic(4096), "bytes_per_launch": 5.0 * 4 * H,
+                        "traffic": measured_traffic(dom, 4096), "bytes_per_launch": nbytes,
                         "copy_attainable_gbs": copy_bandwidth(), "kernel_source_hash": kernel_source_hash()}}
     print(json.dumps(out), flush=True)
     return 0
@@ -576,9 +623,10 @@ def main() -> int:
                          "point sources only, CG with and without the preconditioner; hermiticity: plain CG on a "
                          "deliberately non-Hermitian operator vs eps and kappa; strips2048: noise-boosted strip "
                          "refinement vs the exact fill")
-    ap.add_argument("--precond", default="cxx", choices=list(PRECONDS),
-                    help="inner-CG preconditioner (every workload): cxx (Px C Px, default), split (E E, the "
-                         "paper's split form) or none; the 2048^2 line also times the others")
+    ap.add_argument("--precond", default="block", choices=list(PRECONDS),
+                    help="inner-CG preconditioner (every workload): block (per-frequency band solves plus "
+                         "dense blocks, default), cxx (Px C Px), split (E E, the paper's split form) or none; "
+                         "the 2048^2 line also times the others")
     ap.add_argument("--cg", default="standard", choices=list(CGS),
                     help="inner-CG recurrence (every workload): standard (Hestenes-Stiefel) or single "
                          "(single-reduction, one launch fewer per iteration); the 2048^2 line times both")
@@ -619,16 +667,23 @@ def bench_grid2048(args) -> int:
     configure(plan64, args)
     n_m = prob.n_masked
 
-    dt64, st64, col64_ms, _ = time_solves(F, plan64, d, seed, rtol, args.steps, args.warmup, F.FILL_K_COL)
+    info = plan32.block_info() if args.precond == "block" else None
+    # the dominant kernel of the mixed path (largest time per solve), then the
+    # timed solves with every launch of it bracketed by HIP events
+    names = KERNELS_OF[args.precond]
+    breakdown = kernel_breakdown(F, plan32, d, seed, rtol, names)
+    dom = max(breakdown, key=lambda k: breakdown[k]["ms_per_solve"])
+    print("# kernels per mixed solve (ms): " + ", ".join(f"{k} {v['ms_per_solve']:.3f}" for k, v in breakdown.items()),
+          file=sys.stderr, flush=True)
+
+    dt64, st64, dom64_ms, _ = time_solves(F, plan64, d, seed, rtol, args.steps, args.warmup, TIMED[dom])
     print(f"# fp64: {args.steps / dt64:.2f} solves/s, {st64['iters_inner']} iterations", file=sys.stderr, flush=True)
-    dt32, st32, col32_ms, col32_n = time_solves(F, plan32, d, seed, rtol, args.steps, args.warmup, F.FILL_K_COL)
+    dt32, st32, dom32_ms, dom32_n = time_solves(F, plan32, d, seed, rtol, args.steps, args.warmup, TIMED[dom])
     print(f"# mixed: {args.steps / dt32:.2f} solves/s, {st32['iters_inner']} inner iterations, "
           f"{st32['iters_outer']} refinements", file=sys.stderr, flush=True)
 
-    # dominant kernel of the mixed path: the FP32 column pass, average launch
-    # duration over the timed region (HIP events on the plan's stream)
-    nbytes = kernel_bytes("col", 4, nx, ny, n_m)
-    achieved = nbytes / (col32_ms * 1e-3) / 1e9
+    nbytes = kernel_bytes(dom, 4, nx, ny, n_m, info)
+    achieved = nbytes / (dom32_ms * 1e-3) / 1e9
     kernel_ms = None
     if args.kernel_ms:
         kernel_ms = {name: {k: pl.time_kernel(getattr(F, f"FILL_K_{k.upper()}"), args.reps)
@@ -654,11 +709,13 @@ def bench_grid2048(args) -> int:
                    "rel_resid": st32["rel_resid"]},
         "fp64_path": {"value": args.steps / dt64, "unit": "solves/s", "ms_per_step": dt64 / args.steps * 1e3,
                       "iters": st64["iters_inner"], "rel_resid": st64["rel_resid"]},
-        "col_kernel_ms_in_solve": {"f32": col32_ms, "f64": col64_ms},
+        "kernels_per_mixed_solve": breakdown,
+        "dominant_kernel_ms_in_solve": {"f32": dom32_ms, "f64": dom64_ms},
+        "block_preconditioner": info,
         "kernel_ms_isolated": kernel_ms,
-        "roofline": {"bound": "hbm", "kernel": "col_kernel<float,2048>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": f"{KERNEL_NAMES[dom]}<float> (2048^2)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(2048), "bytes_per_launch": nbytes, "launches_timed": col32_n,
+                     "traffic": measured_traffic(dom, 2048), "bytes_per_launch": nbytes, "launches_timed": dom32_n,
                      "copy_attainable_gbs": copy_bandwidth(),
                      "kernel_source_hash": kernel_source_hash()},
     }
@@ -668,7 +725,9 @@ def bench_grid2048(args) -> int:
     if args.batch > 0:
         out["batched_2048"] = bench_batch_2048(F, prob, args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, st64["iters_inner"])
+        # the oracle solves by its split-form PCG (Sec. 2.4): its iteration
+        # count is that of the same FP64 recurrence on the GPU
+        out["cpu_baseline"] = cpu_baseline(prob, out["preconditioners"]["fp64_split_standard"]["iters_inner"])
     print(json.dumps(out), flush=True)
     return 0
 

@@ -71,6 +71,17 @@ enum fill_precond {
   FILL_PRECOND_BLOCK = 3   /* M^-1 = block (additive Schwarz) inverse of A: see fill_plan_set_precond */
 };
 
+/* Size of a plan's block preconditioner (fill_get_block_info). */
+typedef struct {
+  int runs;               /* band runs, all problems */
+  int blocks;             /* dense blocks, all problems */
+  int64_t band_rows;      /* sum over runs of the rows padded to a multiple of 32 */
+  int64_t block_pixels;   /* sum over blocks of their pixels n */
+  int64_t block_entries;  /* sum over blocks of the stored inverse entries n * 4 ceil(n / 4) */
+  int64_t bytes;          /* device memory it holds */
+  int elem_bytes;         /* 4 (FP32-operator plan) or 8 (FP64 plan) */
+} fill_block_info;
+
 /* Recurrences of the inner CG (fill_plan_set_cg). */
 enum fill_cg_variant {
   FILL_CG_STANDARD = 0,         /* Hestenes-Stiefel: two reduction points per iteration (default) */
@@ -178,10 +189,11 @@ int fill_plan_set_inner_tol(fill_plan plan, double tol);
  *                       GPU apply), in the plan's precision; the time and
  *                       memory grow with the band height times nx and with
  *                       the sum of squared piece sizes.  It is rebuilt by
- *                       fill_plan_set_pk / fill_plan_set_bands.  One-problem
- *                       plans only, spectra with P(kx, ky) = P(kx, -ky); else
- *                       FILL_EINVAL (FILL_ENOTSPD if a factor is not positive
- *                       definite).  Used with the standard CG recurrence.
+ *                       fill_plan_set_pk / fill_plan_set_bands.  Batched
+ *                       plans build one per problem.  Spectra must satisfy
+ *                       P(kx, ky) = P(kx, -ky), else FILL_EINVAL
+ *                       (FILL_ENOTSPD if a factor is not positive definite).
+ *                       Used with the standard CG recurrence.
  */
 int fill_plan_set_precond(fill_plan plan, int mode);
 
@@ -203,6 +215,15 @@ int fill_plan_set_precond(fill_plan plan, int mode);
  * recurrence.  Returns FILL_EINVAL for an unknown variant.
  */
 int fill_plan_set_cg(fill_plan plan, int variant);
+
+/*
+ * Size of the plan's block preconditioner (its runs, blocks and memory), for
+ * the traffic of its kernels: per apply the band solves read
+ * 2 * (nx/2 + 1) * 32 * band_rows factor values and read and write the runs'
+ * spectra, nx/2 * band_rows complex values; the block products read
+ * block_entries inverse entries.  FILL_EINVAL if it is not built.
+ */
+int fill_get_block_info(fill_plan plan, fill_block_info* out);
 
 /*
  * Lanczos data of the solves (Sec. 6.4): record the CG step lengths alpha_j
@@ -450,7 +471,10 @@ enum fill_kernel {
   FILL_K_COL = 1,    /* column pass: FFT along y, times 1/P, inverse FFT along y */
   FILL_K_C2R = 2,    /* row pass: half spectrum -> masked pixels (compact) */
   FILL_K_APPLY = 3,  /* the three in sequence: one apply of A = Px C^-1 Px */
-  FILL_K_PROJ = 4    /* row pass between the two C^{1/2} applies of E E r */
+  FILL_K_PROJ = 4,   /* row pass between the two C^{1/2} applies of E E r */
+  FILL_K_BAND = 5,   /* block preconditioner: banded per-frequency solves of the band runs */
+  FILL_K_BLOCKMV = 6, /* block preconditioner: dense products with the block inverses */
+  FILL_K_COMBINE = 7 /* block preconditioner: combination and the r.z / r.r partials */
 };
 
 /*
@@ -463,7 +487,8 @@ int fill_time_kernel(fill_plan plan, int kernel, int prec, int reps, double* avg
 
 /*
  * Measurement helper: from now on, bracket every launch of one kernel
- * (FILL_K_R2C, FILL_K_COL, FILL_K_C2R or FILL_K_PROJ; -1 = off) in precision
+ * (FILL_K_R2C, FILL_K_COL, FILL_K_C2R, FILL_K_PROJ, FILL_K_BAND, FILL_K_BLOCKMV or
+ * FILL_K_COMBINE; -1 = off) in precision
  * prec during solves on this plan with a pair of HIP events on the plan's
  * stream.  Resets the accumulated totals.
  */

@@ -90,6 +90,10 @@ struct BlockDev {
   std::vector<void*> allocs;
   std::vector<fillb::Run> runs;
   std::vector<size_t> run_brow;  // offset of each run's virtual row offsets in brow_off
+  std::vector<int> run_prob;     // problem of each run
+  int* run_prob_d = nullptr;
+  int* block_prob = nullptr;     // problem of each block
+  fill_block_info info{};
   int max_hp = 0, nblocks = 0;
   int* brow_off = nullptr;
   int* bpos = nullptr;           // 0, 1, 2, ...: a run's pixel index relative to its first pixel
@@ -435,60 +439,123 @@ void block_free(fill_plan p) {
   p->blk = BlockDev();
 }
 
-// Build the block preconditioner for the plan's mask, spectrum and precision.
+// Layout of problem b: kernel of C^-1 from a unit impulse (one FP64 apply with
+// problem b's table), its row transform for the band symbols, then the host
+// construction.
+int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
+  const int nx = p->nx, ny = p->ny, nc = p->ncol;
+  const size_t npix = p->npix;
+  const int tab = p->npk > 1 ? b : 0;
+  const double* P = p->hpk.data() + (size_t)tab * p->nt;
+  for (int iy = 1; iy < ny; ++iy)
+    for (int ix = 0; ix < nc; ++ix) {
+      const double u = P[(size_t)iy * nc + ix], v = P[(size_t)((ny - iy) % ny) * nc + ix];
+      if (std::fabs(u - v) > 1e-12 * std::max(u, v))
+        return fail(FILL_EINVAL, "block preconditioner: the spectrum must satisfy P(kx, ky) = P(kx, -ky)");
+    }
+  std::vector<double> kmap(npix, 0.0), tsym;
+  double* din = nullptr;
+  double* dout = nullptr;
+  std::vector<void*> tmp;
+  auto release = [&]() {
+    for (void* a : tmp) (void)hipFree(a);
+  };
+  if (hipMalloc(&din, npix * sizeof(double)) != hipSuccess) return fail(FILL_ENOMEM, "block set-up workspace");
+  tmp.push_back(din);
+  if (hipMalloc(&dout, npix * sizeof(double)) != hipSuccess) {
+    release();
+    return fail(FILL_ENOMEM, "block set-up workspace");
+  }
+  tmp.push_back(dout);
+  kmap[0] = 1.0;
+  int rc = FILL_OK;
+  hipError_t e = hipMemcpy(din, kmap.data(), npix * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
+    ai.full_in = din;
+    ao.full_out = dout;
+    rc = apply3<double>(p, R2C_FULL, ai, p->Dinv64 + (size_t)tab * p->nt, C2R_FULL, ao, nullptr);
+  }
+  if (rc == FILL_OK && e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (rc == FILL_OK && e == hipSuccess) e = hipMemcpy(kmap.data(), dout, npix * sizeof(double), hipMemcpyDeviceToHost);
+  // band symbols t_kx(d): the row transform of the kernel (real: k is even in x)
+  const int ncx = nx / 2;
+  std::vector<double2> xt((size_t)ncx * ny);
+  if (rc == FILL_OK && e == hipSuccess) {
+    RowArgs<double> at = row_base<double>(p, 1);
+    at.full_in = dout;
+    e = launch_r2c<double>(R2C_FULL, at, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) e = hipMemcpy(xt.data(), p->Xt, xt.size() * sizeof(double2), hipMemcpyDeviceToHost);
+  }
+  release();
+  if (rc != FILL_OK) return rc;
+  if (e != hipSuccess) return fail(FILL_EHIP, std::string("block set-up: ") + hipGetErrorString(e));
+  tsym.assign((size_t)ny * nc, 0.0);
+  for (int d = 0; d < ny; ++d) {
+    tsym[(size_t)d * nc] = xt[d].x;        // DC: column 0, real part
+    tsym[(size_t)d * nc + ncx] = xt[d].y;  // Nyquist: column 0, imaginary part
+    for (int kx = 1; kx < ncx; ++kx) tsym[(size_t)d * nc + kx] = xt[(size_t)kx * ny + d].x;
+  }
+  std::string err;
+  if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, kmap.data(), tsym.data(), L, &err) != 0)
+    return fail(FILL_ENOTSPD, "problem " + std::to_string(b) + ": " + err);
+  return FILL_OK;
+}
+
+// Build the block preconditioner for every problem of the plan (its mask,
+// spectrum and precision): the problems' layouts are laid end to end, with
+// compact indices offset by the problems' compact offsets.
 int block_setup(fill_plan p) {
   static_assert(fillb::NBMAX == kBlockMax, "block size limit");
   HIP_TRY(hipStreamSynchronize(p->stream));
   drop_graphs(p, false);  // captured chunks hold the old tables
   block_free(p);
-  if (p->nprob != 1) return fail(FILL_EINVAL, "the block preconditioner takes one-problem plans");
-  const int nx = p->nx, ny = p->ny, nc = p->ncol;
-  const size_t npix = p->npix;
-  for (int iy = 1; iy < ny; ++iy)
-    for (int ix = 0; ix < nc; ++ix) {
-      const double a = p->hpk[(size_t)iy * nc + ix], b = p->hpk[(size_t)((ny - iy) % ny) * nc + ix];
-      if (std::fabs(a - b) > 1e-12 * std::max(a, b))
-        return fail(FILL_EINVAL, "block preconditioner: the spectrum must satisfy P(kx, ky) = P(kx, -ky)");
+  const int np = p->nprob;
+  fillb::Layout L;  // merged
+  std::vector<int> run_prob, block_prob;
+  L.boff.push_back(0);
+  for (int b = 0; b < np; ++b) {
+    fillb::Layout Lb;
+    FILL_TRY(block_layout_for(p, b, &Lb));
+    const int co = p->coff[b];
+    size_t ro = 0;
+    for (fillb::Run r : Lb.runs) {
+      r.cb0 += co;
+      r.bt_off += L.bt_total;
+      r.fs_off += L.fs_total;
+      L.runs.push_back(r);
+      run_prob.push_back(b);
+      for (int j = 0; j <= r.hp; ++j) L.brow_off.push_back(Lb.brow_off[ro + j] + co);
+      ro += (size_t)r.hp + 1;
     }
-  // kernel of C^-1: C^-1 applied to a unit impulse at pixel 0, in FP64
-  std::vector<double> kmap(npix, 0.0), tsym;
-  {
-    double* din = nullptr;
-    double* dout = nullptr;
-    FILL_TRY(balloc(p, &din, npix));
-    FILL_TRY(balloc(p, &dout, npix));
-    kmap[0] = 1.0;
-    HIP_TRY(hipMemcpy(din, kmap.data(), npix * sizeof(double), hipMemcpyHostToDevice));
-    RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
-    ai.full_in = din;
-    ao.full_out = dout;
-    FILL_TRY(apply3<double>(p, R2C_FULL, ai, p->Dinv64, C2R_FULL, ao, nullptr));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    HIP_TRY(hipMemcpy(kmap.data(), dout, npix * sizeof(double), hipMemcpyDeviceToHost));
-    // band symbols t_kx(d): the row transform of the kernel (real: k is even in x)
-    RowArgs<double> at = row_base<double>(p, 1);
-    at.full_in = dout;
-    HIP_TRY(launch_r2c<double>(R2C_FULL, at, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    const int ncx = nx / 2;
-    std::vector<double2> xt((size_t)ncx * ny);
-    HIP_TRY(hipMemcpy(xt.data(), p->Xt, xt.size() * sizeof(double2), hipMemcpyDeviceToHost));
-    tsym.assign((size_t)ny * nc, 0.0);
-    for (int d = 0; d < ny; ++d) {
-      tsym[(size_t)d * nc] = xt[d].x;        // DC: column 0, real part
-      tsym[(size_t)d * nc + ncx] = xt[d].y;  // Nyquist: column 0, imaginary part
-      for (int kx = 1; kx < ncx; ++kx) tsym[(size_t)d * nc + kx] = xt[(size_t)kx * ny + d].x;
+    L.bt_total += Lb.bt_total;
+    L.fs_total += Lb.fs_total;
+    L.fwd.insert(L.fwd.end(), Lb.fwd.begin(), Lb.fwd.end());
+    L.bwd.insert(L.bwd.end(), Lb.bwd.begin(), Lb.bwd.end());
+    L.max_run_pixels = std::max(L.max_run_pixels, Lb.max_run_pixels);
+    const int nbase = (int)L.bidx.size();
+    const size_t mbase = L.binv.size();
+    for (size_t q = 1; q < Lb.boff.size(); ++q) {
+      L.boff.push_back(Lb.boff[q] + nbase);
+      L.moff.push_back(Lb.moff[q - 1] + mbase);
+      block_prob.push_back(b);
     }
-    block_free(p);
+    for (int c : Lb.bidx) L.bidx.push_back(c + co);
+    L.binv.insert(L.binv.end(), Lb.binv.begin(), Lb.binv.end());
+    const int ebase = L.cst.empty() ? 0 : L.cst.back();
+    if (L.cst.empty()) L.cst.push_back(0);
+    for (int c = 1; c <= Lb.n_m; ++c) L.cst.push_back(Lb.cst[c] + ebase);
+    for (int e : Lb.cix) L.cix.push_back(e + nbase);
+    L.inb.insert(L.inb.end(), Lb.inb.begin(), Lb.inb.end());
+    L.n_m += Lb.n_m;
   }
-  fillb::Layout L;
-  std::string err;
-  if (fillb::build_layout(nx, ny, p->hmask.data(), kmap.data(), tsym.data(), &L, &err) != 0)
-    return fail(FILL_ENOTSPD, err);
+  if (L.cst.empty()) L.cst.push_back(0);
   BlockDev& B = p->blk;
   const bool f32 = p->prec == FILL_PREC_FP32_OP;
   const size_t ts = f32 ? sizeof(float) : sizeof(double);
   B.runs = L.runs;
+  B.run_prob = run_prob;
   size_t ro = 0;
   std::vector<int> hp, bpos(std::max(L.max_run_pixels, 1));
   std::vector<size_t> bt, fs;
@@ -507,6 +574,8 @@ int block_setup(fill_plan p) {
   FILL_TRY(bupload(p, &B.run_hp, hp));
   FILL_TRY(bupload(p, &B.run_bt, bt));
   FILL_TRY(bupload(p, &B.run_fs, fs));
+  FILL_TRY(bupload(p, &B.run_prob_d, run_prob));
+  FILL_TRY(bupload(p, &B.block_prob, block_prob));
   FILL_TRY(bupload(p, &B.boff, L.boff));
   FILL_TRY(bupload(p, &B.bidx, L.bidx));
   FILL_TRY(bupload(p, &B.moff, L.moff));
@@ -530,6 +599,15 @@ int block_setup(fill_plan p) {
     FILL_TRY(bupload_as<double>(p, &B.bwd, L.bwd));
     FILL_TRY(bupload_as<double>(p, &B.binv, L.binv));
   }
+  B.info.runs = (int)L.runs.size();
+  B.info.blocks = B.nblocks;
+  for (const fillb::Run& r : L.runs) B.info.band_rows += r.hp;
+  B.info.block_pixels = (int64_t)L.bidx.size();
+  B.info.block_entries = (int64_t)L.binv.size();
+  B.info.elem_bytes = (int)ts;
+  B.info.bytes = (int64_t)((L.fwd.size() + L.bwd.size() + L.binv.size() + L.bidx.size() + 2 * L.bt_total) * ts +
+                           (L.brow_off.size() + bpos.size() + L.boff.size() + L.bidx.size() + L.cst.size() +
+                            L.cix.size()) * sizeof(int) + L.inb.size());
   B.built = true;
   return FILL_OK;
 }
@@ -563,7 +641,7 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
     a.row_off = B.brow_off + B.run_brow[q];
     a.pos = B.bpos - run.cb0;  // pos[c] = c - cb0: the pixel index within the run's rows
     a.Xt = static_cast<cplx<T>*>(B.Bt) + run.bt_off;
-    a.sc = sc;
+    a.sc = sc ? sc + B.run_prob[q] : nullptr;
     return a;
   };
   for (int q = 0; q < nruns; ++q) {
@@ -580,8 +658,11 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
     ba.run_bt = B.run_bt;
     ba.run_fs = B.run_fs;
     ba.ncol = p->nx / 2;
+    ba.run_prob = B.run_prob_d;
     ba.sc = sc;
-    HIP_TRY(launch_band_solve<T>(ba, nruns, B.max_hp, p->stream));
+    FILL_TRY(timed_launch<T>(p, FILL_K_BAND, [&](hipEvent_t e0, hipEvent_t e1) {
+      return launch_band_solve<T>(ba, nruns, B.max_hp, p->stream, e0, e1);
+    }));
   }
   for (int q = 0; q < nruns; ++q) {
     RowArgs<T> a = run_args(q);
@@ -595,8 +676,11 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
   bk.bidx = B.bidx;
   bk.moff = B.moff;
   bk.binv = static_cast<const T*>(B.binv);
+  bk.block_prob = B.block_prob;
   bk.sc = sc;
-  HIP_TRY(launch_block_mv<T>(bk, B.nblocks, p->stream));
+  FILL_TRY(timed_launch<T>(p, FILL_K_BLOCKMV, [&](hipEvent_t e0, hipEvent_t e1) {
+    return launch_block_mv<T>(bk, B.nblocks, p->stream, e0, e1);
+  }));
   const int nb = TypeSel<T>::nblk(p);
   CombArgs<T> cb;
   cb.z = z;
@@ -606,11 +690,16 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
   cb.cix = B.cix;
   cb.inb = B.inb;
   cb.row_off = p->row_off;
+  cb.comp_off = p->comp_off;
+  cb.ny = p->ny;
+  cb.part_stride = (size_t)p->ny;
   cb.rows = p->ny / nb;
   cb.part0 = part0;
   cb.part1 = part1;
   cb.sc = sc;
-  HIP_TRY(launch_combine<T>(cb, nb, p->stream));
+  FILL_TRY(timed_launch<T>(p, FILL_K_COMBINE, [&](hipEvent_t e0, hipEvent_t e1) {
+    return launch_combine<T>(cb, nb, p->nprob, p->stream, e0, e1);
+  }));
   return FILL_OK;
 }
 
@@ -1572,6 +1661,14 @@ int fill_plan_set_precond(fill_plan p, int mode) {
   return FILL_OK;
 }
 
+int fill_get_block_info(fill_plan p, fill_block_info* out) {
+  g_last_error.clear();
+  if (!p || !out) return fail(FILL_EINVAL, "NULL argument");
+  if (!p->blk.built) return fail(FILL_EINVAL, "the block preconditioner is not built");
+  *out = p->blk.info;
+  return FILL_OK;
+}
+
 int fill_plan_set_cg(fill_plan p, int variant) {
   g_last_error.clear();
   if (!p || (variant != FILL_CG_STANDARD && variant != FILL_CG_SINGLE_REDUCTION))
@@ -1881,7 +1978,7 @@ int fill_time_kernel(fill_plan p, int kernel, int prec, int reps, double* avg_ms
 int fill_kernel_timing(fill_plan p, int kernel, int prec) {
   g_last_error.clear();
   if (!p) return fail(FILL_EINVAL, "NULL plan");
-  if (kernel < -1 || kernel > FILL_K_PROJ || kernel == FILL_K_APPLY) return fail(FILL_EINVAL, "unknown kernel");
+  if (kernel < -1 || kernel > FILL_K_COMBINE || kernel == FILL_K_APPLY) return fail(FILL_EINVAL, "unknown kernel");
   if (prec != FILL_PREC_FP64 && prec != FILL_PREC_FP32_OP) return fail(FILL_EINVAL, "unknown precision");
   FILL_TRY(drain_timing(p));
   p->timed_kernel = kernel;

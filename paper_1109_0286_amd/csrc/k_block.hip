@@ -59,8 +59,8 @@ __device__ __forceinline__ void load32(double (&f)[32], const double* p) {
 template <typename T>
 __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   extern __shared__ unsigned char band_smem[];
-  if (a.sc != nullptr && a.sc->done) return;
   const int col = blockIdx.x, run = blockIdx.y;
+  if (a.sc != nullptr && a.sc[a.run_prob[run]].done) return;
   const int hp = a.run_hp[run];
   cplx<T>* X = a.Bt + a.run_bt[run] + (size_t)col * hp;
   T* sre = reinterpret_cast<T*>(band_smem);
@@ -161,8 +161,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
   __shared__ T rv[kBlockMax];
   __shared__ T red[kBlkWaves][kBlkRows];
-  if (a.sc != nullptr && a.sc->done) return;
   const int b = blockIdx.y, t = threadIdx.x;
+  if (a.sc != nullptr && a.sc[a.block_prob[b]].done) return;
   const int o = a.boff[b], n = a.boff[b + 1] - o;
   const int r0 = blockIdx.x * kBlkRows;
   if (r0 >= n) return;
@@ -209,9 +209,11 @@ constexpr int kCombThreads = 1024;
 
 template <typename T>
 __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
-  if (a.sc != nullptr && a.sc->done) return;
-  const int blk = blockIdx.x;
-  const int c0 = a.row_off[blk * a.rows], c1 = a.row_off[(blk + 1) * a.rows];
+  const int blk = blockIdx.x, pb = blockIdx.y;
+  if (a.sc != nullptr && a.sc[pb].done) return;
+  const int* ro = a.row_off + (size_t)pb * (a.ny + 1);
+  const int base = a.comp_off ? a.comp_off[pb] : 0;
+  const int c0 = base + ro[blk * a.rows], c1 = base + ro[(blk + 1) * a.rows];
   double acc0 = 0.0, acc1 = 0.0;
   for (int c = c0 + (int)threadIdx.x; c < c1; c += kCombThreads) {
     T zc = a.inb[c] ? a.z[c] : T(0);
@@ -225,8 +227,8 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
   if (a.part0) {
     block_sum2<kCombThreads>(acc0, acc1);
     if (threadIdx.x == 0) {
-      a.part0[blk] = acc0;
-      if (a.part1) a.part1[blk] = acc1;
+      a.part0[(size_t)pb * a.part_stride + blk] = acc0;
+      if (a.part1) a.part1[(size_t)pb * a.part_stride + blk] = acc1;
     }
   }
 }
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s) {
+hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nruns <= 0) return hipSuccess;
   const size_t lds = (size_t)2 * max_hp * sizeof(T);
   if (lds > 64 * 1024) {
@@ -242,30 +244,33 @@ hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStr
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(band_solve_kernel<T>, dim3(a.ncol, nruns), dim3(64), lds, s, a);
+  if (e0) hipExtLaunchKernelGGL(band_solve_kernel<T>, dim3(a.ncol, nruns), dim3(64), lds, s, e0, e1, 0, a);
+  else hipLaunchKernelGGL(band_solve_kernel<T>, dim3(a.ncol, nruns), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s) {
+hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(block_mv_kernel<T>, dim3((kBlockMax + kBlkRows - 1) / kBlkRows, nblocks), dim3(kBlkThreads), 0, s,
-                     a);
+  const dim3 grid((kBlockMax + kBlkRows - 1) / kBlkRows, nblocks);
+  if (e0) hipExtLaunchKernelGGL(block_mv_kernel<T>, grid, dim3(kBlkThreads), 0, s, e0, e1, 0, a);
+  else hipLaunchKernelGGL(block_mv_kernel<T>, grid, dim3(kBlkThreads), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_combine(const CombArgs<T>& a, int nblk, hipStream_t s) {
-  if (nblk <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(combine_kernel<T>, dim3(nblk), dim3(kCombThreads), 0, s, a);
+hipError_t launch_combine(const CombArgs<T>& a, int nblk, int nprob, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (nblk <= 0 || nprob <= 0) return hipErrorInvalidValue;
+  if (e0) hipExtLaunchKernelGGL(combine_kernel<T>, dim3(nblk, nprob), dim3(kCombThreads), 0, s, e0, e1, 0, a);
+  else hipLaunchKernelGGL(combine_kernel<T>, dim3(nblk, nprob), dim3(kCombThreads), 0, s, a);
   return hipGetLastError();
 }
 
-template hipError_t launch_band_solve<float>(const BandArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_band_solve<double>(const BandArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_block_mv<float>(const BlockArgs<float>&, int, hipStream_t);
-template hipError_t launch_block_mv<double>(const BlockArgs<double>&, int, hipStream_t);
-template hipError_t launch_combine<float>(const CombArgs<float>&, int, hipStream_t);
-template hipError_t launch_combine<double>(const CombArgs<double>&, int, hipStream_t);
+template hipError_t launch_band_solve<float>(const BandArgs<float>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_band_solve<double>(const BandArgs<double>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_block_mv<float>(const BlockArgs<float>&, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_block_mv<double>(const BlockArgs<double>&, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_combine<float>(const CombArgs<float>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_combine<double>(const CombArgs<double>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace fillk

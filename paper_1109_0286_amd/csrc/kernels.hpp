@@ -125,6 +125,7 @@ template <typename T> struct BandArgs {
   const size_t* run_bt;
   const size_t* run_fs;
   int ncol;               // nx/2
+  const int* run_prob;    // problem of each run (its CG scalars: sc + problem)
   const CGScalars* sc;
 };
 template <typename T> struct BlockArgs {
@@ -134,6 +135,7 @@ template <typename T> struct BlockArgs {
   const int* bidx;        // compact indices of the blocks' pixels
   const size_t* moff;     // offsets of the n x n inverses
   const T* binv;
+  const int* block_prob;  // problem of each block
   const CGScalars* sc;
 };
 template <typename T> struct CombArgs {
@@ -143,7 +145,10 @@ template <typename T> struct CombArgs {
   const int* cst;         // n_m+1: block entries covering each element (CSR)
   const int* cix;
   const uint8_t* inb;     // element lies in a band run
-  const int* row_off;
+  const int* row_off;     // ny+1 per problem, relative to the problem's compact offset
+  const int* comp_off;    // nprob+1 compact offsets
+  int ny;
+  size_t part_stride;     // partial slots per problem
   int rows;               // rows per workgroup (partials per row block)
   double* part0;          // r.z partials (or null)
   double* part1;          // r.r partials (or null)

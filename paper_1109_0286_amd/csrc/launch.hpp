@@ -32,9 +32,12 @@ template <typename T> hipError_t launch_xr(bool init, const RowArgs<T>& a, int n
 // Block preconditioner: banded per-frequency solves of nruns band runs (the
 // largest padded to max_hp rows), dense block products, combination with the
 // r.z / r.r partials over nblk row blocks.
-template <typename T> hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s);
-template <typename T> hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s);
-template <typename T> hipError_t launch_combine(const CombArgs<T>& a, int nblk, hipStream_t s);
+template <typename T>
+hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_combine(const CombArgs<T>& a, int nblk, int nprob, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 // Reset the device CG scalars of nprob problems at the start of an inner solve.
 hipError_t launch_cg_init(CGScalars* sc, const double* tol2, const int* cap, const int* active, int nprob,

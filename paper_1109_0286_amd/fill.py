@@ -48,7 +48,7 @@ EXPORTS = (
     "fill_last_error", "fill_plan_set_precond", "fill_plan_set_lanczos", "fill_get_lanczos",
     "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew", "fill_strips_create",
     "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
-    "fill_strips_refine", "fill_laplace", "fill_plan_set_cg",
+    "fill_strips_refine", "fill_laplace", "fill_plan_set_cg", "fill_get_block_info",
 )
 
 FILL_PRECOND_NONE = 0
@@ -64,11 +64,19 @@ FILL_K_COL = 1
 FILL_K_C2R = 2
 FILL_K_APPLY = 3
 FILL_K_PROJ = 4
+FILL_K_BAND = 5
+FILL_K_BLOCKMV = 6
+FILL_K_COMBINE = 7
 
 
 class fill_stats(C.Structure):
     _fields_ = [("iters_inner", C.c_int), ("iters_outer", C.c_int), ("n_masked", C.c_int),
                 ("status", C.c_int), ("rel_resid", C.c_double), ("solve_ms", C.c_double)]
+
+
+class BlockInfo(C.Structure):
+    _fields_ = [("runs", C.c_int), ("blocks", C.c_int), ("band_rows", C.c_int64), ("block_pixels", C.c_int64),
+                ("block_entries", C.c_int64), ("bytes", C.c_int64), ("elem_bytes", C.c_int)]
 
 
 class FillError(RuntimeError):
@@ -99,6 +107,7 @@ def _load() -> C.CDLL:
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
         "fill_plan_set_precond": (i32, [vp, i32]),
         "fill_plan_set_cg": (i32, [vp, i32]),
+        "fill_get_block_info": (i32, [vp, C.POINTER(BlockInfo)]),
         "fill_plan_set_graph": (i32, [vp, i32]),
         "fill_plan_set_skew": (i32, [vp, dbl]),
         "fill_strips_create": (i32, [i32, i32, vp, vp, dbl, i32, vp, vp, dbl, i32, i32, vp, C.POINTER(vp)]),
@@ -270,6 +279,14 @@ def fill_plan_set_precond(plan, mode):
     return _check(_lib.fill_plan_set_precond(plan, int(mode)), "fill_plan_set_precond")
 
 
+def fill_get_block_info(plan) -> dict:
+    """Runs, blocks, padded band rows, block pixels, stored inverse entries,
+    bytes and element size of the plan's block preconditioner."""
+    out = BlockInfo()
+    _check(_lib.fill_get_block_info(plan, C.byref(out)), "fill_get_block_info")
+    return {f: getattr(out, f) for f, _ in BlockInfo._fields_}
+
+
 def fill_plan_set_cg(plan, variant):
     """variant: FILL_CG_STANDARD or FILL_CG_SINGLE_REDUCTION."""
     return _check(_lib.fill_plan_set_cg(plan, int(variant)), "fill_plan_set_cg")
@@ -421,6 +438,10 @@ class Plan:
     def set_cg(self, variant):
         """Inner-CG recurrence: FILL_CG_STANDARD (default) or FILL_CG_SINGLE_REDUCTION."""
         fill_plan_set_cg(self.handle, variant)
+
+    def block_info(self) -> dict:
+        """Size of the block preconditioner (FILL_PRECOND_BLOCK must be selected)."""
+        return fill_get_block_info(self.handle)
 
     def set_graph(self, on):
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""
@@ -587,6 +608,10 @@ class BatchPlan:
     def set_cg(self, variant):
         """Inner-CG recurrence: FILL_CG_STANDARD (default) or FILL_CG_SINGLE_REDUCTION."""
         fill_plan_set_cg(self.handle, variant)
+
+    def block_info(self) -> dict:
+        """Size of the block preconditioner (FILL_PRECOND_BLOCK must be selected)."""
+        return fill_get_block_info(self.handle)
 
     def set_graph(self, on):
         """Replay the inner-CG chunks as a captured HIP graph (default) or launch kernels one by one."""

@@ -5,8 +5,10 @@ N is 2048 (the headline workload) or 4096 (the wide cut).  RUN_DIR holds
 trace/trace_kernel_stats.csv (kernel trace of `bench.py`),
 fetch/fetch_counter_collection.csv and write/write_counter_collection.csv
 (FETCH_SIZE / WRITE_SIZE runs of `bench.py ... --calib-copy`) and bench.json
-(the bench line of the same workload without the profiler).  Writes
-profiles/fill_N_kernel_stats.md and profiles/col_kernel_f32_N_traffic.{json,md}.
+(the bench line of the same workload without the profiler).  The kernel
+whose roofline the bench line reports (its dominant kernel) is the one the
+counter runs select (KERNEL below).  Writes profiles/fill_N_kernel_stats.md and
+profiles/<kernel>_f32_N_traffic.{json,md}.
 """
 
 from __future__ import annotations
@@ -27,23 +29,30 @@ BENCH_ARGS = {
 TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $OUT/p{n}/trace -o trace "
              "--output-format csv -- python $R/bench.py {a}")
 PMC_CMD = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --kernel-include-regex "
-           "\"col_kernel<float|copyBuffer\" -d $OUT/p{n}/{d} -o {d} --output-format csv -- "
+           "\"{k}<float|copyBuffer\" -d $OUT/p{n}/{d} -o {d} --output-format csv -- "
            "python $R/bench.py {a} --calib-copy")
 CALIB = 256 << 20
-MODES = ("Modes: r2c 0 compact, 1 p = z + beta p, 2 x += alpha p / r -= alpha q, 3 full map, 4 white noise; "
-         "c2r 0 compact (+dot), 1 z with r.z and r.r, 2 FP64 residual, 3 realization, 4 full map.")
+MODES = ("Modes: r2c 0 compact, 1 p = z + beta p, 2 x += alpha p / r -= alpha q, 3 full map, 4 white noise, "
+         "5 single-reduction update; c2r 0 compact (+dot), 1 z with r.z and r.r, 2 FP64 residual, 3 realization, "
+         "4 full map.  With the block preconditioner the r2c / c2r compact launches also transform the band "
+         "runs' rows.")
+
+
+def dominant(clean: dict) -> str:
+    """Kernel name (e.g. band_solve_kernel) of the bench line's roofline."""
+    return clean["roofline"]["kernel"].split("<")[0]
 
 
 def bench_numbers(clean: dict, n: int) -> tuple[float, str]:
-    """(live in-solve col<float,n> average in us, one line on the run)."""
+    """(live in-solve average of the dominant FP32 kernel in us, one line on the run)."""
     if n == 2048:
-        live = clean["col_kernel_ms_in_solve"]["f32"] * 1e3
+        live = clean["dominant_kernel_ms_in_solve"]["f32"] * 1e3
         line = (f"mixed {clean['value']:.2f} solves/s ({clean['config']['iters_inner']} inner iterations, "
                 f"{clean['config']['iters_outer']} refinements), FP64 {clean['fp64_path']['value']:.2f} solves/s "
                 f"({clean['fp64_path']['iters']} iterations), preconditioner {clean['config']['preconditioner']}")
     else:
         m, d = clean["paths"]["mixed"], clean["paths"]["fp64"]
-        live = m["col_kernel_ms"] * 1e3
+        live = m["dominant_kernel_ms"] * 1e3
         line = (f"mixed {m['solves_per_s']:.2f} solves/s ({m['iters_inner']} inner iterations, "
                 f"{m['iters_outer']} refinements), FP64 {d['solves_per_s']:.2f} solves/s ({d['iters_inner']} "
                 f"iterations), preconditioner {clean['config']['preconditioner']}")
@@ -55,15 +64,20 @@ def main(run: str, n: int) -> None:
     ta, pa = BENCH_ARGS[n]
     rows = list(csv.DictReader(open(os.path.join(run, "trace", "trace_kernel_stats.csv"))))
     clean = json.loads(open(os.path.join(run, "bench.json")).read().strip().splitlines()[-1])
-    name = f"col_kernel<float, {n}, false>"
-    col_rocprof = next(float(r["AverageNs"]) / 1e3 for r in rows if name in r["Name"])
+    kern = dominant(clean)
+    # the FP32 instance of the kernel at this size (all launches of the run)
+    sel = [r for r in rows if kern + "<float" in r["Name"] and (f", {n}" in r["Name"] or kern in
+                                                                 ("band_solve_kernel", "block_mv_kernel",
+                                                                  "combine_kernel"))]
+    calls = sum(int(r["Calls"]) for r in sel)
+    col_rocprof = sum(float(r["TotalDurationNs"]) for r in sel) / max(calls, 1) / 1e3
     live, line = bench_numbers(clean, n)
     roof = clean["roofline"]
     with open(os.path.join(ROOT, "profiles", f"fill_{n}_kernel_stats.md"), "w") as f:
         f.write(f"# Kernel statistics: {n}x{n} fill, FP64 and FP32-operator paths (rocprofv3)\n\n")
         f.write("Command (R = repository root, OUT = an output directory):\n\n```\n" + TRACE_CMD.format(n=n, a=ta) +
                 "\n```\n\n")
-        f.write(f"- `col_kernel<float,{n}>` average under rocprofv3 (every launch of the run): {col_rocprof:.2f} us; "
+        f.write(f"- `{kern}<float>` average under rocprofv3 (every launch of the run): {col_rocprof:.2f} us; "
                 f"bench.py without the profiler (HIP events timestamped by each dispatch, timed region of the "
                 f"mixed path): {live:.2f} us.\n")
         f.write(f"- bench.py without the profiler: {line}.\n")
@@ -77,7 +91,7 @@ def main(run: str, n: int) -> None:
 
     def load(kind):
         rr = list(csv.DictReader(open(os.path.join(run, kind, f"{kind}_counter_collection.csv"))))
-        col = [float(r["Counter_Value"]) for r in rr if name in r["Kernel_Name"]]
+        col = [float(r["Counter_Value"]) for r in rr if kern + "<float" in r["Kernel_Name"]]
         # the calibration copies are the run's last three copy dispatches
         copies = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rr
                         if "copyBuffer" in r["Kernel_Name"])
@@ -88,17 +102,17 @@ def main(run: str, n: int) -> None:
     wk, wc, _ = load("write")
     fs, ws = CALIB / (fc * 1024), CALIB / (wc * 1024)
     traffic = fk * 1024 * fs + wk * 1024 * ws
-    alg = 5 * 4 * n * (n // 2)
-    out = {"kernel": f"col_kernel<float,{n}>", "workload": f"{n}x{n} fill, FP32 column pass",
+    alg = roof["bytes_per_launch"]
+    out = {"kernel": f"{kern}<float> ({n}x{n})", "workload": f"{n}x{n} fill, FP32 {kern}",
            "fetch_kib_per_dispatch_median": fk, "write_kib_per_dispatch_median": wk, "dispatches": cnt,
            "calib_copy_bytes": CALIB, "calib_fetch_kib": fc, "calib_write_kib": wc,
            "fetch_scale": fs, "write_scale": ws, "traffic_bytes": traffic, "algorithmic_bytes": alg,
            "source_hash": bench.kernel_source_hash(),
-           "commands": [PMC_CMD.format(c="FETCH_SIZE", d="fetch", n=n, a=pa),
-                        PMC_CMD.format(c="WRITE_SIZE", d="write", n=n, a=pa)]}
-    json.dump(out, open(os.path.join(ROOT, "profiles", f"col_kernel_f32_{n}_traffic.json"), "w"), indent=1)
-    with open(os.path.join(ROOT, "profiles", f"col_kernel_f32_{n}_traffic.md"), "w") as f:
-        f.write(f"# HBM traffic of col_kernel<float,{n}> ({n}x{n} workload), rocprofv3 counters\n\n")
+           "commands": [PMC_CMD.format(c="FETCH_SIZE", d="fetch", n=n, a=pa, k=kern),
+                        PMC_CMD.format(c="WRITE_SIZE", d="write", n=n, a=pa, k=kern)]}
+    json.dump(out, open(os.path.join(ROOT, "profiles", f"{kern}_f32_{n}_traffic.json"), "w"), indent=1)
+    with open(os.path.join(ROOT, "profiles", f"{kern}_f32_{n}_traffic.md"), "w") as f:
+        f.write(f"# HBM traffic of {kern}<float> ({n}x{n} workload), rocprofv3 counters\n\n")
         f.write("Commands (R = repository root, OUT = an output directory):\n\n```\n" + "\n".join(out["commands"]) +
                 "\n```\n\n")
         f.write(f"- FETCH_SIZE median {fk:.1f} KiB per dispatch over {cnt} dispatches; "

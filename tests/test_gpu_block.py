@@ -12,7 +12,8 @@
 * its CG coefficients equal the oracle's block PCG's over the first steps;
 * graph replays are bitwise equal to direct launches; a new spectrum rebuilds
   it; a fully masked grid returns the unconstrained draw;
-* errors: batch plans, spectra not symmetric in ky, FILL_OP_MINV without it.
+* a batched plan (own masks and spectra per problem) matches the oracle;
+* errors: spectra not symmetric in ky, FILL_OP_MINV without it.
 
 FP32 bar for M^-1: the band factors and block inverses are rounded to FP32
 and the substitutions run in FP32, so the result carries a relative error of
@@ -209,12 +210,39 @@ def test_all_masked_returns_unconstrained_draw(F):
     assert rel(x, s) < 1e-9
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
+def test_batch_matches_oracle(F, prec, tol):
+    # three problems of one size, own masks (one with a band, one holes only,
+    # one fully masked row set plus a large piece), per-problem spectra
+    n = 256
+    masks, Ps, ds = [], [], []
+    for i in range(3):
+        P = W.damped_power_law(n, n, 2.0 + i, n / (6 + 2 * i), 1e-7)
+        if i == 0:
+            m = W.band_holes_mask(n, n, W.band_rows(n, 0.12), 12, 2.0, 8.0, 90)
+        elif i == 1:
+            m = W.band_holes_mask(n, n, None, 20, 2.0, 8.0, 91)
+        else:
+            m = np.zeros((n, n), np.uint8)
+            m[100:130] = 1
+            m[180:230, 40:90] = 1
+        masks.append(m)
+        Ps.append(P)
+        ds.append(W.observed_map(P, n, n, 95 + i, m))
+    bp = F.BatchPlan(n, n, np.stack(masks), np.stack(Ps), prec=prec)
+    bp.set_precond(F.FILL_PRECOND_BLOCK)
+    xb = host(bp.realize(dev(np.stack(ds)), [4, 5, 6], 1e-12 if prec == 0 else 1e-10))
+    for i in range(3):
+        ref = OF.fill_realize(ds[i], masks[i], Ps[i], 4 + i, 1e-13)
+        assert rel(xb[i], ref.x_out, masks[i] != 0) < tol, i
+    st = bp.stats()
+    assert all(s["status"] == 0 for s in st)
+    assert max(s["iters_inner"] for s in st) < 60
+
+
 def test_errors(F):
     mask, P = case("short")
     ny, nx = mask.shape
-    bp = F.BatchPlan(nx, ny, np.stack([mask, mask]), P)
-    with pytest.raises(Exception):
-        bp.set_precond(F.FILL_PRECOND_BLOCK)
     Pa = P.copy()
     Pa[1, 3] *= 1.5  # P(kx, ky) != P(kx, -ky)
     plan = F.Plan(nx, ny, mask, Pa)
