@@ -478,10 +478,12 @@ enum fill_kernel {
 };
 
 /*
- * Measurement helper: launch one kernel of the A apply `reps` times on the
- * plan's stream with the arguments a CG iteration uses, bracketed by HIP
- * events on that stream; *avg_ms = elapsed / reps.  prec selects the FP64 or
- * FP32 kernels.  Overwrites the plan's workspaces (not d_obs/x_out).
+ * Measurement helper: launch one kernel of the A apply, or of the block
+ * preconditioner (FILL_K_BAND, FILL_K_BLOCKMV, FILL_K_COMBINE: it must be
+ * built, and prec must be the plan's precision), `reps` times on the plan's
+ * stream with the arguments a CG iteration uses, bracketed by HIP events on
+ * that stream; *avg_ms = elapsed / reps.  prec selects the FP64 or FP32
+ * kernels.  Overwrites the plan's workspaces (not d_obs/x_out).
  */
 int fill_time_kernel(fill_plan plan, int kernel, int prec, int reps, double* avg_ms);
 

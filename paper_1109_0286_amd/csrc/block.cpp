@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <thread>
 
 namespace fillb {
@@ -280,15 +282,39 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
     return -1;
   }
 
-  // ---- combine tables
+  // ---- block product work items and their output segments
+  std::vector<size_t> segb(nb);  // seg offset of block b's first column chunk
+  for (int b = 0; b < nb; ++b) {
+    const int n = L->boff[b + 1] - L->boff[b], ncc = (n + BCOLS - 1) / BCOLS;
+    segb[b] = L->seg_total;
+    for (int cc = 0; cc < ncc; ++cc)
+      for (int r0 = 0; r0 < n; r0 += BROWS) {
+        L->items.push_back(b);
+        L->items.push_back(r0);
+        L->items.push_back(cc * BCOLS);
+        L->items.push_back((int)(L->seg_total + (size_t)cc * n));
+      }
+    L->seg_total += (size_t)n * ncc;
+  }
+  if (L->seg_total > (size_t)INT32_MAX) {
+    *err = "block preconditioner: too many block outputs";
+    return -1;
+  }
+
+  // ---- combine tables: every column chunk of every block covering an element
   L->cst.assign(n_m + 1, 0);
-  for (int b = 0; b < nb; ++b)
-    for (int i = L->boff[b]; i < L->boff[b + 1]; ++i) L->cst[L->bidx[i] + 1] += 1;
+  for (int b = 0; b < nb; ++b) {
+    const int n = L->boff[b + 1] - L->boff[b], ncc = (n + BCOLS - 1) / BCOLS;
+    for (int i = L->boff[b]; i < L->boff[b + 1]; ++i) L->cst[L->bidx[i] + 1] += ncc;
+  }
   for (int c = 0; c < n_m; ++c) L->cst[c + 1] += L->cst[c];
   L->cix.assign(L->cst[n_m], 0);
   std::vector<int> fill(L->cst.begin(), L->cst.end() - 1);
-  for (int b = 0; b < nb; ++b)
-    for (int i = L->boff[b]; i < L->boff[b + 1]; ++i) L->cix[fill[L->bidx[i]]++] = i;
+  for (int b = 0; b < nb; ++b) {
+    const int n = L->boff[b + 1] - L->boff[b], ncc = (n + BCOLS - 1) / BCOLS;
+    for (int i = 0; i < n; ++i)
+      for (int cc = 0; cc < ncc; ++cc) L->cix[fill[L->bidx[L->boff[b] + i]]++] = (int)(segb[b] + (size_t)cc * n + i);
+  }
   L->inb.assign(n_m, 0);
   for (const Run& r : L->runs)
     for (int c = r.cb0; c < r.cb0 + r.h * nx; ++c) L->inb[c] = 1;

@@ -33,6 +33,8 @@ constexpr int HALO = 4;      // Chebyshev growth of each cell into the mask
 constexpr int TILE = 16;     // cell grid for large pieces
 constexpr int CMAX = 1024;   // largest piece kept whole
 constexpr int NBMAX = 2048;  // largest block (dense inverse)
+constexpr int BROWS = 256;   // rows of a block product work item
+constexpr int BCOLS = 128;   // columns of a block product work item
 
 // Column stride of a block inverse of n pixels (16-byte aligned columns in FP32).
 inline int block_ld(int n) { return (n + 3) / 4 * 4; }
@@ -52,13 +54,18 @@ struct Layout {
   size_t fs_total = 0;         // values of all runs' streams (each of fwd and bwd)
   std::vector<double> fwd, bwd;
   // blocks
-  std::vector<int> boff;       // nblocks+1 offsets into bidx / seg
+  std::vector<int> boff;       // nblocks+1 offsets into bidx
   std::vector<int> bidx;       // compact indices of each block's pixels
+  // block product work items, 4 ints each: block, first row, first column,
+  // offset of the item's output rows in seg (the item's column chunk of the
+  // block has its own n outputs: seg holds sum_b n_b ceil(n_b / BCOLS) values)
+  std::vector<int> items;
+  size_t seg_total = 0;
   std::vector<size_t> moff;    // offsets of each block's inverse: n columns of stride block_ld(n)
   std::vector<double> binv;
   // combine: contributions of block entries to compact elements (CSR), band flags
   std::vector<int> cst;        // n_m+1
-  std::vector<int> cix;        // entries: positions in seg
+  std::vector<int> cix;        // entries: positions in seg (one per column chunk of each covering block)
   std::vector<uint8_t> inb;    // 1 if the element lies in a band run
   int max_run_pixels = 0;
 };

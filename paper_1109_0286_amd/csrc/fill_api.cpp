@@ -93,6 +93,8 @@ struct BlockDev {
   std::vector<int> run_prob;     // problem of each run
   int* run_prob_d = nullptr;
   int* block_prob = nullptr;     // problem of each block
+  int* items = nullptr;          // block product work items
+  int nitems = 0;
   fill_block_info info{};
   int max_hp = 0, nblocks = 0;
   int* brow_off = nullptr;
@@ -536,17 +538,27 @@ int block_setup(fill_plan p) {
     L.max_run_pixels = std::max(L.max_run_pixels, Lb.max_run_pixels);
     const int nbase = (int)L.bidx.size();
     const size_t mbase = L.binv.size();
+    const int bbase = (int)L.boff.size() - 1;
+    const size_t sbase = L.seg_total;
     for (size_t q = 1; q < Lb.boff.size(); ++q) {
       L.boff.push_back(Lb.boff[q] + nbase);
       L.moff.push_back(Lb.moff[q - 1] + mbase);
       block_prob.push_back(b);
     }
+    for (size_t q = 0; q < Lb.items.size(); q += 4) {
+      L.items.push_back(Lb.items[q] + bbase);
+      L.items.push_back(Lb.items[q + 1]);
+      L.items.push_back(Lb.items[q + 2]);
+      L.items.push_back((int)(Lb.items[q + 3] + sbase));
+    }
+    L.seg_total += Lb.seg_total;
+    if (L.seg_total > (size_t)INT32_MAX) return fail(FILL_EINVAL, "block preconditioner: too many block outputs");
     for (int c : Lb.bidx) L.bidx.push_back(c + co);
     L.binv.insert(L.binv.end(), Lb.binv.begin(), Lb.binv.end());
     const int ebase = L.cst.empty() ? 0 : L.cst.back();
     if (L.cst.empty()) L.cst.push_back(0);
     for (int c = 1; c <= Lb.n_m; ++c) L.cst.push_back(Lb.cst[c] + ebase);
-    for (int e : Lb.cix) L.cix.push_back(e + nbase);
+    for (int e : Lb.cix) L.cix.push_back((int)(e + sbase));
     L.inb.insert(L.inb.end(), Lb.inb.begin(), Lb.inb.end());
     L.n_m += Lb.n_m;
   }
@@ -577,6 +589,8 @@ int block_setup(fill_plan p) {
   FILL_TRY(bupload(p, &B.run_prob_d, run_prob));
   FILL_TRY(bupload(p, &B.block_prob, block_prob));
   FILL_TRY(bupload(p, &B.boff, L.boff));
+  FILL_TRY(bupload(p, &B.items, L.items));
+  B.nitems = (int)(L.items.size() / 4);
   FILL_TRY(bupload(p, &B.bidx, L.bidx));
   FILL_TRY(bupload(p, &B.moff, L.moff));
   FILL_TRY(bupload(p, &B.cst, L.cst));
@@ -587,7 +601,7 @@ int block_setup(fill_plan p) {
     FILL_TRY(balloc(p, &bt_raw, std::max<size_t>(L.bt_total, 1) * 2 * ts));
     B.Bt = bt_raw;
     uint8_t* seg_raw = nullptr;
-    FILL_TRY(balloc(p, &seg_raw, std::max<size_t>(L.bidx.size(), 1) * ts));
+    FILL_TRY(balloc(p, &seg_raw, std::max<size_t>(L.seg_total, 1) * ts));
     B.seg = seg_raw;
   }
   if (f32) {
@@ -625,9 +639,10 @@ int block_follow_pk(fill_plan p) {
 // r.z and r.r over the row blocks (part0/part1 may be null).  Launches: per
 // band run a forward row transform of its rows, the banded solves of every
 // (run, kx), per run the inverse row transform into z, the dense block
-// products and the combination.
+// products and the combination.  only >= 0 launches that kernel alone
+// (FILL_K_BAND, FILL_K_BLOCKMV or FILL_K_COMBINE: timing).
 template <typename T>
-int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGScalars* sc) {
+int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGScalars* sc, int only = -1) {
   BlockDev& B = p->blk;
   if (!B.built || (sizeof(T) == 4) != (p->prec == FILL_PREC_FP32_OP))
     return fail(FILL_EINVAL, "block preconditioner not built for this precision");
@@ -644,12 +659,28 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
     a.sc = sc ? sc + B.run_prob[q] : nullptr;
     return a;
   };
-  for (int q = 0; q < nruns; ++q) {
+  BlockArgs<T> bk;
+  bk.r = r;
+  bk.seg = static_cast<T*>(B.seg);
+  bk.items = B.items;
+  bk.boff = B.boff;
+  bk.bidx = B.bidx;
+  bk.moff = B.moff;
+  bk.binv = static_cast<const T*>(B.binv);
+  bk.block_prob = B.block_prob;
+  bk.sc = sc;
+  // (running the block products on a second stream beside the band solves
+  // was measured no faster: both are limited by the same memory system)
+  if (only < 0 || only == FILL_K_BLOCKMV)
+    FILL_TRY(timed_launch<T>(p, FILL_K_BLOCKMV, [&](hipEvent_t e0, hipEvent_t e1) {
+      return launch_block_mv<T>(bk, B.nitems, p->stream, e0, e1);
+    }));
+  for (int q = 0; q < nruns && only < 0; ++q) {
     RowArgs<T> a = run_args(q);
     a.v0 = const_cast<T*>(r);
     HIP_TRY(launch_r2c<T>(R2C_COMPACT, a, p->stream));
   }
-  if (nruns > 0) {
+  if (nruns > 0 && (only < 0 || only == FILL_K_BAND)) {
     BandArgs<T> ba;
     ba.Bt = static_cast<cplx<T>*>(B.Bt);
     ba.fwd = static_cast<const T*>(B.fwd);
@@ -664,23 +695,12 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
       return launch_band_solve<T>(ba, nruns, B.max_hp, p->stream, e0, e1);
     }));
   }
-  for (int q = 0; q < nruns; ++q) {
+  for (int q = 0; q < nruns && only < 0; ++q) {
     RowArgs<T> a = run_args(q);
     a.v0 = z;
     HIP_TRY(launch_c2r<T>(C2R_COMPACT, a, p->stream));
   }
-  BlockArgs<T> bk;
-  bk.r = r;
-  bk.seg = static_cast<T*>(B.seg);
-  bk.boff = B.boff;
-  bk.bidx = B.bidx;
-  bk.moff = B.moff;
-  bk.binv = static_cast<const T*>(B.binv);
-  bk.block_prob = B.block_prob;
-  bk.sc = sc;
-  FILL_TRY(timed_launch<T>(p, FILL_K_BLOCKMV, [&](hipEvent_t e0, hipEvent_t e1) {
-    return launch_block_mv<T>(bk, B.nblocks, p->stream, e0, e1);
-  }));
+  if (only >= 0 && only != FILL_K_COMBINE) return FILL_OK;
   const int nb = TypeSel<T>::nblk(p);
   CombArgs<T> cb;
   cb.z = z;
@@ -1336,6 +1356,23 @@ int time_kernel(fill_plan p, int kernel, int reps, double* avg_ms) {
     if (e == hipSuccess && kernel == FILL_K_PROJ) e = launch_proj<T>(false, am, p->stream);
     return e;
   };
+  if (kernel >= FILL_K_BAND) {  // block preconditioner kernels, on the CG vectors
+    if (!p->blk.built) return fail(FILL_EINVAL, "the block preconditioner is not built");
+    FILL_TRY(block_apply<T>(p, v.r, v.z, p->part0, p->part1, nullptr, kernel));  // warm-up
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, p->stream));
+    for (int i = 0; i < reps; ++i) FILL_TRY(block_apply<T>(p, v.r, v.z, p->part0, p->part1, nullptr, kernel));
+    HIP_TRY(hipEventRecord(e1, p->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
+    return FILL_OK;
+  }
   HIP_TRY(launch());  // warm-up
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1969,7 +2006,7 @@ int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t
 int fill_time_kernel(fill_plan p, int kernel, int prec, int reps, double* avg_ms) {
   g_last_error.clear();
   if (!p || !avg_ms || reps < 1) return fail(FILL_EINVAL, "bad argument");
-  if (kernel < FILL_K_R2C || kernel > FILL_K_PROJ) return fail(FILL_EINVAL, "unknown kernel");
+  if (kernel < FILL_K_R2C || kernel > FILL_K_COMBINE) return fail(FILL_EINVAL, "unknown kernel");
   if (prec == FILL_PREC_FP64) return time_kernel<double>(p, kernel, reps, avg_ms);
   if (prec == FILL_PREC_FP32_OP) return time_kernel<float>(p, kernel, reps, avg_ms);
   return fail(FILL_EINVAL, "unknown precision");

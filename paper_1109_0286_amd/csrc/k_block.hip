@@ -3,8 +3,8 @@
 //   band_solve_kernel  per (run, kx): solve (nx T_kx) u = rhat by the banded
 //                      factor L L^T, forward then backward substitution, in
 //                      place on the run's transposed row spectrum;
-//   block_mv_kernel    per (block, 256-row chunk): seg = A_b^-1 r_b (dense
-//                      inverse, FP32/FP64);
+//   block_mv_kernel    per work item (block, 256 rows, 128 columns): partial
+//                      products of A_b^-1 r_b (dense inverse, FP32/FP64);
 //   combine_kernel     per row block: z = band part (already in z on band
 //                      pixels) + the block entries covering each element, and
 //                      the FP64 partials of r.z and r.r.
@@ -52,10 +52,13 @@ __device__ __forceinline__ void load32(double (&f)[32], const double* p) {
 // One wave per (column kx of the run's spectrum, run).  Column 0 carries the
 // DC values in its real parts and the Nyquist values in its imaginary parts,
 // which use the factors of kx = 0 and kx = nx/2.  Window: lane k (mod 32) of
-// each half holds the element i + ((k - i) mod 32) (forward) or
-// i - ((i - k) mod 32) (backward) of the running right-hand side; the head
+// each half (real parts in lanes 0..31, imaginary parts in 32..63, one factor
+// stream read serving both) holds the element i + ((k - i) mod 32) (forward)
+// or i - ((i - k) mod 32) (backward) of the running right-hand side; the head
 // lane of step i (k = i mod 32) finishes element i, which every lane takes
-// with a lane read; the others subtract their coupling times it.
+// with a lane read; the others subtract their coupling times it.  The steps
+// are branch-free: each lane keeps its finished element of the chunk in a
+// register and the chunk's results are stored together.
 template <typename T>
 __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   extern __shared__ unsigned char band_smem[];
@@ -86,18 +89,18 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   for (int c0 = 0; c0 < hp; c0 += 32) {
     if (c0 + 32 < hp) load32(fn, F + c0 + 32);
     const T nxt = (c0 + 32 < hp) ? s[c0 + 32 + k] : T(0);
+    T yo = w;  // this lane's finished element of the chunk (c0 + k)
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
       const T tv = w * f[u];
       const T ylo = lane_value(tv, u), yhi = lane_value(tv, 32 + u);
       const T y = half ? yhi : ylo;
-      if (k == u) {
-        s[c0 + u] = y;
-        w = nxt;
-      } else {
-        w -= f[u] * y;
-      }
+      const bool head = k == u;
+      const T up = w - f[u] * y;
+      yo = head ? y : yo;
+      w = head ? nxt : up;
     }
+    s[c0 + k] = yo;
 #pragma unroll
     for (int u = 0; u < 32; ++u) f[u] = fn[u];
   }
@@ -110,19 +113,19 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   for (int c0 = 0; c0 < hp; c0 += 32) {
     if (c0 + 32 < hp) load32(fn, G + c0 + 32);
     const T nxt = (c0 + 64 <= hp) ? s[hp - 64 - c0 + k] : T(0);
+    T xo = w;  // this lane's finished element of the chunk (hp - 32 - c0 + k)
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
       const int hl = 31 - u;  // head lane of step i = hp - 1 - (c0 + u)
       const T tv = w * f[u];
       const T xlo = lane_value(tv, hl), xhi = lane_value(tv, 32 + hl);
       const T x = half ? xhi : xlo;
-      if (k == hl) {
-        s[hp - 1 - (c0 + u)] = x;
-        w = nxt;
-      } else {
-        w -= f[u] * x;
-      }
+      const bool head = k == hl;
+      const T up = w - f[u] * x;
+      xo = head ? x : xo;
+      w = head ? nxt : up;
     }
+    s[hp - 32 - c0 + k] = xo;
 #pragma unroll
     for (int u = 0; u < 32; ++u) f[u] = fn[u];
   }
@@ -130,10 +133,11 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   for (int i = lane; i < hp; i += 64) X[i] = cplx<T>{sre[i], sim[i]};
 }
 
-constexpr int kBlkThreads = 512;           // 8 waves
+constexpr int kBlkThreads = 256;           // 4 waves
 constexpr int kBlkWaves = kBlkThreads / 64;
-constexpr int kBlkRows = 256;              // rows per workgroup: 4 per lane
-constexpr int kBlkUnroll = 4;              // columns in flight per wave
+constexpr int kBlkRows = 256;              // rows of a work item: 4 per lane
+constexpr int kBlkCols = 128;              // columns of a work item
+constexpr int kBlkUnroll = 8;              // columns in flight per wave
 
 // 4 consecutive entries of a column (16-byte aligned in FP32).
 __device__ __forceinline__ void load4(float (&v)[4], const float* p) {
@@ -152,21 +156,24 @@ __device__ __forceinline__ void load4(double (&v)[4], const double* p) {
   v[3] = b.y;
 }
 
-// seg[o + i] = sum_j Ainv[j][i] r[bidx[o + j]] (the inverse is symmetric;
-// column j is contiguous with stride ld = 4 ceil(n / 4)).  Workgroup (chunk,
-// block) takes rows chunk*256 .. +255, lane l four consecutive rows, wave w
-// the columns j = w (mod 8), kBlkUnroll of them in flight; the waves' sums
-// are added in a fixed order (deterministic).
+// One workgroup per work item (block b, rows r0 .. r0+255, columns
+// c0 .. c0+127): seg[so + i] = sum_{j in the columns} Ainv[j][i] r[bidx[o + j]]
+// (the inverse is symmetric; column j is contiguous with stride
+// ld = 4 ceil(n / 4)).  Lane l takes four consecutive rows, wave w the
+// columns j = c0 + w (mod 4), kBlkUnroll of them in flight; the waves' sums
+// are added in a fixed order, and the column chunks' outputs by the
+// combination (deterministic).
 template <typename T>
 __global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
-  __shared__ T rv[kBlockMax];
+  __shared__ T rv[kBlkCols];
   __shared__ T red[kBlkWaves][kBlkRows];
-  const int b = blockIdx.y, t = threadIdx.x;
+  const int t = threadIdx.x;
+  const int* item = a.items + 4 * (size_t)blockIdx.x;
+  const int b = item[0], r0 = item[1], c0 = item[2], so = item[3];
   if (a.sc != nullptr && a.sc[a.block_prob[b]].done) return;
   const int o = a.boff[b], n = a.boff[b + 1] - o;
-  const int r0 = blockIdx.x * kBlkRows;
-  if (r0 >= n) return;
-  for (int j = t; j < n; j += kBlkThreads) rv[j] = a.r[a.bidx[o + j]];
+  const int c1 = min(n, c0 + kBlkCols);
+  if (t < c1 - c0) rv[t] = a.r[a.bidx[o + c0 + t]];
   __syncthreads();
   const int ld = (n + 3) / 4 * 4;
   const int w = t >> 6, lane = t & 63;
@@ -174,22 +181,22 @@ __global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
   T acc[4] = {T(0), T(0), T(0), T(0)};
   if (row < n) {
     const T* M = a.binv + a.moff[b] + row;
-    int j = w;
-    for (; j + (kBlkUnroll - 1) * kBlkWaves < n; j += kBlkUnroll * kBlkWaves) {
+    int j = c0 + w;
+    for (; j + (kBlkUnroll - 1) * kBlkWaves < c1; j += kBlkUnroll * kBlkWaves) {
       T v[kBlkUnroll][4];
 #pragma unroll
       for (int u = 0; u < kBlkUnroll; ++u) load4(v[u], M + (size_t)(j + u * kBlkWaves) * ld);
 #pragma unroll
       for (int u = 0; u < kBlkUnroll; ++u) {
-        const T rj = rv[j + u * kBlkWaves];
+        const T rj = rv[j + u * kBlkWaves - c0];
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] += v[u][e] * rj;
       }
     }
-    for (; j < n; j += kBlkWaves) {
+    for (; j < c1; j += kBlkWaves) {
       T v[4];
       load4(v, M + (size_t)j * ld);
-      const T rj = rv[j];
+      const T rj = rv[j - c0];
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[e] += v[e] * rj;
     }
@@ -197,11 +204,11 @@ __global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) red[w][4 * lane + e] = acc[e];
   __syncthreads();
-  if (t < kBlkRows && r0 + t < n) {
+  if (r0 + t < n) {
     T s = red[0][t];
 #pragma unroll
     for (int q = 1; q < kBlkWaves; ++q) s += red[q][t];
-    a.seg[o + r0 + t] = s;
+    a.seg[so + r0 + t] = s;
   }
 }
 
@@ -252,7 +259,7 @@ hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStr
 template <typename T>
 hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nblocks <= 0) return hipSuccess;
-  const dim3 grid((kBlockMax + kBlkRows - 1) / kBlkRows, nblocks);
+  const dim3 grid(nblocks);  // nblocks: work items
   if (e0) hipExtLaunchKernelGGL(block_mv_kernel<T>, grid, dim3(kBlkThreads), 0, s, e0, e1, 0, a);
   else hipLaunchKernelGGL(block_mv_kernel<T>, grid, dim3(kBlkThreads), 0, s, a);
   return hipGetLastError();

@@ -130,8 +130,9 @@ template <typename T> struct BandArgs {
 };
 template <typename T> struct BlockArgs {
   const T* r;             // compact input
-  T* seg;                 // per-block outputs
-  const int* boff;        // nblocks+1 offsets into bidx / seg
+  T* seg;                 // outputs of the work items
+  const int* items;       // work items: block, first row, first column, output offset
+  const int* boff;        // nblocks+1 offsets into bidx
   const int* bidx;        // compact indices of the blocks' pixels
   const size_t* moff;     // offsets of the n x n inverses
   const T* binv;

@@ -160,7 +160,7 @@ def test_lanczos_errors(F, grid64):
         plan.lanczos_extremes()  # nothing recorded
     with pytest.raises(F.FillError):
         F.fill_plan_set_lanczos(plan.handle, -1)
-    assert F.fill._lib.fill_plan_set_precond(plan.handle, 3) == F.FILL_EINVAL
+    assert F.fill._lib.fill_plan_set_precond(plan.handle, 4) == F.FILL_EINVAL
     assert F.fill._lib.fill_plan_set_precond(plan.handle, -1) == F.FILL_EINVAL
     plan.set_lanczos(16)
     plan.realize(dev(p.d_obs), p.seed, 1e-10)
