@@ -110,7 +110,6 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
     L->max_run_pixels = std::max(L->max_run_pixels, r.h * nx);
   }
   L->fwd.assign(L->fs_total, 0.0);
-  L->bwd.assign(L->fs_total, 0.0);
   if (!L->runs.empty()) {
     const double* t = tsym;
     std::atomic<int> bad{-1};
@@ -137,24 +136,18 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
             }
           }
         }
-        // streams, lane k, position i (forward, i ascending) or s (backward,
-        // i = hp-1-s descending); the head lane of step i is i mod 32 and
-        // reads 1/L(i,i); lane k != head holds window element i + d (forward,
-        // d = (k - i) mod 32) or i - d (backward, d = (i - k) mod 32) and reads
-        // its coupling L(i+d, i) or L(i, i-d).  Padded rows are the identity.
+        // stream of lane k, position i (forward substitution, i ascending):
+        // the head lane of step i is i mod 32 and reads 1/L(i,i); lane
+        // k != head holds window element i + d, d = (k - i) mod 32, and reads
+        // its coupling L(i+d, i).  Padded rows are the identity.  (The
+        // backward substitution reads the same streams across the lanes:
+        // entries i-31 .. i of lane i mod 32 hold row i of L.)
         for (int k = 0; k < 32; ++k) {
           double* f = L->fwd.data() + r.fs_off + ((size_t)kx * 32 + k) * hp;
-          double* g = L->bwd.data() + r.fs_off + ((size_t)kx * 32 + k) * hp;
           for (int i = 0; i < hp; ++i) {
             const int d = ((k - i) % 32 + 32) % 32;
             if (d == 0) f[i] = i < h ? 1.0 / l(i, i) : 1.0;
             else f[i] = (i + d < h && d < BW) ? l(i + d, i) : 0.0;
-          }
-          for (int s = 0; s < hp; ++s) {
-            const int i = hp - 1 - s;
-            const int d = ((i - k) % 32 + 32) % 32;
-            if (d == 0) g[s] = i < h ? 1.0 / l(i, i) : 1.0;
-            else g[s] = (i < h && i - d >= 0 && d < BW) ? l(i, i - d) : 0.0;
           }
         }
       });

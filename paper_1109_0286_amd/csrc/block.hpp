@@ -51,8 +51,8 @@ struct Layout {
   std::vector<Run> runs;
   std::vector<int> brow_off;   // per run: hp+1 compact offsets of the virtual rows
   size_t bt_total = 0;         // complex values of all runs' spectra
-  size_t fs_total = 0;         // values of all runs' streams (each of fwd and bwd)
-  std::vector<double> fwd, bwd;
+  size_t fs_total = 0;         // values of all runs' factor streams
+  std::vector<double> fwd;     // factor streams (see block.cpp)
   // blocks
   std::vector<int> boff;       // nblocks+1 offsets into bidx
   std::vector<int> bidx;       // compact indices of each block's pixels

@@ -58,7 +58,7 @@ int fail(int code, const std::string& msg) {
 
 constexpr uint64_t kRealizationStream = 0x52;
 constexpr int kChunk = 16;  // CG iterations between host polls (even: keeps the rho parity)
-constexpr int kChunkBlock = 4;  // the same with the block preconditioner (few iterations per solve)
+constexpr int kChunkBlock = 8;  // the same with the block preconditioner (few iterations per solve)
 constexpr int kMaxOuter = 60;
 
 template <typename T> struct Vecs {
@@ -101,7 +101,6 @@ struct BlockDev {
   int* bpos = nullptr;           // 0, 1, 2, ...: a run's pixel index relative to its first pixel
   void* Bt = nullptr;
   void* fwd = nullptr;
-  void* bwd = nullptr;
   int* run_hp = nullptr;
   size_t* run_bt = nullptr;
   size_t* run_fs = nullptr;
@@ -534,7 +533,6 @@ int block_setup(fill_plan p) {
     L.bt_total += Lb.bt_total;
     L.fs_total += Lb.fs_total;
     L.fwd.insert(L.fwd.end(), Lb.fwd.begin(), Lb.fwd.end());
-    L.bwd.insert(L.bwd.end(), Lb.bwd.begin(), Lb.bwd.end());
     L.max_run_pixels = std::max(L.max_run_pixels, Lb.max_run_pixels);
     const int nbase = (int)L.bidx.size();
     const size_t mbase = L.binv.size();
@@ -606,11 +604,9 @@ int block_setup(fill_plan p) {
   }
   if (f32) {
     FILL_TRY(bupload_as<float>(p, &B.fwd, L.fwd));
-    FILL_TRY(bupload_as<float>(p, &B.bwd, L.bwd));
     FILL_TRY(bupload_as<float>(p, &B.binv, L.binv));
   } else {
     FILL_TRY(bupload_as<double>(p, &B.fwd, L.fwd));
-    FILL_TRY(bupload_as<double>(p, &B.bwd, L.bwd));
     FILL_TRY(bupload_as<double>(p, &B.binv, L.binv));
   }
   B.info.runs = (int)L.runs.size();
@@ -619,7 +615,7 @@ int block_setup(fill_plan p) {
   B.info.block_pixels = (int64_t)L.bidx.size();
   B.info.block_entries = (int64_t)L.binv.size();
   B.info.elem_bytes = (int)ts;
-  B.info.bytes = (int64_t)((L.fwd.size() + L.bwd.size() + L.binv.size() + L.bidx.size() + 2 * L.bt_total) * ts +
+  B.info.bytes = (int64_t)((L.fwd.size() + L.binv.size() + L.bidx.size() + 2 * L.bt_total) * ts +
                            (L.brow_off.size() + bpos.size() + L.boff.size() + L.bidx.size() + L.cst.size() +
                             L.cix.size()) * sizeof(int) + L.inb.size());
   B.built = true;
@@ -684,7 +680,6 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
     BandArgs<T> ba;
     ba.Bt = static_cast<cplx<T>*>(B.Bt);
     ba.fwd = static_cast<const T*>(B.fwd);
-    ba.bwd = static_cast<const T*>(B.bwd);
     ba.run_hp = B.run_hp;
     ba.run_bt = B.run_bt;
     ba.run_fs = B.run_fs;

@@ -77,9 +77,8 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   __syncthreads();
   T* s = half ? sim : sre;
   const int kx = (col == 0 && half) ? a.ncol : col;
-  const size_t so = a.run_fs[run] + ((size_t)kx * 32 + k) * hp;
-  const T* F = a.fwd + so;
-  const T* G = a.bwd + so;
+  const T* F0 = a.fwd + a.run_fs[run] + (size_t)kx * 32 * hp;  // this frequency's 32 lane streams
+  const T* F = F0 + (size_t)k * hp;
 
   // forward: L y = rhat.  The element that enters lane k's slot during a
   // chunk (c0 + 32 + k) is read from LDS at the chunk's start.
@@ -107,11 +106,23 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   __syncthreads();
 
   // backward: L^T x = y (the element entering lane k's slot during a chunk
-  // is hp - 64 - c0 + k)
+  // is hp - 64 - c0 + k).  Step i needs row i of L: L(i, i - d) for the lane
+  // holding element i - d, d = (i - k) mod 32, and 1/L(i, i) for the head
+  // lane; these are the entries i - 31 .. i of lane (i mod 32)'s forward
+  // stream, read here across the lanes
+  auto back_load = [&](T (&g)[32], int c) {
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int hl = 31 - u, i = hp - 1 - (c + u);
+      // lanes past the first row (pos < 0) hold nothing: any in-range entry will do
+      const int pos = i - ((hl - k) & 31);
+      g[u] = F0[(size_t)hl * hp + (pos < 0 ? 0 : pos)];
+    }
+  };
   w = s[hp - 32 + k];
-  load32(f, G);
+  back_load(f, 0);
   for (int c0 = 0; c0 < hp; c0 += 32) {
-    if (c0 + 32 < hp) load32(fn, G + c0 + 32);
+    if (c0 + 32 < hp) back_load(fn, c0 + 32);
     const T nxt = (c0 + 64 <= hp) ? s[hp - 64 - c0 + k] : T(0);
     T xo = w;  // this lane's finished element of the chunk (hp - 32 - c0 + k)
 #pragma unroll

@@ -120,7 +120,6 @@ constexpr int kBlockMax = 2048;  // largest block (dense inverse)
 template <typename T> struct BandArgs {
   cplx<T>* Bt;            // the runs' transposed row spectra, run r at run_bt[r]: [nx/2][hp]
   const T* fwd;           // factor streams, run r at run_fs[r]: [(nx/2+1)*32][hp]
-  const T* bwd;
   const int* run_hp;      // padded rows of each run (multiple of 32)
   const size_t* run_bt;
   const size_t* run_fs;
