@@ -407,11 +407,14 @@ __device__ __forceinline__ double unit_open(uint64_t w) {
 }
 
 // Standard normal at row-major pixel index i for (seed, stream).
+// Box-Muller: one standard normal from two 64-bit words.
+__device__ __forceinline__ double box_muller(uint64_t a, uint64_t b) {
+  return sqrt(-2.0 * log(unit_open(a))) * cos(2.0 * 3.14159265358979323846 * unit_open(b));
+}
+
 __device__ __forceinline__ double white_noise_at(uint64_t i, uint64_t seed, uint64_t stream) {
   const u64x4 w = philox4x64_10(i >> 1, 0, 0, 0, seed, stream);
-  const uint64_t a = (i & 1) ? w.w2 : w.w0;
-  const uint64_t b = (i & 1) ? w.w3 : w.w1;
-  return sqrt(-2.0 * log(unit_open(a))) * cos(2.0 * 3.14159265358979323846 * unit_open(b));
+  return (i & 1) ? box_muller(w.w2, w.w3) : box_muller(w.w0, w.w1);
 }
 
 // ---------------------------------------------------------------------------

@@ -134,13 +134,18 @@ struct fill_plan_s {
   int hist_cap = 0;
   double* hist = nullptr;
   std::vector<int> hist_n;
-  // the 16-iteration inner-CG chunk as a HIP graph, captured on first use per
-  // [FP32?][preconditioner + 4 * CG variant][coefficient record] and replayed
-  // by every solve
+  // inner-CG chunks (an even number of iterations, 2..16) as HIP graphs,
+  // captured on first use per [FP32?][preconditioner + 4 * CG variant]
+  // [coefficient record][length / 2] and replayed by every solve
   int use_graph = 1;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph[2][8][2] = {};
-  hipGraphExec_t graph_exec[2][8][2] = {};
+  hipGraph_t graph[2][8][2][9] = {};
+  hipGraphExec_t graph_exec[2][8][2][9] = {};
+  // iterations of the last inner solve per [FP32?][refinement step]: the
+  // length of the first chunk of the next one
+  int pred_iters[2][4] = {};
+  int cur_outer = 0;
+  double* h_rr = nullptr;  // host copy of the r.r partials (pinned)
   int nblk64 = 0, nblk32 = 0;
 
   uint8_t* mask = nullptr;
@@ -368,8 +373,8 @@ int upload_params(fill_plan p) {
 // captured on a private stream on first use (launch helpers follow
 // p->stream, which is switched to that stream for the capture).
 template <typename F>
-int chunk_graph(fill_plan p, int f32, int mode, int rec, F&& chunk, hipGraphExec_t* out) {
-  hipGraphExec_t& ex = p->graph_exec[f32][mode][rec];
+int chunk_graph(fill_plan p, int f32, int mode, int rec, int len, F&& chunk, hipGraphExec_t* out) {
+  hipGraphExec_t& ex = p->graph_exec[f32][mode][rec][len / 2];
   if (!ex) {
     if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     const hipStream_t saved = p->stream;
@@ -391,7 +396,7 @@ int chunk_graph(fill_plan p, int f32, int mode, int rec, F&& chunk, hipGraphExec
       (void)hipGraphDestroy(g);
       return fail(FILL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
     }
-    p->graph[f32][mode][rec] = g;
+    p->graph[f32][mode][rec][len / 2] = g;
   }
   *out = ex;
   return FILL_OK;
@@ -401,12 +406,13 @@ int chunk_graph(fill_plan p, int f32, int mode, int rec, F&& chunk, hipGraphExec
 void drop_graphs(fill_plan p, bool record_only) {
   for (int a = 0; a < 2; ++a)
     for (int m = 0; m < 8; ++m)
-      for (int r = record_only ? 1 : 0; r < 2; ++r) {
-        if (p->graph_exec[a][m][r]) (void)hipGraphExecDestroy(p->graph_exec[a][m][r]);
-        if (p->graph[a][m][r]) (void)hipGraphDestroy(p->graph[a][m][r]);
-        p->graph_exec[a][m][r] = nullptr;
-        p->graph[a][m][r] = nullptr;
-      }
+      for (int r = record_only ? 1 : 0; r < 2; ++r)
+        for (int l = 0; l < 9; ++l) {
+          if (p->graph_exec[a][m][r][l]) (void)hipGraphExecDestroy(p->graph_exec[a][m][r][l]);
+          if (p->graph[a][m][r][l]) (void)hipGraphDestroy(p->graph[a][m][r][l]);
+          p->graph_exec[a][m][r][l] = nullptr;
+          p->graph[a][m][r][l] = nullptr;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -719,24 +725,55 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
 }
 
 // Run inner-CG chunks (graph replays, or direct launches) until every problem
-// is done; per-problem iteration counts and statuses.
-template <typename F>
-int run_chunks(fill_plan p, hipGraphExec_t exec, F&& chunk, std::vector<int>& iters, std::vector<int>& status) {
+// is done: a first chunk of len0 iterations, then chunks of len1; chunk(len)
+// launches one directly, exec(len) returns its graph or null.  After each
+// chunk the host reads the device state and, with rr_part (the r.r partials
+// of the last iteration, nb per problem), also ends a problem whose r.r meets
+// its tolerance: the device would only see that at the next chunk's first
+// step.  Per-problem iteration counts and statuses.
+template <typename C, typename E>
+int run_chunks(fill_plan p, int len0, int len1, C&& chunk, E&& exec, const double* rr_part, int nb,
+               std::vector<int>& iters, std::vector<int>& status) {
   const int np = p->nprob;
+  std::vector<int> host_done(np, 0), it_done(np, 0);
+  static const int one = 1;
+  int len = len0;
   for (;;) {
-    if (exec) HIP_TRY(hipGraphLaunch(exec, p->stream));
-    else FILL_TRY(chunk());
+    hipGraphExec_t ex = nullptr;
+    FILL_TRY(exec(len, &ex));
+    if (ex) HIP_TRY(hipGraphLaunch(ex, p->stream));
+    else FILL_TRY(chunk(len));
     HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
+    if (rr_part) {
+      if (!p->h_rr) HIP_TRY(hipHostMalloc((void**)&p->h_rr, (size_t)np * p->ny * sizeof(double), hipHostMallocDefault));
+      HIP_TRY(hipMemcpyAsync(p->h_rr, rr_part, (size_t)np * p->ny * sizeof(double), hipMemcpyDeviceToHost,
+                             p->stream));
+    }
     HIP_TRY(hipStreamSynchronize(p->stream));
     bool all = true;
-    for (int b = 0; b < np; ++b) all = all && p->h_sc[b].done;
+    for (int b = 0; b < np; ++b) {
+      if (p->h_sc[b].done || host_done[b]) continue;
+      if (rr_part) {
+        double rr = 0.0;
+        for (int i = 0; i < nb; ++i) rr += p->h_rr[(size_t)b * p->ny + i];
+        if (rr <= p->h_sc[b].tol2) {
+          host_done[b] = 1;
+          it_done[b] = p->h_sc[b].iter;
+          // stop it on the device too (other problems may run more chunks)
+          HIP_TRY(hipMemcpyAsync(&p->sc[b].done, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
+          continue;
+        }
+      }
+      all = false;
+    }
     if (all) break;
+    len = len1;
   }
   iters.resize(np);
   status.resize(np);
   for (int b = 0; b < np; ++b) {
-    iters[b] = p->h_sc[b].iter;
-    status[b] = p->h_sc[b].status;
+    iters[b] = host_done[b] ? it_done[b] : p->h_sc[b].iter;
+    status[b] = host_done[b] ? 0 : p->h_sc[b].status;
   }
   return FILL_OK;
 }
@@ -834,18 +871,21 @@ int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status
     u.hist = hist;
     u.hist_cap = p->hist_cap;
   }
-  auto chunk = [&]() -> int {
-    for (int k = 0; k < kChunk; ++k) {
+  auto chunk = [&](int len) -> int {
+    for (int k = 0; k < len; ++k) {
       const RowArgs<T>& u = up[k & 1];
       FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(R2C_CG1UPDATE, u, p->stream, a, b); }));
       FILL_TRY(tail(p->sc));
     }
     return FILL_OK;
   };
-  hipGraphExec_t exec = nullptr;
-  if (p->use_graph && p->timed_kernel < 0)
-    FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode + 4, hist != nullptr, chunk, &exec));
-  return run_chunks(p, exec, chunk, iters, status);
+  auto exec = [&](int len, hipGraphExec_t* out) -> int {
+    *out = nullptr;
+    if (p->use_graph && p->timed_kernel < 0)
+      FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode + 4, hist != nullptr, len, [&]() { return chunk(len); }, out));
+    return FILL_OK;
+  };
+  return run_chunks(p, kChunk, kChunk, chunk, exec, nullptr, nb, iters, status);
 }
 
 // Inner preconditioned CG for every active problem on A d = r (r in v.r with
@@ -929,8 +969,8 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   e_out.part1 = p->part1;
   e_out.sc = p->sc;
 
-  auto chunk = [&]() -> int {
-    for (int k = 0; k < (mode == FILL_PRECOND_BLOCK ? kChunkBlock : kChunk); ++k) {
+  auto chunk = [&](int len) -> int {
+    for (int k = 0; k < len; ++k) {
       const int par = k & 1;
       FILL_TRY(apply3<T>(p, R2C_PUPDATE, pa_in[par], Dinv, C2R_COMPACT, pa_out, p->sc, p->skew));
       if (mode == FILL_PRECOND_SPLIT) FILL_TRY(apply_EE<T>(p, R2C_XRUPDATE, e_in[par], e_mid, e_out, p->sc));
@@ -947,9 +987,22 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   // Every argument of the chunk is a plan-owned pointer or a constant, so the
   // chunk is captured once and replayed (not while a kernel is being timed:
   // timed launches carry their own events).
-  hipGraphExec_t exec = nullptr;
-  if (p->use_graph && p->timed_kernel < 0) FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode, hist != nullptr, chunk, &exec));
-  return run_chunks(p, exec, chunk, iters, status);
+  auto exec = [&](int len, hipGraphExec_t* out) -> int {
+    *out = nullptr;
+    if (p->use_graph && p->timed_kernel < 0)
+      FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode, hist != nullptr, len, [&]() { return chunk(len); }, out));
+    return FILL_OK;
+  };
+  // chunk lengths: even (the rho parity), the first one the length of the
+  // same refinement step's last inner solve
+  const int len1 = mode == FILL_PRECOND_BLOCK ? kChunkBlock : kChunk;
+  const int pred = p->pred_iters[sizeof(T) == 4][std::min(p->cur_outer, 3)];
+  const int len0 = pred > 0 ? std::min(16, std::max(2, (pred + 1) / 2 * 2)) : len1;
+  FILL_TRY(run_chunks(p, len0, len1, chunk, exec, p->part1, nb, iters, status));
+  int mx = 0;
+  for (int b = 0; b < np; ++b) mx = std::max(mx, iters[b]);
+  p->pred_iters[sizeof(T) == 4][std::min(p->cur_outer, 3)] = mx;
+  return FILL_OK;
 }
 
 // Solve A u = v for every problem (v, u compact FP64), each to true relative residual rtol.
@@ -963,6 +1016,7 @@ int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
   std::vector<int> it, st;
   p->hist_n.assign(np, 0);
   bool first = true;
+  int pass = 0;
   for (int b = 0; b < np; ++b) {
     p->pstats[b].iters_inner = 0;
     p->pstats[b].iters_outer = 0;
@@ -1011,6 +1065,7 @@ int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
     }
     if (nactive == 0) break;
     FILL_TRY(upload_params(p));
+    p->cur_outer = pass++;
     if (p->prec == FILL_PREC_FP64) {
       HIP_TRY(launch_scale_f64(p->v64.r, p->res, p->dp.scale, p->comp_off, p->n_m_max, np, p->stream));
       FILL_TRY(inner_pcg<double>(p, it, st, first));
@@ -1773,6 +1828,7 @@ void fill_plan_destroy(fill_plan p) {
   for (void* a : p->allocs) (void)hipFree(a);
   for (void* a : p->blk.allocs) (void)hipFree(a);
   if (p->h_sc) (void)hipHostFree(p->h_sc);
+  if (p->h_rr) (void)hipHostFree(p->h_rr);
   if (p->h_sum) (void)hipHostFree(p->h_sum);
   if (p->par_host) (void)hipHostFree(p->par_host);
   delete p;

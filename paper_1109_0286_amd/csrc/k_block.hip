@@ -5,7 +5,7 @@
 //                      place on the run's transposed row spectrum;
 //   block_mv_kernel    per work item (block, 256 rows, 128 columns): partial
 //                      products of A_b^-1 r_b (dense inverse, FP32/FP64);
-//   combine_kernel     per row block: z = band part (already in z on band
+//   combine_kernel     per slice of the compact range: z = band part (already in z on band
 //                      pixels) + the block entries covering each element, and
 //                      the FP64 partials of r.z and r.r.
 // The row transforms of the band runs are the r2c / c2r kernels of the
@@ -229,9 +229,11 @@ template <typename T>
 __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
   const int blk = blockIdx.x, pb = blockIdx.y;
   if (a.sc != nullptr && a.sc[pb].done) return;
-  const int* ro = a.row_off + (size_t)pb * (a.ny + 1);
+  // equal slices of the problem's compact range (as many as row blocks)
+  const long long nm = a.row_off[(size_t)pb * (a.ny + 1) + a.ny];
+  const int nblk = gridDim.x;
   const int base = a.comp_off ? a.comp_off[pb] : 0;
-  const int c0 = base + ro[blk * a.rows], c1 = base + ro[(blk + 1) * a.rows];
+  const int c0 = base + (int)(nm * blk / nblk), c1 = base + (int)(nm * (blk + 1) / nblk);
   double acc0 = 0.0, acc1 = 0.0;
   for (int c = c0 + (int)threadIdx.x; c < c1; c += kCombThreads) {
     T zc = a.inb[c] ? a.z[c] : T(0);

@@ -538,18 +538,31 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
       v[e] = C{ldr[(2 * l) * N + x], ldr[(2 * l + 1) * N + x]};
     }
     __syncthreads();
-  } else {
+  } else if constexpr (MODE == R2C_FULL) {
     const size_t ra = (size_t)(y0 + 2 * l) * a.nx, rb = ra + a.nx;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int x = tid + e * TPL;
-      if constexpr (MODE == R2C_FULL) {
-        v[e] = C{(T)a.full_in[ra + x], (T)a.full_in[rb + x]};
-      } else {
-        v[e] = C{(T)white_noise_at(ra + x, a.seed, a.stream), (T)white_noise_at(rb + x, a.seed, a.stream)};
-      }
+      v[e] = C{(T)a.full_in[ra + x], (T)a.full_in[rb + x]};
     }
     tw_stage<PL>(twq, a.tw, t, NT);  // after the row loads: one round trip for both
+  } else {
+    // white noise: pixels 2j and 2j+1 share one Philox block, so each thread
+    // draws whole pairs of the row block into LDS, then takes its elements
+    const uint64_t pair0 = ((uint64_t)y0 * a.nx) >> 1;  // nx is even
+    for (int j = t; j < ROWS * N / 2; j += NT) {
+      const u64x4 w = philox4x64_10(pair0 + j, 0, 0, 0, a.seed, a.stream);
+      ldr[2 * j] = (T)box_muller(w.w0, w.w1);
+      ldr[2 * j + 1] = (T)box_muller(w.w2, w.w3);
+    }
+    tw_stage<PL>(twq, a.tw, t, NT);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = tid + e * TPL;
+      v[e] = C{ldr[(2 * l) * N + x], ldr[(2 * l + 1) * N + x]};
+    }
+    __syncthreads();  // the FFT reuses the LDS
   }
 
   C* line = lds + l * LE;
@@ -973,8 +986,9 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
 // alpha = rho / (p.q) (partials in red0), x += alpha p, r -= alpha q, then the
 // per-block partial sums of r.r into part0 and part1 (r.z = r.r), which the
 // next p = r + beta p pass reads.  INIT only sums the current r.  Block b of
-// grid.x covers the compact range of rows [b*rows, (b+1)*rows), the row
-// blocks of the row passes, so both passes see the same number of partials.
+// grid.x covers the b-th of grid.x equal slices of the problem's compact
+// range; there are as many as row blocks of the row passes, so both passes
+// see the same number of partials.
 constexpr int kXrThreads = 256;
 
 template <typename T, bool INIT>
@@ -987,8 +1001,11 @@ __global__ __launch_bounds__(kXrThreads) void xr_kernel(RowArgs<T> a_in, int row
     coef = (T)cg_scalar_step<R2C_XRUPDATE, kXrThreads>(a, &stop);
     if (stop) return;
   }
-  const int blk = blockIdx.x;
-  const int c0 = a.row_off[blk * rows], c1 = a.row_off[(blk + 1) * rows];
+  // equal slices of the problem's compact range (row blocks would leave the
+  // few workgroups on a band with nearly all the work)
+  const int blk = blockIdx.x, nblk = gridDim.x;
+  const long long nm = a.row_off[(size_t)nblk * rows];
+  const int c0 = (int)(nm * blk / nblk), c1 = (int)(nm * (blk + 1) / nblk);
   double acc = 0.0, unused = 0.0;
   for (int c = c0 + (int)threadIdx.x; c < c1; c += kXrThreads) {
     T r;
