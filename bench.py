@@ -655,16 +655,20 @@ def main() -> int:
                          "point sources only, CG with and without the preconditioner; hermiticity: plain CG on a "
                          "deliberately non-Hermitian operator vs eps and kappa; strips2048: noise-boosted strip "
                          "refinement vs the exact fill")
-    ap.add_argument("--precond", default="block", choices=list(PRECONDS),
+    ap.add_argument("--precond", default=None, choices=list(PRECONDS),
                     help="inner-CG preconditioner (every workload): block (per-frequency band solves plus "
-                         "dense blocks, default), cxx (Px C Px), split (E E, the paper's split form) or none; "
-                         "the 2048^2 line also times the others")
+                         "dense blocks, the default), cxx (Px C Px, the default for grad16, whose spectrum "
+                         "changes every step: the block preconditioner would be rebuilt on the host each "
+                         "time), split (E E, the paper's split form) or none; the 2048^2 line also times "
+                         "the others")
     ap.add_argument("--cg", default="standard", choices=list(CGS),
                     help="inner-CG recurrence (every workload): standard (Hestenes-Stiefel) or single "
                          "(single-reduction, one launch fewer per iteration); the 2048^2 line times both")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with three plain 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
+    if args.precond is None:
+        args.precond = "cxx" if args.workload == "grad16" else "block"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); batches and Monte-Carlo "
               "draws would shard across GPUs by problem, which this build does not launch.", file=sys.stderr)

@@ -101,6 +101,9 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
     }
   }
   const int ncol = nx / 2, nk = nx / 2 + 1;
+  // 32 zeros before the first stream: the backward substitution's loads for
+  // the lanes past the first row reach up to 31 values before a stream
+  if (!L->runs.empty()) L->fs_total = 32;
   for (Run& r : L->runs) {
     r.bt_off = L->bt_total;
     L->bt_total += (size_t)ncol * r.hp;
@@ -136,18 +139,20 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
             }
           }
         }
-        // stream of lane k, position i (forward substitution, i ascending):
-        // the head lane of step i is i mod 32 and reads 1/L(i,i); lane
+        // The factor is stored unit-diagonal, L = Lu D (Lu(i, j) = L(i, j) /
+        // L(j, j)).  Stream of lane k, position i (forward substitution, i
+        // ascending): the head lane of step i is i mod 32 and reads
+        // 1/L(i,i)^2 (the scaling between the two substitutions); lane
         // k != head holds window element i + d, d = (k - i) mod 32, and reads
-        // its coupling L(i+d, i).  Padded rows are the identity.  (The
+        // its coupling Lu(i+d, i).  Padded rows are the identity.  (The
         // backward substitution reads the same streams across the lanes:
-        // entries i-31 .. i of lane i mod 32 hold row i of L.)
+        // entries i-31 .. i-1 of lane i mod 32 hold row i of Lu.)
         for (int k = 0; k < 32; ++k) {
           double* f = L->fwd.data() + r.fs_off + ((size_t)kx * 32 + k) * hp;
           for (int i = 0; i < hp; ++i) {
             const int d = ((k - i) % 32 + 32) % 32;
-            if (d == 0) f[i] = i < h ? 1.0 / l(i, i) : 1.0;
-            else f[i] = (i + d < h && d < BW) ? l(i + d, i) : 0.0;
+            if (d == 0) f[i] = i < h ? 1.0 / (l(i, i) * l(i, i)) : 1.0;
+            else f[i] = (i + d < h && d < BW) ? l(i + d, i) / l(i, i) : 0.0;
           }
         }
       });

@@ -18,8 +18,10 @@
 // The applies of the band factors run as two sequential substitutions, one
 // wave per (run, kx): lanes 0..31 carry the real parts, 32..63 the imaginary
 // parts, lane k holding the window element j = k (mod 32).  The factor is
-// stored as one stream per (kx, lane) in the order the substitution uses it
-// (see block.cpp), so each lane reads its own contiguous stream.
+// stored unit-diagonal (L = Lu D, D^-2 in the diagonal slots) as one stream
+// per (kx, lane) in the order the forward substitution uses it (see
+// block.cpp), so each lane reads its own contiguous stream; 32 zeros precede
+// the first run's streams.
 #pragma once
 
 #include <cstdint>

@@ -10,6 +10,8 @@
 //                      the FP64 partials of r.z and r.r.
 // The row transforms of the band runs are the r2c / c2r kernels of the
 // operator, launched on each run's rows as a grid of its own.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -17,14 +19,32 @@ namespace fillk {
 
 namespace {
 
-__device__ __forceinline__ float lane_value(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+// Lane U of the caller's half of the wave (lanes 0..31 get lane U, lanes
+// 32..63 get lane 32 + U).  FP32: two lane reads and a select; FP64:
+// ds_swizzle in bit mode (and_mask 0, or_mask U: every lane reads lane U of
+// its group of 32) on both words, which measured faster there than four
+// lane reads.
+template <int U>
+__device__ __forceinline__ float half_lane(float v, bool hi) {
+  const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), U));
+  const float up = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + U));
+  return hi ? up : lo;
 }
-__device__ __forceinline__ double lane_value(double v, int l) {
+template <int U>
+__device__ __forceinline__ double half_lane(double v, bool) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), U << 5);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), U << 5);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Calls fn(std::integral_constant<int, U>) for U = B .. E-1 in order.
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
 }
 
 // 32 consecutive values of one lane's stream (aligned to 32 elements).
@@ -51,14 +71,19 @@ __device__ __forceinline__ void load32(double (&f)[32], const double* p) {
 
 // One wave per (column kx of the run's spectrum, run).  Column 0 carries the
 // DC values in its real parts and the Nyquist values in its imaginary parts,
-// which use the factors of kx = 0 and kx = nx/2.  Window: lane k (mod 32) of
-// each half (real parts in lanes 0..31, imaginary parts in 32..63, one factor
-// stream read serving both) holds the element i + ((k - i) mod 32) (forward)
-// or i - ((i - k) mod 32) (backward) of the running right-hand side; the head
-// lane of step i (k = i mod 32) finishes element i, which every lane takes
-// with a lane read; the others subtract their coupling times it.  The steps
-// are branch-free: each lane keeps its finished element of the chunk in a
-// register and the chunk's results are stored together.
+// which use the factors of kx = 0 and kx = nx/2.  The factor is stored
+// unit-diagonal, L = Lu D: the forward pass solves Lu z = rhat and keeps
+// z D^-2 = D^-1 y, the right-hand side of the backward pass Lu^T x = D^-1 y.
+// Window: lane k (mod 32) of each half (real parts in lanes 0..31, imaginary
+// parts in 32..63, one factor stream read serving both) holds the element
+// i + ((k - i) mod 32) (forward) or i - ((i - k) mod 32) (backward) of the
+// running right-hand side; the head lane of step i (k = i mod 32) holds the
+// finished element i, which every lane of its half takes with a lane read,
+// the others subtracting their coupling times it.  The steps are
+// branch-free: each lane keeps its finished element of the chunk in a
+// register and the chunk's results are stored together; the factor entries
+// of the next chunk are loaded during the current one (two register sets
+// taking turns).
 template <typename T>
 __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   extern __shared__ unsigned char band_smem[];
@@ -79,66 +104,70 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   const int kx = (col == 0 && half) ? a.ncol : col;
   const T* F0 = a.fwd + a.run_fs[run] + (size_t)kx * 32 * hp;  // this frequency's 32 lane streams
   const T* F = F0 + (size_t)k * hp;
+  T w;
+  T fa[32], fb[32];
 
-  // forward: L y = rhat.  The element that enters lane k's slot during a
-  // chunk (c0 + 32 + k) is read from LDS at the chunk's start.
-  T w = s[k];
-  T f[32], fn[32];
-  load32(f, F);
-  for (int c0 = 0; c0 < hp; c0 += 32) {
+  // forward: Lu z = rhat, stored as z D^-2 (lane k's stream holds D^-2 of
+  // element i at the steps i where k is the head).  The element that enters
+  // lane k's slot during a chunk (c0 + 32 + k) is read from LDS at the
+  // chunk's start.
+  auto fwd_chunk = [&](const T (&f)[32], T (&fn)[32], int c0) {
     if (c0 + 32 < hp) load32(fn, F + c0 + 32);
     const T nxt = (c0 + 32 < hp) ? s[c0 + 32 + k] : T(0);
-    T yo = w;  // this lane's finished element of the chunk (c0 + k)
-#pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const T tv = w * f[u];
-      const T ylo = lane_value(tv, u), yhi = lane_value(tv, 32 + u);
-      const T y = half ? yhi : ylo;
+    T zo = w, dg = T(1);  // this lane's finished element of the chunk (c0 + k) and its D^-2
+    static_for<0, 32>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const T z = half_lane<u>(w, half);
       const bool head = k == u;
-      const T up = w - f[u] * y;
-      yo = head ? y : yo;
+      const T up = w - f[u] * z;
+      zo = head ? w : zo;
+      dg = head ? f[u] : dg;
       w = head ? nxt : up;
-    }
-    s[c0 + k] = yo;
-#pragma unroll
-    for (int u = 0; u < 32; ++u) f[u] = fn[u];
+    });
+    s[c0 + k] = zo * dg;
+  };
+  w = s[k];
+  load32(fa, F);
+  for (int c0 = 0; c0 < hp; c0 += 64) {
+    fwd_chunk(fa, fb, c0);
+    if (c0 + 32 < hp) fwd_chunk(fb, fa, c0 + 32);
   }
   __syncthreads();
 
-  // backward: L^T x = y (the element entering lane k's slot during a chunk
-  // is hp - 64 - c0 + k).  Step i needs row i of L: L(i, i - d) for the lane
-  // holding element i - d, d = (i - k) mod 32, and 1/L(i, i) for the head
-  // lane; these are the entries i - 31 .. i of lane (i mod 32)'s forward
-  // stream, read here across the lanes
-  auto back_load = [&](T (&g)[32], int c) {
+  // backward: Lu^T x = D^-1 y (the element entering lane k's slot during a
+  // chunk is hp - 64 - c0 + k).  Step i = hp - 1 - (c0 + u) needs row i of
+  // Lu: Lu(i, i - d) for the lane holding element i - d, d = (i - k) mod 32,
+  // which is entry i - d of the forward stream of lane hl = i mod 32 = 31 - u
+  // (hp is a multiple of 32).  Its offset from F0 + hp - 63 - c0 is po[u]
+  // below, the same for every chunk; lanes past the first row read the
+  // zero guard or the previous stream and hold nothing that is used.
+  unsigned po[32];
 #pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int hl = 31 - u, i = hp - 1 - (c + u);
-      // lanes past the first row (pos < 0) hold nothing: any in-range entry will do
-      const int pos = i - ((hl - k) & 31);
-      g[u] = F0[(size_t)hl * hp + (pos < 0 ? 0 : pos)];
-    }
+  for (int u = 0; u < 32; ++u) po[u] = (unsigned)(31 * hp + 62 - u * (hp + 1) - ((31 - u - k) & 31));
+  auto back_load = [&](T (&g)[32], int c0) {
+    const T* Fb = F0 + (hp - 63 - c0);
+#pragma unroll
+    for (int u = 0; u < 32; ++u) g[u] = Fb[po[u]];
   };
-  w = s[hp - 32 + k];
-  back_load(f, 0);
-  for (int c0 = 0; c0 < hp; c0 += 32) {
+  auto bwd_chunk = [&](const T (&f)[32], T (&fn)[32], int c0) {
     if (c0 + 32 < hp) back_load(fn, c0 + 32);
     const T nxt = (c0 + 64 <= hp) ? s[hp - 64 - c0 + k] : T(0);
     T xo = w;  // this lane's finished element of the chunk (hp - 32 - c0 + k)
-#pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int hl = 31 - u;  // head lane of step i = hp - 1 - (c0 + u)
-      const T tv = w * f[u];
-      const T xlo = lane_value(tv, hl), xhi = lane_value(tv, 32 + hl);
-      const T x = half ? xhi : xlo;
+    static_for<0, 32>([&](auto uc) {
+      constexpr int u = decltype(uc)::value, hl = 31 - u;  // head lane of step i = hp - 1 - (c0 + u)
+      const T x = half_lane<hl>(w, half);
       const bool head = k == hl;
       const T up = w - f[u] * x;
-      xo = head ? x : xo;
+      xo = head ? w : xo;
       w = head ? nxt : up;
-    }
+    });
     s[hp - 32 - c0 + k] = xo;
-#pragma unroll
-    for (int u = 0; u < 32; ++u) f[u] = fn[u];
+  };
+  w = s[hp - 32 + k];
+  back_load(fa, 0);
+  for (int c0 = 0; c0 < hp; c0 += 64) {
+    bwd_chunk(fa, fb, c0);
+    if (c0 + 32 < hp) bwd_chunk(fb, fa, c0 + 32);
   }
   __syncthreads();
   for (int i = lane; i < hp; i += 64) X[i] = cplx<T>{sre[i], sim[i]};
