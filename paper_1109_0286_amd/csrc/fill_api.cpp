@@ -796,8 +796,7 @@ int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status
   const bool pre = mode != FILL_PRECOND_NONE;
   double* hist = record && p->hist_cap > 0 ? p->hist : nullptr;
   const size_t vb = (size_t)std::max(p->n_m_total, 1) * sizeof(T);
-  HIP_TRY(hipMemsetAsync(v.x, 0, vb, p->stream));
-  HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
+  // r holds the scaled residual and x = p = 0 (the caller's scale pass)
   HIP_TRY(hipMemsetAsync(v.q, 0, vb, p->stream));
   // without a preconditioner the r.r partials of the r2c pass alternate
   // between two buffers by iteration parity
@@ -889,8 +888,8 @@ int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status
 }
 
 // Inner preconditioned CG for every active problem on A d = r (r in v.r with
-// ||r|| = 1, d in v.x); tolerances, caps and the active set are in the device
-// parameters.  Returns per-problem iteration counts and statuses.
+// ||r|| = 1, d in v.x; x and p are zero on entry); tolerances, caps and the
+// active set are in the device parameters.  Returns per-problem iteration counts and statuses.
 template <typename T>
 int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bool record) {
   if (p->cg_variant == FILL_CG_SINGLE_REDUCTION && p->precond != FILL_PRECOND_BLOCK)
@@ -900,9 +899,7 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   const T* Dinv = TypeSel<T>::Dinv(p);
   const int mode = p->precond;
   double* hist = record && p->hist_cap > 0 ? p->hist : nullptr;
-  const size_t vb = (size_t)std::max(p->n_m_total, 1) * sizeof(T);
-  HIP_TRY(hipMemsetAsync(v.x, 0, vb, p->stream));
-  HIP_TRY(hipMemsetAsync(v.p, 0, vb, p->stream));
+  // r holds the scaled residual and x = p = 0 (the caller's scale pass)
 
   // z = M^-1 r: E (E r), Px C Px r, or r without a preconditioner; the
   // partial sums (r.z, r.r) feed the first iteration
@@ -1008,9 +1005,7 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
 // Solve A u = v for every problem (v, u compact FP64), each to true relative residual rtol.
 int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
   const int np = p->nprob;
-  const size_t nb8 = (size_t)std::max(p->n_m_total, 1) * sizeof(double);
-  HIP_TRY(hipMemsetAsync(p->u, 0, nb8, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->res, p->b, nb8, hipMemcpyDeviceToDevice, p->stream));
+  // the first refinement step scales v itself (res = v - A 0) and clears u
   std::vector<double> rnorm2 = bnorm2, prev(np, 1.0);
   std::vector<int> total(np, 0), outer(np, 0), done(np, 0), status(np, FILL_OK);
   std::vector<int> it, st;
@@ -1063,15 +1058,20 @@ int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
       p->hp.cap[b] = p->max_iter - total[b];
       ++nactive;
     }
-    if (nactive == 0) break;
+    if (nactive == 0) {
+      if (first) HIP_TRY(hipMemsetAsync(p->u, 0, (size_t)std::max(p->n_m_total, 1) * sizeof(double), p->stream));
+      break;
+    }
     FILL_TRY(upload_params(p));
     p->cur_outer = pass++;
     if (p->prec == FILL_PREC_FP64) {
-      HIP_TRY(launch_scale_f64(p->v64.r, p->res, p->dp.scale, p->comp_off, p->n_m_max, np, p->stream));
+      HIP_TRY(launch_scale_init_f64(p->v64.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v64.x, p->v64.p,
+                                    first ? p->u : nullptr, p->n_m_max, np, p->stream));
       FILL_TRY(inner_pcg<double>(p, it, st, first));
       HIP_TRY(launch_axpy_f64(p->u, p->v64.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
     } else {
-      HIP_TRY(launch_scale_to_f32(p->v32.r, p->res, p->dp.scale, p->comp_off, p->n_m_max, np, p->stream));
+      HIP_TRY(launch_scale_init_f32(p->v32.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v32.x, p->v32.p,
+                                    first ? p->u : nullptr, p->n_m_max, np, p->stream));
       FILL_TRY(inner_pcg<float>(p, it, st, first));
       HIP_TRY(launch_axpy_f32(p->u, p->v32.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
     }

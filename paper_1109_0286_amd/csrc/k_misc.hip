@@ -59,6 +59,23 @@ __global__ void k_scale(TO* out, const TI* in, const double* scale, const int* c
     out[c] = (TO)((double)in[c] * s);
 }
 
+// out = s in, with z0 and z1 (and zu when given) cleared over the same range
+// (the start of an inner solve: r = scaled residual, x = p = 0; on the first
+// refinement step also the FP64 solution u = 0).
+template <typename TO>
+__global__ void k_scale_init(TO* out, const double* in, const double* scale, const int* comp_off, TO* z0, TO* z1,
+                             double* zu) {
+  const int b = blockIdx.y;
+  const int c0 = comp_off[b], c1 = comp_off[b + 1];
+  const double s = scale[b];
+  for (int c = c0 + blockIdx.x * blockDim.x + threadIdx.x; c < c1; c += gridDim.x * blockDim.x) {
+    out[c] = (TO)(in[c] * s);
+    z0[c] = TO(0);
+    z1[c] = TO(0);
+    if (zu) zu[c] = 0.0;
+  }
+}
+
 template <typename TX>
 __global__ void k_axpy(double* y, const TX* x, const double* a, const int* comp_off) {
   const int b = blockIdx.y;
@@ -131,6 +148,18 @@ hipError_t launch_scale_to_f32(float* out, const double* in, const double* scale
 hipError_t launch_scale_f64(double* out, const double* in, const double* scale, const int* comp_off, int nmax,
                             int nprob, hipStream_t s) {
   hipLaunchKernelGGL((k_scale<double, double>), grid_for(nmax, nprob), dim3(256), 0, s, out, in, scale, comp_off);
+  return hipGetLastError();
+}
+hipError_t launch_scale_init_f32(float* out, const double* in, const double* scale, const int* comp_off, float* z0,
+                                 float* z1, double* zu, int nmax, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_init<float>), grid_for(nmax, nprob), dim3(256), 0, s, out, in, scale, comp_off, z0, z1,
+                     zu);
+  return hipGetLastError();
+}
+hipError_t launch_scale_init_f64(double* out, const double* in, const double* scale, const int* comp_off, double* z0,
+                                 double* z1, double* zu, int nmax, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_init<double>), grid_for(nmax, nprob), dim3(256), 0, s, out, in, scale, comp_off, z0, z1,
+                     zu);
   return hipGetLastError();
 }
 hipError_t launch_axpy_f64(double* y, const double* x, const double* a, const int* comp_off, int nmax, int nprob,

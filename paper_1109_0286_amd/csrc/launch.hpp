@@ -50,6 +50,11 @@ hipError_t launch_scale_to_f32(float* out, const double* in, const double* scale
                                int nprob, hipStream_t s);
 hipError_t launch_scale_f64(double* out, const double* in, const double* scale, const int* comp_off, int nmax,
                             int nprob, hipStream_t s);
+// out = scale * in, z0 = z1 = 0 (and zu = 0 when not null) over every problem's range
+hipError_t launch_scale_init_f32(float* out, const double* in, const double* scale, const int* comp_off, float* z0,
+                                 float* z1, double* zu, int nmax, int nprob, hipStream_t s);
+hipError_t launch_scale_init_f64(double* out, const double* in, const double* scale, const int* comp_off, double* z0,
+                                 double* z1, double* zu, int nmax, int nprob, hipStream_t s);
 hipError_t launch_axpy_f64(double* y, const double* x, const double* a, const int* comp_off, int nmax, int nprob,
                            hipStream_t s);
 hipError_t launch_axpy_f32(double* y, const float* x, const double* a, const int* comp_off, int nmax, int nprob,
