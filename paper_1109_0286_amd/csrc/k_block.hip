@@ -254,6 +254,52 @@ __global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
 
 constexpr int kCombThreads = 1024;
 
+// z[c] += the covering block entries of element c, taken four at a time (the
+// four index loads, then the four value loads, then the additions in order).
+template <typename T>
+__device__ __forceinline__ T add_entries(const CombArgs<T>& a, T zc, int e, int e1) {
+  for (; e + 4 <= e1; e += 4) {
+    const int i0 = a.cix[e], i1 = a.cix[e + 1], i2 = a.cix[e + 2], i3 = a.cix[e + 3];
+    const T s0 = a.seg[i0], s1 = a.seg[i1], s2 = a.seg[i2], s3 = a.seg[i3];
+    zc += s0;
+    zc += s1;
+    zc += s2;
+    zc += s3;
+  }
+  for (; e < e1; ++e) zc += a.seg[a.cix[e]];
+  return zc;
+}
+
+// 4 consecutive values at p (16-byte aligned in FP32, 32 in FP64).
+__device__ __forceinline__ void ld4(float (&v)[4], const float* p) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+__device__ __forceinline__ void ld4(double (&v)[4], const double* p) {
+  const double2 q0 = *reinterpret_cast<const double2*>(p);
+  const double2 q1 = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = q0.x;
+  v[1] = q0.y;
+  v[2] = q1.x;
+  v[3] = q1.y;
+}
+__device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
+  *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+}
+
+// One workgroup per equal slice of a problem's compact range.  In a slice of
+// at least 4 elements per thread, elements up to the first multiple of 4 and
+// after the last one go one per thread and the rest four consecutive ones per
+// thread, with vector loads of the band flags, z, r and the CSR starts (most
+// elements are band pixels with no block entry); smaller slices go one
+// element per thread.
 template <typename T>
 __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
   const int blk = blockIdx.x, pb = blockIdx.y;
@@ -263,16 +309,48 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
   const int nblk = gridDim.x;
   const int base = a.comp_off ? a.comp_off[pb] : 0;
   const int c0 = base + (int)(nm * blk / nblk), c1 = base + (int)(nm * (blk + 1) / nblk);
+  const int t = threadIdx.x;
   double acc0 = 0.0, acc1 = 0.0;
-  for (int c = c0 + (int)threadIdx.x; c < c1; c += kCombThreads) {
+  auto one = [&](int c) {
     T zc = a.inb[c] ? a.z[c] : T(0);
-    const int e1 = a.cst[c + 1];
-    for (int e = a.cst[c]; e < e1; ++e) zc += a.seg[a.cix[e]];
+    zc = add_entries(a, zc, a.cst[c], a.cst[c + 1]);
     a.z[c] = zc;
     const double rc = (double)a.r[c];
     acc0 += rc * (double)zc;
     acc1 += rc * rc;
+  };
+  // groups of 4 only where every thread gets at least one (small slices keep
+  // one element per thread: more elements in flight)
+  const bool quads = c1 - c0 >= 4 * kCombThreads;
+  const int ca = quads ? min(c1, (c0 + 3) & ~3) : c1;  // first multiple of 4
+  const int cb = ca + ((c1 - ca) & ~3);                // end of the groups of 4
+  for (int c = c0 + t; c < ca; c += kCombThreads) one(c);
+  for (int c = ca + 4 * t; c < cb; c += 4 * kCombThreads) {
+    const uchar4 fl = *reinterpret_cast<const uchar4*>(a.inb + c);
+    const int4 st = *reinterpret_cast<const int4*>(a.cst + c);
+    const int se = a.cst[c + 4];
+    T zv[4], rv[4];
+    ld4(zv, a.z + c);
+    ld4(rv, a.r + c);
+    zv[0] = fl.x ? zv[0] : T(0);
+    zv[1] = fl.y ? zv[1] : T(0);
+    zv[2] = fl.z ? zv[2] : T(0);
+    zv[3] = fl.w ? zv[3] : T(0);
+    if (se != st.x) {
+      zv[0] = add_entries(a, zv[0], st.x, st.y);
+      zv[1] = add_entries(a, zv[1], st.y, st.z);
+      zv[2] = add_entries(a, zv[2], st.z, st.w);
+      zv[3] = add_entries(a, zv[3], st.w, se);
+    }
+    st4(a.z + c, zv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double rc = (double)rv[k];
+      acc0 += rc * (double)zv[k];
+      acc1 += rc * rc;
+    }
   }
+  for (int c = cb + t; c < c1; c += kCombThreads) one(c);
   if (a.part0) {
     block_sum2<kCombThreads>(acc0, acc1);
     if (threadIdx.x == 0) {

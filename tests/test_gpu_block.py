@@ -2,7 +2,8 @@
 
 * M^-1 applied on the GPU (FILL_OP_MINV) equals the oracle's block
   preconditioner element by element: a short band (no truncation), a tall
-  band (truncated Toeplitz per kx), holes across the periodic edges, a piece
+  band (truncated Toeplitz per kx), two band runs in one problem, holes
+  across the periodic edges, a piece
   cut into cells, a fully masked row that is not a band, and the 256^2 / 512^2
   band + holes workloads; FP64 to 1e-9, FP32 to the bar below;
 * the fill with it reaches the oracle's solution (1e-9 FP64 at rtol 1e-12,
@@ -78,6 +79,16 @@ def case(name):
         m[180:230, 50:100] = 1  # 2500 pixels: cut into cells
         m[5, :127] = 1         # a row that is masked but for one pixel
         return m, P
+    if name == "two":
+        # two band runs in one problem (a tall one and a short one) and a hole
+        # between them: the second run's factor streams follow the first's
+        ny, nx = 256, 64
+        P = W.damped_power_law(nx, ny, 2.0, 10.0, 1e-6)
+        m = np.zeros((ny, nx), np.uint8)
+        m[20:60] = 1
+        m[150:170] = 1
+        disk(m, 100, 30, 5)
+        return m, P
     p = W.make_problem("grid2048", n=int(name))
     return p.mask, p.P
 
@@ -89,11 +100,13 @@ def plan_block(F, mask, P, prec):
     return plan
 
 
-@pytest.mark.parametrize("name", ["short", "mix", "256", "512"])
+@pytest.mark.parametrize("name", ["short", "mix", "two", "256", "512"])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-3)])
 def test_minv_matches_oracle(F, name, prec, tol):
     mask, P = case(name)
     M = B.BlockPrecond(mask, P)
+    if name == "two":
+        assert M.runs == [(20, 40), (150, 20)]
     rng = np.random.default_rng(11)
     r = np.where(mask != 0, rng.standard_normal(mask.shape), 0.0)
     ref = M.apply(r)
