@@ -149,7 +149,8 @@ int fill_plan_create_batch(int nx, int ny, int nprob, const uint8_t* masks, cons
 int fill_plan_nprob(fill_plan plan);
 
 /* Replace the spectrum of an existing plan (host Pk, same layout/rules; n_pk
- * tables as at creation). */
+ * tables as at creation).  A spectrum equal bit for bit to the plan's current
+ * one is a no-op (no upload, no preconditioner rebuild). */
 int fill_plan_set_pk(fill_plan plan, const double* Pk);
 
 /* Iteration cap of the CG solves (default 20000 summed over refinement steps). */
@@ -431,8 +432,10 @@ int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t
  * strictly increasing), ln P(k) piecewise linear in ln k between nodes and
  * constant outside [lnk_nodes[0], lnk_nodes[nbands-1]] (k = 0 takes
  * theta[0]).  Computes the tables of every problem of the plan from theta
- * (host arrays; replaces any previous spectrum).  The model stands in for
- * the paper's P = w C + N (Sec. 3) when the spectrum is to be differentiated.
+ * (host arrays; replaces any previous spectrum; tables equal bit for bit to
+ * the current ones are not uploaded again and do not rebuild the block
+ * preconditioner).  The model stands in for the paper's P = w C + N (Sec. 3)
+ * when the spectrum is to be differentiated.
  */
 int fill_plan_set_bands(fill_plan plan, int nbands, const double* lnk_nodes, const double* theta);
 

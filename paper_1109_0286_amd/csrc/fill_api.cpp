@@ -1720,9 +1720,17 @@ int fill_plan_create_batch(int nx, int ny, int nprob, const uint8_t* masks, cons
 
 int fill_plan_nprob(fill_plan p) { return p ? p->nprob : 0; }
 
+// True if Pk (npk tables) equals the spectrum the plan holds, bit for bit:
+// then there is nothing to upload and no preconditioner to rebuild.
+bool same_pk(fill_plan p, const double* Pk) {
+  const size_t n = (size_t)p->npk * p->nt;
+  return p->hpk.size() == n && std::memcmp(p->hpk.data(), Pk, n * sizeof(double)) == 0;
+}
+
 int fill_plan_set_pk(fill_plan p, const double* Pk) {
   g_last_error.clear();
   if (!p || !Pk) return fail(FILL_EINVAL, "NULL argument");
+  if (same_pk(p, Pk)) return FILL_OK;
   HIP_TRY(hipStreamSynchronize(p->stream));
   FILL_TRY(upload_pk(p, Pk, p->npk));
   return block_follow_pk(p);
@@ -1934,6 +1942,7 @@ int fill_plan_set_bands(fill_plan p, int nbands, const double* lnk_nodes, const 
     p->nbands = nbands;
   }
   HIP_TRY(hipMemcpy(p->lnk, lnk_nodes, nbands * sizeof(double), hipMemcpyHostToDevice));
+  if (same_pk(p, Pk.data())) return FILL_OK;
   FILL_TRY(upload_pk(p, Pk.data(), p->npk));
   return block_follow_pk(p);
 }

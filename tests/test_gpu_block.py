@@ -202,6 +202,11 @@ def test_new_spectrum_rebuilds(F):
     mask, P = case("256")
     d = W.observed_map(P, 256, 256, 9, mask)
     plan = plan_block(F, mask, P, 0)
+    info = plan.block_info()
+    plan.set_pk(P.copy())  # the same spectrum: a no-op
+    assert plan.block_info() == info
+    x = host(plan.realize(dev(d), 3, 1e-12))
+    assert rel(x, OF.fill_realize(d, mask, P, 3, 1e-13).x_out, mask != 0) < 1e-9
     P2 = W.damped_power_law(256, 256, 1.0, 40.0, 1e-6)
     plan.set_pk(P2)
     x = host(plan.realize(dev(d), 3, 1e-12))
