@@ -657,10 +657,10 @@ def main() -> int:
                          "refinement vs the exact fill")
     ap.add_argument("--precond", default=None, choices=list(PRECONDS),
                     help="inner-CG preconditioner (every workload): block (per-frequency band solves plus "
-                         "dense blocks, the default), cxx (Px C Px, the default for grad16, whose spectrum "
-                         "changes every step: the block preconditioner would be rebuilt on the host each "
-                         "time), split (E E, the paper's split form) or none; the 2048^2 line also times "
-                         "the others")
+                         "dense blocks, the default), cxx (Px C Px, the default for grad16: with the band "
+                         "model's spectrum the block preconditioner takes more iterations, and it is rebuilt "
+                         "on the host whenever the band powers change), split (E E, the paper's split form) "
+                         "or none; the 2048^2 line also times the others")
     ap.add_argument("--cg", default="standard", choices=list(CGS),
                     help="inner-CG recurrence (every workload): standard (Hestenes-Stiefel) or single "
                          "(single-reduction, one launch fewer per iteration); the 2048^2 line times both")
