@@ -184,7 +184,7 @@ int fill_plan_set_inner_tol(fill_plan plan, double tol);
  *                       and factored by banded Cholesky); every other
  *                       connected piece of the mask (4-neighbours, periodic;
  *                       pieces over 1024 pixels are cut into 16 x 16 cells),
- *                       grown by 4 pixels into the mask, is solved exactly by a
+ *                       grown by 8 pixels into the mask, is solved exactly by a
  *                       dense inverse (at most 2048 pixels).  Selecting it
  *                       builds these on the host from the kernel of C^-1 (one
  *                       GPU apply), in the plan's precision; the time and

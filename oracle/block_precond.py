@@ -13,7 +13,7 @@ symmetric Toeplitz system per frequency kx.  The solution it leads to is the
 same (it only changes the CG path); the definition below fixes the operator so
 that the GPU's application of it can be checked element by element.
 
-Definition (parameters BW = 32, HALO = 4, TILE = 16, CMAX = 1024, NBMAX = 2048):
+Definition (parameters BW = 32, HALO = 8, TILE = 16, CMAX = 1024, NBMAX = 2048):
 
 1. Band runs: maximal runs of consecutive rows y0..y0+h-1 (not wrapping)
    whose every pixel is masked, with h <= ny - 2 BW.
@@ -47,7 +47,7 @@ import scipy.ndimage as ndi
 __all__ = ["BW", "HALO", "TILE", "CMAX", "NBMAX", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
            "BlockPrecond", "pcg_block"]
 
-BW, HALO, TILE, CMAX, NBMAX = 32, 4, 16, 1024, 2048
+BW, HALO, TILE, CMAX, NBMAX = 32, 8, 16, 1024, 2048
 
 
 def kernel_cinv(P: np.ndarray) -> np.ndarray:

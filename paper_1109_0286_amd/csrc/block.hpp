@@ -31,7 +31,7 @@
 namespace fillb {
 
 constexpr int BW = 32;       // band bandwidth (one window lane per coupled row)
-constexpr int HALO = 4;      // Chebyshev growth of each cell into the mask
+constexpr int HALO = 8;      // Chebyshev growth of each cell into the mask
 constexpr int TILE = 16;     // cell grid for large pieces
 constexpr int CMAX = 1024;   // largest piece kept whole
 constexpr int NBMAX = 2048;  // largest block (dense inverse)
