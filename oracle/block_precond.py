@@ -13,17 +13,21 @@ symmetric Toeplitz system per frequency kx.  The solution it leads to is the
 same (it only changes the CG path); the definition below fixes the operator so
 that the GPU's application of it can be checked element by element.
 
-Definition (parameters BW = 32, HALO = 8, TILE = 16, CMAX = 1024, NBMAX = 2048):
+Definition (parameters BW = 32, HALO = 8, TILE = 16, CMAX = 1024, NBMAX = 2048,
+PIVOT_MIN = 1e-9):
 
 1. Band runs: maximal runs of consecutive rows y0..y0+h-1 (not wrapping)
    whose every pixel is masked, with h <= ny - 2 BW.
 2. Band part, per run and per kx = 0..nx/2:
    t_kx(d) = sum_dx k(d mod ny, dx) cos(2 pi kx dx / nx)   (real: k is even
    in dx and, for spectra symmetric under ky -> -ky, in dy), T_kx[i, j] =
-   t_kx(i - j) for |i - j| < BW and 0 beyond, plus sigma_kx on the diagonal,
-   sigma_kx = 2 sum_{d = BW}^{h-1} |t_kx(d)|: a bound (Gershgorin) on the norm
-   of the discarded part, so that T_kx stays positive definite however slowly
-   t_kx decays (sigma_kx = 0 when h <= BW); the band rows' part of M^-1 r is
+   t_kx(i - j) for |i - j| < BW and 0 beyond, plus sigma_kx on the diagonal.
+   sigma_kx = 0 if the truncated matrix is safely positive definite: every
+   pivot of its Cholesky factorization exceeds PIVOT_MIN times its diagonal
+   entry t_kx(0); otherwise sigma_kx = 2 sum_{d = BW}^{h-1} |t_kx(d)|, a bound
+   (Gershgorin) on the norm of the discarded part, so that T_kx stays positive
+   definite however slowly t_kx decays (the shift costs iterations where it
+   is not needed).  The band rows' part of M^-1 r is
    IDFT_x(T_kx^-1 DFT_x(r on the run)).
 3. The other masked pixels (outside band runs) split into connected components
    (4-neighbours, periodic); a component of more than CMAX pixels, or whose
@@ -44,10 +48,11 @@ import numpy as np
 import scipy.fft as sfft
 import scipy.ndimage as ndi
 
-__all__ = ["BW", "HALO", "TILE", "CMAX", "NBMAX", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
+__all__ = ["BW", "HALO", "TILE", "CMAX", "NBMAX", "PIVOT_MIN", "safely_pd", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
            "BlockPrecond", "pcg_block"]
 
 BW, HALO, TILE, CMAX, NBMAX = 32, 8, 16, 1024, 2048
+PIVOT_MIN = 1e-9
 
 
 def kernel_cinv(P: np.ndarray) -> np.ndarray:
@@ -142,6 +147,16 @@ def blocks(mask: np.ndarray, cell_list: list) -> list:
     return out
 
 
+def safely_pd(T: np.ndarray) -> bool:
+    """True if the Cholesky factorization of the symmetric matrix T has every
+    pivot L_ii^2 above PIVOT_MIN T_ii (False if it breaks down)."""
+    try:
+        L = np.linalg.cholesky(T)
+    except np.linalg.LinAlgError:
+        return False
+    return bool(np.all(np.diag(L) ** 2 > PIVOT_MIN * np.diag(T)))
+
+
 class BlockPrecond:
     """M^-1 of the definition above for one mask and spectrum (FP64)."""
 
@@ -157,8 +172,9 @@ class BlockPrecond:
             d = np.abs(np.arange(h)[:, None] - np.arange(h)[None, :])
             Ts = np.zeros((nx // 2 + 1, h, h))
             for kx in range(nx // 2 + 1):
-                sigma = 2.0 * np.abs(t[bw:h, kx]).sum()
-                Ts[kx] = np.where(d < bw, t[d, kx], 0.0) + sigma * np.eye(h)
+                Ts[kx] = np.where(d < bw, t[d, kx], 0.0)
+                if not safely_pd(Ts[kx]):
+                    Ts[kx] += 2.0 * np.abs(t[bw:h, kx]).sum() * np.eye(h)
             self.band_T.append(Ts)
         self.cells = cells(mask, self.runs)
         self.blocks = blocks(mask, self.cells)

@@ -119,24 +119,34 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
     for (const Run& r : L->runs) {
       const int h = r.h, hp = r.hp;
       parallel_for(nk, [&](int kx) {
-        double sigma = 0.0;  // Gershgorin bound of the part beyond the bandwidth
-        for (int d = BW; d < h; ++d) sigma += 2.0 * std::fabs(t[(size_t)d * nk + kx]);
-        // banded Cholesky of nx T_kx: Lb[i*BW + d] = L(i, i-d)
+        // banded Cholesky of nx T_kx: Lb[i*BW + d] = L(i, i-d); false if a
+        // pivot is not above pivot_min (its square root is not taken then)
         std::vector<double> Lb((size_t)h * BW, 0.0);
         auto l = [&](int i, int j) -> double& { return Lb[(size_t)i * BW + (i - j)]; };
-        for (int i = 0; i < h; ++i) {
-          for (int j = std::max(0, i - BW + 1); j <= i; ++j) {
-            double s = (double)nx * (t[(size_t)(i - j) * nk + kx] + (i == j ? sigma : 0.0));
-            for (int m = std::max(0, i - BW + 1); m < j; ++m) s -= l(i, m) * l(j, m);
-            if (i == j) {
-              if (!(s > 0.0)) {
-                bad = kx;
-                return;
+        auto factor = [&](double sigma, double pivot_min) {
+          for (int i = 0; i < h; ++i) {
+            for (int j = std::max(0, i - BW + 1); j <= i; ++j) {
+              double s = (double)nx * (t[(size_t)(i - j) * nk + kx] + (i == j ? sigma : 0.0));
+              for (int m = std::max(0, i - BW + 1); m < j; ++m) s -= l(i, m) * l(j, m);
+              if (i == j) {
+                if (!(s > pivot_min)) return false;
+                l(i, i) = std::sqrt(s);
+              } else {
+                l(i, j) = s / l(j, j);
               }
-              l(i, i) = std::sqrt(s);
-            } else {
-              l(i, j) = s / l(j, j);
             }
+          }
+          return true;
+        };
+        // the plain truncation where it is safely positive definite (every
+        // pivot above PIVOT_MIN times the diagonal nx t_kx(0)), else the
+        // shift by the Gershgorin bound of the part beyond the bandwidth
+        if (!factor(0.0, PIVOT_MIN * (double)nx * t[kx])) {
+          double sigma = 0.0;
+          for (int d = BW; d < h; ++d) sigma += 2.0 * std::fabs(t[(size_t)d * nk + kx]);
+          if (!factor(sigma, 0.0)) {
+            bad = kx;
+            return;
           }
         }
         // The factor is stored unit-diagonal, L = Lu D (Lu(i, j) = L(i, j) /

@@ -6,8 +6,10 @@
 //               per kx = 0..nx/2 the matrix nx T_kx, T_kx[i][j] = t_kx(i - j)
 //               for |i - j| < BW plus sigma_kx on the diagonal, where
 //               t_kx(d) = sum_dx k(d, dx) cos(2 pi kx dx/nx) (k the kernel of
-//               C^-1) and sigma_kx = 2 sum_{BW <= d < h} |t_kx(d)| bounds the
-//               discarded part (keeps T_kx positive definite), factored as
+//               C^-1); sigma_kx = 0 if every Cholesky pivot of the truncation
+//               exceeds PIVOT_MIN times its diagonal, else
+//               sigma_kx = 2 sum_{BW <= d < h} |t_kx(d)|, which bounds the
+//               discarded part (keeps T_kx positive definite); factored as
 //               L L^T (banded Cholesky);
 //   cells       connected pieces (4-neighbours, periodic) of the masked pixels
 //               outside the runs; a piece of more than CMAX pixels, or whose
@@ -35,6 +37,7 @@ constexpr int HALO = 8;      // Chebyshev growth of each cell into the mask
 constexpr int TILE = 16;     // cell grid for large pieces
 constexpr int CMAX = 1024;   // largest piece kept whole
 constexpr int NBMAX = 2048;  // largest block (dense inverse)
+constexpr double PIVOT_MIN = 1e-9;  // band truncation kept unshifted if every Cholesky pivot exceeds this x diagonal
 constexpr int BROWS = 256;   // rows of a block product work item
 constexpr int BCOLS = 128;   // columns of a block product work item
 

@@ -6,8 +6,10 @@
   parts found by brute-force flood fill and dilation;
 * on a band taller than the bandwidth, each x-frequency goes through the
   truncated Toeplitz matrix formed from the dense covariance, shifted by the
-  Gershgorin bound of the discarded part; with a slowly decaying kernel the
-  plain truncation is indefinite and the shifted one is not;
+  Gershgorin bound of the discarded part unless the truncation is safely
+  positive definite (decided here from eigenvalues); with a slowly decaying
+  kernel some frequencies' plain truncation is indefinite and gets the shift,
+  the others keep the plain truncation;
 * exactness: band-only and single-hole masks give M^-1 A = I;
 * M^-1 is symmetric positive definite;
 * structure: periodic components, tiling above CMAX, band-run rules;
@@ -120,6 +122,19 @@ def test_short_band_and_holes_equal_sum_of_inverses():
     assert np.abs(Md - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
+def expected_shift(T, t):
+    """The diagonal shift the definition adds to the truncated matrix T of the
+    symbols t, decided from eigenvalues: Cholesky pivots are at least the
+    smallest eigenvalue, so lambda_min > PIVOT_MIN t(0) means no shift and
+    lambda_min < 0 means the Gershgorin bound of the discarded part; a case
+    in between is not decidable this way and fails."""
+    lam = np.linalg.eigvalsh(T).min()
+    if lam > B.PIVOT_MIN * t[0]:
+        return 0.0
+    assert lam < 0.0, "borderline case"
+    return 2.0 * np.abs(t[B.BW:]).sum()
+
+
 def test_tall_band_uses_truncated_toeplitz_per_frequency():
     ny, nx, h, y0 = 160, 32, 40, 60    # 40 rows > BW = 32
     P = spectrum(nx, ny)
@@ -134,8 +149,8 @@ def test_tall_band_uses_truncated_toeplitz_per_frequency():
         t = np.array([sum(Ab[0, d * nx + x] * np.cos(2 * np.pi * kx * x / nx) for x in range(nx))
                       for d in range(h)])
         d = np.abs(np.arange(h)[:, None] - np.arange(h)[None, :])
-        sigma = 2.0 * np.abs(t[B.BW:]).sum()   # Gershgorin bound of the discarded part
-        T = np.where(d < B.BW, t[d], 0.0) + sigma * np.eye(h)
+        T = np.where(d < B.BW, t[d], 0.0)
+        T += expected_shift(T, t) * np.eye(h)
         a = rng.standard_normal(h)
         u = np.zeros((ny, nx))
         u[y0:y0 + h] = a[:, None] * np.cos(2 * np.pi * kx * np.arange(nx) / nx)[None, :]
@@ -156,6 +171,14 @@ def test_slow_decay_truncation_needs_the_shift():
     assert plain_min < 0.0
     M = B.BlockPrecond(mask, P)
     assert min(np.linalg.eigvalsh(T).min() for T in M.band_T[0]) > 0.0
+    # frequencies whose truncation is safely positive definite keep it unshifted
+    kept = 0
+    for kx in range(nx // 2 + 1):
+        T0 = np.where(d < B.BW, t[d, kx], 0.0)
+        sh = expected_shift(T0, t[:, kx])
+        assert np.abs(M.band_T[0][kx] - (T0 + sh * np.eye(h))).max() <= 1e-12 * abs(t[0, kx])
+        kept += sh == 0.0
+    assert 0 < kept < nx // 2 + 1
     # the shifted factor still approximates the band well: M^-1 A close to I
     rng = np.random.default_rng(4)
     v = np.where(mask != 0, rng.standard_normal((ny, nx)), 0.0)
