@@ -180,8 +180,10 @@ int fill_plan_set_inner_tol(fill_plan plan, double tol);
  *                       built on the short range of C^-1.  Runs of fully
  *                       masked rows (bands, at most ny - 64 rows) are solved
  *                       exactly per x-frequency kx (their part of A is one
- *                       symmetric Toeplitz matrix per kx, kept to bandwidth 32
- *                       and factored by banded Cholesky); every other
+ *                       symmetric Toeplitz matrix per kx, kept to bandwidth 32,
+ *                       shifted by a bound of the discarded part where the
+ *                       truncation is not safely positive definite, and
+ *                       factored by banded Cholesky); every other
  *                       connected piece of the mask (4-neighbours, periodic;
  *                       pieces over 1024 pixels are cut into 16 x 16 cells),
  *                       grown by 8 pixels into the mask, is solved exactly by a
