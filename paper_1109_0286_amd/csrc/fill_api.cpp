@@ -1722,7 +1722,7 @@ int fill_plan_nprob(fill_plan p) { return p ? p->nprob : 0; }
 
 // True if Pk (npk tables) equals the spectrum the plan holds, bit for bit:
 // then there is nothing to upload and no preconditioner to rebuild.
-bool same_pk(fill_plan p, const double* Pk) {
+static bool same_pk(fill_plan p, const double* Pk) {
   const size_t n = (size_t)p->npk * p->nt;
   return p->hpk.size() == n && std::memcmp(p->hpk.data(), Pk, n * sizeof(double)) == 0;
 }
