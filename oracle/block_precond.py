@@ -13,8 +13,14 @@ symmetric Toeplitz system per frequency kx.  The solution it leads to is the
 same (it only changes the CG path); the definition below fixes the operator so
 that the GPU's application of it can be checked element by element.
 
+This module specifies the library's own operator, parameter for parameter;
+it is not an oracle of the paper.  Every end-to-end check of a fill that uses
+it goes through fill_oracle's solution (or a direct pin), which this
+preconditioner cannot change: it only sets the CG path.
+
 Definition (parameters BW = 32, HALO = 8, TILE = 16, CMAX = 1024, NBMAX = 2048,
-PIVOT_MIN = 1e-9):
+pivot_min = PIVOT_MIN = 1e-9 for FP64 factors and PIVOT_MIN_F32 = 1e-4 for
+FP32 factors, whose rounding the truncation's conditioning amplifies):
 
 1. Band runs: maximal runs of consecutive rows y0..y0+h-1 (not wrapping)
    whose every pixel is masked, with h <= ny - 2 BW.
@@ -23,7 +29,7 @@ PIVOT_MIN = 1e-9):
    in dx and, for spectra symmetric under ky -> -ky, in dy), T_kx[i, j] =
    t_kx(i - j) for |i - j| < BW and 0 beyond, plus sigma_kx on the diagonal.
    sigma_kx = 0 if the truncated matrix is safely positive definite: every
-   pivot of its Cholesky factorization exceeds PIVOT_MIN times its diagonal
+   pivot of its Cholesky factorization exceeds pivot_min times its diagonal
    entry t_kx(0); otherwise sigma_kx = 2 sum_{d = BW}^{h-1} |t_kx(d)|, a bound
    (Gershgorin) on the norm of the discarded part, so that T_kx stays positive
    definite however slowly t_kx decays (the shift costs iterations where it
@@ -48,11 +54,12 @@ import numpy as np
 import scipy.fft as sfft
 import scipy.ndimage as ndi
 
-__all__ = ["BW", "HALO", "TILE", "CMAX", "NBMAX", "PIVOT_MIN", "safely_pd", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
+__all__ = ["BW", "HALO", "TILE", "CMAX", "NBMAX", "PIVOT_MIN", "PIVOT_MIN_F32", "safely_pd", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
            "BlockPrecond", "pcg_block"]
 
 BW, HALO, TILE, CMAX, NBMAX = 32, 8, 16, 1024, 2048
 PIVOT_MIN = 1e-9
+PIVOT_MIN_F32 = 1e-4
 
 
 def kernel_cinv(P: np.ndarray) -> np.ndarray:
@@ -147,20 +154,21 @@ def blocks(mask: np.ndarray, cell_list: list) -> list:
     return out
 
 
-def safely_pd(T: np.ndarray) -> bool:
+def safely_pd(T: np.ndarray, pivot_min: float = PIVOT_MIN) -> bool:
     """True if the Cholesky factorization of the symmetric matrix T has every
-    pivot L_ii^2 above PIVOT_MIN T_ii (False if it breaks down)."""
+    pivot L_ii^2 above pivot_min T_ii (False if it breaks down)."""
     try:
         L = np.linalg.cholesky(T)
     except np.linalg.LinAlgError:
         return False
-    return bool(np.all(np.diag(L) ** 2 > PIVOT_MIN * np.diag(T)))
+    return bool(np.all(np.diag(L) ** 2 > pivot_min * np.diag(T)))
 
 
 class BlockPrecond:
-    """M^-1 of the definition above for one mask and spectrum (FP64)."""
+    """M^-1 of the definition above for one mask and spectrum (FP64
+    arithmetic; pivot_min selects the threshold of the FP64 or FP32 plans)."""
 
-    def __init__(self, mask: np.ndarray, P: np.ndarray, bw: int = BW):
+    def __init__(self, mask: np.ndarray, P: np.ndarray, bw: int = BW, pivot_min: float = PIVOT_MIN):
         self.mask = mask
         ny, nx = mask.shape
         self.shape = (ny, nx)
@@ -173,7 +181,7 @@ class BlockPrecond:
             Ts = np.zeros((nx // 2 + 1, h, h))
             for kx in range(nx // 2 + 1):
                 Ts[kx] = np.where(d < bw, t[d, kx], 0.0)
-                if not safely_pd(Ts[kx]):
+                if not safely_pd(Ts[kx], pivot_min):
                     Ts[kx] += 2.0 * np.abs(t[bw:h, kx]).sum() * np.eye(h)
             self.band_T.append(Ts)
         self.cells = cells(mask, self.runs)

@@ -341,8 +341,23 @@ class FillResult:
     info: PCGInfo
 
 
+def _solve(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float, max_iter: int, solver: str):
+    """A u = v to true relative residual rtol.  solver "split" is the paper's
+    split-preconditioned CG (Sec. 2.4); "block" is PCG with the block
+    preconditioner of oracle.block_precond, which converges in far fewer
+    iterations on wide cuts.  Both stop on the same true residual
+    ||v - A u|| <= rtol ||v|| of this module's A, so the solution they return
+    does not depend on the preconditioner (it only sets the CG path)."""
+    if solver == "split":
+        return pcg_split(v, mask, P, rtol, max_iter)
+    if solver == "block":
+        from .block_precond import pcg_block
+        return pcg_block(v, mask, P, rtol, max_iter)
+    raise ValueError(f"unknown solver {solver!r}")
+
+
 def fill_realize(d_obs: np.ndarray, mask: np.ndarray, P: np.ndarray, seed: int,
-                 rtol: float, max_iter: int = 20000) -> FillResult:
+                 rtol: float, max_iter: int = 20000, solver: str = "split") -> FillResult:
     """Constrained realization by the Hoffman-Ribak construction (Sec. 2.3).
 
     s = C^{1/2} w; t = Py (d_obs - s); v = -Px C^-1 t; solve A u = v;
@@ -351,16 +366,16 @@ def fill_realize(d_obs: np.ndarray, mask: np.ndarray, P: np.ndarray, seed: int,
     s = unconstrained_realization(P, seed)
     t = _Py(d_obs - s, mask)
     v = rhs(t, mask, P)
-    u, info = pcg_split(v, mask, P, rtol, max_iter)
+    u, info = _solve(v, mask, P, rtol, max_iter, solver)
     x = np.where(mask != 0, s + u, d_obs)
     return FillResult(x, s, u, info)
 
 
 def fill_mean(d_obs: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float,
-              max_iter: int = 20000) -> FillResult:
+              max_iter: int = 20000, solver: str = "split") -> FillResult:
     """The conditional mean (Wiener fill) x_ML = M y on masked pixels (Sec. 2.1)."""
     t = _Py(d_obs, mask)
     v = rhs(t, mask, P)
-    u, info = pcg_split(v, mask, P, rtol, max_iter)
+    u, info = _solve(v, mask, P, rtol, max_iter, solver)
     x = np.where(mask != 0, u, d_obs)
     return FillResult(x, np.zeros_like(d_obs), u, info)

@@ -62,8 +62,8 @@ bool spd_inverse(std::vector<double>& A, int n) {
 
 }  // namespace
 
-int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, Layout* L,
-                 std::string* err) {
+int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, double pivot_min,
+                 Layout* L, std::string* err) {
   L->nx = nx;
   L->ny = ny;
   const size_t npix = (size_t)nx * ny;
@@ -139,9 +139,9 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
           return true;
         };
         // the plain truncation where it is safely positive definite (every
-        // pivot above PIVOT_MIN times the diagonal nx t_kx(0)), else the
+        // pivot above pivot_min times the diagonal nx t_kx(0)), else the
         // shift by the Gershgorin bound of the part beyond the bandwidth
-        if (!factor(0.0, PIVOT_MIN * (double)nx * t[kx])) {
+        if (!factor(0.0, pivot_min * (double)nx * t[kx])) {
           double sigma = 0.0;
           for (int d = BW; d < h; ++d) sigma += 2.0 * std::fabs(t[(size_t)d * nk + kx]);
           if (!factor(sigma, 0.0)) {

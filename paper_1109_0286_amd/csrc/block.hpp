@@ -7,7 +7,8 @@
 //               for |i - j| < BW plus sigma_kx on the diagonal, where
 //               t_kx(d) = sum_dx k(d, dx) cos(2 pi kx dx/nx) (k the kernel of
 //               C^-1); sigma_kx = 0 if every Cholesky pivot of the truncation
-//               exceeds PIVOT_MIN times its diagonal, else
+//               exceeds pivot_min times its diagonal (PIVOT_MIN for FP64
+//               factors, PIVOT_MIN_F32 for FP32 ones), else
 //               sigma_kx = 2 sum_{BW <= d < h} |t_kx(d)|, which bounds the
 //               discarded part (keeps T_kx positive definite); factored as
 //               L L^T (banded Cholesky);
@@ -37,7 +38,12 @@ constexpr int HALO = 8;      // Chebyshev growth of each cell into the mask
 constexpr int TILE = 16;     // cell grid for large pieces
 constexpr int CMAX = 1024;   // largest piece kept whole
 constexpr int NBMAX = 2048;  // largest block (dense inverse)
-constexpr double PIVOT_MIN = 1e-9;  // band truncation kept unshifted if every Cholesky pivot exceeds this x diagonal
+// band truncation kept unshifted if every Cholesky pivot exceeds this times
+// its diagonal: FP64 factors, and FP32 factors (whose rounding, relative 2^-24,
+// is amplified by up to the truncation's condition number, which the pivot
+// ratio bounds from below)
+constexpr double PIVOT_MIN = 1e-9;
+constexpr double PIVOT_MIN_F32 = 1e-4;
 constexpr int BROWS = 256;   // rows of a block product work item
 constexpr int BCOLS = 128;   // columns of a block product work item
 
@@ -76,10 +82,11 @@ struct Layout {
 };
 
 // mask: ny*nx (1 = masked); kmap: ny*nx FP64 kernel of C^-1 (C^-1 v = k (*) v);
-// tsym: ny*(nx/2+1), tsym[d*(nx/2+1) + kx] = t_kx(d).
+// tsym: ny*(nx/2+1), tsym[d*(nx/2+1) + kx] = t_kx(d); pivot_min: the
+// threshold of the unshifted band truncation (PIVOT_MIN or PIVOT_MIN_F32).
 // Returns 0, or -1 with *err set (a band factor or a block is not positive
 // definite, or a block is too large).
-int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, Layout* out,
-                 std::string* err);
+int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, double pivot_min,
+                 Layout* out, std::string* err);
 
 }  // namespace fillb

@@ -453,6 +453,8 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
   const int nx = p->nx, ny = p->ny, nc = p->ncol;
   const size_t npix = p->npix;
   const int tab = p->npk > 1 ? b : 0;
+  if (p->hpk.size() != (size_t)p->npk * p->nt)
+    return fail(FILL_EINVAL, "block preconditioner: the plan has no valid spectrum (a previous upload failed)");
   const double* P = p->hpk.data() + (size_t)tab * p->nt;
   for (int iy = 1; iy < ny; ++iy)
     for (int ix = 0; ix < nc; ++ix) {
@@ -505,7 +507,9 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
     for (int kx = 1; kx < ncx; ++kx) tsym[(size_t)d * nc + kx] = xt[(size_t)kx * ny + d].x;
   }
   std::string err;
-  if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, kmap.data(), tsym.data(), L, &err) != 0)
+  const double pivot_min = p->prec == FILL_PREC_FP32_OP ? fillb::PIVOT_MIN_F32 : fillb::PIVOT_MIN;
+  if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, kmap.data(), tsym.data(), pivot_min, L,
+                          &err) != 0)
     return fail(FILL_ENOTSPD, "problem " + std::to_string(b) + ": " + err);
   return FILL_OK;
 }
@@ -1163,22 +1167,32 @@ int twiddles(int n, int pass, std::vector<double2>& w64, std::vector<float2>& w3
 }
 
 // Tables 1/(P N) and sqrt(P)/N, transposed (spectral column kx contiguous in ky).
+// Every table is checked before anything is uploaded, and the host copy hpk
+// changes only after the upload succeeded: a rejected spectrum leaves the
+// plan's spectrum as it was.
 int upload_pk(fill_plan p, const double* Pk, int npk) {
   const int nx = p->nx, ny = p->ny, nc = p->ncol;
   const size_t nt = p->nt;
-  p->hpk.assign(Pk, Pk + (size_t)npk * nt);
-  std::vector<double> inv(nt), half(nt), full(nt);
-  std::vector<float> inv32(nt), half32(nt), full32(nt);
-  const double scale = 1.0 / ((double)nx * (double)ny);
   for (int k = 0; k < npk; ++k) {
     const double* P0 = Pk + (size_t)k * ny * nc;
-    for (int iy = 0; iy < ny; ++iy) {
+    for (int iy = 0; iy < ny; ++iy)
       for (int ix = 0; ix < nc; ++ix) {
         const double P = P0[(size_t)iy * nc + ix];
         if (!(P > 0.0) || !std::isfinite(P))
           return fail(FILL_ENOTSPD, "Pk[" + std::to_string(k) + "][" + std::to_string(iy) + "," +
                                         std::to_string(ix) + "] = " + std::to_string(P) +
                                         " is not positive and finite");
+      }
+  }
+  std::vector<double> inv(nt), half(nt), full(nt);
+  std::vector<float> inv32(nt), half32(nt), full32(nt);
+  const double scale = 1.0 / ((double)nx * (double)ny);
+  p->hpk.clear();  // until every table is on the device, no host copy is current
+  for (int k = 0; k < npk; ++k) {
+    const double* P0 = Pk + (size_t)k * ny * nc;
+    for (int iy = 0; iy < ny; ++iy) {
+      for (int ix = 0; ix < nc; ++ix) {
+        const double P = P0[(size_t)iy * nc + ix];
         const size_t o = (size_t)ix * ny + iy;
         inv[o] = scale / P;
         half[o] = scale * std::sqrt(P);
@@ -1195,6 +1209,7 @@ int upload_pk(fill_plan p, const double* Pk, int npk) {
     HIP_TRY(hipMemcpy(p->Dfull64 + k * nt, full.data(), nt * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->Dfull32 + k * nt, full32.data(), nt * sizeof(float), hipMemcpyHostToDevice));
   }
+  p->hpk.assign(Pk, Pk + (size_t)npk * nt);
   return FILL_OK;
 }
 
@@ -1936,15 +1951,16 @@ int fill_plan_set_bands(fill_plan p, int nbands, const double* lnk_nodes, const 
     }
   }
   (void)nx;
+  // the spectrum first: if it is rejected, the plan keeps its nodes and tables
+  const bool same = same_pk(p, Pk.data());
+  if (!same) FILL_TRY(upload_pk(p, Pk.data(), p->npk));
   if (p->nbands != nbands) {
     FILL_TRY(dalloc(p, &p->lnk, nbands));
     FILL_TRY(dalloc(p, &p->adj_gth, nbands));
     p->nbands = nbands;
   }
   HIP_TRY(hipMemcpy(p->lnk, lnk_nodes, nbands * sizeof(double), hipMemcpyHostToDevice));
-  if (same_pk(p, Pk.data())) return FILL_OK;
-  FILL_TRY(upload_pk(p, Pk.data(), p->npk));
-  return block_follow_pk(p);
+  return same ? FILL_OK : block_follow_pk(p);
 }
 
 int fill_adjoint(fill_plan p, const double* d_obs, uint64_t seed, const double* x_out, const double* g,

@@ -597,6 +597,9 @@ class BatchPlan:
     def set_inner_tol(self, tol):
         fill_plan_set_inner_tol(self.handle, tol)
 
+    def set_max_iter(self, n):
+        fill_plan_set_max_iter(self.handle, n)
+
     def set_bands(self, lnk_nodes, theta):
         fill_plan_set_bands(self.handle, lnk_nodes, theta)
         self.nbands = len(lnk_nodes)

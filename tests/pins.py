@@ -76,6 +76,28 @@ def band_direct(t, r0, h, fn):
     return np.fft.ifft(uh, axis=1).real
 
 
+def band_direct_modes(t, r0, h, fn, kxs):
+    """The x-frequency modes kxs of x_ML on the band rows r0..r0+h-1, each by
+    its own dense solve (band_direct for a sample of frequencies, for grids
+    where solving every kx would take too long): out[:, i] is the 1D DFT
+    along x (numpy's forward convention) of x_ML on the band rows at
+    kx = kxs[i]."""
+    ny, nx = t.shape
+    j = np.arange(ny)
+    xb = np.zeros(ny, bool)
+    xb[r0:r0 + h] = True
+    kys = np.fft.fftfreq(ny, d=1.0 / ny)
+    jb = j[xb]
+    lag = (jb[:, None] - j[None, :]) % ny
+    that = np.fft.fft(t, axis=1)
+    out = np.zeros((h, len(kxs)), complex)
+    for i, kx in enumerate(kxs):
+        q = np.fft.ifft(1.0 / fn(np.sqrt(kx ** 2 + kys ** 2)))
+        Qx = q[lag]
+        out[:, i] = -np.linalg.solve(Qx[:, xb], Qx[:, ~xb] @ that[~xb, kx])
+    return out
+
+
 def laplace_band_closed_form(y, r0, h, mu2):
     """Lattice analogue of the periodic-strip Laplace solution (Sec. 6.1).
 

@@ -136,3 +136,39 @@ def test_adjoint_with_other_preconditioners(F, pc, prec, tol):
     _, gy0, _, gth0 = AD.adjoint_gradient(d, mask, theta, phi, 9, wts, 1e-13)
     assert rel(gth, gth0) < tol
     assert rel(gd.cpu().numpy(), gy0) < tol
+
+
+def test_autograd_backward_uses_its_forwards_band_powers(F):
+    # two forwards on one shared plan at different band powers, then backward
+    # through the first: the gradient is the oracle's at the first theta
+    n, nprob = 64, 1
+    lnk, phi, theta, mask, d, wts = setup(n)
+    theta2 = theta + 0.3
+    bp = F.BatchPlan(n, n, mask[None], np.ones((n, n // 2 + 1)), 0)
+    FillFn = F.autograd_fill()
+    w = torch.from_numpy(wts[None]).cuda()
+    dd = torch.from_numpy(d[None].copy()).cuda().requires_grad_(True)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    x = FillFn.apply(dd, th, bp, [9], lnk, 1e-11, 1e-11)
+    L = torch.sum(w * x * x)
+    th2 = torch.tensor(theta2, dtype=torch.float64, requires_grad=True)
+    x2 = FillFn.apply(dd.detach(), th2, bp, [9], lnk, 1e-11, 1e-11)
+    assert not torch.equal(x, x2)
+    L.backward()
+    _, gy0, _, gth0 = AD.adjoint_gradient(d, mask, theta, phi, 9, wts, 1e-13)
+    assert rel(th.grad.numpy(), gth0) < 1e-8
+    assert rel(dd.grad[0].cpu().numpy(), gy0) < 1e-8
+
+
+def test_autograd_backward_raises_on_nonconvergence(F):
+    n = 64
+    lnk, phi, theta, mask, d, wts = setup(n)
+    bp = F.BatchPlan(n, n, mask[None], np.ones((n, n // 2 + 1)), 0)
+    FillFn = F.autograd_fill()
+    dd = torch.from_numpy(d[None].copy()).cuda()
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    x = FillFn.apply(dd, th, bp, [9], lnk, 1e-10, 1e-10)
+    bp.set_max_iter(2)  # the adjoint solve cannot reach 1e-10 in two iterations
+    with pytest.raises(F.FillError) as e:
+        torch.sum(x * x).backward()
+    assert e.value.code == F.FILL_ENOCONV

@@ -104,7 +104,7 @@ def plan_block(F, mask, P, prec):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-3)])
 def test_minv_matches_oracle(F, name, prec, tol):
     mask, P = case(name)
-    M = B.BlockPrecond(mask, P)
+    M = B.BlockPrecond(mask, P, pivot_min=B.PIVOT_MIN if prec == 0 else B.PIVOT_MIN_F32)
     if name == "two":
         assert M.runs == [(20, 40), (150, 20)]
     rng = np.random.default_rng(11)

@@ -103,7 +103,15 @@ def test_iterations_close_to_standard(F, prec, pc):
         st = plan.stats()
         assert st["status"] == 0 and st["rel_resid"] <= 1e-8
         it[cg] = st["iters_inner"]
-    assert abs(it[1] - it[0]) <= 0.10 * it[0] + 2, it
+    # Same iterates in exact arithmetic; in floating point the single-reduction
+    # recurrence carries A p by its own recurrence (s = w + beta s), whose
+    # rounding drifts from the explicit product at a different rate.  In FP64
+    # the counts agree within 5%.  With FP32 operators the drift is 2^-24 per
+    # step instead of 2^-53, and each refinement restart cuts it at a
+    # different point, so the counts may part by up to 10% (measured: 495 and
+    # 535 at this size).  The paper gives no counts: parity unpinned.
+    bound = 0.05 if prec == 0 else 0.10
+    assert abs(it[1] - it[0]) <= bound * it[0] + 2, it
 
 
 @pytest.mark.parametrize("prec", [0, 1])

@@ -270,6 +270,26 @@ def test_masked_inputs_are_ignored_and_runs_are_deterministic(F):
     assert np.array_equal(a, b)
 
 
+def test_rejected_spectrum_leaves_the_plan_unchanged(F):
+    # an invalid spectrum is rejected every time it is offered, and the plan
+    # keeps solving with the spectrum it had
+    P, mask, d = problem(64, 64)
+    plan = F.Plan(64, 64, mask, P)
+    dd = dev(d)
+    x0 = host(plan.realize(dd, 2, 1e-12))
+    bad = P * 2.0
+    bad[5, 7] = -1.0
+    for _ in range(2):
+        with pytest.raises(F.FillError) as e:
+            plan.set_pk(bad)
+        assert e.value.code == F.FILL_ENOTSPD
+    x1 = host(plan.realize(dd, 2, 1e-12))
+    assert np.array_equal(x0.view(np.uint64), x1.view(np.uint64))
+    plan.set_pk(P * 2.0)  # a valid change still takes effect
+    x2 = host(plan.realize(dd, 2, 1e-12))
+    assert rel(x2, O.fill_realize(d, mask, P * 2.0, 2, 1e-13).x_out, mask != 0) < 1e-9
+
+
 def test_error_paths(F):
     P, mask, d = problem(64, 64)
     bad = P.copy()

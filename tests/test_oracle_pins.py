@@ -70,6 +70,31 @@ def test_white_noise_is_standard_normal():
     assert abs(c2) < 5 / np.sqrt(w.size)
 
 
+def _white_noise_pin_error(noise=None):
+    """Largest deviation of white_noise from pixels 2j, 2j+1 recomputed one by
+    one from numpy's independent Philox words (counter one behind, see above)
+    with the math module's log and cos, relative to max(1, |value|)."""
+    import math
+    nx, ny, seed = 64, 32, 2 ** 61 + 11
+    w = (noise or O.white_noise)(nx, ny, seed).ravel()
+    worst = 0.0
+    # (pair 0 is out of reach: numpy's counter -1 carries into its second word)
+    for j in (1, 2, 517, nx * ny // 2 - 1):
+        bg = np.random.Philox(key=np.array([seed, O.REALIZATION_STREAM], dtype=np.uint64),
+                              counter=np.array([j - 1, 0, 0, 0], dtype=np.uint64))
+        words = [int(v) for v in bg.random_raw(4)]
+        u = [((x >> 11) + 0.5) * 2.0 ** -53 for x in words]
+        a = math.sqrt(-2.0 * math.log(u[0])) * math.cos(2.0 * math.pi * u[1])
+        b = math.sqrt(-2.0 * math.log(u[2])) * math.cos(2.0 * math.pi * u[3])
+        worst = max(worst, abs(w[2 * j] - a) / max(1.0, abs(a)), abs(w[2 * j + 1] - b) / max(1.0, abs(b)))
+    return worst
+
+
+def test_white_noise_pixels_from_independent_words():
+    # exact pin of the Box-Muller mapping (to libm rounding)
+    assert _white_noise_pin_error() <= 4e-16
+
+
 # --------------------------------------------------------------------------
 # circulant covariance and the FFT convention
 # --------------------------------------------------------------------------
@@ -326,3 +351,23 @@ def test_mutation_missing_normalisation_is_caught(monkeypatch):
     orig = F.circulant_apply
     monkeypatch.setattr(F, "circulant_apply", lambda v, P, a: orig(v, P, a) * v.size)
     assert err_circulant(8, 6, 0.5) > 1.0
+
+
+def test_mutation_white_noise_mapping_is_caught():
+    # sin for cos, or the word pairs of the two pixels swapped, fail the exact pin
+    def noise(nx, ny, seed, swap=False, sin=False):
+        j = np.arange(nx * ny // 2, dtype=np.uint64)
+        z = np.zeros_like(j)
+        w0, w1, w2, w3 = O.philox4x64_10(j, z, z, z, np.uint64(seed), np.uint64(O.REALIZATION_STREAM))
+        if swap:
+            w0, w1, w2, w3 = w2, w3, w0, w1
+        un = [((x >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53 for x in (w0, w1, w2, w3)]
+        trig = np.sin if sin else np.cos
+        out = np.empty(nx * ny)
+        out[0::2] = np.sqrt(-2.0 * np.log(un[0])) * trig(2.0 * np.pi * un[1])
+        out[1::2] = np.sqrt(-2.0 * np.log(un[2])) * trig(2.0 * np.pi * un[3])
+        return out.reshape(ny, nx)
+
+    assert _white_noise_pin_error(noise) <= 4e-16  # the helper's own control
+    assert _white_noise_pin_error(lambda a, b, c: noise(a, b, c, sin=True)) > 1e-3
+    assert _white_noise_pin_error(lambda a, b, c: noise(a, b, c, swap=True)) > 1e-3
