@@ -131,8 +131,13 @@ def test_band_only_4096_sampled_modes_match_direct_solve(F, prec):
     plan = F.Plan(n, n, mask, P, prec)
     plan.set_precond(F.FILL_PRECOND_BLOCK)
     assert plan.block_info()["band_rows"] == 1248
-    rtol = 1e-12 if prec == 0 else 1e-10
-    x = host(plan.mean(dev(d), rtol))
+    # FP64 at 1e-13: the error of a solve stopped at rtol is up to kappa(A)
+    # rtol, and at 1e-12 it measured 1.1e-9 on these modes
+    rtol = 1e-13 if prec == 0 else 1e-10
+    x = host(plan.mean(dev(d), rtol, allow_noconv=True))
+    st = plan.stats()
+    print(f"band-only 4096^2 prec={prec}: {st['iters_inner']} iterations, rel resid {st['rel_resid']:.2e}")
+    assert st["rel_resid"] <= (1e-12 if prec == 0 else 1e-10)
     del plan
     kxs = [0, 1, 2, 7, 64, 511, 1500, 2048]
     want = band_direct_modes(np.where(mask != 0, 0.0, d), r0, h, lambda k: _p_of_k(k, 4.0, 512.0, 1e-7), kxs)
