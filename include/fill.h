@@ -423,6 +423,25 @@ int fill_apply(fill_plan plan, int op, int prec, const double* in, double* out);
 int fill_realize_unconstrained(fill_plan plan, uint64_t seed, double* out);
 
 /*
+ * fill_realize_unconstrained without allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same draw, bit for bit, as
+ * fill_realize_unconstrained: the transposed half spectrum of the three
+ * passes lives in a file-scope device array of the library (64 MiB per GPU,
+ * held until the process ends) instead of the plan's workspace.
+ *   plan  created beforehand (plan creation allocates); its device must be
+ *         the current device, else FILL_EINVAL.
+ *   out   device, ny*nx doubles (caller-owned).
+ * Limit: (nx/2) * ny * 16 bytes <= 64 MiB, i.e. nx * ny <= 8388608 (up to
+ * 2048 x 4096), else FILL_EINVAL.  Calls hipMalloc/hipFree never.  The
+ * kernels are enqueued on the plan's stream and the call returns without
+ * synchronising: out is ready when the stream reaches that point.  Every call
+ * on one GPU shares that GPU's array (each call overwrites all it reads), so
+ * calls that overlap on one GPU (on different streams or host threads) race.
+ */
+int fill_realize_unconstrained_noalloc(fill_plan plan, uint64_t seed, double* out);
+
+/*
  * Raw Philox4x64-10 words (Salmon et al. 2011) for counters (j, 0, 0, 0),
  * j = 0..n_blocks-1, key (seed, stream): out is device, 4*n_blocks uint64,
  * block j at out[4j..4j+3].  Runs on the null stream and synchronises.

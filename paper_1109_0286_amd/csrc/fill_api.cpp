@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <utility>
@@ -118,6 +119,7 @@ struct BlockDev {
 
 struct fill_plan_s {
   int nx = 0, ny = 0, ncol = 0, prec = 0, nprob = 1, npk = 1;
+  int device = 0;  // the HIP device current at creation
   size_t npix = 0, nt = 0;
   hipStream_t stream = nullptr;
   std::vector<int> n_m, coff;
@@ -1719,6 +1721,39 @@ int read_lanczos(fill_plan p, int problem, std::vector<double>& al, std::vector<
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of fill_realize_unconstrained_noalloc: the transposed half spectrum
+// of the draw lives in this file-scope device array instead of the plan's
+// workspace, so the call allocates nothing.  Each GPU holds its own copy, at
+// its own address, for the life of the process.  In host code the name
+// `scratch` is only a host-side stand-in: kernels are given the device address
+// obtained once per device with hipGetSymbolAddress (scratch_address()).
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device
+// (resolved on the first call for that device, then kept).
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(FILL_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FILL_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return FILL_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int fill_supported_size(int n) { return size_ok(n) ? 1 : 0; }
@@ -2071,6 +2106,35 @@ int fill_realize_unconstrained(fill_plan p, uint64_t seed, double* out) {
   return FILL_OK;
 }
 
+int fill_realize_unconstrained_noalloc(fill_plan p, uint64_t seed, double* out) {
+  g_last_error.clear();
+  if (!p || !out) return fail(FILL_EINVAL, "NULL argument");
+  const size_t need = (size_t)(p->nx / 2) * p->ny * sizeof(double2);
+  if (need > kNoAllocScratchBytes)
+    return fail(FILL_EINVAL, "grid " + std::to_string(p->nx) + "x" + std::to_string(p->ny) + " needs " +
+                                 std::to_string(need) + " bytes of spectrum scratch; the limit is " +
+                                 std::to_string(kNoAllocScratchBytes) + " (nx * ny <= 8388608)");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != p->device) return fail(FILL_EINVAL, "the plan's device must be the current device");
+  void* sp = nullptr;
+  FILL_TRY(scratch_address(cur, &sp));
+  // the same three passes as fill_realize_unconstrained, on the scratch
+  // spectrum; every pass overwrites what the next one reads, so nothing needs
+  // clearing between calls
+  RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
+  ai.Xt = ao.Xt = static_cast<cplx<double>*>(sp);
+  ai.seed = seed;
+  ai.stream = kRealizationStream;
+  ao.full_out = out;
+  ColArgs<double> ca = col_base<double>(p, 1, p->Dhalf64, nullptr);
+  ca.Xt = static_cast<cplx<double>*>(sp);
+  HIP_TRY(launch_r2c<double>(R2C_NOISE, ai, p->stream, nullptr, nullptr));
+  HIP_TRY(launch_col<double>(p->ny, ca, p->stream, nullptr, nullptr));
+  HIP_TRY(launch_c2r<double>(C2R_REALIZE, ao, p->stream, nullptr, nullptr));
+  return FILL_OK;
+}
+
 int fill_philox_words(uint64_t seed, uint64_t stream, int64_t n_blocks, uint64_t* out) {
   g_last_error.clear();
   if (!out || n_blocks < 0) return fail(FILL_EINVAL, "bad argument");
@@ -2154,6 +2218,10 @@ int plan_create_impl(int nx, int ny, int nprob, const uint8_t* masks, const doub
   p->npix = (size_t)nx * ny;
   p->nt = (size_t)p->ncol * ny;
   p->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(FILL_EHIP, "hipGetDevice failed");
+  }
   const int r64 = row_block_rows<double>(nx), r32 = row_block_rows<float>(nx);
   if (r64 <= 0 || r32 <= 0 || ny % r64 || ny % r32) {
     delete p;

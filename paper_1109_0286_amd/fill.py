@@ -49,6 +49,7 @@ EXPORTS = (
     "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew", "fill_strips_create",
     "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
     "fill_strips_refine", "fill_laplace", "fill_plan_set_cg", "fill_get_block_info",
+    "fill_realize_unconstrained_noalloc",
 )
 
 FILL_PRECOND_NONE = 0
@@ -127,6 +128,7 @@ def _load() -> C.CDLL:
         "fill_get_stats": (i32, [vp, C.POINTER(fill_stats)]),
         "fill_apply": (i32, [vp, i32, i32, vp, vp]),
         "fill_realize_unconstrained": (i32, [vp, u64, vp]),
+        "fill_realize_unconstrained_noalloc": (i32, [vp, u64, vp]),
         "fill_philox_words": (i32, [u64, u64, C.c_int64, vp]),
         "fill_time_kernel": (i32, [vp, i32, i32, i32, C.POINTER(dbl)]),
         "fill_kernel_timing": (i32, [vp, i32, i32]),
@@ -349,6 +351,11 @@ def fill_apply(plan, op, prec, in_ptr, out_ptr):
 
 def fill_realize_unconstrained(plan, seed, out_ptr):
     return _check(_lib.fill_realize_unconstrained(plan, C.c_uint64(seed), out_ptr), "fill_realize_unconstrained")
+
+
+def fill_realize_unconstrained_noalloc(plan, seed, out_ptr):
+    return _check(_lib.fill_realize_unconstrained_noalloc(plan, C.c_uint64(seed), out_ptr),
+                  "fill_realize_unconstrained_noalloc")
 
 
 def fill_philox_words(seed, stream, n_blocks, out_ptr):
