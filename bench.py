@@ -747,7 +747,7 @@ def bench_grid2048(args) -> int:
                                "10% band + 200 holes r~U(2,12), rtol 1e-8, 1 realization per step",
                    "preconditioner": args.precond, "cg": args.cg,
                    "n_masked": n_m, "iters_inner": st32["iters_inner"], "iters_outer": st32["iters_outer"],
-                   "rel_resid": st32["rel_resid"]},
+                   "rel_resid": st32["rel_resid"], "whole_graph": st32.get("whole_graph")},
         "fp64_path": {"value": args.steps / dt64, "unit": "solves/s", "ms_per_step": dt64 / args.steps * 1e3,
                       "iters": st64["iters_inner"], "rel_resid": st64["rel_resid"]},
         "kernels_per_mixed_solve": breakdown,

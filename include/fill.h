@@ -104,6 +104,7 @@ typedef struct fill_stats {
   int status;            /* fill_status of the last solve */
   double rel_resid;      /* true FP64 ||v - A u|| / ||v|| at return, last solve */
   double solve_ms;       /* wall time of the last solve, host clock */
+  int whole_graph;       /* 1: the last solve ran as one graph replay (see fill_plan_set_graph) */
 } fill_stats;
 
 /*
@@ -274,13 +275,27 @@ int fill_lanczos_extremes(fill_plan plan, int problem, double* lam_min, double* 
 int fill_plan_set_skew(fill_plan plan, double eps);
 
 /*
- * Graph replay of the inner CG (default 1).  The inner CG runs in chunks of
- * 16 iterations between host checks of the device convergence flags; with 1
- * each chunk is captured once per plan (per precision, preconditioner and
- * coefficient record) as a HIP graph on a private stream and replayed on the
- * plan's stream by every later solve; with 0 the kernels are launched one by
- * one.  Both give bitwise identical results.  Chunks are launched directly
- * while fill_kernel_timing is on.
+ * Graph replay (default 1).  The decisions of the refinement loop (when to
+ * stop, the next inner tolerance and scaling) are taken on the device, after
+ * every step.  A solve runs in one of two ways:
+ *   - step by step: the host reads the device state after each refinement
+ *     step; the inner CG runs in chunks of 16 iterations (8 with the block
+ *     preconditioner) between host checks, each chunk captured once per plan
+ *     (per precision, preconditioner and coefficient record) as a HIP graph
+ *     and replayed (with 0: launched one by one, bitwise the same);
+ *   - as one graph: when the previous solve on the plan was of the same kind
+ *     (realize or mean, preconditioner, recurrence; not the single-reduction
+ *     recurrence without the block preconditioner) and took at most 8
+ *     refinement steps and 128 inner iterations, the whole solve (start
+ *     passes, that many steps of that many iterations, assembly) is captured
+ *     once and replayed, and the host waits only at its end.  A problem that
+ *     converges early stops on the device; one that needs more iterations
+ *     than the previous solve had its inner solve cut there and the
+ *     refinement continues, step by step after the graph if needed.  With
+ *     the same iteration counts the result is bitwise that of the step-by-step
+ *     solve; otherwise it differs within the tolerance.
+ * fill_stats.whole_graph tells which way the last solve ran.  Kernels are
+ * launched directly while fill_kernel_timing is on.
  */
 int fill_plan_set_graph(fill_plan plan, int on);
 

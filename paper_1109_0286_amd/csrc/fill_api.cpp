@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -82,6 +83,7 @@ struct Params {
   const double** in_tab;
   double** out_tab;
   uint64_t* seeds;
+  SolveCfg* cfg;      // refinement settings of the call
 };
 
 // Device side of the block preconditioner (FILL_PRECOND_BLOCK), built for the
@@ -147,7 +149,16 @@ struct fill_plan_s {
   // length of the first chunk of the next one
   int pred_iters[2][4] = {};
   int cur_outer = 0;
-  double* h_rr = nullptr;  // host copy of the r.r partials (pinned)
+  // refinement state on the device (control kernels) and its host copy
+  SolveState* st = nullptr;
+  SolveState* h_st = nullptr;
+  // the last solve's refinement steps and inner iterations per step (maximum
+  // over problems) for a key (operation, preconditioner, recurrence): with
+  // them a solve runs as one captured graph, no host round trip inside
+  int pred_key = -1, pred_R = 0;
+  int last_whole_graph = 0;  // the last solve ran as one graph replay
+  int pred_L[kStateIts] = {};
+  std::map<std::vector<int>, std::pair<hipGraph_t, hipGraphExec_t>> solve_graphs;
   int nblk64 = 0, nblk32 = 0;
 
   uint8_t* mask = nullptr;
@@ -357,15 +368,6 @@ int apply_EE(fill_plan p, int rm, const RowArgs<T>& ai, const RowArgs<T>& amid, 
   return FILL_OK;
 }
 
-// Per-problem sums of the FP64 partials of a row pass -> host (synchronises).
-int read_sums(fill_plan p, const double* part, int nblk, std::vector<double>& out) {
-  HIP_TRY(launch_sum(p->dsum, part, (size_t)p->ny, nblk, p->nprob, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->h_sum, p->dsum, p->nprob * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  out.assign(p->h_sum, p->h_sum + p->nprob);
-  return FILL_OK;
-}
-
 int upload_params(fill_plan p) {
   HIP_TRY(hipMemcpyAsync(p->par_dev, p->par_host, p->par_bytes, hipMemcpyHostToDevice, p->stream));
   return FILL_OK;
@@ -404,8 +406,14 @@ int chunk_graph(fill_plan p, int f32, int mode, int rec, int len, F&& chunk, hip
   return FILL_OK;
 }
 
-// Drop captured chunk graphs (all, or only those that record coefficients).
+// Drop captured chunk graphs (all, or only those that record coefficients),
+// and every captured whole-solve graph.
 void drop_graphs(fill_plan p, bool record_only) {
+  for (auto& kv : p->solve_graphs) {
+    if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+    if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+  }
+  p->solve_graphs.clear();
   for (int a = 0; a < 2; ++a)
     for (int m = 0; m < 8; ++m)
       for (int r = record_only ? 1 : 0; r < 2; ++r)
@@ -730,56 +738,51 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
   return FILL_OK;
 }
 
+// Arguments of the refinement control kernels.
+RefineArgs refine_args(fill_plan p) {
+  RefineArgs a;
+  a.st = p->st;
+  a.cfg = p->dp.cfg;
+  a.sc = p->sc;
+  a.scale = p->dp.scale;
+  a.unscale = p->dp.unscale;
+  a.tol2 = p->dp.tol2;
+  a.cap = p->dp.cap;
+  a.active = p->dp.active;
+  a.nprob = p->nprob;
+  return a;
+}
+
 // Run inner-CG chunks (graph replays, or direct launches) until every problem
 // is done: a first chunk of len0 iterations, then chunks of len1; chunk(len)
 // launches one directly, exec(len) returns its graph or null.  After each
-// chunk the host reads the device state and, with rr_part (the r.r partials
-// of the last iteration, nb per problem), also ends a problem whose r.r meets
-// its tolerance: the device would only see that at the next chunk's first
-// step.  Per-problem iteration counts and statuses.
+// chunk a device check (rr_part: the r.r partials of the last iteration, nb
+// per problem) also stops a problem whose r.r meets its tolerance, which the
+// kernels would only see at the next chunk's first step; then the host reads
+// the CG scalars.  Per-problem iteration counts and statuses.
 template <typename C, typename E>
 int run_chunks(fill_plan p, int len0, int len1, C&& chunk, E&& exec, const double* rr_part, int nb,
                std::vector<int>& iters, std::vector<int>& status) {
   const int np = p->nprob;
-  std::vector<int> host_done(np, 0), it_done(np, 0);
-  static const int one = 1;
   int len = len0;
   for (;;) {
     hipGraphExec_t ex = nullptr;
     FILL_TRY(exec(len, &ex));
     if (ex) HIP_TRY(hipGraphLaunch(ex, p->stream));
     else FILL_TRY(chunk(len));
+    if (rr_part) HIP_TRY(launch_rr_check(p->sc, rr_part, nb, (size_t)p->ny, np, p->stream));
     HIP_TRY(hipMemcpyAsync(p->h_sc, p->sc, np * sizeof(CGScalars), hipMemcpyDeviceToHost, p->stream));
-    if (rr_part) {
-      if (!p->h_rr) HIP_TRY(hipHostMalloc((void**)&p->h_rr, (size_t)np * p->ny * sizeof(double), hipHostMallocDefault));
-      HIP_TRY(hipMemcpyAsync(p->h_rr, rr_part, (size_t)np * p->ny * sizeof(double), hipMemcpyDeviceToHost,
-                             p->stream));
-    }
     HIP_TRY(hipStreamSynchronize(p->stream));
     bool all = true;
-    for (int b = 0; b < np; ++b) {
-      if (p->h_sc[b].done || host_done[b]) continue;
-      if (rr_part) {
-        double rr = 0.0;
-        for (int i = 0; i < nb; ++i) rr += p->h_rr[(size_t)b * p->ny + i];
-        if (rr <= p->h_sc[b].tol2) {
-          host_done[b] = 1;
-          it_done[b] = p->h_sc[b].iter;
-          // stop it on the device too (other problems may run more chunks)
-          HIP_TRY(hipMemcpyAsync(&p->sc[b].done, &one, sizeof(int), hipMemcpyHostToDevice, p->stream));
-          continue;
-        }
-      }
-      all = false;
-    }
+    for (int b = 0; b < np; ++b) all = all && p->h_sc[b].done;
     if (all) break;
     len = len1;
   }
   iters.resize(np);
   status.resize(np);
   for (int b = 0; b < np; ++b) {
-    iters[b] = host_done[b] ? it_done[b] : p->h_sc[b].iter;
-    status[b] = host_done[b] ? 0 : p->h_sc[b].status;
+    iters[b] = p->h_sc[b].iter;
+    status[b] = p->h_sc[b].status;
   }
   return FILL_OK;
 }
@@ -795,7 +798,7 @@ int run_chunks(fill_plan p, int len0, int len1, C&& chunk, E&& exec, const doubl
 //   none:    r2c (with r.r of the new r) -> col(1/P) -> c2r(w; w.r)
 // (one launch fewer per iteration than the standard form).
 template <typename T>
-int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bool record) {
+int inner_pcg_cg1(fill_plan p, bool record, int fixed) {
   Vecs<T>& v = TypeSel<T>::vecs(p);
   const int nb = TypeSel<T>::nblk(p), np = p->nprob;
   const int mode = p->precond;
@@ -854,7 +857,6 @@ int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status
     FILL_TRY(timed_launch<T>(p, FILL_K_R2C, [&](hipEvent_t a, hipEvent_t b) { return launch_r2c<T>(R2C_COMPACT, ai, p->stream, a, b); }));
     FILL_TRY(tail(nullptr));
   }
-  HIP_TRY(launch_cg_init(p->sc, p->dp.tol2, p->dp.cap, p->dp.active, np, p->stream));
 
   RowArgs<T> up[2];
   for (int par = 0; par < 2; ++par) {
@@ -890,16 +892,26 @@ int inner_pcg_cg1(fill_plan p, std::vector<int>& iters, std::vector<int>& status
       FILL_TRY(chunk_graph(p, sizeof(T) == 4, mode + 4, hist != nullptr, len, [&]() { return chunk(len); }, out));
     return FILL_OK;
   };
-  return run_chunks(p, kChunk, kChunk, chunk, exec, nullptr, nb, iters, status);
+  if (fixed > 0) FILL_TRY(chunk(fixed));
+  else {
+    std::vector<int> iters, status;
+    FILL_TRY(run_chunks(p, kChunk, kChunk, chunk, exec, nullptr, nb, iters, status));
+  }
+  HIP_TRY(launch_ctl_after(refine_args(p), nullptr, nb, (size_t)p->ny, record, p->stream));
+  return FILL_OK;
 }
 
 // Inner preconditioned CG for every active problem on A d = r (r in v.r with
 // ||r|| = 1, d in v.x; x and p are zero on entry); tolerances, caps and the
-// active set are in the device parameters.  Returns per-problem iteration counts and statuses.
+// active set are in the device parameters.  fixed > 0: exactly `fixed`
+// iterations are enqueued (problems that converge earlier stop on the
+// device), with no host interaction; else chunks run until the host sees
+// every problem done.  Either way the control kernel then accounts for the
+// solve in the device refinement state.
 template <typename T>
-int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bool record) {
+int inner_pcg(fill_plan p, bool record, int fixed) {
   if (p->cg_variant == FILL_CG_SINGLE_REDUCTION && p->precond != FILL_PRECOND_BLOCK)
-    return inner_pcg_cg1<T>(p, iters, status, record);
+    return inner_pcg_cg1<T>(p, record, fixed);
   Vecs<T>& v = TypeSel<T>::vecs(p);
   const int nb = TypeSel<T>::nblk(p), np = p->nprob;
   const T* Dinv = TypeSel<T>::Dinv(p);
@@ -926,7 +938,6 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
     a0.part1 = p->part1;
     HIP_TRY(launch_xr<T>(true, a0, nb, p->stream));
   }
-  HIP_TRY(launch_cg_init(p->sc, p->dp.tol2, p->dp.cap, p->dp.active, np, p->stream));
 
   // Iteration k (parity k % 2), all scalars on the device:
   //   q = A p, with beta = (r.z)/rho and p = z + beta p fused in front
@@ -998,118 +1009,115 @@ int inner_pcg(fill_plan p, std::vector<int>& iters, std::vector<int>& status, bo
   };
   // chunk lengths: even (the rho parity), the first one the length of the
   // same refinement step's last inner solve
-  const int len1 = mode == FILL_PRECOND_BLOCK ? kChunkBlock : kChunk;
-  const int pred = p->pred_iters[sizeof(T) == 4][std::min(p->cur_outer, 3)];
-  const int len0 = pred > 0 ? std::min(16, std::max(2, (pred + 1) / 2 * 2)) : len1;
-  FILL_TRY(run_chunks(p, len0, len1, chunk, exec, p->part1, nb, iters, status));
-  int mx = 0;
-  for (int b = 0; b < np; ++b) mx = std::max(mx, iters[b]);
-  p->pred_iters[sizeof(T) == 4][std::min(p->cur_outer, 3)] = mx;
+  if (fixed > 0) {
+    FILL_TRY(chunk(fixed));
+  } else {
+    const int len1 = mode == FILL_PRECOND_BLOCK ? kChunkBlock : kChunk;
+    const int pred = p->pred_iters[sizeof(T) == 4][std::min(p->cur_outer, 3)];
+    const int len0 = pred > 0 ? std::min(16, std::max(2, (pred + 1) / 2 * 2)) : len1;
+    std::vector<int> iters, status;
+    FILL_TRY(run_chunks(p, len0, len1, chunk, exec, p->part1, nb, iters, status));
+    int mx = 0;
+    for (int b = 0; b < np; ++b) mx = std::max(mx, iters[b]);
+    p->pred_iters[sizeof(T) == 4][std::min(p->cur_outer, 3)] = mx;
+  }
+  HIP_TRY(launch_ctl_after(refine_args(p), p->part1, nb, (size_t)p->ny, record, p->stream));
   return FILL_OK;
 }
 
-// Solve A u = v for every problem (v, u compact FP64), each to true relative residual rtol.
-int solve(fill_plan p, const std::vector<double>& bnorm2, double rtol) {
+// One refinement step for every active problem (Sec. 2.4 solve with FP64
+// true residuals): r = res / ||res|| (v itself at the first step, which also
+// clears u), the inner CG (host-checked chunks, or exactly `fixed`
+// iterations), u += ||res|| d, the FP64 true residual res = v - A u, its
+// per-problem norms and the device's decision of the next step.  Every
+// scalar is read from and written to the device state: nothing here waits
+// for the host.
+int refine_step(fill_plan p, bool first, int fixed) {
   const int np = p->nprob;
-  // the first refinement step scales v itself (res = v - A 0) and clears u
-  std::vector<double> rnorm2 = bnorm2, prev(np, 1.0);
-  std::vector<int> total(np, 0), outer(np, 0), done(np, 0), status(np, FILL_OK);
-  std::vector<int> it, st;
-  p->hist_n.assign(np, 0);
-  bool first = true;
-  int pass = 0;
-  for (int b = 0; b < np; ++b) {
-    p->pstats[b].iters_inner = 0;
-    p->pstats[b].iters_outer = 0;
-    p->pstats[b].rel_resid = 0.0;
+  if (p->prec == FILL_PREC_FP64) {
+    HIP_TRY(launch_scale_init_f64(p->v64.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v64.x, p->v64.p,
+                                  first ? p->u : nullptr, p->n_m_max, np, p->stream));
+    FILL_TRY(inner_pcg<double>(p, first, fixed));
+    HIP_TRY(launch_axpy_f64(p->u, p->v64.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
+  } else {
+    HIP_TRY(launch_scale_init_f32(p->v32.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v32.x, p->v32.p,
+                                  first ? p->u : nullptr, p->n_m_max, np, p->stream));
+    FILL_TRY(inner_pcg<float>(p, first, fixed));
+    HIP_TRY(launch_axpy_f32(p->u, p->v32.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
   }
-  for (;;) {
-    int nactive = 0;
-    for (int b = 0; b < np; ++b) {
-      p->hp.active[b] = 0;
-      p->hp.scale[b] = 0.0;
-      p->hp.unscale[b] = 0.0;
-      p->hp.tol2[b] = 0.0;
-      p->hp.cap[b] = 1;
-      if (done[b]) continue;
-      if (bnorm2[b] == 0.0) {
-        done[b] = 1;
-        p->pstats[b].rel_resid = 0.0;
-        continue;
-      }
-      const double rel = std::sqrt(rnorm2[b] / bnorm2[b]);
-      p->pstats[b].rel_resid = rel;
-      if (!(rel == rel)) {
-        done[b] = 1;
-        status[b] = FILL_ENOTSPD;
-        continue;
-      }
-      if (rel <= rtol) {
-        done[b] = 1;
-        continue;
-      }
-      if (total[b] >= p->max_iter || outer[b] >= kMaxOuter || (outer[b] >= 3 && rel > 0.5 * prev[b])) {
-        done[b] = 1;
-        status[b] = FILL_ENOCONV;
-        continue;
-      }
-      prev[b] = rel;
-      const double rn = std::sqrt(rnorm2[b]);
-      const double target = rtol / rel;  // inner relative reduction that reaches rtol
-      const double tol = p->prec == FILL_PREC_FP64 ? 0.5 * target : std::max(0.5 * target, p->inner_tol32);
-      p->hp.active[b] = 1;
-      p->hp.scale[b] = 1.0 / rn;
-      p->hp.unscale[b] = rn;
-      p->hp.tol2[b] = tol * tol;
-      p->hp.cap[b] = p->max_iter - total[b];
-      ++nactive;
-    }
-    if (nactive == 0) {
-      if (first) HIP_TRY(hipMemsetAsync(p->u, 0, (size_t)std::max(p->n_m_total, 1) * sizeof(double), p->stream));
-      break;
-    }
-    FILL_TRY(upload_params(p));
-    p->cur_outer = pass++;
-    if (p->prec == FILL_PREC_FP64) {
-      HIP_TRY(launch_scale_init_f64(p->v64.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v64.x, p->v64.p,
-                                    first ? p->u : nullptr, p->n_m_max, np, p->stream));
-      FILL_TRY(inner_pcg<double>(p, it, st, first));
-      HIP_TRY(launch_axpy_f64(p->u, p->v64.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
-    } else {
-      HIP_TRY(launch_scale_init_f32(p->v32.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v32.x, p->v32.p,
-                                    first ? p->u : nullptr, p->n_m_max, np, p->stream));
-      FILL_TRY(inner_pcg<float>(p, it, st, first));
-      HIP_TRY(launch_axpy_f32(p->u, p->v32.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
-    }
-    for (int b = 0; b < np; ++b) {
-      if (!p->hp.active[b]) continue;
-      if (first) p->hist_n[b] = std::min(it[b], p->hist_cap);
-      total[b] += it[b];
-      outer[b] += 1;
-      p->pstats[b].iters_inner = total[b];
-      p->pstats[b].iters_outer = outer[b];
-      if (st[b] == -6) {
-        done[b] = 1;
-        status[b] = FILL_ENOTSPD;
-      }
-    }
+  RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
+  ai.v0 = p->u;
+  ao.v0 = p->res;
+  ao.v1 = p->b;
+  ao.part0 = p->part0;
+  FILL_TRY(apply3<double>(p, R2C_COMPACT, ai, p->Dinv64, C2R_RESID, ao, nullptr));
+  HIP_TRY(launch_ctl(refine_args(p), p->part0, (size_t)p->ny, p->nblk64, false, p->stream));
+  return FILL_OK;
+}
+
+// The refinement state on the host (synchronises the stream).
+int read_state(fill_plan p) {
+  HIP_TRY(hipMemcpyAsync(p->h_st, p->st, p->nprob * sizeof(SolveState), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return FILL_OK;
+}
+
+// Every problem done, by the host copy of the state.
+bool all_done(fill_plan p) {
+  for (int b = 0; b < p->nprob; ++b)
+    if (!p->h_st[b].done) return false;
+  return true;
+}
+
+// Host-driven refinement: with the state on the host, run steps (each read
+// back) until every problem is done.  first: no step has run yet in this
+// solve (the first one clears u and records the CG coefficients).
+int refine_host(fill_plan p, bool first) {
+  if (first && all_done(p))  // nothing to solve: u = 0
+    HIP_TRY(hipMemsetAsync(p->u, 0, (size_t)std::max(p->n_m_total, 1) * sizeof(double), p->stream));
+  for (int pass = 0; !all_done(p); ++pass) {
+    p->cur_outer = pass;
+    FILL_TRY(refine_step(p, first, 0));
     first = false;
-    // true FP64 residual res = v - A u, every problem
-    RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
-    ai.v0 = p->u;
-    ao.v0 = p->res;
-    ao.v1 = p->b;
-    ao.part0 = p->part0;
-    FILL_TRY(apply3<double>(p, R2C_COMPACT, ai, p->Dinv64, C2R_RESID, ao, nullptr));
-    FILL_TRY(read_sums(p, p->part0, p->nblk64, rnorm2));
+    FILL_TRY(read_state(p));
   }
-  int worst = FILL_OK;
+  return FILL_OK;
+}
+
+// Per-call settings of the control kernels (uploaded with the parameters).
+void set_cfg(fill_plan p, double rtol) {
+  SolveCfg& c = *p->hp.cfg;
+  c.rtol = rtol;
+  c.inner_tol = p->inner_tol32;
+  c.max_iter = p->max_iter;
+  c.max_outer = kMaxOuter;
+  c.fp64 = p->prec == FILL_PREC_FP64 ? 1 : 0;
+  c.pad = 0;
+}
+
+// Statistics and status from the host copy of the final state; the step
+// counts become the prediction for the next solve of the same key.
+int finish_solve(fill_plan p, int key) {
+  const int np = p->nprob;
+  int worst = FILL_OK, R = 0;
+  int L[kStateIts] = {};
   for (int b = 0; b < np; ++b) {
-    if (bnorm2[b] > 0.0) p->pstats[b].rel_resid = std::sqrt(rnorm2[b] / bnorm2[b]);
-    p->pstats[b].status = status[b];
-    if (status[b] == FILL_ENOTSPD) worst = FILL_ENOTSPD;
-    else if (status[b] == FILL_ENOCONV && worst == FILL_OK) worst = FILL_ENOCONV;
+    const SolveState& s = p->h_st[b];
+    fill_stats& ps = p->pstats[b];
+    ps.iters_inner = s.total;
+    ps.iters_outer = s.outer;
+    ps.rel_resid = s.bnorm2 > 0.0 ? std::sqrt(s.rnorm2 / s.bnorm2) : 0.0;
+    ps.status = s.status == -6 ? FILL_ENOTSPD : s.status == -4 ? FILL_ENOCONV : FILL_OK;
+    ps.whole_graph = p->last_whole_graph;
+    if (b < (int)p->hist_n.size()) p->hist_n[b] = s.outer > 0 ? std::min(s.first_iters, p->hist_cap) : 0;
+    if (ps.status == FILL_ENOTSPD) worst = FILL_ENOTSPD;
+    else if (ps.status == FILL_ENOCONV && worst == FILL_OK) worst = FILL_ENOCONV;
+    R = std::max(R, s.outer);
+    for (int j = 0; j < std::min(s.outer, kStateIts); ++j) L[j] = std::max(L[j], s.its[j]);
   }
+  p->pred_key = key;
+  p->pred_R = R;
+  std::memcpy(p->pred_L, L, sizeof(L));
   if (worst == FILL_ENOTSPD) return fail(FILL_ENOTSPD, "CG breakdown (p.Ap <= 0 or r.Mr <= 0) or non-finite residual");
   if (worst == FILL_ENOCONV) return fail(FILL_ENOCONV, "no convergence to the requested true residual");
   return FILL_OK;
@@ -1283,7 +1291,7 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
   FILL_TRY(dalloc(p, &p->sc, np));
   // per-call parameter block: same layout on host (pinned) and device
   const size_t n8 = (size_t)np * 8;
-  p->par_bytes = 8 * n8;
+  p->par_bytes = 8 * n8 + sizeof(SolveCfg);
   char* dpar = nullptr;
   FILL_TRY(dalloc(p, &dpar, p->par_bytes));
   p->par_dev = dpar;
@@ -1298,9 +1306,13 @@ int plan_build(fill_plan p, const uint8_t* mask, const double* Pk) {
     q.in_tab = reinterpret_cast<const double**>(base + 5 * n8);
     q.out_tab = reinterpret_cast<double**>(base + 6 * n8);
     q.seeds = reinterpret_cast<uint64_t*>(base + 7 * n8);
+    q.cfg = reinterpret_cast<SolveCfg*>(base + 8 * n8);
   };
   carve(dpar, p->dp);
   carve(static_cast<char*>(p->par_host), p->hp);
+  FILL_TRY(dalloc(p, &p->st, np));
+  HIP_TRY(hipHostMalloc((void**)&p->h_st, np * sizeof(SolveState), hipHostMallocDefault));
+  std::memset(p->h_st, 0, np * sizeof(SolveState));
   HIP_TRY(hipHostMalloc((void**)&p->h_sc, np * sizeof(CGScalars), hipHostMallocDefault));
   HIP_TRY(hipHostMalloc((void**)&p->h_sum, np * sizeof(double), hipHostMallocDefault));
   p->pstats.assign(np, fill_stats{});
@@ -1327,28 +1339,136 @@ int check_maps(fill_plan p, const double* const* d, double* const* x) {
   return FILL_OK;
 }
 
-// After x_out and t = Py (d - s) (or Py d) are in place: RHS, solve, assembly.
-int rhs_solve_assemble(fill_plan p, double rtol) {
+// The first passes of a solve: x_out and t = Py (d - s) (or Py d for the
+// mean), then the right-hand side v = -Px C^-1 t with its norms, and the
+// device's decision of the first refinement step.  Per-call maps and seeds
+// come from the parameter tables, so the passes can be captured.
+int enqueue_start(fill_plan p, bool mean) {
   const int np = p->nprob;
+  if (mean) {
+    HIP_TRY(launch_mean_prep(p->dp.out_tab, p->tfull, p->dp.in_tab, p->mask, p->npix, np, p->stream));
+  } else {
+    // s = C^{1/2} w; x_out = mask ? s : d; t = mask ? 0 : d - s
+    RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
+    ai.seeds = p->dp.seeds;
+    ai.stream = kRealizationStream;
+    ao.fin_tab = p->dp.in_tab;
+    ao.fout_tab = p->dp.out_tab;
+    ao.full_in = p->tfull;  // non-null: the observed-data branch (the maps come from the tables)
+    ao.full_out2 = p->tfull;
+    FILL_TRY(apply3<double>(p, R2C_NOISE, ai, p->Dhalf64, C2R_REALIZE, ao, nullptr));
+  }
   RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
   ai.full_in = p->tfull;
   ao.v0 = p->b;
   ao.scale = -1.0;
   ao.part0 = p->part0;
   FILL_TRY(apply3<double>(p, R2C_FULL, ai, p->Dinv64, C2R_COMPACT, ao, nullptr));
-  std::vector<double> bnorm2;
-  FILL_TRY(read_sums(p, p->part0, p->nblk64, bnorm2));
-  const int st = solve(p, bnorm2, rtol);
-  if (st != FILL_OK && st != FILL_ENOCONV) return st;
-  HIP_TRY(launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, np, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  return st;
+  HIP_TRY(launch_ctl(refine_args(p), p->part0, (size_t)p->ny, p->nblk64, true, p->stream));
+  return FILL_OK;
+}
+
+// Key of the predictions: operation, preconditioner, recurrence.
+int solve_key(fill_plan p, bool mean) { return (mean ? 1 : 0) + 2 * p->precond + 16 * p->cg_variant; }
+
+// Whether this solve can run as one captured graph: the same kind of solve
+// ran last on this plan, with at most kStateIts refinement steps and few
+// iterations (with hundreds of iterations per solve the host's checks cost
+// nothing that matters), graphs are on and no kernel is being timed.  The
+// single-reduction recurrence clears a vector with a memset at its start,
+// which is kept out of graphs.
+bool whole_graph_ok(fill_plan p, bool mean) {
+  if (!p->use_graph || p->timed_kernel >= 0 || p->n_m_total == 0) return false;
+  if (p->cg_variant == FILL_CG_SINGLE_REDUCTION && p->precond != FILL_PRECOND_BLOCK) return false;
+  if (p->pred_key != solve_key(p, mean) || p->pred_R < 1 || p->pred_R > kStateIts) return false;
+  int sum = 0;
+  for (int j = 0; j < p->pred_R; ++j) {
+    if (p->pred_L[j] < 1) return false;
+    sum += p->pred_L[j];
+  }
+  return sum <= 128;
+}
+
+// The whole solve as one graph (captured on first use per key and step
+// lengths): start passes, pred_R refinement steps of pred_L[j] inner
+// iterations each, and the assembly x_out += u, which runs only if every
+// problem is done by then (otherwise the host continues the refinement).
+int whole_graph(fill_plan p, bool mean, hipGraphExec_t* out) {
+  std::vector<int> key = {mean ? 1 : 0, p->prec, p->precond, p->cg_variant, p->hist_cap > 0 ? 1 : 0, p->pred_R};
+  for (int j = 0; j < p->pred_R; ++j) key.push_back(p->pred_L[j]);
+  auto it = p->solve_graphs.find(key);
+  if (it != p->solve_graphs.end()) {
+    *out = it->second.second;
+    return FILL_OK;
+  }
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  const hipStream_t saved = p->stream;
+  p->stream = p->cap_stream;
+  const hipError_t e0 = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  int rc = FILL_OK;
+  if (e0 == hipSuccess) {
+    rc = enqueue_start(p, mean);
+    for (int j = 0; j < p->pred_R && rc == FILL_OK; ++j) {
+      p->cur_outer = j;
+      rc = refine_step(p, j == 0, p->pred_L[j]);
+    }
+    if (rc == FILL_OK) {
+      const hipError_t e = launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, p->nprob,
+                                              p->stream, p->st);
+      if (e != hipSuccess) rc = fail(FILL_EHIP, std::string("launch_scatter_add: ") + hipGetErrorString(e));
+    }
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e1 = e0 == hipSuccess ? hipStreamEndCapture(p->cap_stream, &g) : hipSuccess;
+  p->stream = saved;
+  if (e0 != hipSuccess) return fail(FILL_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e0));
+  if (rc < 0 || e1 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (rc < 0) return rc;
+    return fail(FILL_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e1));
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(FILL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  }
+  p->solve_graphs[key] = {g, ex};
+  *out = ex;
+  return FILL_OK;
+}
+
+// After the parameters are uploaded: the solve (one graph replay when the
+// previous solve's step counts are known, else step by step with the host
+// reading the state after each), then the assembly x_out += u.
+int run_solve(fill_plan p, bool mean) {
+  const bool graph = whole_graph_ok(p, mean);
+  p->last_whole_graph = 0;
+  if (graph) {
+    hipGraphExec_t ex = nullptr;
+    FILL_TRY(whole_graph(p, mean, &ex));
+    HIP_TRY(hipGraphLaunch(ex, p->stream));
+  } else {
+    FILL_TRY(enqueue_start(p, mean));
+  }
+  FILL_TRY(read_state(p));
+  const bool done = all_done(p);
+  p->last_whole_graph = graph && done ? 1 : 0;
+  if (!graph || !done) {
+    // not every problem finished inside the graph (or no graph): continue
+    // step by step, then assemble
+    FILL_TRY(refine_host(p, !graph));
+    HIP_TRY(launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, p->nprob, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  return finish_solve(p, solve_key(p, mean));
 }
 
 void finish_stats(fill_plan p, int st, double ms) {
-  fill_stats agg{0, 0, p->n_m_total, st, 0.0, ms};
+  fill_stats agg{0, 0, p->n_m_total, st, 0.0, ms, p->last_whole_graph};
   for (int b = 0; b < p->nprob; ++b) {
     p->pstats[b].solve_ms = ms;
+    p->pstats[b].whole_graph = p->last_whole_graph;
     agg.iters_inner = std::max(agg.iters_inner, p->pstats[b].iters_inner);
     agg.iters_outer = std::max(agg.iters_outer, p->pstats[b].iters_outer);
     agg.rel_resid = std::max(agg.rel_resid, p->pstats[b].rel_resid);
@@ -1377,27 +1497,16 @@ int realize_impl(fill_plan p, const double* const* d, const uint64_t* seeds, dou
     p->hp.seeds[b] = mean ? 0 : seeds[b];
   }
   if (p->n_m_total == 0) {
+    p->last_whole_graph = 0;
     for (int b = 0; b < np; ++b)
       HIP_TRY(hipMemcpyAsync(x[b], d[b], p->npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
     finish_stats(p, FILL_OK, std::chrono::duration<double, std::milli>(clk::now() - t0).count());
     return FILL_OK;
   }
+  set_cfg(p, rtol);
   FILL_TRY(upload_params(p));
-  if (mean) {
-    HIP_TRY(launch_mean_prep(p->dp.out_tab, p->tfull, p->dp.in_tab, p->mask, p->npix, np, p->stream));
-  } else {
-    // s = C^{1/2} w; x_out = mask ? s : d; t = mask ? 0 : d - s
-    RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
-    ai.seeds = p->dp.seeds;
-    ai.stream = kRealizationStream;
-    ao.fin_tab = p->dp.in_tab;
-    ao.fout_tab = p->dp.out_tab;
-    ao.full_in = d[0];  // non-null: selects the observed-data branch
-    ao.full_out2 = p->tfull;
-    FILL_TRY(apply3<double>(p, R2C_NOISE, ai, p->Dhalf64, C2R_REALIZE, ao, nullptr));
-  }
-  const int st = rhs_solve_assemble(p, rtol);
+  const int st = run_solve(p, mean);
   finish_stats(p, st, std::chrono::duration<double, std::milli>(clk::now() - t0).count());
   return st;
 }
@@ -1505,15 +1614,18 @@ int adjoint_impl(fill_plan p, const double* const* d, const uint64_t* seeds, con
   FILL_TRY(adjoint_workspace(p));
   HIP_TRY(hipStreamSynchronize(p->stream));
   for (int b = 0; b < np; ++b) p->hp.in_tab[b] = g[b];
+  set_cfg(p, rtol);
   FILL_TRY(upload_params(p));
   // lambda = A^-1 g_x for every problem (the plan's precision, FP64 refinement)
   HIP_TRY(launch_adj_gather(p->b, const_cast<double* const*>(p->dp.in_tab), p->pos, p->comp_off, p->n_m_max, np,
                             p->stream));
   HIP_TRY(launch_cnorm2(p->dsum, p->b, p->comp_off, np, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->h_sum, p->dsum, np * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  std::vector<double> bnorm2(p->h_sum, p->h_sum + np);
-  const int st = solve(p, bnorm2, rtol);
+  HIP_TRY(launch_ctl(refine_args(p), p->dsum, 1, 1, true, p->stream));
+  FILL_TRY(read_state(p));
+  FILL_TRY(refine_host(p, true));
+  // (no prediction key: the adjoint solve always runs step by step)
+  p->last_whole_graph = 0;
+  const int st = finish_solve(p, -2);
   if (st != FILL_OK && st != FILL_ENOCONV) return st;
   if (p->nbands > 0) HIP_TRY(hipMemsetAsync(p->adj_gth, 0, p->nbands * sizeof(double), p->stream));
   for (int b = 0; b < np; ++b) {
@@ -1886,8 +1998,8 @@ void fill_plan_destroy(fill_plan p) {
   for (void* a : p->allocs) (void)hipFree(a);
   for (void* a : p->blk.allocs) (void)hipFree(a);
   if (p->h_sc) (void)hipHostFree(p->h_sc);
-  if (p->h_rr) (void)hipHostFree(p->h_rr);
   if (p->h_sum) (void)hipHostFree(p->h_sum);
+  if (p->h_st) (void)hipHostFree(p->h_st);
   if (p->par_host) (void)hipHostFree(p->par_host);
   delete p;
 }

@@ -18,37 +18,16 @@ inline dim3 grid_for(size_t n, int ny = 1) {
 }
 }  // namespace
 
-// Start of an inner solve: rho[0] = 1 so that the first iteration's
-// p = z + beta p (p = 0) is p = z for any finite beta.  Inactive problems
-// (converged or failed in the refinement loop) are marked done at once.
-__global__ void k_cg_init(CGScalars* sc, const double* tol2, const int* cap, const int* active, int nprob) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nprob) return;
-  CGScalars& s = sc[b];
-  s.rho[0] = 1.0;
-  s.rho[1] = 1.0;
-  s.alpha = 0.0;
-  s.beta = 0.0;
-  s.alph[0] = __builtin_huge_val();  // single-reduction CG: the first alpha is rho / mu
-  s.alph[1] = __builtin_huge_val();
-  s.rr = 0.0;
-  s.tol2 = tol2[b];
-  s.done = active[b] ? 0 : 1;
-  s.iter = 0;
-  s.max_iter = cap[b];
-  s.status = 0;
-  s.cap = 0;
-}
-
-// out[b] = sum of part[b*stride + i], i < n: fixed order (thread t adds
-// i = t, t+RT, ...; then a fixed tree), hence deterministic.
-__global__ __launch_bounds__(RT) void k_sum(double* out, const double* part, size_t stride, int n) {
-  const double* p = part + (size_t)blockIdx.x * stride;
+// Sum of p[0..n) by a workgroup of RT threads in a fixed order (thread t adds
+// i = t, t+RT, ...; then a fixed tree), hence deterministic; the result is
+// valid in thread 0.
+__device__ __forceinline__ double fixed_sum(const double* p, int n) {
   double v = 0.0, w = 0.0;
   for (int i = threadIdx.x; i < n; i += RT) v += p[i];
   block_sum2<RT>(v, w);
-  if (threadIdx.x == 0) out[blockIdx.x] = v;
+  return v;
 }
+
 
 template <typename TO, typename TI>
 __global__ void k_scale(TO* out, const TI* in, const double* scale, const int* comp_off) {
@@ -86,7 +65,11 @@ __global__ void k_axpy(double* y, const TX* x, const double* a, const int* comp_
     y[c] += s * (double)x[c];
 }
 
-__global__ void k_scatter_add(double* const* full, const double* c, const int* pos, const int* comp_off) {
+__global__ void k_scatter_add(double* const* full, const double* c, const int* pos, const int* comp_off,
+                              const SolveState* gate, int nprob) {
+  if (gate)
+    for (int i = 0; i < nprob; ++i)
+      if (!gate[i].done) return;
   const int b = blockIdx.y;
   const int c0 = comp_off[b], c1 = comp_off[b + 1];
   double* f = full[b];
@@ -102,6 +85,136 @@ __global__ void k_scatter_f32(double* full, const float* c, const int* pos, int 
 }
 __global__ void k_gather(double* c, const double* full, const int* pos, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = full[pos[i]];
+}
+
+// ---------------------------------------------------------------------------
+// Refinement control: the decisions of the FP64 refinement loop around the
+// inner CG solves, taken on the device (one workgroup, one thread per problem)
+// so that a solve needs no host round trip between its steps.
+// ---------------------------------------------------------------------------
+// The next step of problem b from its state (thread 0 of its workgroup):
+// stop (converged, failed, out of budget, stalled) or the parameters of the
+// next inner solve, whose CG scalars are reset here as well.
+__device__ void ctl_decide_one(const RefineArgs& a, int b) {
+  SolveState& s = a.st[b];
+  const SolveCfg& c = *a.cfg;
+  int act = 0;
+  double scale = 0.0, unscale = 0.0, tol2 = 0.0;
+  int cap = 1;
+  if (!s.done) {
+    const double rel = s.bnorm2 == 0.0 ? 0.0 : sqrt(s.rnorm2 / s.bnorm2);
+    s.rel = rel;
+    if (s.bnorm2 == 0.0) {  // v = 0: u = 0 is exact
+      s.done = 1;
+    } else if (!(rel == rel)) {
+      s.done = 1;
+      s.status = -6;
+    } else if (rel <= c.rtol) {
+      s.done = 1;
+    } else if (s.total >= c.max_iter || s.outer >= c.max_outer || (s.outer >= 3 && !s.cut && rel > 0.5 * s.prev)) {
+      // out of iterations or steps, or stalled: three steps in and the last
+      // one (an inner solve that reached its tolerance) did not halve the residual
+      s.done = 1;
+      s.status = -4;
+    } else {
+      s.prev = rel;
+      const double rn = sqrt(s.rnorm2);
+      const double target = c.rtol / rel;  // inner relative reduction that reaches rtol
+      const double tol = c.fp64 ? 0.5 * target : fmax(0.5 * target, c.inner_tol);
+      act = 1;
+      scale = 1.0 / rn;
+      unscale = rn;
+      tol2 = tol * tol;
+      cap = c.max_iter - s.total;
+    }
+  }
+  a.active[b] = act;
+  a.scale[b] = scale;
+  a.unscale[b] = unscale;
+  a.tol2[b] = tol2;
+  a.cap[b] = cap;
+  // CG scalars of the next inner solve: rho[0] = 1 so that the first
+  // iteration's p = z + beta p (p = 0) is p = z for any finite beta; a
+  // problem without a step is done at once
+  CGScalars& g = a.sc[b];
+  g.rho[0] = 1.0;
+  g.rho[1] = 1.0;
+  g.alpha = 0.0;
+  g.beta = 0.0;
+  g.alph[0] = __builtin_huge_val();  // single-reduction CG: the first alpha is rho / mu
+  g.alph[1] = __builtin_huge_val();
+  g.rr = 0.0;
+  g.tol2 = tol2;
+  g.done = act ? 0 : 1;
+  g.iter = 0;
+  g.max_iter = cap;
+  g.status = 0;
+  g.cap = 0;
+}
+
+__global__ __launch_bounds__(RT) void k_ctl(RefineArgs a, const double* part, size_t stride, int n, int begin) {
+  const int b = blockIdx.x;
+  const double sum = fixed_sum(part + (size_t)b * stride, n);
+  if (threadIdx.x != 0) return;
+  SolveState& s = a.st[b];
+  if (begin) {
+    s.bnorm2 = sum;
+    s.rnorm2 = sum;
+    s.prev = 1.0;
+    s.rel = 1.0;
+    s.total = 0;
+    s.outer = 0;
+    s.done = 0;
+    s.status = 0;
+    s.first_iters = 0;
+    s.cut = 0;
+    for (int j = 0; j < kStateIts; ++j) s.its[j] = 0;
+  } else {
+    s.rnorm2 = sum;
+  }
+  ctl_decide_one(a, b);
+}
+
+// r.r of the last CG iteration of problem b meets its tolerance (the
+// iteration after it would stop there).
+__device__ __forceinline__ bool rr_met(const CGScalars& c, const double* rr_part, int nb, size_t stride, int b) {
+  const double rr = fixed_sum(rr_part + (size_t)b * stride, nb);
+  return rr <= c.tol2;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(RT) void k_ctl_after(RefineArgs a, const double* rr_part, int nb, size_t stride,
+                                                  int first) {
+  const int b = blockIdx.x;
+  if (!a.active[b]) return;  // no inner solve ran for this problem
+  const CGScalars& c = a.sc[b];
+  const bool check = !c.done && rr_part;
+  const bool met = check ? rr_met(c, rr_part, nb, stride, b) : false;
+  if (threadIdx.x != 0) return;
+  SolveState& s = a.st[b];
+  const int it = c.iter;
+  int stat = c.status;
+  bool conv = c.done != 0;
+  if (met) {
+    conv = true;
+    stat = 0;
+  }
+  s.cut = conv ? 0 : 1;
+  if (first) s.first_iters = it;
+  if (s.outer < kStateIts) s.its[s.outer] = it;
+  s.total += it;
+  s.outer += 1;
+  if (stat == -6) {
+    s.done = 1;
+    s.status = -6;
+  }
+}
+
+__global__ __launch_bounds__(RT) void k_rr_check(CGScalars* sc, const double* rr_part, int nb, size_t stride) {
+  const int b = blockIdx.x;
+  CGScalars& c = sc[b];
+  if (c.done) return;
+  const bool met = rr_met(c, rr_part, nb, stride, b);
+  if (threadIdx.x == 0 && met) c.done = 1;
 }
 
 // Conditional-mean set-up: x_out = mask ? 0 : d, t = mask ? 0 : d (problem blockIdx.y).
@@ -131,15 +244,6 @@ __global__ void k_philox_words(uint64_t* out, uint64_t seed, uint64_t stream, in
   }
 }
 
-hipError_t launch_cg_init(CGScalars* sc, const double* tol2, const int* cap, const int* active, int nprob,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init, dim3((nprob + 63) / 64), dim3(64), 0, s, sc, tol2, cap, active, nprob);
-  return hipGetLastError();
-}
-hipError_t launch_sum(double* out, const double* part, size_t stride, int n, int nprob, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum, dim3(nprob), dim3(RT), 0, s, out, part, stride, n);
-  return hipGetLastError();
-}
 hipError_t launch_scale_to_f32(float* out, const double* in, const double* scale, const int* comp_off, int nmax,
                                int nprob, hipStream_t s) {
   hipLaunchKernelGGL((k_scale<float, double>), grid_for(nmax, nprob), dim3(256), 0, s, out, in, scale, comp_off);
@@ -173,8 +277,21 @@ hipError_t launch_axpy_f32(double* y, const float* x, const double* a, const int
   return hipGetLastError();
 }
 hipError_t launch_scatter_add(double* const* full, const double* c, const int* pos, const int* comp_off, int nmax,
-                              int nprob, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_add, grid_for(nmax, nprob), dim3(256), 0, s, full, c, pos, comp_off);
+                              int nprob, hipStream_t s, const SolveState* gate) {
+  hipLaunchKernelGGL(k_scatter_add, grid_for(nmax, nprob), dim3(256), 0, s, full, c, pos, comp_off, gate, nprob);
+  return hipGetLastError();
+}
+hipError_t launch_ctl(const RefineArgs& a, const double* part, size_t stride, int n, bool begin, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl, dim3(a.nprob), dim3(RT), 0, s, a, part, stride, n, begin ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_ctl_after(const RefineArgs& a, const double* rr_part, int nb, size_t stride, bool first,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_after, dim3(a.nprob), dim3(RT), 0, s, a, rr_part, nb, stride, first ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_rr_check(CGScalars* sc, const double* rr_part, int nb, size_t stride, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_rr_check, dim3(nprob), dim3(RT), 0, s, sc, rr_part, nb, stride);
   return hipGetLastError();
 }
 hipError_t launch_scatter(double* full, const double* c, const int* pos, int n, hipStream_t s) {

@@ -40,6 +40,49 @@ struct CGScalars {
   int pad;
 };
 
+// Refinement-loop state of one problem (the Sec. 2.4 solve with FP64 true
+// residuals), resident on the device: the control kernels between the inner
+// CG solves decide each next step from it, so a whole solve can run without
+// the host; the host reads it back when the solve ends.
+struct SolveState {
+  double bnorm2;    // ||v||^2
+  double rnorm2;    // ||v - A u||^2 of the last true residual
+  double prev;      // relative residual before the last inner solve
+  double rel;       // relative residual now
+  int total;        // inner iterations so far
+  int outer;        // refinement steps so far
+  int done;         // converged or failed: no further step
+  int status;       // 0, -4 (no convergence), -6 (breakdown or non-finite residual)
+  int first_iters;  // iterations of the first inner solve
+  int cut;          // the last inner solve stopped at its iteration budget above its tolerance
+  int its[8];       // iterations of inner solves 0..7
+};
+constexpr int kStateIts = 8;
+
+// Per-call settings of the refinement loop (device copy).
+struct SolveCfg {
+  double rtol;       // true relative residual to reach
+  double inner_tol;  // floor of the FP32-operator inner tolerance
+  int max_iter;      // inner iterations summed over refinement steps
+  int max_outer;     // refinement steps
+  int fp64;          // FP64 inner solves: tolerance 0.5 rtol / rel without the floor
+  int pad;
+};
+
+// Arguments of the control kernels: the state, the per-call settings, and the
+// parameters and CG scalars of the next inner solve that they write.
+struct RefineArgs {
+  SolveState* st;
+  const SolveCfg* cfg;
+  CGScalars* sc;        // reset for the next inner solve when it is decided
+  double* scale;        // r = scale * res
+  double* unscale;      // u += unscale * x
+  double* tol2;
+  int* cap;
+  int* active;
+  int nprob;
+};
+
 enum R2CMode {
   R2C_COMPACT = 0,   // input v0[c]
   R2C_PUPDATE = 1,   // p = z + beta p   (v0 = z, v1 = p), input p

@@ -8,6 +8,7 @@
 namespace fillk {
 
 struct CGScalars;
+struct RefineArgs;
 template <typename T> struct RowArgs;
 template <typename T> struct ColArgs;
 template <typename T> struct BandArgs;
@@ -39,11 +40,6 @@ hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s, hi
 template <typename T>
 hipError_t launch_combine(const CombArgs<T>& a, int nblk, int nprob, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
-// Reset the device CG scalars of nprob problems at the start of an inner solve.
-hipError_t launch_cg_init(CGScalars* sc, const double* tol2, const int* cap, const int* active, int nprob,
-                          hipStream_t s);
-// out[b] = fixed-order sum of part[b*stride .. b*stride+n)
-hipError_t launch_sum(double* out, const double* part, size_t stride, int n, int nprob, hipStream_t s);
 
 // Per-problem elementwise helpers over compact vectors (problem b: comp_off[b]..comp_off[b+1]).
 hipError_t launch_scale_to_f32(float* out, const double* in, const double* scale, const int* comp_off, int nmax,
@@ -59,8 +55,24 @@ hipError_t launch_axpy_f64(double* y, const double* x, const double* a, const in
                            hipStream_t s);
 hipError_t launch_axpy_f32(double* y, const float* x, const double* a, const int* comp_off, int nmax, int nprob,
                            hipStream_t s);
+struct SolveState;
+// gate (may be null): skip unless every one of the nprob states is done
 hipError_t launch_scatter_add(double* const* full, const double* c, const int* pos, const int* comp_off, int nmax,
-                              int nprob, hipStream_t s);
+                              int nprob, hipStream_t s, const SolveState* gate = nullptr);
+// Refinement control, one workgroup per problem.  The per-problem sum of
+// part[b*stride .. b*stride+n) (fixed order) is ||v||^2 (begin: the state is
+// reset) or ||v - A u||^2; then the next step is decided (active, scale,
+// unscale, tol2, cap and the CG scalars of the next inner solve; done and
+// status for problems that stop).
+hipError_t launch_ctl(const RefineArgs& a, const double* part, size_t stride, int n, bool begin, hipStream_t s);
+// After an inner solve: iterations and status from the CG scalars; a problem
+// not yet stopped whose last r.r partials (rr_part, nb per problem; may be
+// null) meet its tolerance counts as converged.
+hipError_t launch_ctl_after(const RefineArgs& a, const double* rr_part, int nb, size_t stride, bool first,
+                            hipStream_t s);
+// Between inner-CG chunks: stop every problem whose last r.r partials meet
+// its tolerance (the same test, in the same summation order, as above).
+hipError_t launch_rr_check(CGScalars* sc, const double* rr_part, int nb, size_t stride, int nprob, hipStream_t s);
 hipError_t launch_mean_prep(double* const* x_out, double* t, const double* const* d, const uint8_t* mask,
                             size_t npix, int nprob, hipStream_t s);
 

@@ -72,7 +72,8 @@ FILL_K_COMBINE = 7
 
 class fill_stats(C.Structure):
     _fields_ = [("iters_inner", C.c_int), ("iters_outer", C.c_int), ("n_masked", C.c_int),
-                ("status", C.c_int), ("rel_resid", C.c_double), ("solve_ms", C.c_double)]
+                ("status", C.c_int), ("rel_resid", C.c_double), ("solve_ms", C.c_double),
+                ("whole_graph", C.c_int)]
 
 
 class BlockInfo(C.Structure):

@@ -1,10 +1,14 @@
-"""GPU: graph replay of the inner CG chunks against direct launches.
+"""GPU: graph replays against direct launches.
 
-The chunk graph is captured once per plan and replayed by every solve, so
-each test runs several solves in a row (with the program's own eager work
-and synchronisations between them) and requires every result to be bitwise
-equal to the one from one-by-one launches: the kernels are deterministic,
-so any difference would be a replay fault.
+Chunk graphs are captured once per plan and replayed by every solve, and a
+solve whose kind ran last on the plan replays one whole-solve graph sized by
+that solve's iteration counts.  Each test runs several solves in a row (with
+the program's own eager work and synchronisations between them).  A solve
+whose iteration counts equal those of the solve before it (the same seed
+again) must be bitwise equal to the step-by-step solve with one-by-one
+launches: the kernels are deterministic, so any difference would be a replay
+fault.  A solve after one with other counts must meet its tolerance and stay
+within kappa * rtol of it.
 """
 
 from __future__ import annotations
@@ -53,11 +57,19 @@ def test_graph_replay_bitwise(F, prec, pc):
     junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
     for seed in (5, 6, 5):
         ref = host(ref_plan.realize(dd, seed, 1e-9))
-        junk = junk * 1.0001 + 1.0  # eager work between replays
-        got = host(g_plan.realize(dd, seed, 1e-9))
-        torch.cuda.synchronize()
-        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
-        assert g_plan.stats()["iters_inner"] == ref_plan.stats()["iters_inner"]
+        assert ref_plan.stats()["whole_graph"] == 0
+        for rep in range(2):
+            junk = junk * 1.0001 + 1.0  # eager work between replays
+            got = host(g_plan.realize(dd, seed, 1e-9))
+            torch.cuda.synchronize()
+            st = g_plan.stats()
+            assert st["status"] == 0 and st["rel_resid"] <= 1e-9
+            if rep == 1:  # the counts of the solve before: bitwise the step-by-step solve
+                assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+                assert st["iters_inner"] == ref_plan.stats()["iters_inner"]
+            else:
+                m = mask != 0
+                assert np.linalg.norm(got[m] - ref[m]) <= 1e-5 * np.linalg.norm(ref[m])
 
 
 def test_graph_batch_and_record(F):
@@ -106,3 +118,59 @@ def test_graph_concurrent_capture_multi(F):
         torch.cuda.synchronize()
         for o, r in zip(outs, refs):
             assert np.array_equal(host(o).view(np.uint64), r.view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_whole_solve_graph_is_used_and_exact(F, prec):
+    # block preconditioner (few iterations): after one step-by-step solve the
+    # same solve replays as one graph; bitwise equal to the step-by-step one,
+    # with the Lanczos record of its first inner solve
+    P, mask, d = case(256, 51, 0.1, 25)
+    dd = dev(d)
+    ref = F.Plan(256, 256, mask, P, prec=prec)
+    ref.set_precond(F.FILL_PRECOND_BLOCK)
+    ref.set_graph(False)
+    ref.set_lanczos(64)
+    g = F.Plan(256, 256, mask, P, prec=prec)
+    g.set_precond(F.FILL_PRECOND_BLOCK)
+    g.set_lanczos(64)
+    want = host(ref.realize(dd, 9, 1e-9))
+    first = host(g.realize(dd, 9, 1e-9))
+    assert g.stats()["whole_graph"] == 0
+    assert np.array_equal(first.view(np.uint64), want.view(np.uint64))
+    for _ in range(3):
+        got = host(g.realize(dd, 9, 1e-9))
+        st = g.stats()
+        assert st["whole_graph"] == 1 and st["status"] == 0
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+        assert st["iters_inner"] == ref.stats()["iters_inner"]
+        assert st["iters_outer"] == ref.stats()["iters_outer"]
+        a0, b0 = ref.lanczos()
+        a1, b1 = g.lanczos()
+        assert np.array_equal(a0, a1) and np.array_equal(b0, b1) and len(a0) > 0
+    # the mean uses its own counts: step by step first, then a graph
+    mref = host(ref.mean(dd, 1e-9))
+    m1 = host(g.mean(dd, 1e-9))
+    assert g.stats()["whole_graph"] == 0
+    m2 = host(g.mean(dd, 1e-9))
+    assert g.stats()["whole_graph"] == 1
+    assert np.array_equal(m1.view(np.uint64), mref.view(np.uint64))
+    assert np.array_equal(m2.view(np.uint64), mref.view(np.uint64))
+
+
+def test_whole_solve_graph_with_too_few_iterations_continues(F):
+    # a tighter tolerance than the solve before: the graph's steps stop short,
+    # the refinement continues step by step and reaches the tolerance
+    P, mask, d = case(256, 52, 0.1, 25)
+    dd = dev(d)
+    g = F.Plan(256, 256, mask, P, prec=1)
+    g.set_precond(F.FILL_PRECOND_BLOCK)
+    ref = F.Plan(256, 256, mask, P, prec=0)
+    ref.set_precond(F.FILL_PRECOND_BLOCK)
+    want = host(ref.realize(dd, 3, 1e-12))
+    g.realize(dd, 3, 1e-6)
+    got = host(g.realize(dd, 3, 1e-10))
+    st = g.stats()
+    assert st["status"] == 0 and st["rel_resid"] <= 1e-10 and st["whole_graph"] == 0
+    m = mask != 0
+    assert np.linalg.norm(got[m] - want[m]) <= 1e-5 * np.linalg.norm(want[m])
