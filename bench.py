@@ -247,16 +247,18 @@ def bench_batch_2048(F, prob, args) -> dict:
             "rel_resid_max": max(v["rel_resid"] for v in st)}
 
 
-def bench_mixed64(args) -> int:
+def mixed64_result(F, args, steps, warmup) -> dict:
     """64 problems of uneven sizes {256..1024}^2, FP32 operators, rtol 1e-6:
-    one batched plan per size on its own stream, all run concurrently."""
+    one batched plan per size, solved as a group (after a first step-by-step
+    call, one graph launch per step with a branch per size); the same plans
+    driven by host threads (fill_realize_multi) are timed beside it."""
     import torch
-    import paper_1109_0286_amd as F
     import workloads as W
     probs = W.make_mixed_batch()
     groups = {}
     for p in probs:
         groups.setdefault(p.nx, []).append(p)
+    t_setup = time.perf_counter()
     plans, ds, seeds = [], [], []
     for n, ps in sorted(groups.items()):
         plans.append(F.BatchPlan(n, n, np.stack([p.mask for p in ps]), ps[0].P, F.FILL_PREC_FP32_OP,
@@ -265,28 +267,73 @@ def bench_mixed64(args) -> int:
         ds.append(torch.from_numpy(np.stack([p.d_obs for p in ps])).cuda())
         seeds.append([p.seed for p in ps])
     torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
     outs = [torch.empty_like(d) for d in ds]
-    for _ in range(args.warmup):
-        F.realize_multi(plans, ds, seeds, 1e-6, outs=outs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        F.realize_multi(plans, ds, seeds, 1e-6, outs=outs)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    group = F.Group(plans)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    dt = timed(lambda: group.realize(ds, seeds, 1e-6, outs=outs))
+    graph = group.last_graph()
     iters = [s["iters_inner"] for pl in plans for s in pl.stats()]
+    resid = max(s["rel_resid"] for pl in plans for s in pl.stats())
+    dt_threads = timed(lambda: F.realize_multi(plans, ds, seeds, 1e-6, outs=outs))
+    group.close()
+    for pl in plans:
+        pl.close()
+    return {"value": len(probs) * steps / dt, "unit": "solves/s", "steps": steps, "ms_per_step": dt / steps * 1e3,
+            "one_graph_launch": graph, "problems": len(probs),
+            "problems_per_size": {str(k): len(v) for k, v in sorted(groups.items())},
+            "iters_inner_max": max(iters), "iters_inner_mean": float(np.mean(iters)), "rel_resid_max": resid,
+            "host_threads_solves_per_s": len(probs) * steps / dt_threads, "plan_setup_s": setup_s}
+
+
+def bench_mixed64(args) -> int:
+    """64 problems of uneven sizes {256..1024}^2 as one group (own line)."""
+    import paper_1109_0286_amd as F
+    r = mixed64_result(F, args, args.steps, args.warmup)
     out = {"metric": "constrained-realization solves/s, 64 problems of uneven sizes (one batched step)",
-           "value": len(probs) * args.steps / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+           "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement",
            "data": "synthetic",
            "config": {"workload": "64 problems, n ~ U{256,512,768,1024}, band U(5,20)% + U{20..100} holes "
-                                  "r~U(2,10), damping n/8, rtol 1e-6; one batched plan per size, 4 streams",
-                      "problems_per_size": {str(k): len(v) for k, v in sorted(groups.items())},
-                      "iters_inner_max": max(iters), "iters_inner_mean": float(np.mean(iters)),
-                      "preconditioner": args.precond, "cg": args.cg}}
+                                  "r~U(2,10), damping n/8, rtol 1e-6; one batched plan per size, one group",
+                      "preconditioner": args.precond, "cg": args.cg},
+           "group": r}
     print(json.dumps(out), flush=True)
     return 0
+
+
+def grid4096_result(F, args, steps, warmup) -> dict:
+    """4096^2 wide cut: solves/s, iterations and refinements of the mixed and
+    FP64 paths at rtol 1e-8 (no per-kernel pass: the --workload grid4096 line
+    has those)."""
+    import torch
+    import workloads as W
+    prob = W.make_problem("grid4096")
+    d = torch.from_numpy(prob.d_obs).cuda()
+    res = {}
+    for name, prec in (("mixed", F.FILL_PREC_FP32_OP), ("fp64", F.FILL_PREC_FP64)):
+        t0 = time.perf_counter()
+        plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, prec)
+        configure(plan, args)
+        setup_s = time.perf_counter() - t0
+        dt, st, _, _ = time_solves(F, plan, d, prob.seed, prob.rtol, steps, warmup, -1)
+        res[name] = {"solves_per_s": steps / dt, "ms_per_solve": dt / steps * 1e3, "iters_inner": st["iters_inner"],
+                     "iters_outer": st["iters_outer"], "rel_resid": st["rel_resid"],
+                     "whole_graph": st.get("whole_graph"), "plan_setup_s": setup_s}
+        plan.close()
+    return {"value": res["mixed"]["solves_per_s"], "unit": "solves/s", "steps": steps, "n_masked": prob.n_masked,
+            "paths": res}
 
 
 def masked_errors(F, prob, d, plans: dict, rtol: float) -> dict:
@@ -643,6 +690,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="leave the mixed64 and grid4096 sub-results out of the default line")
     ap.add_argument("--kernel-ms", action="store_true",
                     help="also time each kernel in isolation (back-to-back launches)")
     ap.add_argument("--reps", type=int, default=50, help="launches per isolated kernel timing")
@@ -767,6 +816,13 @@ def bench_grid2048(args) -> int:
     out["preconditioners"] = compare_preconds(F, prob, d, args)
     if args.batch > 0:
         out["batched_2048"] = bench_batch_2048(F, prob, args)
+    if not args.no_extra:
+        # the Monte-Carlo batch of uneven sizes and the 4096^2 wide cut, so
+        # that the default line carries them (their own lines: --workload)
+        plan32.close()
+        plan64.close()
+        out["mixed64"] = mixed64_result(F, args, max(2, args.steps // 2), max(2, args.warmup))
+        out["grid4096"] = grid4096_result(F, args, max(2, args.steps // 2), max(2, args.warmup))
     if not args.no_cpu_baseline:
         # the oracle solves by its split-form PCG (Sec. 2.4): its iteration
         # count is that of the same FP64 recurrence on the GPU

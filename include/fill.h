@@ -417,6 +417,36 @@ int fill_mean_batch(fill_plan plan, const double* const* d_obs, double* const* x
 int fill_realize_multi(int nplans, const fill_plan* plans, const double* const* const* d_obs,
                        const uint64_t* const* seeds, double* const* const* x_out, double rtol);
 
+/*
+ * A group of batched plans solved together (a Monte-Carlo step over maps of
+ * uneven sizes, Sec. 1: one batched plan per grid size, each with its own
+ * masks, spectra, data and seeds).  The group refers to the plans (which must
+ * outlive it and appear once each) and launches on `stream`.
+ *
+ * fill_group_realize runs fill_realize_batch on every plan (d_obs[i],
+ * seeds[i], x_out[i] as there).  The first call, and any call after which a
+ * plan's step counts change, runs the plans step by step, each on its own
+ * stream and host thread; once every plan's previous solve gives its step
+ * counts (see fill_plan_set_graph: same kind of solve, at most 8 steps and
+ * 128 inner iterations, graphs on), the plans' solves are captured as one
+ * HIP graph -- one branch per plan, each branch the plan's whole solve with
+ * its per-problem descriptors (map pointers, seeds, refinement state) read
+ * from device tables and every convergence decision taken on the device --
+ * and every later call is that graph launched once on the group's stream,
+ * with one host wait at the end.  A plan whose problems need more steps than
+ * predicted continues step by step after the graph.  Results as
+ * fill_realize_batch per plan; returns the worst status (fill_last_error
+ * names the plan).  fill_group_last_graph: 1 if the last call ran as one
+ * graph launch.  fill_group_destroy releases the group (not the plans; NULL
+ * is accepted).
+ */
+typedef struct fill_group_s* fill_group;
+int fill_group_create(int nplans, const fill_plan* plans, void* stream, fill_group* out);
+int fill_group_realize(fill_group group, const double* const* const* d_obs, const uint64_t* const* seeds,
+                       double* const* const* x_out, double rtol);
+int fill_group_last_graph(fill_group group);
+void fill_group_destroy(fill_group group);
+
 /* Statistics of the last solve on this plan (for a batch: iteration counts
  * and residual are the maxima over problems, n_masked the total). */
 int fill_get_stats(fill_plan plan, fill_stats* out);

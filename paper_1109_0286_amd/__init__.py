@@ -7,7 +7,7 @@ The package is a thin binding of libfill.so (C ABI, include/fill.h).
 """
 
 from .fill import *  # noqa: F401,F403
-from .fill import Plan, BatchPlan, Strips, realize_multi, philox_words, EXPORTS, LIB_PATH  # noqa: F401
+from .fill import Plan, BatchPlan, Group, Strips, realize_multi, philox_words, EXPORTS, LIB_PATH  # noqa: F401
 
 
 def autograd_fill():

@@ -157,6 +157,7 @@ struct fill_plan_s {
   // them a solve runs as one captured graph, no host round trip inside
   int pred_key = -1, pred_R = 0;
   int last_whole_graph = 0;  // the last solve ran as one graph replay
+  unsigned gen = 0;          // bumped whenever captured graphs are dropped (groups re-capture)
   int pred_L[kStateIts] = {};
   std::map<std::vector<int>, std::pair<hipGraph_t, hipGraphExec_t>> solve_graphs;
   int nblk64 = 0, nblk32 = 0;
@@ -225,6 +226,21 @@ struct fill_plan_s {
   size_t events_used = 0;
   double timed_ms = 0.0;
   long long timed_count = 0;
+};
+
+// A group of batched plans solved together (fill_group_*): the graph that
+// holds every plan's predicted solve as one branch, and what it was captured
+// for (each plan's step counts and graph generation).
+struct fill_group_s {
+  std::vector<fill_plan> plans;
+  hipStream_t stream = nullptr;   // where the group's graph is launched
+  hipStream_t cap = nullptr;      // capture origin
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  std::vector<int> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int last_graph = 0;             // the last call ran as one graph launch
 };
 
 namespace {
@@ -409,6 +425,7 @@ int chunk_graph(fill_plan p, int f32, int mode, int rec, int len, F&& chunk, hip
 // Drop captured chunk graphs (all, or only those that record coefficients),
 // and every captured whole-solve graph.
 void drop_graphs(fill_plan p, bool record_only) {
+  ++p->gen;
   for (auto& kv : p->solve_graphs) {
     if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
     if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
@@ -1389,6 +1406,19 @@ bool whole_graph_ok(fill_plan p, bool mean) {
   return sum <= 128;
 }
 
+// The predicted solve on p->stream: start passes, pred_R refinement steps of
+// pred_L[j] inner iterations each, and the assembly x_out += u, which runs
+// only if every problem is done by then (otherwise the host continues).
+int enqueue_whole_solve(fill_plan p, bool mean) {
+  FILL_TRY(enqueue_start(p, mean));
+  for (int j = 0; j < p->pred_R; ++j) {
+    p->cur_outer = j;
+    FILL_TRY(refine_step(p, j == 0, p->pred_L[j]));
+  }
+  HIP_TRY(launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, p->nprob, p->stream, p->st));
+  return FILL_OK;
+}
+
 // The whole solve as one graph (captured on first use per key and step
 // lengths): start passes, pred_R refinement steps of pred_L[j] inner
 // iterations each, and the assembly x_out += u, which runs only if every
@@ -1405,19 +1435,7 @@ int whole_graph(fill_plan p, bool mean, hipGraphExec_t* out) {
   const hipStream_t saved = p->stream;
   p->stream = p->cap_stream;
   const hipError_t e0 = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-  int rc = FILL_OK;
-  if (e0 == hipSuccess) {
-    rc = enqueue_start(p, mean);
-    for (int j = 0; j < p->pred_R && rc == FILL_OK; ++j) {
-      p->cur_outer = j;
-      rc = refine_step(p, j == 0, p->pred_L[j]);
-    }
-    if (rc == FILL_OK) {
-      const hipError_t e = launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, p->nprob,
-                                              p->stream, p->st);
-      if (e != hipSuccess) rc = fail(FILL_EHIP, std::string("launch_scatter_add: ") + hipGetErrorString(e));
-    }
-  }
+  const int rc = e0 == hipSuccess ? enqueue_whole_solve(p, mean) : FILL_OK;
   hipGraph_t g = nullptr;
   const hipError_t e1 = e0 == hipSuccess ? hipStreamEndCapture(p->cap_stream, &g) : hipSuccess;
   p->stream = saved;
@@ -1478,24 +1496,31 @@ void finish_stats(fill_plan p, int st, double ms) {
 
 using clk = std::chrono::steady_clock;
 
-int realize_impl(fill_plan p, const double* const* d, const uint64_t* seeds, double* const* x, double rtol,
+// Checks of a call and its parameters into the plan's pinned staging block
+// (after the previous call's upload has completed).
+int prepare_call(fill_plan p, const double* const* d, const uint64_t* seeds, double* const* x, double rtol,
                  bool mean) {
-  g_last_error.clear();
   if (!p) return fail(FILL_EINVAL, "NULL plan");
   if (!(rtol > 0.0)) return fail(FILL_EINVAL, "rtol must be > 0");
   FILL_TRY(check_maps(p, d, x));
   if (!mean && !seeds) return fail(FILL_EINVAL, "NULL seeds");
-  const auto t0 = clk::now();
-  const int np = p->nprob;
-  // the previous call's parameter upload must have completed before the
-  // pinned staging block is rewritten
   HIP_TRY(hipStreamSynchronize(p->stream));
-  for (int b = 0; b < np; ++b) {
+  for (int b = 0; b < p->nprob; ++b) {
     p->pstats[b] = fill_stats{0, 0, p->n_m[b], 0, 0.0, 0.0};
     p->hp.in_tab[b] = d[b];
     p->hp.out_tab[b] = x[b];
     p->hp.seeds[b] = mean ? 0 : seeds[b];
   }
+  set_cfg(p, rtol);
+  return FILL_OK;
+}
+
+int realize_impl(fill_plan p, const double* const* d, const uint64_t* seeds, double* const* x, double rtol,
+                 bool mean) {
+  g_last_error.clear();
+  const auto t0 = clk::now();
+  FILL_TRY(prepare_call(p, d, seeds, x, rtol, mean));
+  const int np = p->nprob;
   if (p->n_m_total == 0) {
     p->last_whole_graph = 0;
     for (int b = 0; b < np; ++b)
@@ -1504,7 +1529,6 @@ int realize_impl(fill_plan p, const double* const* d, const uint64_t* seeds, dou
     finish_stats(p, FILL_OK, std::chrono::duration<double, std::milli>(clk::now() - t0).count());
     return FILL_OK;
   }
-  set_cfg(p, rtol);
   FILL_TRY(upload_params(p));
   const int st = run_solve(p, mean);
   finish_stats(p, st, std::chrono::duration<double, std::milli>(clk::now() - t0).count());
@@ -1833,6 +1857,90 @@ int read_lanczos(fill_plan p, int problem, std::vector<double>& al, std::vector<
 
 }  // namespace
 
+namespace {
+
+void group_drop_graph(fill_group g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+  g->key.clear();
+}
+
+// The group's graph for the plans' current predictions: one branch per plan
+// (forked from and joined into the capture origin), each the plan's whole
+// predicted solve on its own capture stream.
+int group_graph(fill_group g) {
+  std::vector<int> key;
+  for (fill_plan p : g->plans) {
+    key.push_back((int)p->gen);
+    key.push_back(p->hist_cap > 0 ? 1 : 0);
+    key.push_back(p->pred_R);
+    for (int j = 0; j < p->pred_R; ++j) key.push_back(p->pred_L[j]);
+  }
+  if (g->exec && key == g->key) return FILL_OK;
+  group_drop_graph(g);
+  if (!g->cap) HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+  for (fill_plan p : g->plans)
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  const hipError_t e0 = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+  if (e0 != hipSuccess) return fail(FILL_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e0));
+  int rc = FILL_OK;
+  hipError_t e = hipEventRecord(g->fork, g->cap);
+  for (size_t i = 0; i < g->plans.size() && rc == FILL_OK && e == hipSuccess; ++i) {
+    fill_plan p = g->plans[i];
+    e = hipStreamWaitEvent(p->cap_stream, g->fork, 0);
+    if (e != hipSuccess) break;
+    const hipStream_t saved = p->stream;
+    p->stream = p->cap_stream;
+    rc = enqueue_whole_solve(p, false);
+    p->stream = saved;
+    if (rc != FILL_OK) break;
+    e = hipEventRecord(g->join[i], p->cap_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(g->cap, g->join[i], 0);
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(g->cap, &graph);
+  if (rc != FILL_OK || e != hipSuccess || e1 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != FILL_OK) return rc;
+    return fail(FILL_EHIP, std::string("group capture: ") + hipGetErrorString(e != hipSuccess ? e : e1));
+  }
+  const hipError_t e2 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    g->exec = nullptr;
+    (void)hipGraphDestroy(graph);
+    return fail(FILL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  }
+  g->graph = graph;
+  g->key = key;
+  return FILL_OK;
+}
+
+// Plans i of the group in threads of their own: each runs fn(i) (a solve on
+// its own stream).  Returns the worst status; g_last_error names the plan.
+template <typename Fn> int per_plan_threads(int n, Fn&& fn) {
+  std::vector<int> rc(n, FILL_OK);
+  std::vector<std::string> err(n);
+  std::vector<std::thread> th;
+  for (int i = 0; i < n; ++i)
+    th.emplace_back([&, i] {
+      g_last_error.clear();
+      rc[i] = fn(i);
+      err[i] = g_last_error;
+    });
+  for (auto& t : th) t.join();
+  int worst = FILL_OK;
+  for (int i = 0; i < n; ++i)
+    if (rc[i] != FILL_OK && (worst == FILL_OK || worst == FILL_ENOCONV)) {
+      worst = rc[i];
+      g_last_error = "plan " + std::to_string(i) + ": " + err[i];
+    }
+  return worst;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // Scratch of fill_realize_unconstrained_noalloc: the transposed half spectrum
 // of the draw lives in this file-scope device array instead of the plan's
@@ -2027,24 +2135,101 @@ int fill_realize_multi(int nplans, const fill_plan* plans, const double* const* 
                        const uint64_t* const* seeds, double* const* const* x_out, double rtol) {
   g_last_error.clear();
   if (nplans < 1 || !plans || !d_obs || !seeds || !x_out) return fail(FILL_EINVAL, "bad argument");
-  std::vector<int> rc(nplans, FILL_OK);
-  std::vector<std::string> err(nplans);
-  std::vector<std::thread> th;
+  return per_plan_threads(nplans, [&](int i) { return realize_impl(plans[i], d_obs[i], seeds[i], x_out[i], rtol, false); });
+}
+
+int fill_group_create(int nplans, const fill_plan* plans, void* stream, fill_group* out) {
+  g_last_error.clear();
+  if (!out) return fail(FILL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nplans < 1 || !plans) return fail(FILL_EINVAL, "need at least one plan");
   for (int i = 0; i < nplans; ++i) {
-    th.emplace_back([&, i] {
-      rc[i] = realize_impl(plans[i], d_obs[i], seeds[i], x_out[i], rtol, false);
-      err[i] = g_last_error;
+    if (!plans[i]) return fail(FILL_EINVAL, "NULL plan " + std::to_string(i));
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(FILL_EINVAL, "plan " + std::to_string(i) + " appears twice");
+  }
+  fill_group g = new (std::nothrow) fill_group_s();
+  if (!g) return fail(FILL_ENOMEM, "host allocation");
+  g->plans.assign(plans, plans + nplans);
+  g->stream = static_cast<hipStream_t>(stream);
+  g->join.assign(nplans, nullptr);
+  hipError_t e = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming);
+  for (int i = 0; i < nplans && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&g->join[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    fill_group_destroy(g);
+    return fail(FILL_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return FILL_OK;
+}
+
+int fill_group_realize(fill_group g, const double* const* const* d_obs, const uint64_t* const* seeds,
+                       double* const* const* x_out, double rtol) {
+  g_last_error.clear();
+  if (!g || !d_obs || !seeds || !x_out) return fail(FILL_EINVAL, "bad argument");
+  const int n = (int)g->plans.size();
+  const auto t0 = clk::now();
+  bool graph = true;
+  for (int i = 0; i < n; ++i) {
+    fill_plan p = g->plans[i];
+    if (!d_obs[i] || !seeds[i] || !x_out[i]) return fail(FILL_EINVAL, "NULL arrays for plan " + std::to_string(i));
+    FILL_TRY(prepare_call(p, d_obs[i], seeds[i], x_out[i], rtol, false));
+    graph = graph && whole_graph_ok(p, false);
+  }
+  g->last_graph = 0;
+  if (!graph) {
+    // step by step, each plan on its own stream and host thread; the solves
+    // give the step counts the next call's graph is captured for
+    return per_plan_threads(n, [&](int i) {
+      fill_plan p = g->plans[i];
+      const auto t1 = clk::now();
+      int rc = upload_params(p);
+      if (rc == FILL_OK) rc = run_solve(p, false);
+      finish_stats(p, rc, std::chrono::duration<double, std::milli>(clk::now() - t1).count());
+      return rc;
     });
   }
-  for (auto& t : th) t.join();
-  int worst = FILL_OK;
-  for (int i = 0; i < nplans; ++i) {
-    if (rc[i] != FILL_OK && (worst == FILL_OK || worst == FILL_ENOCONV)) {
-      worst = rc[i];
-      g_last_error = "plan " + std::to_string(i) + ": " + err[i];
+  FILL_TRY(group_graph(g));
+  for (fill_plan p : g->plans)
+    HIP_TRY(hipMemcpyAsync(p->par_dev, p->par_host, p->par_bytes, hipMemcpyHostToDevice, g->stream));
+  HIP_TRY(hipGraphLaunch(g->exec, g->stream));
+  for (fill_plan p : g->plans)
+    HIP_TRY(hipMemcpyAsync(p->h_st, p->st, p->nprob * sizeof(SolveState), hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  bool all = true;
+  for (fill_plan p : g->plans) all = all && all_done(p);
+  g->last_graph = all ? 1 : 0;
+  const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  return per_plan_threads(n, [&](int i) {
+    fill_plan p = g->plans[i];
+    p->last_whole_graph = g->last_graph;
+    int rc = FILL_OK;
+    if (!all_done(p)) {  // this plan's steps did not suffice: continue on its own stream
+      rc = refine_host(p, false);
+      if (rc == FILL_OK) {
+        const hipError_t e = launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, p->nprob,
+                                                p->stream);
+        if (e == hipSuccess) (void)hipStreamSynchronize(p->stream);
+        else rc = fail(FILL_EHIP, std::string("launch_scatter_add: ") + hipGetErrorString(e));
+      }
     }
-  }
-  return worst;
+    if (rc == FILL_OK) rc = finish_solve(p, solve_key(p, false));
+    finish_stats(p, rc, ms);
+    return rc;
+  });
+}
+
+int fill_group_last_graph(fill_group g) { return g ? g->last_graph : 0; }
+
+void fill_group_destroy(fill_group g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  group_drop_graph(g);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  if (g->fork) (void)hipEventDestroy(g->fork);
+  for (hipEvent_t e : g->join)
+    if (e) (void)hipEventDestroy(e);
+  delete g;
 }
 
 int fill_laplace(fill_plan p, const double* d_obs, double* x_out, int nkernels, double r0, double ratio, int iters) {

@@ -49,7 +49,8 @@ EXPORTS = (
     "fill_lanczos_extremes", "fill_plan_set_graph", "fill_plan_set_skew", "fill_strips_create",
     "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
     "fill_strips_refine", "fill_laplace", "fill_plan_set_cg", "fill_get_block_info",
-    "fill_realize_unconstrained_noalloc",
+    "fill_realize_unconstrained_noalloc", "fill_group_create", "fill_group_realize", "fill_group_last_graph",
+    "fill_group_destroy",
 )
 
 FILL_PRECOND_NONE = 0
@@ -100,6 +101,10 @@ def _load() -> C.CDLL:
         "fill_realize_batch": (i32, [vp, vp, vp, vp, dbl]),
         "fill_mean_batch": (i32, [vp, vp, vp, dbl]),
         "fill_realize_multi": (i32, [i32, vp, vp, vp, vp, dbl]),
+        "fill_group_create": (i32, [i32, vp, vp, C.POINTER(vp)]),
+        "fill_group_realize": (i32, [vp, vp, vp, vp, dbl]),
+        "fill_group_last_graph": (i32, [vp]),
+        "fill_group_destroy": (None, [vp]),
         "fill_get_stats_batch": (i32, [vp, C.POINTER(fill_stats)]),
         "fill_plan_set_bands": (i32, [vp, i32, vp, vp]),
         "fill_adjoint": (i32, [vp, vp, u64, vp, vp, vp, vp, vp, dbl]),
@@ -231,6 +236,44 @@ def fill_realize_multi(plans, d_ptrs, seeds, x_ptrs, rtol, allow_noconv=False):
         xx[i] = C.cast(x, C.c_void_p)
         ss[i] = C.cast(s, C.c_void_p)
     return _check(_lib.fill_realize_multi(n, _ptr_array(plans), dd, ss, xx, float(rtol)), "fill_realize_multi", ok)
+
+
+def _plan_arrays(d_ptrs, seeds, x_ptrs):
+    """Per-plan host arrays of device pointers and seeds (and what keeps them alive)."""
+    n = len(d_ptrs)
+    keep = []
+    dd = (C.c_void_p * n)()
+    xx = (C.c_void_p * n)()
+    ss = (C.c_void_p * n)()
+    for i in range(n):
+        a, x = _ptr_array(d_ptrs[i]), _ptr_array(x_ptrs[i])
+        s = (C.c_uint64 * len(seeds[i]))(*[int(v) for v in seeds[i]])
+        keep += [a, x, s]
+        dd[i] = C.cast(a, C.c_void_p)
+        xx[i] = C.cast(x, C.c_void_p)
+        ss[i] = C.cast(s, C.c_void_p)
+    return dd, ss, xx, keep
+
+
+def fill_group_create(plans, stream) -> int:
+    out = C.c_void_p()
+    _check(_lib.fill_group_create(len(plans), _ptr_array(plans), stream, C.byref(out)), "fill_group_create")
+    return out.value
+
+
+def fill_group_realize(group, d_ptrs, seeds, x_ptrs, rtol, allow_noconv=False):
+    """d_ptrs/x_ptrs/seeds: per plan of the group, one entry per problem."""
+    ok = (FILL_OK, FILL_ENOCONV) if allow_noconv else (FILL_OK,)
+    dd, ss, xx, _keep = _plan_arrays(d_ptrs, seeds, x_ptrs)
+    return _check(_lib.fill_group_realize(group, dd, ss, xx, float(rtol)), "fill_group_realize", ok)
+
+
+def fill_group_last_graph(group) -> bool:
+    return bool(_lib.fill_group_last_graph(group))
+
+
+def fill_group_destroy(group):
+    _lib.fill_group_destroy(group)
 
 
 def fill_get_stats_batch(plan) -> list:
@@ -680,6 +723,48 @@ def realize_multi(plans, d_obs_list, seeds_list, rtol, outs=None, allow_noconv=F
                        [[o[b].data_ptr() for b in range(p.nprob)] for p, o in zip(plans, outs)],
                        rtol, allow_noconv)
     return outs
+
+
+class Group:
+    """Several BatchPlans (for example one per grid size) solved together:
+    after a first step-by-step call, every call is one graph launch on the
+    group's stream (see fill_group_realize)."""
+
+    def __init__(self, plans, stream=None):
+        import torch
+        self.plans = list(plans)
+        dev = self.plans[0].device
+        with torch.cuda.device(dev):
+            s = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = s
+        self.handle = fill_group_create([p.handle for p in self.plans], s.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fill_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def realize(self, d_obs_list, seeds_list, rtol, outs=None, allow_noconv=False):
+        import torch
+        outs = outs if outs is not None else [torch.empty_like(d) for d in d_obs_list]
+        for d, o in zip(d_obs_list, outs):
+            _dev_ptr(d, torch.float64)
+            _dev_ptr(o, torch.float64)
+        fill_group_realize(self.handle,
+                           [[d[b].data_ptr() for b in range(p.nprob)] for p, d in zip(self.plans, d_obs_list)],
+                           seeds_list,
+                           [[o[b].data_ptr() for b in range(p.nprob)] for p, o in zip(self.plans, outs)],
+                           rtol, allow_noconv)
+        return outs
+
+    def last_graph(self) -> bool:
+        return fill_group_last_graph(self.handle)
 
 
 def _check_strips(code: int, where: str, ok=(FILL_OK,)) -> int:
