@@ -636,6 +636,45 @@ def bench_grid4096(args) -> int:
     return 0
 
 
+def bench_warm4096(args) -> int:
+    """The Laplace warm start (Sec. 6.1, 6.3) on the 4096^2 wide cut: CG
+    iterations and time of FP64 solves at rtol 1e-8 from u0 = 0 and from the
+    kernel Laplace relaxation (25 and 100 sweeps), with the split (E E) and
+    the block preconditioners."""
+    import torch
+    import paper_1109_0286_amd as F
+    import workloads as W
+    prob = W.make_problem("grid4096")
+    d = torch.from_numpy(prob.d_obs).cuda()
+    x = torch.empty_like(d)
+    rows = []
+    for pc in ("split", "block"):
+        plan = F.Plan(prob.nx, prob.ny, prob.mask, prob.P, F.FILL_PREC_FP64)
+        plan.set_precond(PRECONDS[pc])
+        for sweeps in (0, 25, 100):
+            plan.set_warm_start(sweeps)
+            plan.realize(d, prob.seed, prob.rtol, out=x)  # set-up (kernel spectra, classes)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.realize(d, prob.seed, prob.rtol, out=x)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = plan.stats()
+            rows.append({"precond": pc, "sweeps": sweeps, "iters_inner": st["iters_inner"],
+                         "iters_outer": st["iters_outer"], "ms_per_solve": dt * 1e3, "rel_resid": st["rel_resid"]})
+            print(f"# {pc} sweeps {sweeps}: {st['iters_inner']} iterations, {dt * 1e3:.1f} ms", file=sys.stderr,
+                  flush=True)
+        plan.close()
+    out = {"metric": "CG iterations and ms per FP64 solve at 4096^2 with and without the Laplace warm start",
+           "value": None, "unit": "iterations", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "4096x4096 torus, 30% band + 500 holes r~U(2,16), damping 512, rtol 1e-8; "
+                                  "Laplace kernels 8, r0 1.5, ratio 2"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_grad16(args) -> int:
     """Forward fill + adjoint of a loss sum(w x^2), w ~ U(0,1), for 16 1024^2
     maps (10% band + 100 holes r~U(2,10)) with P(k) from 50 log-spaced band
@@ -698,7 +737,8 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=4,
                     help="realizations per launch in the batched 2048^2 leg (0: skip it)")
     ap.add_argument("--workload", default="grid2048",
-                    choices=["grid2048", "mixed64", "grid4096", "grad16", "holes2048", "hermiticity", "strips2048"],
+                    choices=["grid2048", "mixed64", "grid4096", "grad16", "holes2048", "hermiticity", "strips2048",
+                             "warm4096"],
                     help="grid2048: the headline line; mixed64: 64 problems of uneven sizes; grid4096: the wide "
                          "cut; grad16: forward + adjoint of 16 1024^2 maps with 50 band powers; holes2048: "
                          "point sources only, CG with and without the preconditioner; hermiticity: plain CG on a "
@@ -735,6 +775,8 @@ def main() -> int:
         return bench_hermiticity(args)
     if args.workload == "strips2048":
         return bench_strips2048(args)
+    if args.workload == "warm4096":
+        return bench_warm4096(args)
     return bench_grid2048(args)
 
 

@@ -317,6 +317,20 @@ int fill_plan_set_graph(fill_plan plan, int on);
 int fill_laplace(fill_plan plan, const double* d_obs, double* x_out, int nkernels, double r0, double ratio, int iters);
 
 /*
+ * Warm start of the solves of a one-problem plan (Sec. 6.1, 6.3: the paper
+ * fills the far interior of a wide cut with its kernel Laplace solver before
+ * refining): with iters > 0 every later fill_realize / fill_mean starts the CG
+ * refinement from u0 = the fill_laplace relaxation (nkernels, r0, ratio,
+ * iters sweeps) of y - s_y (y for the mean) instead of u0 = 0, i.e. its first
+ * step solves A d = v - A u0.  The solution (to rtol) is the same; the
+ * relaxation's FFT convolutions are extra work, and the solves run step by
+ * step (no whole-solve graph).  iters = 0 (default) turns it off.  Arguments
+ * as fill_laplace; FILL_EINVAL for a batched plan or a kernel that does not
+ * fit the grid.
+ */
+int fill_plan_set_warm_start(fill_plan plan, int iters, int nkernels, double r0, double ratio);
+
+/*
  * Noise-boosted strip refinement (Sec. 6.2 subdivision, Sec. 6.4 refinement):
  * an approximate maximum-likelihood fill by a few CG iterations on nested
  * strips along the boundary of the masked region.

@@ -212,6 +212,9 @@ struct fill_plan_s {
   // kernel-based Laplace relaxation (Sec. 6.3): kernel spectra and classes
   int lap_k = 0;
   double lap_r0 = 0.0, lap_ratio = 0.0;
+  // Laplace warm start of the solves (fill_plan_set_warm_start): sweeps (0 = off) and kernels
+  int ws_iters = 0, ws_k = 8;
+  double ws_r0 = 1.5, ws_ratio = 2.0;
   std::vector<double*> lap_tab;
   std::vector<int> lap_used;
   uint8_t* lap_cls = nullptr;
@@ -1049,16 +1052,18 @@ int inner_pcg(fill_plan p, bool record, int fixed) {
 // per-problem norms and the device's decision of the next step.  Every
 // scalar is read from and written to the device state: nothing here waits
 // for the host.
-int refine_step(fill_plan p, bool first, int fixed) {
+int refine_step(fill_plan p, bool first, int fixed, bool warm = false) {
   const int np = p->nprob;
+  // from v with u = 0, unless a warm start has put u and res = v - A u in place
+  const bool from_v = first && !warm;
   if (p->prec == FILL_PREC_FP64) {
-    HIP_TRY(launch_scale_init_f64(p->v64.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v64.x, p->v64.p,
-                                  first ? p->u : nullptr, p->n_m_max, np, p->stream));
+    HIP_TRY(launch_scale_init_f64(p->v64.r, from_v ? p->b : p->res, p->dp.scale, p->comp_off, p->v64.x, p->v64.p,
+                                  from_v ? p->u : nullptr, p->n_m_max, np, p->stream));
     FILL_TRY(inner_pcg<double>(p, first, fixed));
     HIP_TRY(launch_axpy_f64(p->u, p->v64.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
   } else {
-    HIP_TRY(launch_scale_init_f32(p->v32.r, first ? p->b : p->res, p->dp.scale, p->comp_off, p->v32.x, p->v32.p,
-                                  first ? p->u : nullptr, p->n_m_max, np, p->stream));
+    HIP_TRY(launch_scale_init_f32(p->v32.r, from_v ? p->b : p->res, p->dp.scale, p->comp_off, p->v32.x, p->v32.p,
+                                  from_v ? p->u : nullptr, p->n_m_max, np, p->stream));
     FILL_TRY(inner_pcg<float>(p, first, fixed));
     HIP_TRY(launch_axpy_f32(p->u, p->v32.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
   }
@@ -1089,12 +1094,12 @@ bool all_done(fill_plan p) {
 // Host-driven refinement: with the state on the host, run steps (each read
 // back) until every problem is done.  first: no step has run yet in this
 // solve (the first one clears u and records the CG coefficients).
-int refine_host(fill_plan p, bool first) {
-  if (first && all_done(p))  // nothing to solve: u = 0
+int refine_host(fill_plan p, bool first, bool warm = false) {
+  if (first && !warm && all_done(p))  // nothing to solve: u = 0
     HIP_TRY(hipMemsetAsync(p->u, 0, (size_t)std::max(p->n_m_total, 1) * sizeof(double), p->stream));
   for (int pass = 0; !all_done(p); ++pass) {
     p->cur_outer = pass;
-    FILL_TRY(refine_step(p, first, 0));
+    FILL_TRY(refine_step(p, first, 0, warm));
     first = false;
     FILL_TRY(read_state(p));
   }
@@ -1395,7 +1400,7 @@ int solve_key(fill_plan p, bool mean) { return (mean ? 1 : 0) + 2 * p->precond +
 // single-reduction recurrence clears a vector with a memset at its start,
 // which is kept out of graphs.
 bool whole_graph_ok(fill_plan p, bool mean) {
-  if (!p->use_graph || p->timed_kernel >= 0 || p->n_m_total == 0) return false;
+  if (!p->use_graph || p->timed_kernel >= 0 || p->n_m_total == 0 || p->ws_iters > 0) return false;
   if (p->cg_variant == FILL_CG_SINGLE_REDUCTION && p->precond != FILL_PRECOND_BLOCK) return false;
   if (p->pred_key != solve_key(p, mean) || p->pred_R < 1 || p->pred_R > kStateIts) return false;
   int sum = 0;
@@ -1456,6 +1461,26 @@ int whole_graph(fill_plan p, bool mean, hipGraphExec_t* out) {
   return FILL_OK;
 }
 
+int laplace_run(fill_plan p, const double* in, int nkernels, double r0, double ratio, int iters, const double** out);
+
+// Warm start of the solve (Sec. 6.1, 6.3: the far interior of a wide cut is
+// nearly harmonic): the kernel Laplace relaxation of t = Py (d - s) (or Py d)
+// gives u on the masked pixels, then res = v - A u (FP64) and the device's
+// decision of the first step from it.  One-problem plans.
+int warm_start(fill_plan p) {
+  const double* lap = nullptr;
+  FILL_TRY(laplace_run(p, p->tfull, p->ws_k, p->ws_r0, p->ws_ratio, p->ws_iters, &lap));
+  HIP_TRY(launch_gather(p->u, lap, p->pos, p->n_m[0], p->stream));
+  RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
+  ai.v0 = p->u;
+  ao.v0 = p->res;
+  ao.v1 = p->b;
+  ao.part0 = p->part0;
+  FILL_TRY(apply3<double>(p, R2C_COMPACT, ai, p->Dinv64, C2R_RESID, ao, nullptr));
+  HIP_TRY(launch_ctl(refine_args(p), p->part0, (size_t)p->ny, p->nblk64, false, p->stream));
+  return FILL_OK;
+}
+
 // After the parameters are uploaded: the solve (one graph replay when the
 // previous solve's step counts are known, else step by step with the host
 // reading the state after each), then the assembly x_out += u.
@@ -1469,13 +1494,15 @@ int run_solve(fill_plan p, bool mean) {
   } else {
     FILL_TRY(enqueue_start(p, mean));
   }
+  const bool warm = !graph && p->ws_iters > 0;
+  if (warm) FILL_TRY(warm_start(p));
   FILL_TRY(read_state(p));
   const bool done = all_done(p);
   p->last_whole_graph = graph && done ? 1 : 0;
   if (!graph || !done) {
     // not every problem finished inside the graph (or no graph): continue
     // step by step, then assemble
-    FILL_TRY(refine_host(p, !graph));
+    FILL_TRY(refine_host(p, !graph, warm));
     HIP_TRY(launch_scatter_add(p->dp.out_tab, p->u, p->pos, p->comp_off, p->n_m_max, p->nprob, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
   }
@@ -1791,6 +1818,44 @@ int laplace_setup(fill_plan p, int nk, double r0, double ratio) {
   p->lap_k = nk;
   p->lap_r0 = r0;
   p->lap_ratio = ratio;
+  return FILL_OK;
+}
+
+// Arguments of the Laplace relaxation (one-problem plans; the largest kernel
+// must fit the grid).
+int laplace_check(fill_plan p, int nkernels, double r0, double ratio, int iters) {
+  if (p->nprob != 1) return fail(FILL_EINVAL, "the Laplace relaxation needs a one-problem plan");
+  if (nkernels < 1 || nkernels > 16 || !(r0 >= 1.0) || !(ratio > 1.0) || iters < 1)
+    return fail(FILL_EINVAL, "need 1 <= nkernels <= 16, r0 >= 1, ratio > 1, iters >= 1");
+  const double rmax = r0 * std::pow(ratio, (double)(nkernels - 1));
+  if (!(2.0 * std::floor(rmax) + 1.0 <= (double)std::min(p->nx, p->ny)))
+    return fail(FILL_EINVAL, "the largest Laplace kernel does not fit the grid");
+  return FILL_OK;
+}
+
+// `iters` Jacobi sweeps of the kernel relaxation from in (observed pixels
+// kept, masked ones from 0); *out points to the plan's buffer holding the
+// result (valid until the next relaxation).
+int laplace_run(fill_plan p, const double* in, int nkernels, double r0, double ratio, int iters, const double** out) {
+  FILL_TRY(laplace_setup(p, nkernels, r0, ratio));
+  const size_t npix = p->npix;
+  double* a = p->lap_x[0];
+  double* b = p->lap_x[1];
+  double* avg = p->lap_x[2];
+  HIP_TRY(launch_select_observed(a, in, p->mask, npix, p->stream));
+  HIP_TRY(hipMemcpyAsync(b, a, npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  // Jacobi sweeps: every used kernel's average of the current map, written to its class
+  for (int it = 0; it < iters; ++it) {
+    for (int j : p->lap_used) {
+      RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
+      ai.full_in = a;
+      ao.full_out = avg;
+      FILL_TRY(apply3<double>(p, R2C_FULL, ai, p->lap_tab[j], C2R_FULL, ao, nullptr));
+      HIP_TRY(launch_take_class(b, avg, p->lap_cls, j, npix, p->stream));
+    }
+    std::swap(a, b);
+  }
+  *out = a;
   return FILL_OK;
 }
 
@@ -2235,32 +2300,23 @@ void fill_group_destroy(fill_group g) {
 int fill_laplace(fill_plan p, const double* d_obs, double* x_out, int nkernels, double r0, double ratio, int iters) {
   g_last_error.clear();
   if (!p || !d_obs || !x_out) return fail(FILL_EINVAL, "NULL argument");
-  if (p->nprob != 1) return fail(FILL_EINVAL, "fill_laplace needs a one-problem plan");
   if (d_obs == x_out) return fail(FILL_EINVAL, "x_out may not alias d_obs");
-  if (nkernels < 1 || nkernels > 16 || !(r0 >= 1.0) || !(ratio > 1.0) || iters < 1)
-    return fail(FILL_EINVAL, "need 1 <= nkernels <= 16, r0 >= 1, ratio > 1, iters >= 1");
-  const double rmax = r0 * std::pow(ratio, (double)(nkernels - 1));
-  if (!(2.0 * std::floor(rmax) + 1.0 <= (double)std::min(p->nx, p->ny)))
-    return fail(FILL_EINVAL, "the largest Laplace kernel does not fit the grid");
-  FILL_TRY(laplace_setup(p, nkernels, r0, ratio));
-  const size_t npix = p->npix;
-  double* a = p->lap_x[0];
-  double* b = p->lap_x[1];
-  double* avg = p->lap_x[2];
-  HIP_TRY(launch_select_observed(a, d_obs, p->mask, npix, p->stream));
-  HIP_TRY(hipMemcpyAsync(b, a, npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-  // Jacobi sweeps: every used kernel's average of the current map, written to its class
-  for (int it = 0; it < iters; ++it) {
-    for (int j : p->lap_used) {
-      RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
-      ai.full_in = a;
-      ao.full_out = avg;
-      FILL_TRY(apply3<double>(p, R2C_FULL, ai, p->lap_tab[j], C2R_FULL, ao, nullptr));
-      HIP_TRY(launch_take_class(b, avg, p->lap_cls, j, npix, p->stream));
-    }
-    std::swap(a, b);
-  }
-  HIP_TRY(hipMemcpyAsync(x_out, a, npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  FILL_TRY(laplace_check(p, nkernels, r0, ratio, iters));
+  const double* res = nullptr;
+  FILL_TRY(laplace_run(p, d_obs, nkernels, r0, ratio, iters, &res));
+  HIP_TRY(hipMemcpyAsync(x_out, res, p->npix * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  return FILL_OK;
+}
+
+int fill_plan_set_warm_start(fill_plan p, int iters, int nkernels, double r0, double ratio) {
+  g_last_error.clear();
+  if (!p) return fail(FILL_EINVAL, "NULL plan");
+  if (iters < 0) return fail(FILL_EINVAL, "iters must be >= 0");
+  if (iters > 0) FILL_TRY(laplace_check(p, nkernels, r0, ratio, iters));
+  p->ws_iters = iters;
+  p->ws_k = nkernels;
+  p->ws_r0 = r0;
+  p->ws_ratio = ratio;
   return FILL_OK;
 }
 

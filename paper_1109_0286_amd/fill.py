@@ -50,7 +50,7 @@ EXPORTS = (
     "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
     "fill_strips_refine", "fill_laplace", "fill_plan_set_cg", "fill_get_block_info",
     "fill_realize_unconstrained_noalloc", "fill_group_create", "fill_group_realize", "fill_group_last_graph",
-    "fill_group_destroy",
+    "fill_group_destroy", "fill_plan_set_warm_start",
 )
 
 FILL_PRECOND_NONE = 0
@@ -121,6 +121,7 @@ def _load() -> C.CDLL:
         "fill_strips_mean": (i32, [vp, vp, vp]),
         "fill_strips_refine": (i32, [vp, vp]),
         "fill_laplace": (i32, [vp, vp, vp, i32, dbl, dbl, i32]),
+        "fill_plan_set_warm_start": (i32, [vp, i32, i32, dbl, dbl]),
         "fill_strips_mask": (i32, [vp, i32, vp]),
         "fill_strips_plan": (i32, [vp, i32, C.POINTER(vp)]),
         "fill_strips_last_error": (C.c_char_p, []),
@@ -338,6 +339,11 @@ def fill_plan_set_cg(plan, variant):
     return _check(_lib.fill_plan_set_cg(plan, int(variant)), "fill_plan_set_cg")
 
 
+def fill_plan_set_warm_start(plan, iters, nkernels=8, r0=1.5, ratio=2.0):
+    return _check(_lib.fill_plan_set_warm_start(plan, int(iters), int(nkernels), float(r0), float(ratio)),
+                  "fill_plan_set_warm_start")
+
+
 def fill_plan_set_skew(plan, eps):
     return _check(_lib.fill_plan_set_skew(plan, float(eps)), "fill_plan_set_skew")
 
@@ -509,6 +515,10 @@ class Plan:
     def set_skew(self, eps):
         """Non-Hermitian study: inner-CG A applies use Px C^-1 (I + eps K) Px (0 restores A)."""
         fill_plan_set_skew(self.handle, eps)
+
+    def set_warm_start(self, iters, nkernels=8, r0=1.5, ratio=2.0):
+        """Start later solves from the Laplace relaxation of the data (iters sweeps; 0 = off)."""
+        fill_plan_set_warm_start(self.handle, iters, nkernels, r0, ratio)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""
@@ -682,6 +692,10 @@ class BatchPlan:
     def set_skew(self, eps):
         """Non-Hermitian study: inner-CG A applies use Px C^-1 (I + eps K) Px (0 restores A)."""
         fill_plan_set_skew(self.handle, eps)
+
+    def set_warm_start(self, iters, nkernels=8, r0=1.5, ratio=2.0):
+        """Start later solves from the Laplace relaxation of the data (iters sweeps; 0 = off)."""
+        fill_plan_set_warm_start(self.handle, iters, nkernels, r0, ratio)
 
     def set_lanczos(self, cap):
         """Record up to cap CG coefficients of the first inner solve of later solves."""
