@@ -171,6 +171,11 @@ template <> struct FFTPlanV<128, 0> : RadixPlan<128, 16, 16, 8> {};
 template <> struct FFTPlanV<256, 0> : RadixPlan<256, 16, 16, 16> {};
 template <> struct FFTPlanV<512, 0> : RadixPlan<512, 16, 16, 16, 2> {};
 template <> struct FFTPlanV<768, 0> : RadixPlan<768, 24, 8, 8, 4, 3> {};
+template <> struct FFTPlanV<96, 0> : RadixPlan<96, 24, 8, 4, 3> {};
+template <> struct FFTPlanV<192, 0> : RadixPlan<192, 24, 8, 8, 3> {};
+template <> struct FFTPlanV<384, 0> : RadixPlan<384, 24, 8, 4, 4, 3> {};
+template <> struct FFTPlanV<1536, 0> : RadixPlan<1536, 24, 8, 8, 8, 3> {};
+template <> struct FFTPlanV<3072, 0> : RadixPlan<3072, 24, 8, 8, 4, 4, 3> {};
 template <> struct FFTPlanV<1024, 0> : RadixPlan<1024, 16, 16, 16, 4> {};
 template <> struct FFTPlanV<2048, 0> : RadixPlan<2048, 16, 16, 16, 8> {};
 template <> struct FFTPlanV<4096, 0> : RadixPlan<4096, 16, 16, 16, 16> {};
@@ -185,6 +190,11 @@ template <> struct FFTPlanV<16, 1> : FFTPlanV<16, 0> {};
 template <> struct FFTPlanV<32, 1> : FFTPlanV<32, 0> {};
 template <> struct FFTPlanV<64, 1> : FFTPlanV<64, 0> {};
 template <> struct FFTPlanV<768, 1> : FFTPlanV<768, 0> {};
+template <> struct FFTPlanV<96, 1> : FFTPlanV<96, 0> {};
+template <> struct FFTPlanV<192, 1> : FFTPlanV<192, 0> {};
+template <> struct FFTPlanV<384, 1> : FFTPlanV<384, 0> {};
+template <> struct FFTPlanV<1536, 1> : FFTPlanV<1536, 0> {};
+template <> struct FFTPlanV<3072, 1> : FFTPlanV<3072, 0> {};
 
 enum FFTPass { kRowPass = 0, kColPass = 1 };
 

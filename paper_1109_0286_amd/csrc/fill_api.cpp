@@ -1147,7 +1147,8 @@ int finish_solve(fill_plan p, int key) {
 
 bool size_ok(int n) {
   switch (n) {
-    case 16: case 32: case 64: case 128: case 256: case 512: case 768: case 1024: case 2048: case 4096:
+    case 16: case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024:
+    case 1536: case 2048: case 3072: case 4096:
       return true;
   }
   return false;

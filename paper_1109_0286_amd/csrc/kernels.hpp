@@ -1134,7 +1134,8 @@ hipError_t launch_c2r_n(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t
   return hipErrorInvalidValue;
 }
 
-#define FILL_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(768) X(1024) X(2048) X(4096)
+#define FILL_FOR_EACH_N(X) \
+  X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
 
 template <typename T>
 hipError_t launch_r2c(int mode, const RowArgs<T>& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {

@@ -37,9 +37,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_host_only_calls():
     import paper_1109_0286_amd as F
-    for n in (16, 32, 64, 128, 256, 512, 768, 1024, 2048, 4096):
+    for n in (16, 32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096):
         assert F.fill_supported_size(n)
-    for n in (0, 8, 100, 1000, 8192, -1):
+    for n in (0, 8, 48, 100, 1000, 6144, 8192, -1):
         assert not F.fill_supported_size(n)
     assert F.fill_strerror(F.FILL_OK) == "ok"
     assert "converge" in F.fill_strerror(F.FILL_ENOCONV)

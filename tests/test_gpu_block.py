@@ -119,7 +119,7 @@ def test_minv_matches_oracle(F, name, prec, tol):
     assert np.all(got[~m] == 0.0)
 
 
-@pytest.mark.parametrize("nx,ny,seed", [(256, 256, 71), (768, 512, 72), (1024, 128, 73)])
+@pytest.mark.parametrize("nx,ny,seed", [(256, 256, 71), (768, 512, 72), (1024, 128, 73), (384, 1536, 74)])
 @pytest.mark.parametrize("prec,tol,rtol", [(0, 1e-9, 1e-12), (1, 1e-5, 1e-10)])
 def test_fill_matches_oracle(F, nx, ny, seed, prec, tol, rtol):
     P = W.damped_power_law(nx, ny, 4.0, min(nx, ny) / 8, 1e-7)

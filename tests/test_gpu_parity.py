@@ -105,7 +105,7 @@ def oracle_op(op, v, mask, P):
 
 
 @pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (128, 512), (768, 768), (1024, 64), (4096, 16),
-                                   (32, 4096), (2048, 2048)])
+                                   (32, 4096), (2048, 2048), (96, 192), (384, 1536), (3072, 96), (192, 3072)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_operator_apply_matches_oracle(F, nx, ny, prec):
     P, mask, _ = problem(nx, ny, n_holes=max(1, nx * ny // 20000))
@@ -166,7 +166,7 @@ def test_fill_grid64_at_its_tolerance(F):
     assert rel(x, ref.x_out, p.mask != 0) < 1e-7
 
 
-@pytest.mark.parametrize("nx,ny,seed", [(256, 256, 1), (512, 256, 9), (768, 768, 4)])
+@pytest.mark.parametrize("nx,ny,seed", [(256, 256, 1), (512, 256, 9), (768, 768, 4), (384, 192, 12), (96, 384, 13)])
 def test_fill_fp64_matches_oracle(F, nx, ny, seed):
     P, mask, d = problem(nx, ny, n_holes=nx * ny // 6000)
     x, st, _ = run_fill(F, P, mask, d, 0, seed, 1e-12, allow_noconv=True)
@@ -177,7 +177,7 @@ def test_fill_fp64_matches_oracle(F, nx, ny, seed):
     assert np.array_equal(x[~m].view(np.uint64), d[~m].view(np.uint64))
 
 
-@pytest.mark.parametrize("nx,ny,seed", [(256, 256, 1), (1024, 512, 3), (768, 768, 4)])
+@pytest.mark.parametrize("nx,ny,seed", [(256, 256, 1), (1024, 512, 3), (768, 768, 4), (1536, 384, 14)])
 def test_fill_mixed_matches_oracle(F, nx, ny, seed):
     P, mask, d = problem(nx, ny, n_holes=nx * ny // 6000)
     x, st, _ = run_fill(F, P, mask, d, 1, seed, 1e-8)
