@@ -699,7 +699,7 @@ def bench_grad16(args) -> int:
     def step():
         th.grad = None
         dd = d.clone().requires_grad_(True)
-        x = FillFn.apply(dd, th, bp, seeds, lnk, 1e-8, 1e-10)
+        x = FillFn.apply(dd, th, bp, seeds, lnk, 1e-8, 1e-10, True)  # ENOCONV reported below, not raised
         loss = torch.sum(w * x * x)
         loss.backward()
         return float(loss.detach())
@@ -712,13 +712,25 @@ def bench_grad16(args) -> int:
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    adj = bp.stats()  # the last adjoint solve, per problem
+    # set-up cost of a change of band powers with the block preconditioner
+    # (host build of its band factors and dense block inverses)
+    bp2 = F.BatchPlan(n, n, masks, P, F.FILL_PREC_FP32_OP)
+    bp2.set_precond(PRECONDS["block"])
+    t1 = time.perf_counter()
+    bp2.set_bands(lnk, theta + 0.01)
+    block_rebuild_s = time.perf_counter() - t1
+    bp2.close()
     out = {"metric": "forward + adjoint steps/s, 16 x 1024^2 maps, 50 band powers", "value": args.steps / dt,
            "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 operators + f64 dots/scalars/refinement", "data": "synthetic",
            "config": {"workload": "16 x 1024^2, 10% band + 100 holes r~U(2,10), 50 log-spaced band powers, "
                                   "loss sum(w x^2) w~U(0,1), forward rtol 1e-8, adjoint rtol 1e-10",
-                      "preconditioner": args.precond, "cg": args.cg}}
+                      "preconditioner": args.precond, "cg": args.cg},
+           "adjoint_status": [s["status"] for s in adj], "adjoint_rel_resid_max": max(s["rel_resid"] for s in adj),
+           "adjoint_iters_max": max(s["iters_inner"] for s in adj),
+           "block_preconditioner_rebuild_s_per_band_change": block_rebuild_s}
     print(json.dumps(out), flush=True)
     return 0
 

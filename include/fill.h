@@ -467,8 +467,9 @@ int fill_group_realize(fill_group group, const double* const* const* d_obs, cons
 int fill_group_last_graph(fill_group group);
 void fill_group_destroy(fill_group group);
 
-/* Statistics of the last solve on this plan (for a batch: iteration counts
- * and residual are the maxima over problems, n_masked the total). */
+/* Statistics of the last solve on this plan (fill_realize, fill_mean or the
+ * adjoint solve of fill_adjoint; for a batch: iteration counts and residual
+ * are the maxima over problems, n_masked the total). */
 int fill_get_stats(fill_plan plan, fill_stats* out);
 
 /* Per-problem statistics of the last solve: out has nprob entries. */

@@ -82,16 +82,18 @@ def fill_loss(d_obs, mask, theta, phi, seed, wts, rtol=1e-13) -> float:
     return float(np.sum(wts * x * x))
 
 
-def adjoint_gradient(d_obs, mask, theta, phi, seed, wts, rtol=1e-13):
-    """(L, dL/dy, dL/d ln P half-spectrum, dL/dtheta) by the adjoint recipe above."""
+def adjoint_gradient(d_obs, mask, theta, phi, seed, wts, rtol=1e-13, solver="split"):
+    """(L, dL/dy, dL/d ln P half-spectrum, dL/dtheta) by the adjoint recipe
+    above.  solver: the oracle CG of both solves (fill_oracle's "split" or
+    "cxx"; both stop on the same true residual)."""
     ny, nx = d_obs.shape
     N = nx * ny
     P = pk_from_bands(theta, phi)
-    r = F.fill_realize(d_obs, mask, P, seed, rtol)
+    r = F.fill_realize(d_obs, mask, P, seed, rtol, solver=solver)
     x, s, u = r.x_out, r.s, r.u
     L = float(np.sum(wts * x * x))
     g = 2.0 * wts * x
-    lam, _ = F.pcg_split(_Px(g, mask), mask, P, rtol)
+    lam, _ = F._solve(_Px(g, mask), mask, P, rtol, 20000, solver)
     cl = F.circulant_apply(lam, P, -1.0)
     grad_y = _Py(g - cl, mask)
     h = _Px(g, mask) + _Py(cl, mask)

@@ -343,13 +343,16 @@ class FillResult:
 
 def _solve(v: np.ndarray, mask: np.ndarray, P: np.ndarray, rtol: float, max_iter: int, solver: str):
     """A u = v to true relative residual rtol.  solver "split" is the paper's
-    split-preconditioned CG (Sec. 2.4); "block" is PCG with the block
+    split-preconditioned CG (Sec. 2.4); "cxx" is PCG with M^-1 = Px C Px (one
+    apply fewer per iteration); "block" is PCG with the block
     preconditioner of oracle.block_precond, which converges in far fewer
     iterations on wide cuts.  Both stop on the same true residual
     ||v - A u|| <= rtol ||v|| of this module's A, so the solution they return
     does not depend on the preconditioner (it only sets the CG path)."""
     if solver == "split":
         return pcg_split(v, mask, P, rtol, max_iter)
+    if solver == "cxx":
+        return pcg_cxx(v, mask, P, rtol, max_iter)
     if solver == "block":
         from .block_precond import pcg_block
         return pcg_block(v, mask, P, rtol, max_iter)

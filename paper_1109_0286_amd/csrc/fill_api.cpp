@@ -1665,6 +1665,7 @@ int adjoint_impl(fill_plan p, const double* const* d, const uint64_t* seeds, con
     if (!d[b] || !x[b] || !g[b] || !gy[b]) return fail(FILL_EINVAL, "NULL map for problem " + std::to_string(b));
   FILL_TRY(adjoint_workspace(p));
   HIP_TRY(hipStreamSynchronize(p->stream));
+  const auto t_adj = clk::now();
   for (int b = 0; b < np; ++b) p->hp.in_tab[b] = g[b];
   set_cfg(p, rtol);
   FILL_TRY(upload_params(p));
@@ -1678,6 +1679,7 @@ int adjoint_impl(fill_plan p, const double* const* d, const uint64_t* seeds, con
   // (no prediction key: the adjoint solve always runs step by step)
   p->last_whole_graph = 0;
   const int st = finish_solve(p, -2);
+  finish_stats(p, st, std::chrono::duration<double, std::milli>(clk::now() - t_adj).count());
   if (st != FILL_OK && st != FILL_ENOCONV) return st;
   if (p->nbands > 0) HIP_TRY(hipMemsetAsync(p->adj_gth, 0, p->nbands * sizeof(double), p->stream));
   for (int b = 0; b < np; ++b) {

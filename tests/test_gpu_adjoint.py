@@ -78,7 +78,7 @@ def test_adjoint_matches_gpu_central_differences(F):
 
     h = 1e-4
     scale = np.abs(gth).max()
-    for b in (0, 12, 25, 49):
+    for b in range(len(theta)):  # every band power
         e = np.zeros_like(theta)
         e[b] = h
         fd = (loss(theta + e, d) - loss(theta - e, d)) / (2 * h)
@@ -172,3 +172,45 @@ def test_autograd_backward_raises_on_nonconvergence(F):
     with pytest.raises(F.FillError) as e:
         torch.sum(x * x).backward()
     assert e.value.code == F.FILL_ENOCONV
+
+
+@pytest.fixture(scope="module")
+def grad1024():
+    # the differentiation workload's grid: 1024^2, 10% band + 100 holes
+    # r~U(2,10), 50 band powers; the oracle's adjoint with Px C Px PCG to 1e-12
+    # for both of its solves
+    n = 1024
+    lnk = AD.band_nodes(n, 50)
+    phi = AD.band_weights(n, n, lnk)
+    kb = np.exp(lnk)
+    theta = np.log(1.0 / (kb ** 2 + 4) * np.exp(-(kb / (n / 8)) ** 2) + 1e-7)
+    mask = W.band_holes_mask(n, n, W.band_rows(n, 0.1), 100, 2.0, 10.0, 500)
+    d = W.observed_map(AD.pk_from_bands(theta, phi), n, n, 600, mask)
+    wts = np.random.default_rng(7).uniform(0, 1, (n, n))
+    print("oracle adjoint at 1024^2", flush=True)
+    ref = AD.adjoint_gradient(d, mask, theta, phi, 1, wts, 1e-12, solver="cxx")
+    return n, lnk, theta, mask, d, wts, ref
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,rtol,tol", [(0, 1e-12, 1e-8), (1, 1e-10, 1e-6)])
+def test_adjoint_at_1024_matches_oracle(F, grad1024, prec, rtol, tol):
+    n, lnk, theta, mask, d, wts, (L0, gy0, gP0, gth0) = grad1024
+    plan = F.Plan(n, n, mask, np.ones((n, n // 2 + 1)), prec)
+    plan.set_precond(F.FILL_PRECOND_CXX)
+    plan.set_bands(lnk, theta)
+    dd = torch.from_numpy(d).cuda()
+    x = plan.realize(dd, 1, rtol, allow_noconv=True)
+    st = plan.stats()
+    L = float(torch.sum(torch.from_numpy(wts).cuda() * x * x))
+    g = (2.0 * torch.from_numpy(wts).cuda() * x).contiguous()
+    gd, gth, glp = plan.adjoint(dd, 1, x, g, rtol, want_logP=True, allow_noconv=True)
+    sa = plan.stats()
+    print(f"prec {prec}: forward {st['iters_inner']} / {st['iters_outer']} rel resid {st['rel_resid']:.2e}; "
+          f"adjoint status {sa['status']} rel resid {sa['rel_resid']:.2e}")
+    print(f"  L rel {abs(L - L0) / abs(L0):.2e}, theta {rel(gth, gth0):.2e}, "
+          f"y {rel(gd.cpu().numpy(), gy0):.2e}, lnP {rel(glp, gP0):.2e}")
+    assert abs(L - L0) < tol * abs(L0)
+    assert rel(gth, gth0) < tol
+    assert rel(gd.cpu().numpy(), gy0) < tol
+    assert rel(glp, gP0) < tol
