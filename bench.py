@@ -131,6 +131,23 @@ def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int, info=
     raise ValueError(kernel)
 
 
+def kernel_rooflines(breakdown: dict, nx: int, ny: int, n_m: int, info) -> dict:
+    """Algorithmic GB/s and fraction of the HBM peak of each FP32 kernel of
+    the mixed solve's CG iteration (its in-solve average per launch), with
+    the counter-measured HBM bytes per launch where the committed counter
+    runs match the kernel sources."""
+    out = {}
+    for k, v in breakdown.items():
+        try:
+            nbytes = kernel_bytes(k, 4, nx, ny, n_m, info)
+        except (ValueError, TypeError, KeyError):
+            continue
+        gbs = nbytes / (v["ms_per_launch"] * 1e-3) / 1e9
+        out[k] = {"bytes_per_launch": nbytes, "us_per_launch": v["ms_per_launch"] * 1e3, "achieved_gbs": gbs,
+                  "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(k, nx)}
+    return out
+
+
 def work_launches(kernel: str, st: dict, precond: str) -> int:
     """Launches of `kernel` in one solve that do work (stats st of that
     solve): chunk graphs run whole chunks, and launches after convergence
@@ -627,6 +644,7 @@ def bench_grid4096(args) -> int:
                       "cg": args.cg},
            "paths": res,
            "kernels_per_mixed_solve": breakdown,
+           "kernel_roofline": kernel_rooflines(breakdown, prob.nx, prob.ny, prob.n_masked, info),
            "block_preconditioner": info,
            "roofline": {"bound": "hbm", "kernel": f"{KERNEL_NAMES[dom]}<float> (4096^2)", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -743,6 +761,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave the mixed64 and grid4096 sub-results out of the default line")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="leave the comparison of preconditioners out of the default line (profiling runs)")
     ap.add_argument("--kernel-ms", action="store_true",
                     help="also time each kernel in isolation (back-to-back launches)")
     ap.add_argument("--reps", type=int, default=50, help="launches per isolated kernel timing")
@@ -867,7 +887,9 @@ def bench_grid2048(args) -> int:
     }
     out["masked_rel_l2_error_vs_fp64_1e-11"] = masked_errors(F, prob, d, {"mixed": plan32, "fp64": plan64}, rtol)
     out["lanczos_fp64"] = lanczos_report(plan64, d, seed, rtol)
-    out["preconditioners"] = compare_preconds(F, prob, d, args)
+    out["kernel_roofline"] = kernel_rooflines(breakdown, nx, ny, n_m, info)
+    if not args.no_compare:
+        out["preconditioners"] = compare_preconds(F, prob, d, args)
     if args.batch > 0:
         out["batched_2048"] = bench_batch_2048(F, prob, args)
     if not args.no_extra:
@@ -880,7 +902,9 @@ def bench_grid2048(args) -> int:
     if not args.no_cpu_baseline:
         # the oracle solves by its split-form PCG (Sec. 2.4): its iteration
         # count is that of the same FP64 recurrence on the GPU
-        out["cpu_baseline"] = cpu_baseline(prob, out["preconditioners"]["fp64_split_standard"]["iters_inner"])
+        # (312: the split-form FP64 iterations at this workload, when the comparison did not run)
+        it_split = out["preconditioners"]["fp64_split_standard"]["iters_inner"] if "preconditioners" in out else 312
+        out["cpu_baseline"] = cpu_baseline(prob, it_split)
     print(json.dumps(out), flush=True)
     return 0
 
