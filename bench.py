@@ -103,9 +103,10 @@ def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int, info=
     r2c:     p = z + beta p: read z, p, write p, write H complex        -> 2 s H + 3 s n_m
     c2r:     read H complex, write q, read p                            -> 2 s H + 2 s n_m
     proj:    read + write H complex, read the mask                      -> 4 s H + nx ny
-    band:    read the factor stream (32 lanes per row and frequency; the
-             backward sweep reads it again, across the lanes) and the
-             runs' spectra, write them                                 -> 32 (nx/2+1) R s + 4 (nx/2) R s
+    band:    read the factor streams as stored (32 lanes per row and
+             frequency, repeating chunks of the Toeplitz limit once: V
+             values; the backward sweep reads them again, across the
+             lanes) and the runs' spectra, write them                  -> V s + 4 (nx/2) R s
     blockmv: read the inverses, gather r (value + index), write outputs -> Eb s + Nb (2 s + 4)
     combine: read z, r, the band flag and the CSR start, write z, read
              the covering entries (index + value)                     -> n_m (3 s + 5) + Nb (4 + s)
@@ -123,7 +124,8 @@ def kernel_bytes(kernel: str, prec_bytes: int, nx: int, ny: int, n_m: int, info=
     R = info["band_rows"] if info else 0
     Nb = info["block_pixels"] if info else 0
     if kernel == "band":
-        return 32.0 * (nx // 2 + 1) * R * s + 4.0 * (nx // 2) * R * s
+        V = info.get("band_stream_values") or 32.0 * (nx // 2 + 1) * R
+        return V * s + 4.0 * (nx // 2) * R * s
     if kernel == "blockmv":
         return float(info["block_entries"]) * s + Nb * (2.0 * s + 4.0)
     if kernel == "combine":

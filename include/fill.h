@@ -77,9 +77,11 @@ typedef struct {
   int blocks;             /* dense blocks, all problems */
   int64_t band_rows;      /* sum over runs of the rows padded to a multiple of 32 */
   int64_t block_pixels;   /* sum over blocks of their pixels n */
-  int64_t block_entries;  /* sum over blocks of the stored inverse entries n * 4 ceil(n / 4) */
-  int64_t bytes;          /* device memory it holds */
+  int64_t block_entries;  /* sum over blocks of their inverse entries n * 4 ceil(n / 4) */
+  int64_t bytes;          /* device memory it holds (problems with equal factors share them) */
   int elem_bytes;         /* 4 (FP32-operator plan) or 8 (FP64 plan) */
+  int64_t band_stream_values; /* sum over runs of the values of their banded factors as stored
+                                 (repeating chunks of the factor rows stored once) */
 } fill_block_info;
 
 /* Recurrences of the inner CG (fill_plan_set_cg). */

@@ -63,7 +63,7 @@ bool spd_inverse(std::vector<double>& A, int n) {
 }  // namespace
 
 int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, double pivot_min,
-                 Layout* L, std::string* err) {
+                 bool f32, Layout* L, std::string* err) {
   L->nx = nx;
   L->ny = ny;
   const size_t npix = (size_t)nx * ny;
@@ -103,21 +103,22 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
   const int ncol = nx / 2, nk = nx / 2 + 1;
   // 32 zeros before the first stream: the backward substitution's loads for
   // the lanes past the first row reach up to 31 values before a stream
-  if (!L->runs.empty()) L->fs_total = 32;
+  L->fwd.clear();
+  if (!L->runs.empty()) L->fwd.assign(32, 0.0);
   for (Run& r : L->runs) {
     r.bt_off = L->bt_total;
     L->bt_total += (size_t)ncol * r.hp;
-    r.fs_off = L->fs_total;
-    L->fs_total += (size_t)nk * 32 * r.hp;
     for (int j = 0; j <= r.hp; ++j) L->brow_off.push_back(r.cb0 + std::min(j, r.h) * nx);
     L->max_run_pixels = std::max(L->max_run_pixels, r.h * nx);
   }
-  L->fwd.assign(L->fs_total, 0.0);
   if (!L->runs.empty()) {
     const double* t = tsym;
     std::atomic<int> bad{-1};
-    for (const Run& r : L->runs) {
-      const int h = r.h, hp = r.hp;
+    for (Run& r : L->runs) {
+      const int h = r.h, hp = r.hp, nch = hp / 32;
+      r.k0 = (int)L->kx_off.size();
+      std::vector<std::vector<double>> packed(nk);  // per kx: the stored streams
+      std::vector<int> dup(2 * (size_t)nk, 0);
       parallel_for(nk, [&](int kx) {
         // banded Cholesky of nx T_kx: Lb[i*BW + d] = L(i, i-d); false if a
         // pivot is not above pivot_min (its square root is not taken then)
@@ -157,19 +158,60 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
         // its coupling Lu(i+d, i).  Padded rows are the identity.  (The
         // backward substitution reads the same streams across the lanes:
         // entries i-31 .. i-1 of lane i mod 32 hold row i of Lu.)
+        std::vector<double> full((size_t)32 * hp);
         for (int k = 0; k < 32; ++k) {
-          double* f = L->fwd.data() + r.fs_off + ((size_t)kx * 32 + k) * hp;
+          double* f = full.data() + (size_t)k * hp;
           for (int i = 0; i < hp; ++i) {
             const int d = ((k - i) % 32 + 32) % 32;
             if (d == 0) f[i] = i < h ? 1.0 / (l(i, i) * l(i, i)) : 1.0;
             else f[i] = (i + d < h && d < BW) ? l(i + d, i) / l(i, i) : 0.0;
           }
         }
+        // Far from the run's ends the rows of the factor reach their
+        // Toeplitz limit, and whole chunks of 32 positions repeat in every
+        // lane's stream: the longest run of equal consecutive chunks (equal
+        // in the precision the factor is used in) is stored once.
+        auto same = [&](double u, double v) { return f32 ? (float)u == (float)v : u == v; };
+        auto chunk_eq = [&](int c1, int c2) {
+          for (int k = 0; k < 32; ++k) {
+            const double* f = full.data() + (size_t)k * hp;
+            for (int j = 0; j < 32; ++j)
+              if (!same(f[32 * c1 + j], f[32 * c2 + j])) return false;
+          }
+          return true;
+        };
+        int s0 = 0, d = 0;
+        for (int c = 1, a = 0; c < nch; ++c) {
+          if (!chunk_eq(c, c - 1)) a = c;
+          else if (c - a > d) {
+            s0 = a;
+            d = c - a;
+          }
+        }
+        const int len = hp - 32 * d;
+        std::vector<double>& out = packed[kx];
+        out.resize((size_t)32 * len);
+        for (int k = 0; k < 32; ++k)
+          for (int c = 0; c < nch; ++c) {
+            if (c > s0 && c <= s0 + d) continue;
+            const int sc = stored_chunk(c, s0, d);
+            std::copy(full.data() + (size_t)k * hp + 32 * c, full.data() + (size_t)k * hp + 32 * c + 32,
+                      out.data() + (size_t)k * len + 32 * sc);
+          }
+        dup[2 * (size_t)kx] = s0;
+        dup[2 * (size_t)kx + 1] = d;
       });
       if (bad >= 0) {
         *err = "block preconditioner: the band factor of kx = " + std::to_string(bad.load()) +
                " is not positive definite";
         return -1;
+      }
+      for (int kx = 0; kx < nk; ++kx) {
+        L->kx_off.push_back(L->fwd.size());
+        L->kx_dup.push_back(dup[2 * (size_t)kx]);
+        L->kx_dup.push_back(dup[2 * (size_t)kx + 1]);
+        L->fwd.insert(L->fwd.end(), packed[kx].begin(), packed[kx].end());
+        L->stream_values += packed[kx].size();
       }
     }
   }

@@ -54,7 +54,7 @@ struct Run {
   int y0 = 0, h = 0, hp = 0;  // first row, rows, rows padded to a multiple of 32
   int cb0 = 0;                // compact index of the run's first pixel
   size_t bt_off = 0;          // complex offset of the run's spectrum [nx/2][hp]
-  size_t fs_off = 0;          // offset of the run's streams [(nx/2+1)*32][hp]
+  int k0 = 0;                 // index of the run's (kx = 0) entry in kx_off / kx_dup
 };
 
 struct Layout {
@@ -62,8 +62,14 @@ struct Layout {
   std::vector<Run> runs;
   std::vector<int> brow_off;   // per run: hp+1 compact offsets of the virtual rows
   size_t bt_total = 0;         // complex values of all runs' spectra
-  size_t fs_total = 0;         // values of all runs' factor streams
-  std::vector<double> fwd;     // factor streams (see block.cpp)
+  // Factor streams (see block.cpp), per (run, kx): 32 lane streams of
+  // hp - 32 d values at fwd[kx_off], where chunks (32 positions) s0 .. s0 + d
+  // of the full-length streams are equal and stored once, as chunk s0
+  // (kx_dup = {s0, d}; d = 0: nothing shared).  fwd starts with 32 zeros.
+  std::vector<double> fwd;
+  std::vector<size_t> kx_off;
+  std::vector<int> kx_dup;     // 2 per (run, kx)
+  size_t stream_values = 0;    // sum over runs of their streams' values
   // blocks
   std::vector<int> boff;       // nblocks+1 offsets into bidx
   std::vector<int> bidx;       // compact indices of each block's pixels
@@ -83,10 +89,16 @@ struct Layout {
 
 // mask: ny*nx (1 = masked); kmap: ny*nx FP64 kernel of C^-1 (C^-1 v = k (*) v);
 // tsym: ny*(nx/2+1), tsym[d*(nx/2+1) + kx] = t_kx(d); pivot_min: the
-// threshold of the unshifted band truncation (PIVOT_MIN or PIVOT_MIN_F32).
+// threshold of the unshifted band truncation (PIVOT_MIN or PIVOT_MIN_F32);
+// f32: the factor is used in FP32 (chunks of the streams are shared when
+// their values rounded to FP32 are equal; FP64: when they are equal).
 // Returns 0, or -1 with *err set (a band factor or a block is not positive
 // definite, or a block is too large).
 int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, double pivot_min,
-                 Layout* out, std::string* err);
+                 bool f32, Layout* out, std::string* err);
+
+// The stored chunk of chunk c of a (run, kx) whose chunks s0 .. s0 + d share
+// chunk s0's storage.
+inline int stored_chunk(int c, int s0, int d) { return c < s0 ? c : (c <= s0 + d ? s0 : c - d); }
 
 }  // namespace fillb

@@ -106,7 +106,9 @@ struct BlockDev {
   void* fwd = nullptr;
   int* run_hp = nullptr;
   size_t* run_bt = nullptr;
-  size_t* run_fs = nullptr;
+  int* run_k0 = nullptr;
+  size_t* kx_off = nullptr;
+  int* kx_dup = nullptr;
   int* boff = nullptr;
   int* bidx = nullptr;
   size_t* moff = nullptr;
@@ -538,8 +540,8 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
   }
   std::string err;
   const double pivot_min = p->prec == FILL_PREC_FP32_OP ? fillb::PIVOT_MIN_F32 : fillb::PIVOT_MIN;
-  if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, kmap.data(), tsym.data(), pivot_min, L,
-                          &err) != 0)
+  if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, kmap.data(), tsym.data(), pivot_min,
+                          p->prec == FILL_PREC_FP32_OP, L, &err) != 0)
     return fail(FILL_ENOTSPD, "problem " + std::to_string(b) + ": " + err);
   return FILL_OK;
 }
@@ -556,26 +558,57 @@ int block_setup(fill_plan p) {
   fillb::Layout L;  // merged
   std::vector<int> run_prob, block_prob;
   L.boff.push_back(0);
+  // Problems with equal band factors or block inverses (identical masks and
+  // spectra, as in a Monte-Carlo batch) share one stored copy: the first
+  // problem's range of each distinct set, with its per-entry layout.
+  struct Seen {
+    size_t off, n;
+    std::vector<size_t> lay;
+  };
+  std::vector<Seen> band_seen, binv_seen;
+  size_t binv_logical = 0;
   for (int b = 0; b < np; ++b) {
     fillb::Layout Lb;
     FILL_TRY(block_layout_for(p, b, &Lb));
     const int co = p->coff[b];
+    size_t fbase = L.fwd.size();
+    bool fshared = false;
+    std::vector<size_t> flay(Lb.kx_dup.begin(), Lb.kx_dup.end());
+    for (const Seen& q : band_seen)
+      if (q.n == Lb.fwd.size() && q.lay == flay && std::equal(Lb.fwd.begin(), Lb.fwd.end(), L.fwd.begin() + q.off)) {
+        fbase = q.off;
+        fshared = true;
+        break;
+      }
+    if (!fshared && !Lb.fwd.empty()) {
+      band_seen.push_back({L.fwd.size(), Lb.fwd.size(), std::move(flay)});
+      L.fwd.insert(L.fwd.end(), Lb.fwd.begin(), Lb.fwd.end());
+    }
+    const int kbase = (int)L.kx_off.size();
+    for (size_t o : Lb.kx_off) L.kx_off.push_back(o + fbase);
+    L.kx_dup.insert(L.kx_dup.end(), Lb.kx_dup.begin(), Lb.kx_dup.end());
+    L.stream_values += Lb.stream_values;
     size_t ro = 0;
     for (fillb::Run r : Lb.runs) {
       r.cb0 += co;
       r.bt_off += L.bt_total;
-      r.fs_off += L.fs_total;
+      r.k0 += kbase;
       L.runs.push_back(r);
       run_prob.push_back(b);
       for (int j = 0; j <= r.hp; ++j) L.brow_off.push_back(Lb.brow_off[ro + j] + co);
       ro += (size_t)r.hp + 1;
     }
     L.bt_total += Lb.bt_total;
-    L.fs_total += Lb.fs_total;
-    L.fwd.insert(L.fwd.end(), Lb.fwd.begin(), Lb.fwd.end());
     L.max_run_pixels = std::max(L.max_run_pixels, Lb.max_run_pixels);
     const int nbase = (int)L.bidx.size();
-    const size_t mbase = L.binv.size();
+    size_t mbase = L.binv.size();
+    bool mshared = false;
+    for (const Seen& q : binv_seen)
+      if (q.n == Lb.binv.size() && q.lay == Lb.moff && std::equal(Lb.binv.begin(), Lb.binv.end(), L.binv.begin() + q.off)) {
+        mbase = q.off;
+        mshared = true;
+        break;
+      }
     const int bbase = (int)L.boff.size() - 1;
     const size_t sbase = L.seg_total;
     for (size_t q = 1; q < Lb.boff.size(); ++q) {
@@ -592,7 +625,11 @@ int block_setup(fill_plan p) {
     L.seg_total += Lb.seg_total;
     if (L.seg_total > (size_t)INT32_MAX) return fail(FILL_EINVAL, "block preconditioner: too many block outputs");
     for (int c : Lb.bidx) L.bidx.push_back(c + co);
-    L.binv.insert(L.binv.end(), Lb.binv.begin(), Lb.binv.end());
+    binv_logical += Lb.binv.size();
+    if (!mshared && !Lb.binv.empty()) {
+      binv_seen.push_back({L.binv.size(), Lb.binv.size(), Lb.moff});
+      L.binv.insert(L.binv.end(), Lb.binv.begin(), Lb.binv.end());
+    }
     const int ebase = L.cst.empty() ? 0 : L.cst.back();
     if (L.cst.empty()) L.cst.push_back(0);
     for (int c = 1; c <= Lb.n_m; ++c) L.cst.push_back(Lb.cst[c] + ebase);
@@ -607,15 +644,15 @@ int block_setup(fill_plan p) {
   B.runs = L.runs;
   B.run_prob = run_prob;
   size_t ro = 0;
-  std::vector<int> hp, bpos(std::max(L.max_run_pixels, 1));
-  std::vector<size_t> bt, fs;
+  std::vector<int> hp, k0, bpos(std::max(L.max_run_pixels, 1));
+  std::vector<size_t> bt;
   for (const fillb::Run& r : L.runs) {
     B.run_brow.push_back(ro);
     ro += (size_t)r.hp + 1;
     B.max_hp = std::max(B.max_hp, r.hp);
     hp.push_back(r.hp);
     bt.push_back(r.bt_off);
-    fs.push_back(r.fs_off);
+    k0.push_back(r.k0);
   }
   for (size_t i = 0; i < bpos.size(); ++i) bpos[i] = (int)i;
   B.nblocks = (int)L.boff.size() - 1;
@@ -623,7 +660,9 @@ int block_setup(fill_plan p) {
   FILL_TRY(bupload(p, &B.bpos, bpos));
   FILL_TRY(bupload(p, &B.run_hp, hp));
   FILL_TRY(bupload(p, &B.run_bt, bt));
-  FILL_TRY(bupload(p, &B.run_fs, fs));
+  FILL_TRY(bupload(p, &B.run_k0, k0));
+  FILL_TRY(bupload(p, &B.kx_off, L.kx_off));
+  FILL_TRY(bupload(p, &B.kx_dup, L.kx_dup));
   FILL_TRY(bupload(p, &B.run_prob_d, run_prob));
   FILL_TRY(bupload(p, &B.block_prob, block_prob));
   FILL_TRY(bupload(p, &B.boff, L.boff));
@@ -653,11 +692,13 @@ int block_setup(fill_plan p) {
   B.info.blocks = B.nblocks;
   for (const fillb::Run& r : L.runs) B.info.band_rows += r.hp;
   B.info.block_pixels = (int64_t)L.bidx.size();
-  B.info.block_entries = (int64_t)L.binv.size();
+  B.info.block_entries = (int64_t)binv_logical;
+  B.info.band_stream_values = (int64_t)L.stream_values;
   B.info.elem_bytes = (int)ts;
   B.info.bytes = (int64_t)((L.fwd.size() + L.binv.size() + L.bidx.size() + 2 * L.bt_total) * ts +
                            (L.brow_off.size() + bpos.size() + L.boff.size() + L.bidx.size() + L.cst.size() +
-                            L.cix.size()) * sizeof(int) + L.inb.size());
+                            L.cix.size() + L.kx_dup.size()) * sizeof(int) +
+                           L.kx_off.size() * sizeof(size_t) + L.inb.size());
   B.built = true;
   return FILL_OK;
 }
@@ -722,7 +763,10 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
     ba.fwd = static_cast<const T*>(B.fwd);
     ba.run_hp = B.run_hp;
     ba.run_bt = B.run_bt;
-    ba.run_fs = B.run_fs;
+    ba.run_k0 = B.run_k0;
+    ba.kx_off = B.kx_off;
+    ba.kx_dup = B.kx_dup;
+    ba.nruns = nruns;
     ba.ncol = p->nx / 2;
     ba.run_prob = B.run_prob_d;
     ba.sc = sc;

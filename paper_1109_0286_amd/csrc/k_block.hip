@@ -69,6 +69,12 @@ __device__ __forceinline__ void load32(double (&f)[32], const double* p) {
   }
 }
 
+// The stored chunk of chunk c (32 positions of every lane's stream) of a
+// (run, kx) whose chunks s0 .. s0 + d share chunk s0's storage.
+__device__ __forceinline__ int stored_chunk(int c, int s0, int d) {
+  return c < s0 ? c : (c <= s0 + d ? s0 : c - d);
+}
+
 // One wave per (column kx of the run's spectrum, run).  Column 0 carries the
 // DC values in its real parts and the Nyquist values in its imaginary parts,
 // which use the factors of kx = 0 and kx = nx/2.  The factor is stored
@@ -83,51 +89,69 @@ __device__ __forceinline__ void load32(double (&f)[32], const double* p) {
 // branch-free: each lane keeps its finished element of the chunk in a
 // register and the chunk's results are stored together; the factor entries
 // of the next chunk are loaded during the current one (two register sets
-// taking turns).
+// taking turns).  Where the rows have reached their Toeplitz limit the
+// chunks repeat and are stored once: a register set that already holds the
+// repeated chunk is not loaded again.
+// Grid: ncol * nruns workgroups in one dimension.  Workgroup w runs on XCD
+// w mod 8, so w = 8 (nruns g + run) + (col mod 8) with col = 8 g + (w mod 8)
+// sends the runs' waves of one column (one factor, when identical problems
+// share it) to one XCD, one after another.
 template <typename T>
 __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   extern __shared__ unsigned char band_smem[];
-  const int col = blockIdx.x, run = blockIdx.y;
-  if (a.sc != nullptr && a.sc[a.run_prob[run]].done) return;
+  const int w = blockIdx.x, q = w >> 3;
+  const int g = q / a.nruns, run = q - g * a.nruns;
+  const int col = 8 * g + (w & 7);
+  // the problem's state is read beside the run's spectrum column
+  const int prob = a.sc != nullptr ? a.run_prob[run] : 0;
   const int hp = a.run_hp[run];
   cplx<T>* X = a.Bt + a.run_bt[run] + (size_t)col * hp;
   T* sre = reinterpret_cast<T*>(band_smem);
   T* sim = sre + hp;
   const int lane = threadIdx.x, k = lane & 31, half = lane >> 5;
+  const int done = load_done(a.sc != nullptr ? a.sc + prob : nullptr);
+  const int kx = (col == 0 && half) ? a.ncol : col;
+  const int ki = a.run_k0[run] + kx;
+  const T* F0 = a.fwd + a.kx_off[ki];  // this frequency's 32 lane streams
+  const int s0 = a.kx_dup[2 * ki], dd = a.kx_dup[2 * ki + 1];
   for (int i = lane; i < hp; i += 64) {
     const cplx<T> c = X[i];
     sre[i] = c.x;
     sim[i] = c.y;
   }
+  issue_fence();
+  if (__builtin_amdgcn_readfirstlane(done)) return;
   __syncthreads();
   T* s = half ? sim : sre;
-  const int kx = (col == 0 && half) ? a.ncol : col;
-  const T* F0 = a.fwd + a.run_fs[run] + (size_t)kx * 32 * hp;  // this frequency's 32 lane streams
-  const T* F = F0 + (size_t)k * hp;
-  T w;
+  const int L = hp - 32 * dd;  // stream length
+  const T* F = F0 + (size_t)k * L;
+  T w_;
   T fa[32], fb[32];
 
   // forward: Lu z = rhat, stored as z D^-2 (lane k's stream holds D^-2 of
   // element i at the steps i where k is the head).  The element that enters
   // lane k's slot during a chunk (c0 + 32 + k) is read from LDS at the
-  // chunk's start.
+  // chunk's start.  The set loaded for chunk c held chunk c - 2.
   auto fwd_chunk = [&](const T (&f)[32], T (&fn)[32], int c0) {
-    if (c0 + 32 < hp) load32(fn, F + c0 + 32);
+    if (c0 + 32 < hp) {
+      const int c = (c0 >> 5) + 1;
+      if (!(c - 2 >= s0 && c <= s0 + dd)) load32(fn, F + 32 * stored_chunk(c, s0, dd));
+    }
     const T nxt = (c0 + 32 < hp) ? s[c0 + 32 + k] : T(0);
-    T zo = w, dg = T(1);  // this lane's finished element of the chunk (c0 + k) and its D^-2
+    T zo = w_, dg = T(1);  // this lane's finished element of the chunk (c0 + k) and its D^-2
     static_for<0, 32>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
-      const T z = half_lane<u>(w, half);
+      const T z = half_lane<u>(w_, half);
       const bool head = k == u;
-      const T up = w - f[u] * z;
-      zo = head ? w : zo;
+      const T up = w_ - f[u] * z;
+      zo = head ? w_ : zo;
       dg = head ? f[u] : dg;
-      w = head ? nxt : up;
+      w_ = head ? nxt : up;
     });
     s[c0 + k] = zo * dg;
   };
-  w = s[k];
-  load32(fa, F);
+  w_ = s[k];
+  load32(fa, F + 32 * stored_chunk(0, s0, dd));
   for (int c0 = 0; c0 < hp; c0 += 64) {
     fwd_chunk(fa, fb, c0);
     if (c0 + 32 < hp) fwd_chunk(fb, fa, c0 + 32);
@@ -135,35 +159,51 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   __syncthreads();
 
   // backward: Lu^T x = D^-1 y (the element entering lane k's slot during a
-  // chunk is hp - 64 - c0 + k).  Step i = hp - 1 - (c0 + u) needs row i of
-  // Lu: Lu(i, i - d) for the lane holding element i - d, d = (i - k) mod 32,
-  // which is entry i - d of the forward stream of lane hl = i mod 32 = 31 - u
-  // (hp is a multiple of 32).  Its offset from F0 + hp - 63 - c0 is po[u]
-  // below, the same for every chunk; lanes past the first row read the
-  // zero guard or the previous stream and hold nothing that is used.
-  unsigned po[32];
+  // chunk is hp - 64 - c0 + k).  Step i = hp - 1 - (c0 + u) of the chunk
+  // whose rows are forward chunk C = (hp - 32 - c0) / 32 needs row i of Lu:
+  // Lu(i, i - d) for the lane holding element i - d, d = (i - k) mod 32,
+  // which is entry i - d of the forward stream of lane hl = i mod 32 = 31 - u:
+  // offset k of chunk C if k + u <= 31, else of chunk C - 1.  With the two
+  // chunks stored one after the other that is po[u] below from the start of
+  // C's storage; when both share one stored chunk, po[u] + 32 (k + u > 31).
+  // Lanes past the first row read the zero guard or the previous stream and
+  // hold nothing that is used.
+  int po[32];
 #pragma unroll
-  for (int u = 0; u < 32; ++u) po[u] = (unsigned)(31 * hp + 62 - u * (hp + 1) - ((31 - u - k) & 31));
-  auto back_load = [&](T (&g)[32], int c0) {
-    const T* Fb = F0 + (hp - 63 - c0);
+  for (int u = 0; u < 32; ++u) po[u] = (31 - u) * L + k - ((k + u > 31) ? 32 : 0);
+  auto back_load = [&](T (&gr)[32], int c0) {
+    const int C = (hp - 32 - c0) >> 5;
+    const int mC = stored_chunk(C, s0, dd);
+    const T* Fb = F0 + 32 * mC;
+    if (stored_chunk(C - 1, s0, dd) == mC - 1) {
 #pragma unroll
-    for (int u = 0; u < 32; ++u) g[u] = Fb[po[u]];
+      for (int u = 0; u < 32; ++u) gr[u] = Fb[po[u]];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 32; ++u) gr[u] = Fb[po[u] + ((k + u) & 32)];
+    }
   };
+  // the chunks C and C - 1 both shared (the set loaded for the step of
+  // chunk C held the one of chunk C + 2)
+  auto shared2 = [&](int C) { return C > s0 && C <= s0 + dd; };
   auto bwd_chunk = [&](const T (&f)[32], T (&fn)[32], int c0) {
-    if (c0 + 32 < hp) back_load(fn, c0 + 32);
+    if (c0 + 32 < hp) {
+      const int C = ((hp - 32 - c0) >> 5) - 1;
+      if (!(shared2(C) && shared2(C + 2))) back_load(fn, c0 + 32);
+    }
     const T nxt = (c0 + 64 <= hp) ? s[hp - 64 - c0 + k] : T(0);
-    T xo = w;  // this lane's finished element of the chunk (hp - 32 - c0 + k)
+    T xo = w_;  // this lane's finished element of the chunk (hp - 32 - c0 + k)
     static_for<0, 32>([&](auto uc) {
       constexpr int u = decltype(uc)::value, hl = 31 - u;  // head lane of step i = hp - 1 - (c0 + u)
-      const T x = half_lane<hl>(w, half);
+      const T x = half_lane<hl>(w_, half);
       const bool head = k == hl;
-      const T up = w - f[u] * x;
-      xo = head ? w : xo;
-      w = head ? nxt : up;
+      const T up = w_ - f[u] * x;
+      xo = head ? w_ : xo;
+      w_ = head ? nxt : up;
     });
     s[hp - 32 - c0 + k] = xo;
   };
-  w = s[hp - 32 + k];
+  w_ = s[hp - 32 + k];
   back_load(fa, 0);
   for (int c0 = 0; c0 < hp; c0 += 64) {
     bwd_chunk(fa, fb, c0);
@@ -210,10 +250,14 @@ __global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
   const int t = threadIdx.x;
   const int* item = a.items + 4 * (size_t)blockIdx.x;
   const int b = item[0], r0 = item[1], c0 = item[2], so = item[3];
-  if (a.sc != nullptr && a.sc[a.block_prob[b]].done) return;
+  // the problem's state is read beside the block's extent, then the gather
+  const int prob = a.sc != nullptr ? a.block_prob[b] : 0;
   const int o = a.boff[b], n = a.boff[b + 1] - o;
   const int c1 = min(n, c0 + kBlkCols);
+  const int done = load_done(a.sc != nullptr ? a.sc + prob : nullptr);
   if (t < c1 - c0) rv[t] = a.r[a.bidx[o + c0 + t]];
+  issue_fence();
+  if (__builtin_amdgcn_readfirstlane(done)) return;
   __syncthreads();
   const int ld = (n + 3) / 4 * 4;
   const int w = t >> 6, lane = t & 63;
@@ -303,11 +347,13 @@ __device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
 template <typename T>
 __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
   const int blk = blockIdx.x, pb = blockIdx.y;
-  if (a.sc != nullptr && a.sc[pb].done) return;
+  const int done = load_done(a.sc != nullptr ? a.sc + pb : nullptr);
   // equal slices of the problem's compact range (as many as row blocks)
   const long long nm = a.row_off[(size_t)pb * (a.ny + 1) + a.ny];
   const int nblk = gridDim.x;
   const int base = a.comp_off ? a.comp_off[pb] : 0;
+  issue_fence();  // the state and the range in one round trip
+  if (__builtin_amdgcn_readfirstlane(done)) return;
   const int c0 = base + (int)(nm * blk / nblk), c1 = base + (int)(nm * (blk + 1) / nblk);
   const int t = threadIdx.x;
   double acc0 = 0.0, acc1 = 0.0;
@@ -371,8 +417,10 @@ hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStr
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (e0) hipExtLaunchKernelGGL(band_solve_kernel<T>, dim3(a.ncol, nruns), dim3(64), lds, s, e0, e1, 0, a);
-  else hipLaunchKernelGGL(band_solve_kernel<T>, dim3(a.ncol, nruns), dim3(64), lds, s, a);
+  if (a.ncol % 8 != 0 || a.nruns != nruns) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)a.ncol * (unsigned)nruns);
+  if (e0) hipExtLaunchKernelGGL(band_solve_kernel<T>, grid, dim3(64), lds, s, e0, e1, 0, a);
+  else hipLaunchKernelGGL(band_solve_kernel<T>, grid, dim3(64), lds, s, a);
   return hipGetLastError();
 }
 

@@ -162,11 +162,14 @@ template <typename T> struct ColArgs {
 constexpr int kBlockMax = 2048;  // largest block (dense inverse)
 template <typename T> struct BandArgs {
   cplx<T>* Bt;            // the runs' transposed row spectra, run r at run_bt[r]: [nx/2][hp]
-  const T* fwd;           // factor streams, run r at run_fs[r]: [(nx/2+1)*32][hp]
+  const T* fwd;           // factor streams: (run, kx) at kx_off[run_k0[run] + kx]: [32][hp - 32 d]
   const int* run_hp;      // padded rows of each run (multiple of 32)
   const size_t* run_bt;
-  const size_t* run_fs;
-  int ncol;               // nx/2
+  const int* run_k0;      // per run: index of its (kx = 0) entry in kx_off / kx_dup
+  const size_t* kx_off;
+  const int* kx_dup;      // per (run, kx): s0, d (chunks s0 .. s0 + d stored once, as chunk s0)
+  int nruns;
+  int ncol;               // nx/2 (a multiple of 8)
   const int* run_prob;    // problem of each run (its CG scalars: sc + problem)
   const CGScalars* sc;
 };
@@ -232,11 +235,91 @@ template <typename T> __device__ __forceinline__ void bind_caller(RowArgs<T>& a)
   if (a.seeds) a.seed = a.seeds[b];
 }
 
+// A kernel's first batch of loads (the CG state, the previous pass's
+// partials, the row offsets) is issued before it branches on any of them, so
+// that the batch costs one memory round trip instead of one per dependent
+// read.  issue_fence() keeps the loads above it in program order (no pass
+// may sink them below the branch that follows).
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
+// The fields of a problem's CG state that the kernels read, in registers
+// (null state: idle, not done).  Indexing by parity goes through selects so
+// that nothing of it lives in memory.
+struct CGView {
+  double rho0, rho1, alph0, alph1, tol2;
+  int done, iter, max_iter, cap;
+  __device__ __forceinline__ double rho(int p) const { return p ? rho1 : rho0; }
+  __device__ __forceinline__ double alph(int p) const { return p ? alph1 : alph0; }
+};
+// A per-lane zero that the compiler cannot see through.  A uniform address
+// plus it is read by the vector memory path, whose loads return in order with
+// the kernel's other vector loads; a scalar-cache load would not do: those
+// return out of order, so the first use of any scalar load (a kernel
+// argument, say) waits for every one in flight, the state's included.
+__device__ __forceinline__ int lane_zero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+
+// The state a null pointer stands for: idle, not done (all zero).
+static __device__ CGScalars g_idle_state;
+
+// The done flag of a problem's CG state (null: 0), a vector load.
+__device__ __forceinline__ int load_done(const CGScalars* sc) {
+  return ((sc != nullptr ? sc : &g_idle_state) + lane_zero())->done;
+}
+
+// Unconditional vector loads (no branch whose join would wait for them).
+__device__ __forceinline__ CGView load_scalars(const CGScalars* sc_in) {
+  const CGScalars* sc = (sc_in != nullptr ? sc_in : &g_idle_state) + lane_zero();
+  CGView v;
+  v.rho0 = sc->rho[0];
+  v.rho1 = sc->rho[1];
+  v.alph0 = sc->alph[0];
+  v.alph1 = sc->alph[1];
+  v.tol2 = sc->tol2;
+  v.done = sc->done;
+  v.iter = sc->iter;
+  v.max_iter = sc->max_iter;
+  v.cap = sc->cap;
+  return v;
+}
+
+// Per-thread sums of the previous pass's partials (red0, red1 and, for the
+// single-reduction step, red2), four loads in flight per thread before the
+// additions; the order of the additions is fixed.
+template <int NR, int NT, typename T>
+__device__ __forceinline__ void cg_partials(const RowArgs<T>& a, double& s0, double& s1, double& s2) {
+  s0 = s1 = s2 = 0.0;
+  const double* r[3] = {a.red0, a.red1, a.red2};
+  int i = threadIdx.x;
+  for (; i + 3 * NT < a.nred; i += 4 * NT) {
+    double v[NR][4];
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[q][u] = r[q][i + u * NT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s0 += v[0][u];
+      if constexpr (NR > 1) s1 += v[1][u];
+      if constexpr (NR > 2) s2 += v[2][u];
+    }
+  }
+  for (; i < a.nred; i += NT) {
+    s0 += r[0][i];
+    if constexpr (NR > 1) s1 += r[1][i];
+    if constexpr (NR > 2) s2 += r[2][i];
+  }
+}
+
 // One CG scalar step, taken redundantly by every workgroup of the row pass
-// that needs it: the previous pass's per-workgroup partial sums are added in
-// a fixed order, so every workgroup obtains the same bits; workgroup 0 alone
-// persists the new state.  Returns the coefficient (beta or alpha), or sets
-// *stop when the solve ends here.
+// that needs it: the previous pass's per-workgroup partial sums (s0, s1: this
+// thread's share, cg_partials) are added in a fixed order, so every
+// workgroup obtains the same bits; workgroup 0 alone persists the new state.
+// cs is the state as the kernel found it (load_scalars).  Returns the
+// coefficient (beta or alpha), or sets *stop when the solve ends here.
 //   PUPDATE (start of an iteration): rz = r.z, rr = r.r from the previous
 //     E E r pass; stop if rr <= tol2, if the cap was reached or rz <= 0;
 //     beta = rz / rho[parity]; rho[parity^1] = rz.
@@ -245,14 +328,10 @@ template <typename T> __device__ __forceinline__ void bind_caller(RowArgs<T>& a)
 // With a coefficient record (a.hist), workgroup 0 also stores alpha_j and
 // beta_j of iteration j: the data of the Lanczos matrix of the solve.
 template <int MODE, int NT, typename T>
-__device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop) {
+__device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, const CGView& cs, double s0, double s1,
+                                                 bool* stop) {
   __shared__ double s_coef;
   __shared__ int s_stop;
-  double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < a.nred; i += NT) {
-    s0 += a.red0[i];
-    if constexpr (MODE == 1) s1 += a.red1[i];
-  }
   block_sum2<NT>(s0, s1);
   if (threadIdx.x == 0) {
     CGScalars* sc = a.sc;
@@ -261,10 +340,10 @@ __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop
     double coef = 0.0;
     if constexpr (MODE == 1) {  // PUPDATE
       const double rz = s0, rr = s1;
-      if (rr <= sc->tol2) st = 1;
-      else if (sc->cap) { st = 1; stat = -4; }
+      if (rr <= cs.tol2) st = 1;
+      else if (cs.cap) { st = 1; stat = -4; }
       else if (!(rz > 0.0)) { st = 1; stat = -6; }
-      coef = rz / sc->rho[a.parity];
+      coef = rz / cs.rho(a.parity);
       if (w) {
         sc->rr = rr;
         if (st) {
@@ -273,23 +352,23 @@ __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop
         } else {
           sc->rho[a.parity ^ 1] = rz;
           sc->beta = coef;
-          const int j = sc->iter - 1;  // beta_j forms p_{j+1}
+          const int j = cs.iter - 1;  // beta_j forms p_{j+1}
           if (a.hist && j >= 0 && j < a.hist_cap) a.hist[2 * j + 1] = coef;
         }
       }
     } else {  // XRUPDATE
       const double pq = s0;
       if (!(pq > 0.0)) { st = 1; stat = -6; }
-      coef = sc->rho[a.parity ^ 1] / pq;
+      coef = cs.rho(a.parity ^ 1) / pq;
       if (w) {
         if (st) {
           sc->status = stat;
           sc->done = 1;
         } else {
           sc->alpha = coef;
-          if (a.hist && sc->iter < a.hist_cap) a.hist[2 * sc->iter] = coef;
-          sc->iter += 1;
-          if (sc->iter >= sc->max_iter) sc->cap = 1;
+          if (a.hist && cs.iter < a.hist_cap) a.hist[2 * cs.iter] = coef;
+          sc->iter = cs.iter + 1;
+          if (cs.iter + 1 >= cs.max_iter) sc->cap = 1;
         }
       }
     }
@@ -311,15 +390,11 @@ __device__ __forceinline__ double cg_scalar_step(const RowArgs<T>& a, bool* stop
 // Stops as the standard step does (rr <= tol2, the cap, rho or p.Ap not > 0);
 // workgroup 0 persists rho and alpha by parity, the record and the count.
 template <int NT, typename T>
-__device__ __forceinline__ void cg1_scalar_step(const RowArgs<T>& a, bool* stop, double* beta, double* alpha) {
+__device__ __forceinline__ void cg1_scalar_step(const RowArgs<T>& a, const CGView& cs, double s0, double s1,
+                                                double s2, bool* stop, double* beta, double* alpha) {
   __shared__ double s_ab[2];
   __shared__ int s_stop;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, unused = 0.0;
-  for (int i = threadIdx.x; i < a.nred; i += NT) {
-    s0 += a.red0[i];
-    s1 += a.red1[i];
-    s2 += a.red2[i];
-  }
+  double unused = 0.0;
   block_sum2<NT>(s0, s1);
   __syncthreads();
   block_sum2<NT>(s2, unused);
@@ -327,10 +402,10 @@ __device__ __forceinline__ void cg1_scalar_step(const RowArgs<T>& a, bool* stop,
     CGScalars* sc = a.sc;
     const double rz = s0, rr = s1, mu = s2;
     int st = 0, stat = 0;
-    const double b = rz / sc->rho[a.parity];
-    const double pap = mu - b * rz / sc->alph[a.parity];
-    if (rr <= sc->tol2) st = 1;
-    else if (sc->cap) { st = 1; stat = -4; }
+    const double b = rz / cs.rho(a.parity);
+    const double pap = mu - b * rz / cs.alph(a.parity);
+    if (rr <= cs.tol2) st = 1;
+    else if (cs.cap) { st = 1; stat = -4; }
     else if (!(rz > 0.0) || !(pap > 0.0)) { st = 1; stat = -6; }
     const double al = rz / pap;
     if (blockIdx.x == 0) {
@@ -339,7 +414,7 @@ __device__ __forceinline__ void cg1_scalar_step(const RowArgs<T>& a, bool* stop,
         sc->status = stat;
         sc->done = 1;
       } else {
-        const int j = sc->iter;
+        const int j = cs.iter;
         sc->rho[a.parity ^ 1] = rz;
         sc->alph[a.parity ^ 1] = al;
         sc->beta = b;
@@ -347,7 +422,7 @@ __device__ __forceinline__ void cg1_scalar_step(const RowArgs<T>& a, bool* stop,
         if (a.hist && j < a.hist_cap) a.hist[2 * j] = al;
         if (a.hist && j >= 1 && j - 1 < a.hist_cap) a.hist[2 * (j - 1) + 1] = b;  // beta_{j-1} forms p_j
         sc->iter = j + 1;
-        if (j + 1 >= sc->max_iter) sc->cap = 1;
+        if (j + 1 >= cs.max_iter) sc->cap = 1;
       }
     }
     s_ab[0] = b;
@@ -445,7 +520,6 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   __shared__ C lds[LDS_C];
   __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   T* ldr = reinterpret_cast<T*>(lds);
-  if (a.sc != nullptr && a.sc->done) return;
 
   const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
   const int y0 = blk * ROWS;
@@ -455,22 +529,35 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   C v[E];
 
   constexpr bool CG1 = MODE == R2C_CG1UPDATE;
+  // first batch of loads: the row offsets, the state, the partials
+  int c0 = 0, c1 = 0;
+  if constexpr (r2c_is_compact<MODE>()) {
+    c0 = a.row_off[y0];
+    c1 = a.row_off[y0 + ROWS];
+  }
+  const CGView cs = load_scalars(a.sc);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if constexpr (MODE == R2C_PUPDATE) cg_partials<2, NT>(a, s0, s1, s2);
+  else if constexpr (MODE == R2C_XRUPDATE) cg_partials<1, NT>(a, s0, s1, s2);
+  else if constexpr (CG1) cg_partials<3, NT>(a, s0, s1, s2);
+  issue_fence();
+  if (__builtin_amdgcn_readfirstlane(cs.done)) return;
+
   double acc = 0.0;  // CG1: r.r of the new r
   if constexpr (r2c_is_compact<MODE>()) {
     T coef = T(0), coef2 = T(0);  // beta (PUPDATE, CG1) or alpha (XRUPDATE); CG1: alpha
     if constexpr (MODE == R2C_PUPDATE || MODE == R2C_XRUPDATE) {
       bool stop = false;
-      coef = (T)cg_scalar_step<MODE, NT>(a, &stop);
+      coef = (T)cg_scalar_step<MODE, NT>(a, cs, s0, s1, &stop);
       if (stop) return;
     } else if constexpr (CG1) {
       bool stop = false;
       double b = 0.0, al = 0.0;
-      cg1_scalar_step<NT>(a, &stop, &b, &al);
+      cg1_scalar_step<NT>(a, cs, s0, s1, s2, &stop, &b, &al);
       if (stop) return;
       coef = (T)b;
       coef2 = (T)al;
     }
-    const int c0 = a.row_off[y0], c1 = a.row_off[y0 + ROWS];
     if (c0 == c1) {  // no masked pixel in these rows: the spectrum is zero
       for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
       if (CG1 && t == 0 && a.part0) a.part0[blk] = 0.0;
@@ -741,7 +828,6 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
   __shared__ C lds[LDS_C];
   __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   T* ldr = reinterpret_cast<T*>(lds);
-  if (a.sc != nullptr && a.sc->done) return;
 
   const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
   const int y0 = blk * ROWS;
@@ -752,6 +838,11 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
   if constexpr (c2r_is_compact<MODE>()) {
     c0 = a.row_off[y0];
     c1 = a.row_off[y0 + ROWS];
+  }
+  const int done = load_done(a.sc);
+  issue_fence();  // the state and the row offsets in one round trip
+  if (__builtin_amdgcn_readfirstlane(done)) return;
+  if constexpr (c2r_is_compact<MODE>()) {
     if (c0 == c1) {  // nothing to write; partial sums are zero
       if (t == 0) {
         if (a.part0) a.part0[blk] = 0.0;
@@ -843,7 +934,6 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
   __shared__ C lds[LDS_C];
   __shared__ C twq[tw_elems<PL>() > 0 ? tw_elems<PL>() : 1];
   T* ldr = reinterpret_cast<T*>(lds);
-  if (a.sc != nullptr && a.sc->done) return;
 
   const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
   const int y0 = blk * ROWS;
@@ -851,6 +941,9 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void proj_kernel(RowArgs<T
   const int l = t / TPL, tid = t % TPL;
   const size_t ldx = (size_t)a.ldx;
   const int c0 = a.row_off[y0], c1 = a.row_off[y0 + ROWS];
+  const int done = load_done(a.sc);
+  issue_fence();  // the state and the row offsets in one round trip
+  if (__builtin_amdgcn_readfirstlane(done)) return;
   if (c0 == c1) {  // no masked pixel: the projection is zero
     for (int o = t; o < ROWS * (N / 2); o += NT) a.Xt[(size_t)(o / ROWS) * ldx + y0 + (o % ROWS)] = C{T(0), T(0)};
     if (DOT && t == 0) {
@@ -947,7 +1040,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
   a.Xt += (size_t)blockIdx.y * a.xt_stride;
   a.D += (size_t)blockIdx.y * a.d_stride;
   if (a.sc) a.sc += blockIdx.y;
-  if (a.sc != nullptr && a.sc->done) return;
+  const int done = load_done(a.sc);
   const int l = threadIdx.x / TPL, tid = threadIdx.x % TPL;
   const int kx = blockIdx.x * W + l;
   const bool valid = kx < a.ncol;
@@ -961,6 +1054,8 @@ __global__ __launch_bounds__((ColCfg<T, N>::THREADS)) void col_kernel(ColArgs<T>
     dv[e] = valid ? d[tid + e * TPL] : T(0);
   }
   tw_stage<PL>(twq, a.tw, threadIdx.x, CF::THREADS);
+  issue_fence();  // the state and the column in one round trip
+  if (__builtin_amdgcn_readfirstlane(done)) return;
   C* line = lds + l * LE;
   fft_line<C, PL, -1>(v, tid, line, twq);
   if (blockIdx.x == 0) {
@@ -1037,17 +1132,21 @@ constexpr int kXrThreads = 256;
 template <typename T, bool INIT>
 __global__ __launch_bounds__(kXrThreads) void xr_kernel(RowArgs<T> a_in, int rows) {
   RowArgs<T> a = bind_problem(a_in);
-  if (a.sc != nullptr && a.sc->done) return;
-  T coef = T(0);
-  if constexpr (!INIT) {
-    bool stop = false;
-    coef = (T)cg_scalar_step<R2C_XRUPDATE, kXrThreads>(a, &stop);
-    if (stop) return;
-  }
   // equal slices of the problem's compact range (row blocks would leave the
   // few workgroups on a band with nearly all the work)
   const int blk = blockIdx.x, nblk = gridDim.x;
   const long long nm = a.row_off[(size_t)nblk * rows];
+  const CGView cs = load_scalars(a.sc);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if constexpr (!INIT) cg_partials<1, kXrThreads>(a, s0, s1, s2);
+  issue_fence();  // the state, the range and the partials in one round trip
+  if (__builtin_amdgcn_readfirstlane(cs.done)) return;
+  T coef = T(0);
+  if constexpr (!INIT) {
+    bool stop = false;
+    coef = (T)cg_scalar_step<R2C_XRUPDATE, kXrThreads>(a, cs, s0, s1, &stop);
+    if (stop) return;
+  }
   const int c0 = (int)(nm * blk / nblk), c1 = (int)(nm * (blk + 1) / nblk);
   double acc = 0.0, unused = 0.0;
   for (int c = c0 + (int)threadIdx.x; c < c1; c += kXrThreads) {

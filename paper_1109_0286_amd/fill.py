@@ -79,7 +79,8 @@ class fill_stats(C.Structure):
 
 class BlockInfo(C.Structure):
     _fields_ = [("runs", C.c_int), ("blocks", C.c_int), ("band_rows", C.c_int64), ("block_pixels", C.c_int64),
-                ("block_entries", C.c_int64), ("bytes", C.c_int64), ("elem_bytes", C.c_int)]
+                ("block_entries", C.c_int64), ("bytes", C.c_int64), ("elem_bytes", C.c_int),
+                ("band_stream_values", C.c_int64)]
 
 
 class FillError(RuntimeError):
@@ -327,8 +328,9 @@ def fill_plan_set_precond(plan, mode):
 
 
 def fill_get_block_info(plan) -> dict:
-    """Runs, blocks, padded band rows, block pixels, stored inverse entries,
-    bytes and element size of the plan's block preconditioner."""
+    """Runs, blocks, padded band rows, block pixels, inverse entries, bytes,
+    element size and stored band factor values of the plan's block
+    preconditioner."""
     out = BlockInfo()
     _check(_lib.fill_get_block_info(plan, C.byref(out)), "fill_get_block_info")
     return {f: getattr(out, f) for f, _ in BlockInfo._fields_}
