@@ -106,6 +106,7 @@ struct BlockDev {
   void* fwd = nullptr;
   int* run_hp = nullptr;
   size_t* run_bt = nullptr;
+  RunRow* run_rows = nullptr;  // the runs for the row passes
   int* run_k0 = nullptr;
   size_t* kx_off = nullptr;
   int* kx_dup = nullptr;
@@ -567,6 +568,10 @@ int block_setup(fill_plan p) {
   };
   std::vector<Seen> band_seen, binv_seen;
   size_t binv_logical = 0;
+  struct ItemRange {
+    size_t first, n, key;  // the problem's work items and the offset of the inverses they read
+  };
+  std::vector<ItemRange> item_range;
   for (int b = 0; b < np; ++b) {
     fillb::Layout Lb;
     FILL_TRY(block_layout_for(p, b, &Lb));
@@ -616,6 +621,7 @@ int block_setup(fill_plan p) {
       L.moff.push_back(Lb.moff[q - 1] + mbase);
       block_prob.push_back(b);
     }
+    item_range.push_back({L.items.size() / 4, Lb.items.size() / 4, mbase});
     for (size_t q = 0; q < Lb.items.size(); q += 4) {
       L.items.push_back(Lb.items[q] + bbase);
       L.items.push_back(Lb.items[q + 1]);
@@ -638,6 +644,30 @@ int block_setup(fill_plan p) {
     L.n_m += Lb.n_m;
   }
   if (L.cst.empty()) L.cst.push_back(0);
+  // Problems that share their inverses take turns in groups of 8 work items:
+  // work item w runs on XCD w mod 8, so the copies of one item go to one XCD
+  // back to back and read the inverse through its L2.  Others keep their order.
+  {
+    std::vector<int> order;  // work items in launch order
+    std::vector<bool> placed(item_range.size(), false);
+    for (size_t i = 0; i < item_range.size(); ++i) {
+      if (placed[i]) continue;
+      std::vector<size_t> grp;
+      for (size_t j = i; j < item_range.size(); ++j)
+        if (!placed[j] && item_range[j].key == item_range[i].key && item_range[j].n == item_range[i].n) {
+          grp.push_back(j);
+          placed[j] = true;
+        }
+      const size_t n = item_range[i].n;
+      for (size_t i0 = 0; i0 < n; i0 += 8)
+        for (size_t j : grp)
+          for (size_t t = i0; t < std::min(n, i0 + 8); ++t) order.push_back((int)(item_range[j].first + t));
+    }
+    std::vector<int> items(L.items.size());
+    for (size_t w = 0; w < order.size(); ++w)
+      std::copy(L.items.begin() + 4 * (size_t)order[w], L.items.begin() + 4 * (size_t)order[w] + 4, items.begin() + 4 * w);
+    L.items.swap(items);
+  }
   BlockDev& B = p->blk;
   const bool f32 = p->prec == FILL_PREC_FP32_OP;
   const size_t ts = f32 ? sizeof(float) : sizeof(double);
@@ -661,6 +691,12 @@ int block_setup(fill_plan p) {
   FILL_TRY(bupload(p, &B.run_hp, hp));
   FILL_TRY(bupload(p, &B.run_bt, bt));
   FILL_TRY(bupload(p, &B.run_k0, k0));
+  {
+    std::vector<RunRow> rr;
+    for (size_t q = 0; q < L.runs.size(); ++q)
+      rr.push_back(RunRow{B.run_brow[q], L.runs[q].bt_off, L.runs[q].hp, L.runs[q].cb0, run_prob[q], 0});
+    FILL_TRY(bupload(p, &B.run_rows, rr));
+  }
   FILL_TRY(bupload(p, &B.kx_off, L.kx_off));
   FILL_TRY(bupload(p, &B.kx_dup, L.kx_dup));
   FILL_TRY(bupload(p, &B.run_prob_d, run_prob));
@@ -724,16 +760,17 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
   if (!B.built || (sizeof(T) == 4) != (p->prec == FILL_PREC_FP32_OP))
     return fail(FILL_EINVAL, "block preconditioner not built for this precision");
   const int nruns = (int)B.runs.size();
-  auto run_args = [&](int q) {
-    const fillb::Run& run = B.runs[q];
-    RowArgs<T> a = row_base<T>(p, 1);
-    a.ny = run.hp;
-    a.ldx = run.hp;
+  // the row passes of every band run in one launch (blockIdx.y = run)
+  auto run_args = [&]() {
+    RowArgs<T> a = row_base<T>(p, nruns);
+    a.ny = B.max_hp;
+    a.ldx = B.max_hp;
     a.comp_off = nullptr;
-    a.row_off = B.brow_off + B.run_brow[q];
-    a.pos = B.bpos - run.cb0;  // pos[c] = c - cb0: the pixel index within the run's rows
-    a.Xt = static_cast<cplx<T>*>(B.Bt) + run.bt_off;
-    a.sc = sc ? sc + B.run_prob[q] : nullptr;
+    a.row_off = B.brow_off;
+    a.pos = B.bpos;  // pos[c] = c - cb0: the pixel index within the run's rows
+    a.Xt = static_cast<cplx<T>*>(B.Bt);
+    a.sc = sc;
+    a.runs = B.run_rows;
     return a;
   };
   BlockArgs<T> bk;
@@ -752,8 +789,8 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
     FILL_TRY(timed_launch<T>(p, FILL_K_BLOCKMV, [&](hipEvent_t e0, hipEvent_t e1) {
       return launch_block_mv<T>(bk, B.nitems, p->stream, e0, e1);
     }));
-  for (int q = 0; q < nruns && only < 0; ++q) {
-    RowArgs<T> a = run_args(q);
+  if (nruns > 0 && only < 0) {
+    RowArgs<T> a = run_args();
     a.v0 = const_cast<T*>(r);
     HIP_TRY(launch_r2c<T>(R2C_COMPACT, a, p->stream));
   }
@@ -774,8 +811,8 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
       return launch_band_solve<T>(ba, nruns, B.max_hp, p->stream, e0, e1);
     }));
   }
-  for (int q = 0; q < nruns && only < 0; ++q) {
-    RowArgs<T> a = run_args(q);
+  if (nruns > 0 && only < 0) {
+    RowArgs<T> a = run_args();
     a.v0 = z;
     HIP_TRY(launch_c2r<T>(C2R_COMPACT, a, p->stream));
   }

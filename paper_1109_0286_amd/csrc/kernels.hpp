@@ -103,10 +103,24 @@ enum C2RMode {
   C2R_FULL = 4       // full_out = scale*val
 };
 
+// A band run of the block preconditioner as the row passes see it: its rows
+// are a grid of hp rows of its own (row offsets at row_off, pixel positions
+// relative to cb0, spectrum at bt_off complex values), solved with the CG
+// state of problem prob.
+struct RunRow {
+  size_t row_off;
+  size_t bt_off;
+  int hp;
+  int cb0;
+  int prob;
+  int pad;
+};
+
 // Arguments of the row passes.  A launch covers nprob problems of the same
 // grid (blockIdx.y = problem): pointers are problem 0's and bind_problem()
 // moves them to problem blockIdx.y (compact vectors by comp_off, the rest by
-// the strides).
+// the strides).  With runs set, blockIdx.y is a band run instead (ny: the
+// largest run's rows; workgroups past a run's rows return).
 template <typename T> struct RowArgs {
   int nx, ny, ldx;
   int nprob;
@@ -143,6 +157,7 @@ template <typename T> struct RowArgs {
   double* full_out2;
   const uint8_t* mask;
   uint64_t seed, stream;
+  const RunRow* runs;
 };
 
 template <typename T> struct ColArgs {
@@ -203,6 +218,15 @@ template <typename T> struct CombArgs {
 
 template <typename T> __device__ __forceinline__ RowArgs<T> bind_problem(RowArgs<T> a) {
   const int b = blockIdx.y;
+  if (a.runs != nullptr) {
+    const RunRow rr = a.runs[b];
+    a.row_off += rr.row_off;
+    a.pos -= rr.cb0;
+    a.Xt += rr.bt_off;
+    a.ny = a.ldx = rr.hp;
+    if (a.sc) a.sc += rr.prob;
+    return a;
+  }
   if (b == 0) return a;
   const int coff = a.comp_off ? a.comp_off[b] : 0;
   a.row_off += (size_t)b * (a.ny + 1);
@@ -523,6 +547,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
 
   const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
   const int y0 = blk * ROWS;
+  if (y0 >= a.ny) return;  // past a band run's rows
   const int t = threadIdx.x;
   const int l = t / TPL, tid = t % TPL;
   const size_t ldx = (size_t)a.ldx;
@@ -831,6 +856,7 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void c2r_kernel(RowArgs<T>
 
   const int blk = xcd_remap<CF::XG>(blockIdx.x, gridDim.x);
   const int y0 = blk * ROWS;
+  if (y0 >= a.ny) return;  // past a band run's rows
   const int t = threadIdx.x;
   const int l = t / TPL, tid = t % TPL;
   const size_t ldx = (size_t)a.ldx;
