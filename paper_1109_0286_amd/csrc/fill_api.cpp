@@ -749,11 +749,13 @@ int block_follow_pk(fill_plan p) {
 }
 
 // z = M^-1 r (compact vectors of the plan's precision), with the partials of
-// r.z and r.r over the row blocks (part0/part1 may be null).  Launches: per
-// band run a forward row transform of its rows, the banded solves of every
-// (run, kx), per run the inverse row transform into z, the dense block
-// products and the combination.  only >= 0 launches that kernel alone
-// (FILL_K_BAND, FILL_K_BLOCKMV or FILL_K_COMBINE: timing).
+// r.z and r.r over the row blocks (part0/part1 may be null).  Launches: the
+// forward row transforms of the band runs' rows, the banded solves of every
+// (run, kx) together with the dense block products, the inverse row
+// transforms into z and the combination.  only >= 0 launches that kernel
+// alone (FILL_K_BAND: the band solves only, FILL_K_BLOCKMV or
+// FILL_K_COMBINE: timing).
+constexpr size_t kFusedBandLds = 48 * 1024;
 template <typename T>
 int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGScalars* sc, int only = -1) {
   BlockDev& B = p->blk;
@@ -783,9 +785,25 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
   bk.binv = static_cast<const T*>(B.binv);
   bk.block_prob = B.block_prob;
   bk.sc = sc;
-  // (running the block products on a second stream beside the band solves
-  // was measured no faster: both are limited by the same memory system)
-  if (only < 0 || only == FILL_K_BLOCKMV)
+  BandArgs<T> ba;
+  ba.Bt = static_cast<cplx<T>*>(B.Bt);
+  ba.fwd = static_cast<const T*>(B.fwd);
+  ba.run_hp = B.run_hp;
+  ba.run_bt = B.run_bt;
+  ba.run_k0 = B.run_k0;
+  ba.kx_off = B.kx_off;
+  ba.kx_dup = B.kx_dup;
+  ba.nruns = nruns;
+  ba.max_hp = B.max_hp;
+  ba.ncol = p->nx / 2;
+  ba.run_prob = B.run_prob_d;
+  ba.sc = sc;
+  // The band solves and the block products share one launch (timed as the
+  // band kernel) where the band's LDS leaves room for the products'
+  // workgroups beside it.
+  const bool fused = only < 0 && nruns > 0 && B.nitems > 0 && ba.ncol % 4 == 0 &&
+                     (size_t)4 * 2 * B.max_hp * sizeof(T) <= kFusedBandLds;
+  if (!fused && (only < 0 || only == FILL_K_BLOCKMV))
     FILL_TRY(timed_launch<T>(p, FILL_K_BLOCKMV, [&](hipEvent_t e0, hipEvent_t e1) {
       return launch_block_mv<T>(bk, B.nitems, p->stream, e0, e1);
     }));
@@ -794,23 +812,14 @@ int block_apply(fill_plan p, const T* r, T* z, double* part0, double* part1, CGS
     a.v0 = const_cast<T*>(r);
     HIP_TRY(launch_r2c<T>(R2C_COMPACT, a, p->stream));
   }
-  if (nruns > 0 && (only < 0 || only == FILL_K_BAND)) {
-    BandArgs<T> ba;
-    ba.Bt = static_cast<cplx<T>*>(B.Bt);
-    ba.fwd = static_cast<const T*>(B.fwd);
-    ba.run_hp = B.run_hp;
-    ba.run_bt = B.run_bt;
-    ba.run_k0 = B.run_k0;
-    ba.kx_off = B.kx_off;
-    ba.kx_dup = B.kx_dup;
-    ba.nruns = nruns;
-    ba.ncol = p->nx / 2;
-    ba.run_prob = B.run_prob_d;
-    ba.sc = sc;
+  if (fused)
+    FILL_TRY(timed_launch<T>(p, FILL_K_BAND, [&](hipEvent_t e0, hipEvent_t e1) {
+      return launch_band_block<T>(ba, bk, nruns, B.max_hp, B.nitems, p->stream, e0, e1);
+    }));
+  else if (nruns > 0 && (only < 0 || only == FILL_K_BAND))
     FILL_TRY(timed_launch<T>(p, FILL_K_BAND, [&](hipEvent_t e0, hipEvent_t e1) {
       return launch_band_solve<T>(ba, nruns, B.max_hp, p->stream, e0, e1);
     }));
-  }
   if (nruns > 0 && only < 0) {
     RowArgs<T> a = run_args();
     a.v0 = z;

@@ -92,23 +92,18 @@ __device__ __forceinline__ int stored_chunk(int c, int s0, int d) {
 // taking turns).  Where the rows have reached their Toeplitz limit the
 // chunks repeat and are stored once: a register set that already holds the
 // repeated chunk is not loaded again.
-// Grid: ncol * nruns workgroups in one dimension.  Workgroup w runs on XCD
-// w mod 8, so w = 8 (nruns g + run) + (col mod 8) with col = 8 g + (w mod 8)
-// sends the runs' waves of one column (one factor, when identical problems
-// share it) to one XCD, one after another.
+// Column col of band run `run`, one wave (lanes threadIdx.x mod 64); smem:
+// the wave's 2 hp values of LDS.  The workgroup's waves (all of one run)
+// meet at its barriers.
 template <typename T>
-__global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
-  extern __shared__ unsigned char band_smem[];
-  const int w = blockIdx.x, q = w >> 3;
-  const int g = q / a.nruns, run = q - g * a.nruns;
-  const int col = 8 * g + (w & 7);
+__device__ __forceinline__ void band_solve_column(const BandArgs<T>& a, int run, int col, unsigned char* smem) {
   // the problem's state is read beside the run's spectrum column
   const int prob = a.sc != nullptr ? a.run_prob[run] : 0;
   const int hp = a.run_hp[run];
   cplx<T>* X = a.Bt + a.run_bt[run] + (size_t)col * hp;
-  T* sre = reinterpret_cast<T*>(band_smem);
+  T* sre = reinterpret_cast<T*>(smem);
   T* sim = sre + hp;
-  const int lane = threadIdx.x, k = lane & 31, half = lane >> 5;
+  const int lane = threadIdx.x & 63, k = lane & 31, half = lane >> 5;
   const int done = load_done(a.sc != nullptr ? a.sc + prob : nullptr);
   const int kx = (col == 0 && half) ? a.ncol : col;
   const int ki = a.run_k0[run] + kx;
@@ -213,6 +208,33 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
   for (int i = lane; i < hp; i += 64) X[i] = cplx<T>{sre[i], sim[i]};
 }
 
+// Group u of ncol / CPG * nruns groups of CPG consecutive columns of one run.
+// Workgroups run on XCD (index mod 8): when the groups of a run are a
+// multiple of 8, u = 8 (nruns g + run) + (q mod 8) with group q = 8 g +
+// (u mod 8) sends the runs' copies of one group of columns (one factor, when
+// identical problems share it) to one XCD, one after another.
+template <int CPG>
+__device__ __forceinline__ void band_group(int u, int ncol, int nruns, int* run, int* q) {
+  const int nq = ncol / CPG;
+  if (nq % 8 == 0) {
+    const int s = u >> 3, g = s / nruns;
+    *run = s - g * nruns;
+    *q = 8 * g + (u & 7);
+  } else {
+    *run = u / nq;
+    *q = u - *run * nq;
+  }
+}
+
+// One wave per (column, run).
+template <typename T>
+__global__ __launch_bounds__(64) void band_solve_kernel(BandArgs<T> a) {
+  extern __shared__ unsigned char band_smem[];
+  int run, col;
+  band_group<1>(blockIdx.x, a.ncol, a.nruns, &run, &col);
+  band_solve_column(a, run, col, band_smem);
+}
+
 constexpr int kBlkThreads = 256;           // 4 waves
 constexpr int kBlkWaves = kBlkThreads / 64;
 constexpr int kBlkRows = 256;              // rows of a work item: 4 per lane
@@ -244,11 +266,11 @@ __device__ __forceinline__ void load4(double (&v)[4], const double* p) {
 // are added in a fixed order, and the column chunks' outputs by the
 // combination (deterministic).
 template <typename T>
-__global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
+__device__ __forceinline__ void block_mv_item(const BlockArgs<T>& a, int it) {
   __shared__ T rv[kBlkCols];
   __shared__ T red[kBlkWaves][kBlkRows];
   const int t = threadIdx.x;
-  const int* item = a.items + 4 * (size_t)blockIdx.x;
+  const int* item = a.items + 4 * (size_t)it;
   const int b = item[0], r0 = item[1], c0 = item[2], so = item[3];
   // the problem's state is read beside the block's extent, then the gather
   const int prob = a.sc != nullptr ? a.block_prob[b] : 0;
@@ -293,6 +315,28 @@ __global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
 #pragma unroll
     for (int q = 1; q < kBlkWaves; ++q) s += red[q][t];
     a.seg[so + r0 + t] = s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlkThreads) void block_mv_kernel(BlockArgs<T> a) {
+  block_mv_item(a, blockIdx.x);
+}
+
+// The band solves and the block products in one launch: workgroups
+// 0 .. nband-1 take kBlkWaves columns of one run each (a wave per column),
+// the rest one work item of the products each.  The two are independent:
+// the products fill the issue slots the latency-bound substitutions leave.
+template <typename T>
+__global__ __launch_bounds__(kBlkThreads) void band_block_kernel(BandArgs<T> ba, BlockArgs<T> bk, int nband) {
+  extern __shared__ unsigned char band_smem[];
+  if ((int)blockIdx.x < nband) {
+    const int wv = threadIdx.x >> 6;
+    int run, q;
+    band_group<kBlkWaves>(blockIdx.x, ba.ncol, ba.nruns, &run, &q);
+    band_solve_column(ba, run, kBlkWaves * q + wv, band_smem + (size_t)wv * 2 * ba.max_hp * sizeof(T));
+  } else {
+    block_mv_item(bk, (int)blockIdx.x - nband);
   }
 }
 
@@ -417,10 +461,28 @@ hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStr
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (a.ncol % 8 != 0 || a.nruns != nruns) return hipErrorInvalidValue;
+  if (a.nruns != nruns) return hipErrorInvalidValue;
   const dim3 grid((unsigned)a.ncol * (unsigned)nruns);
   if (e0) hipExtLaunchKernelGGL(band_solve_kernel<T>, grid, dim3(64), lds, s, e0, e1, 0, a);
   else hipLaunchKernelGGL(band_solve_kernel<T>, grid, dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_block(const BandArgs<T>& ba, const BlockArgs<T>& bk, int nruns, int max_hp, int nitems,
+                             hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (nruns <= 0 || ba.nruns != nruns || ba.max_hp != max_hp || ba.ncol % kBlkWaves != 0)
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)kBlkWaves * 2 * max_hp * sizeof(T);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&band_block_kernel<T>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int nband = ba.ncol / kBlkWaves * nruns;
+  const dim3 grid((unsigned)(nband + nitems));
+  if (e0) hipExtLaunchKernelGGL(band_block_kernel<T>, grid, dim3(kBlkThreads), lds, s, e0, e1, 0, ba, bk, nband);
+  else hipLaunchKernelGGL(band_block_kernel<T>, grid, dim3(kBlkThreads), lds, s, ba, bk, nband);
   return hipGetLastError();
 }
 
@@ -443,6 +505,10 @@ hipError_t launch_combine(const CombArgs<T>& a, int nblk, int nprob, hipStream_t
 
 template hipError_t launch_band_solve<float>(const BandArgs<float>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_band_solve<double>(const BandArgs<double>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_band_block<float>(const BandArgs<float>&, const BlockArgs<float>&, int, int, int,
+                                             hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_band_block<double>(const BandArgs<double>&, const BlockArgs<double>&, int, int, int,
+                                              hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_block_mv<float>(const BlockArgs<float>&, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_block_mv<double>(const BlockArgs<double>&, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_combine<float>(const CombArgs<float>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);

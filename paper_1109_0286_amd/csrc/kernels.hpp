@@ -184,7 +184,8 @@ template <typename T> struct BandArgs {
   const size_t* kx_off;
   const int* kx_dup;      // per (run, kx): s0, d (chunks s0 .. s0 + d stored once, as chunk s0)
   int nruns;
-  int ncol;               // nx/2 (a multiple of 8)
+  int max_hp;             // the largest run's padded rows
+  int ncol;               // nx/2
   const int* run_prob;    // problem of each run (its CG scalars: sc + problem)
   const CGScalars* sc;
 };

@@ -37,6 +37,11 @@ template <typename T>
 hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T>
 hipError_t launch_block_mv(const BlockArgs<T>& a, int nblocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// Both of the above in one launch (band solves of nruns runs, nitems block
+// product work items); needs nx/2 a multiple of 4.
+template <typename T>
+hipError_t launch_band_block(const BandArgs<T>& ba, const BlockArgs<T>& bk, int nruns, int max_hp, int nitems,
+                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T>
 hipError_t launch_combine(const CombArgs<T>& a, int nblk, int nprob, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 

@@ -39,9 +39,9 @@ MODES = ("Modes: r2c 0 compact, 1 p = z + beta p, 2 x += alpha p / r -= alpha q,
 # FP32 kernels of the mixed solve's CG iteration whose HBM bytes the counter
 # runs measure: bench.py's name -> the kernel-name prefix of its dispatches
 # (r2c: the p = z + beta p pass; c2r: the A p pass, the largest grid of mode 0)
-KERNELS = {"band": "band_solve_kernel<float>", "col": "col_kernel<float, {n}",
+KERNELS = {"bandblock": "band_block_kernel<float>", "col": "col_kernel<float, {n}",
            "r2c": "r2c_kernel<float, {n}, 1>", "c2r": "c2r_kernel<float, {n}, 0>",
-           "blockmv": "block_mv_kernel<float>", "combine": "combine_kernel<float>"}
+           "combine": "combine_kernel<float>"}
 
 
 def pmc_regex(n: int) -> str:
@@ -49,7 +49,7 @@ def pmc_regex(n: int) -> str:
 
 
 def dominant(clean: dict) -> str:
-    """Kernel name (e.g. band_solve_kernel) of the bench line's roofline."""
+    """Kernel name (e.g. band_block_kernel) of the bench line's roofline."""
     return clean["roofline"]["kernel"].split("<")[0]
 
 
@@ -78,7 +78,7 @@ def main(run: str, n: int) -> None:
     # the FP32 instance of the kernel at this size (all launches of the run)
     sel = [r for r in rows if kern + "<float" in r["Name"] and (f", {n}" in r["Name"] or kern in
                                                                  ("band_solve_kernel", "block_mv_kernel",
-                                                                  "combine_kernel"))]
+                                                                  "combine_kernel", "band_block_kernel"))]
     calls = sum(int(r["Calls"]) for r in sel)
     col_rocprof = sum(float(r["TotalDurationNs"]) for r in sel) / max(calls, 1) / 1e3
     live, line = bench_numbers(clean, n)
