@@ -24,46 +24,10 @@ template <typename F> void parallel_for(int n, F&& f) {
   for (auto& t : th) t.join();
 }
 
-// Dense SPD inverse in place (row-major n x n): Cholesky A = L L^T, then
-// A^-1 = L^-T L^-1.  Returns false if a pivot is not positive.
-bool spd_inverse(std::vector<double>& A, int n) {
-  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-  for (int j = 0; j < n; ++j) {
-    double d = a(j, j);
-    for (int m = 0; m < j; ++m) d -= a(j, m) * a(j, m);
-    if (!(d > 0.0)) return false;
-    const double l = std::sqrt(d);
-    a(j, j) = l;
-    for (int i = j + 1; i < n; ++i) {
-      double s = a(i, j);
-      for (int m = 0; m < j; ++m) s -= a(i, m) * a(j, m);
-      a(i, j) = s / l;
-    }
-  }
-  // W = L^-1 (lower), column by column: L w = e_j
-  std::vector<double> W((size_t)n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    for (int i = j; i < n; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int m = j; m < i; ++m) s -= a(i, m) * W[(size_t)m * n + j];
-      W[(size_t)i * n + j] = s / a(i, i);
-    }
-  }
-  // A^-1 = W^T W: (i, j) = sum_{m >= max(i, j)} W[m][i] W[m][j]
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double s = 0.0;
-      for (int m = i; m < n; ++m) s += W[(size_t)m * n + i] * W[(size_t)m * n + j];
-      a(i, j) = s;
-      a(j, i) = s;
-    }
-  return true;
-}
-
 }  // namespace
 
-int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, double pivot_min,
-                 bool f32, Layout* L, std::string* err) {
+int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double pivot_min, bool f32, Layout* L,
+                 std::string* err) {
   L->nx = nx;
   L->ny = ny;
   const size_t npix = (size_t)nx * ny;
@@ -293,7 +257,7 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
     }
   }
 
-  // ---- dense inverses
+  // ---- block layout (the dense inverses are computed on the device)
   const int nb = (int)blocks.size();
   L->boff.assign(nb + 1, 0);
   L->moff.assign(nb, 0);
@@ -303,34 +267,14 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const 
     L->moff[b] = mt;
     mt += blocks[b].size() * (size_t)block_ld((int)blocks[b].size());
   }
+  L->inv_total = mt;
   L->bidx.resize(L->boff[nb]);
-  L->binv.assign(mt, 0.0);
-  std::atomic<int> badb{-1};
-  parallel_for(nb, [&](int b) {
-    const std::vector<int>& px = blocks[b];
-    const int n = (int)px.size();
-    std::vector<double> A((size_t)n * n);
-    for (int i = 0; i < n; ++i) {
-      const int yi = px[i] / nx, xi = px[i] % nx;
-      L->bidx[L->boff[b] + i] = comp_of[px[i]];
-      for (int j = 0; j < n; ++j) {
-        const int yj = px[j] / nx, xj = px[j] % nx;
-        const int dy = ((yi - yj) % ny + ny) % ny, dx = ((xi - xj) % nx + nx) % nx;
-        A[(size_t)i * n + j] = kmap[(size_t)dy * nx + dx];
-      }
+  L->bpix.resize(L->boff[nb]);
+  for (int b = 0; b < nb; ++b)
+    for (size_t i = 0; i < blocks[b].size(); ++i) {
+      L->bpix[L->boff[b] + i] = blocks[b][i];
+      L->bidx[L->boff[b] + i] = comp_of[blocks[b][i]];
     }
-    if (!spd_inverse(A, n)) {
-      badb = b;
-      return;
-    }
-    const int ld = block_ld(n);
-    for (int j = 0; j < n; ++j)
-      std::copy(A.begin() + (size_t)j * n, A.begin() + (size_t)(j + 1) * n, L->binv.begin() + L->moff[b] + (size_t)j * ld);
-  });
-  if (badb >= 0) {
-    *err = "block preconditioner: a block of C^-1 is not positive definite";
-    return -1;
-  }
 
   // ---- block product work items and their output segments
   std::vector<size_t> segb(nb);  // seg offset of block b's first column chunk

@@ -16,7 +16,8 @@
 //               outside the runs; a piece of more than CMAX pixels, or whose
 //               grown block would exceed NBMAX, is cut by the TILE x TILE grid;
 //   blocks      each cell grown by HALO (Chebyshev, periodic) within the mask,
-//               with the dense inverse of C^-1 restricted to its pixels.
+//               with the dense inverse of C^-1 restricted to its pixels (the
+//               layout is built here, the inverses on the device).
 //
 // The applies of the band factors run as two sequential substitutions, one
 // wave per (run, kx): lanes 0..31 carry the real parts, 32..63 the imaginary
@@ -79,7 +80,8 @@ struct Layout {
   std::vector<int> items;
   size_t seg_total = 0;
   std::vector<size_t> moff;    // offsets of each block's inverse: n columns of stride block_ld(n)
-  std::vector<double> binv;
+  size_t inv_total = 0;        // values of all blocks' inverses
+  std::vector<int> bpix;       // pixel (flat index) of each block entry, as bidx
   // combine: contributions of block entries to compact elements (CSR), band flags
   std::vector<int> cst;        // n_m+1
   std::vector<int> cix;        // entries: positions in seg (one per column chunk of each covering block)
@@ -87,15 +89,14 @@ struct Layout {
   int max_run_pixels = 0;
 };
 
-// mask: ny*nx (1 = masked); kmap: ny*nx FP64 kernel of C^-1 (C^-1 v = k (*) v);
-// tsym: ny*(nx/2+1), tsym[d*(nx/2+1) + kx] = t_kx(d); pivot_min: the
-// threshold of the unshifted band truncation (PIVOT_MIN or PIVOT_MIN_F32);
-// f32: the factor is used in FP32 (chunks of the streams are shared when
-// their values rounded to FP32 are equal; FP64: when they are equal).
-// Returns 0, or -1 with *err set (a band factor or a block is not positive
-// definite, or a block is too large).
-int build_layout(int nx, int ny, const uint8_t* mask, const double* kmap, const double* tsym, double pivot_min,
-                 bool f32, Layout* out, std::string* err);
+// mask: ny*nx (1 = masked); tsym: ny*(nx/2+1), tsym[d*(nx/2+1) + kx] =
+// t_kx(d); pivot_min: the threshold of the unshifted band truncation
+// (PIVOT_MIN or PIVOT_MIN_F32); f32: the factor is used in FP32 (chunks of
+// the streams are shared when their values rounded to FP32 are equal; FP64:
+// when they are equal).  Returns 0, or -1 with *err set (a band factor is
+// not positive definite, or a block is too large).
+int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double pivot_min, bool f32, Layout* out,
+                 std::string* err);
 
 // The stored chunk of chunk c of a (run, kx) whose chunks s0 .. s0 + d share
 // chunk s0's storage.

@@ -16,6 +16,7 @@
 // Inner CG (Hestenes-Stiefel) with M^-1 = E E, E = Px C^{1/2} Px: the paper's
 // split form E A E u' = E v, u = E u', has the same iterates u.
 #include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -123,6 +124,7 @@ struct BlockDev {
 }  // namespace
 
 struct fill_plan_s {
+  rocblas_handle rocblas = nullptr;  // block inverses at set-up (created on first use)
   int nx = 0, ny = 0, ncol = 0, prec = 0, nprob = 1, npk = 1;
   int device = 0;  // the HIP device current at creation
   size_t npix = 0, nt = 0;
@@ -479,10 +481,117 @@ void block_free(fill_plan p) {
   p->blk = BlockDev();
 }
 
+// Dense inverses of a layout's blocks on the device: C^-1 on each block's
+// pixels assembled from the kernel map dk (device, FP64), factored and
+// inverted in FP64 by rocSOLVER (potrf, potri), stored in the plan's
+// precision with the layout's column strides.  The blocks go by size class
+// (n rounded up to a multiple of 32, padded with the identity, whose inverse
+// leaves the block's own unchanged), one strided batch per class.  *out
+// (allocated here, null if there are no blocks) holds L.inv_total values.
+constexpr size_t kInvBatchBytes = size_t(256) << 20;
+int block_inverses(fill_plan p, const fillb::Layout& L, const double* dk, void** out) {
+  *out = nullptr;
+  const int nb = (int)L.moff.size();
+  if (nb == 0) return FILL_OK;
+  const bool f32 = p->prec == FILL_PREC_FP32_OP;
+  const size_t ts = f32 ? sizeof(float) : sizeof(double);
+  std::map<int, std::vector<int>> cls;  // class size m -> its blocks
+  for (int b = 0; b < nb; ++b) {
+    const int n = L.boff[b + 1] - L.boff[b];
+    cls[(n + 31) / 32 * 32].push_back(b);
+  }
+  std::vector<int> list;
+  for (const auto& c : cls) list.insert(list.end(), c.second.begin(), c.second.end());
+  void* inv = nullptr;
+  int *dpx = nullptr, *dboff = nullptr, *dlist = nullptr, *dinfo = nullptr;
+  size_t* dmoff = nullptr;
+  double* dA = nullptr;
+  size_t a_cap = 0;
+  auto cleanup = [&](bool keep) {
+    for (void* q : {(void*)dpx, (void*)dboff, (void*)dlist, (void*)dinfo, (void*)dmoff, (void*)dA})
+      if (q) (void)hipFree(q);
+    if (!keep && inv) (void)hipFree(inv);
+  };
+  auto hip_fail = [&](hipError_t e) {
+    cleanup(false);
+    return fail(FILL_EHIP, std::string("block set-up: ") + hipGetErrorString(e));
+  };
+  if (hipMalloc(&inv, L.inv_total * ts) != hipSuccess || hipMalloc(&dpx, L.bpix.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&dboff, L.boff.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&dlist, list.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&dmoff, L.moff.size() * sizeof(size_t)) != hipSuccess ||
+      hipMalloc(&dinfo, 2 * (size_t)nb * sizeof(int)) != hipSuccess) {
+    cleanup(false);
+    return fail(FILL_ENOMEM, "block set-up: inverse workspace");
+  }
+  hipError_t e = hipMemsetAsync(inv, 0, L.inv_total * ts, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(dinfo, 0, 2 * (size_t)nb * sizeof(int), p->stream);
+  if (e == hipSuccess) e = hipMemcpy(dpx, L.bpix.data(), L.bpix.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dboff, L.boff.data(), L.boff.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dlist, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dmoff, L.moff.data(), L.moff.size() * sizeof(size_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e);
+  if ((p->rocblas == nullptr && rocblas_create_handle(&p->rocblas) != rocblas_status_success) ||
+      rocblas_set_stream(p->rocblas, p->stream) != rocblas_status_success) {
+    cleanup(false);
+    return fail(FILL_EHIP, "block set-up: rocBLAS handle");
+  }
+  rocblas_handle h = p->rocblas;
+  size_t off = 0;  // position of the current chunk in list
+  for (const auto& c : cls) {
+    const int m = c.first;
+    const size_t mm = (size_t)m * m;
+    const int per = (int)std::max<size_t>(1, std::min<size_t>(65535, kInvBatchBytes / (mm * sizeof(double))));
+    for (size_t c0 = 0; c0 < c.second.size(); c0 += per) {
+      const int cnt = (int)std::min<size_t>(per, c.second.size() - c0);
+      if ((size_t)cnt * mm > a_cap) {  // grow the batch of matrices (after the work that uses it)
+        if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e);
+        if (dA) (void)hipFree(dA);
+        dA = nullptr;
+        a_cap = (size_t)cnt * mm;
+        if (hipMalloc(&dA, a_cap * sizeof(double)) != hipSuccess) {
+          cleanup(false);
+          return fail(FILL_ENOMEM, "block set-up: inverse workspace");
+        }
+      }
+      int* info_f = dinfo + off;
+      int* info_i = dinfo + nb + off;
+      e = launch_block_assemble(dA, mm, dlist + off, cnt, dboff, dpx, m, dk, p->nx, p->ny, p->stream);
+      if (e != hipSuccess) return hip_fail(e);
+      if (rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, m, dA, m, (rocblas_stride)mm, info_f, cnt) !=
+              rocblas_status_success ||
+          rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, m, dA, m, (rocblas_stride)mm, info_i, cnt) !=
+              rocblas_status_success) {
+        cleanup(false);
+        return fail(FILL_EHIP, "block set-up: rocSOLVER");
+      }
+      e = f32 ? launch_block_store<float>(static_cast<float*>(inv), dmoff, dlist + off, cnt, dboff, dA, mm, m,
+                                          p->stream)
+              : launch_block_store<double>(static_cast<double*>(inv), dmoff, dlist + off, cnt, dboff, dA, mm, m,
+                                           p->stream);
+      if (e != hipSuccess) return hip_fail(e);
+      off += cnt;
+    }
+  }
+  std::vector<int> info(2 * (size_t)nb, 0);
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e);
+  if ((e = hipMemcpy(info.data(), dinfo, info.size() * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e);
+  for (int v : info)
+    if (v != 0) {
+      cleanup(false);
+      return fail(FILL_ENOTSPD, "block preconditioner: a block of C^-1 is not positive definite");
+    }
+  cleanup(true);
+  *out = inv;
+  return FILL_OK;
+}
+
 // Layout of problem b: kernel of C^-1 from a unit impulse (one FP64 apply with
-// problem b's table), its row transform for the band symbols, then the host
-// construction.
-int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
+// problem b's table), its row transform for the band symbols, the host
+// construction, then the dense inverses on the device (*inv, see
+// block_inverses).
+int block_layout_for(fill_plan p, int b, fillb::Layout* L, void** inv) {
   const int nx = p->nx, ny = p->ny, nc = p->ncol;
   const size_t npix = p->npix;
   const int tab = p->npk > 1 ? b : 0;
@@ -495,7 +604,7 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
       if (std::fabs(u - v) > 1e-12 * std::max(u, v))
         return fail(FILL_EINVAL, "block preconditioner: the spectrum must satisfy P(kx, ky) = P(kx, -ky)");
     }
-  std::vector<double> kmap(npix, 0.0), tsym;
+  std::vector<double> impulse(npix, 0.0), tsym;
   double* din = nullptr;
   double* dout = nullptr;
   std::vector<void*> tmp;
@@ -509,9 +618,9 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
     return fail(FILL_ENOMEM, "block set-up workspace");
   }
   tmp.push_back(dout);
-  kmap[0] = 1.0;
+  impulse[0] = 1.0;
   int rc = FILL_OK;
-  hipError_t e = hipMemcpy(din, kmap.data(), npix * sizeof(double), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(din, impulse.data(), npix * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     RowArgs<double> ai = row_base<double>(p, 1), ao = row_base<double>(p, 1);
     ai.full_in = din;
@@ -519,7 +628,6 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
     rc = apply3<double>(p, R2C_FULL, ai, p->Dinv64 + (size_t)tab * p->nt, C2R_FULL, ao, nullptr);
   }
   if (rc == FILL_OK && e == hipSuccess) e = hipStreamSynchronize(p->stream);
-  if (rc == FILL_OK && e == hipSuccess) e = hipMemcpy(kmap.data(), dout, npix * sizeof(double), hipMemcpyDeviceToHost);
   // band symbols t_kx(d): the row transform of the kernel (real: k is even in x)
   const int ncx = nx / 2;
   std::vector<double2> xt((size_t)ncx * ny);
@@ -530,9 +638,10 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e == hipSuccess) e = hipMemcpy(xt.data(), p->Xt, xt.size() * sizeof(double2), hipMemcpyDeviceToHost);
   }
-  release();
-  if (rc != FILL_OK) return rc;
-  if (e != hipSuccess) return fail(FILL_EHIP, std::string("block set-up: ") + hipGetErrorString(e));
+  if (rc != FILL_OK || e != hipSuccess) {
+    release();
+    return rc != FILL_OK ? rc : fail(FILL_EHIP, std::string("block set-up: ") + hipGetErrorString(e));
+  }
   tsym.assign((size_t)ny * nc, 0.0);
   for (int d = 0; d < ny; ++d) {
     tsym[(size_t)d * nc] = xt[d].x;        // DC: column 0, real part
@@ -541,10 +650,14 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L) {
   }
   std::string err;
   const double pivot_min = p->prec == FILL_PREC_FP32_OP ? fillb::PIVOT_MIN_F32 : fillb::PIVOT_MIN;
-  if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, kmap.data(), tsym.data(), pivot_min,
-                          p->prec == FILL_PREC_FP32_OP, L, &err) != 0)
+  if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, tsym.data(), pivot_min,
+                          p->prec == FILL_PREC_FP32_OP, L, &err) != 0) {
+    release();
     return fail(FILL_ENOTSPD, "problem " + std::to_string(b) + ": " + err);
-  return FILL_OK;
+  }
+  rc = block_inverses(p, *L, dout, inv);  // dout: the kernel map
+  release();
+  return rc;
 }
 
 // Build the block preconditioner for every problem of the plan (its mask,
@@ -559,36 +672,65 @@ int block_setup(fill_plan p) {
   fillb::Layout L;  // merged
   std::vector<int> run_prob, block_prob;
   L.boff.push_back(0);
-  // Problems with equal band factors or block inverses (identical masks and
-  // spectra, as in a Monte-Carlo batch) share one stored copy: the first
-  // problem's range of each distinct set, with its per-entry layout.
-  struct Seen {
-    size_t off, n;
-    std::vector<size_t> lay;
+  // Problems with identical masks and spectra (a Monte-Carlo batch) share
+  // one built copy of the factors and inverses: the first such problem's.
+  std::vector<fillb::Layout> kept;  // per built problem, without its factor values
+  kept.reserve(np);
+  struct Built {
+    int prob;
+    size_t fbase, mbase;
   };
-  std::vector<Seen> band_seen, binv_seen;
-  size_t binv_logical = 0;
+  std::vector<Built> built;
+  struct InvPart {
+    void* dev;
+    size_t n, off;
+  };
+  std::vector<InvPart> inv_parts;
+  auto free_parts = [&]() {
+    for (InvPart& q : inv_parts) (void)hipFree(q.dev);
+    inv_parts.clear();
+  };
+  struct PartsGuard {  // frees what an early return leaves
+    std::vector<InvPart>* v;
+    ~PartsGuard() {
+      for (InvPart& q : *v) (void)hipFree(q.dev);
+    }
+  } parts_guard{&inv_parts};
+  size_t inv_total = 0, binv_logical = 0;
   struct ItemRange {
     size_t first, n, key;  // the problem's work items and the offset of the inverses they read
   };
   std::vector<ItemRange> item_range;
+  auto same_problem = [&](int a, int b) {
+    if (std::memcmp(p->hmask.data() + (size_t)a * p->npix, p->hmask.data() + (size_t)b * p->npix, p->npix) != 0)
+      return false;
+    if (p->npk <= 1) return true;
+    return std::memcmp(p->hpk.data() + (size_t)a * p->nt, p->hpk.data() + (size_t)b * p->nt,
+                       p->nt * sizeof(double)) == 0;
+  };
   for (int b = 0; b < np; ++b) {
-    fillb::Layout Lb;
-    FILL_TRY(block_layout_for(p, b, &Lb));
-    const int co = p->coff[b];
-    size_t fbase = L.fwd.size();
-    bool fshared = false;
-    std::vector<size_t> flay(Lb.kx_dup.begin(), Lb.kx_dup.end());
-    for (const Seen& q : band_seen)
-      if (q.n == Lb.fwd.size() && q.lay == flay && std::equal(Lb.fwd.begin(), Lb.fwd.end(), L.fwd.begin() + q.off)) {
-        fbase = q.off;
-        fshared = true;
-        break;
+    int same = -1;
+    for (size_t q = 0; q < built.size() && same < 0; ++q)
+      if (same_problem(built[q].prob, b)) same = (int)q;
+    if (same < 0) {
+      fillb::Layout Lb;
+      void* inv = nullptr;
+      const int rc = block_layout_for(p, b, &Lb, &inv);
+      if (rc != FILL_OK) {
+        free_parts();
+        return rc;
       }
-    if (!fshared && !Lb.fwd.empty()) {
-      band_seen.push_back({L.fwd.size(), Lb.fwd.size(), std::move(flay)});
+      if (inv != nullptr) inv_parts.push_back({inv, Lb.inv_total, inv_total});
+      built.push_back({b, L.fwd.size(), inv_total});
+      inv_total += Lb.inv_total;
       L.fwd.insert(L.fwd.end(), Lb.fwd.begin(), Lb.fwd.end());
+      std::vector<double>().swap(Lb.fwd);
+      kept.push_back(std::move(Lb));
+      same = (int)built.size() - 1;
     }
+    const fillb::Layout& Lb = kept[same];
+    const size_t fbase = built[same].fbase, mbase = built[same].mbase;
+    const int co = p->coff[b];
     const int kbase = (int)L.kx_off.size();
     for (size_t o : Lb.kx_off) L.kx_off.push_back(o + fbase);
     L.kx_dup.insert(L.kx_dup.end(), Lb.kx_dup.begin(), Lb.kx_dup.end());
@@ -606,14 +748,6 @@ int block_setup(fill_plan p) {
     L.bt_total += Lb.bt_total;
     L.max_run_pixels = std::max(L.max_run_pixels, Lb.max_run_pixels);
     const int nbase = (int)L.bidx.size();
-    size_t mbase = L.binv.size();
-    bool mshared = false;
-    for (const Seen& q : binv_seen)
-      if (q.n == Lb.binv.size() && q.lay == Lb.moff && std::equal(Lb.binv.begin(), Lb.binv.end(), L.binv.begin() + q.off)) {
-        mbase = q.off;
-        mshared = true;
-        break;
-      }
     const int bbase = (int)L.boff.size() - 1;
     const size_t sbase = L.seg_total;
     for (size_t q = 1; q < Lb.boff.size(); ++q) {
@@ -629,13 +763,12 @@ int block_setup(fill_plan p) {
       L.items.push_back((int)(Lb.items[q + 3] + sbase));
     }
     L.seg_total += Lb.seg_total;
-    if (L.seg_total > (size_t)INT32_MAX) return fail(FILL_EINVAL, "block preconditioner: too many block outputs");
-    for (int c : Lb.bidx) L.bidx.push_back(c + co);
-    binv_logical += Lb.binv.size();
-    if (!mshared && !Lb.binv.empty()) {
-      binv_seen.push_back({L.binv.size(), Lb.binv.size(), Lb.moff});
-      L.binv.insert(L.binv.end(), Lb.binv.begin(), Lb.binv.end());
+    if (L.seg_total > (size_t)INT32_MAX) {
+      free_parts();
+      return fail(FILL_EINVAL, "block preconditioner: too many block outputs");
     }
+    for (int c : Lb.bidx) L.bidx.push_back(c + co);
+    binv_logical += Lb.inv_total;
     const int ebase = L.cst.empty() ? 0 : L.cst.back();
     if (L.cst.empty()) L.cst.push_back(0);
     for (int c = 1; c <= Lb.n_m; ++c) L.cst.push_back(Lb.cst[c] + ebase);
@@ -717,12 +850,24 @@ int block_setup(fill_plan p) {
     FILL_TRY(balloc(p, &seg_raw, std::max<size_t>(L.seg_total, 1) * ts));
     B.seg = seg_raw;
   }
-  if (f32) {
-    FILL_TRY(bupload_as<float>(p, &B.fwd, L.fwd));
-    FILL_TRY(bupload_as<float>(p, &B.binv, L.binv));
-  } else {
-    FILL_TRY(bupload_as<double>(p, &B.fwd, L.fwd));
-    FILL_TRY(bupload_as<double>(p, &B.binv, L.binv));
+  if (f32) FILL_TRY(bupload_as<float>(p, &B.fwd, L.fwd));
+  else FILL_TRY(bupload_as<double>(p, &B.fwd, L.fwd));
+  {
+    // the built problems' inverses, end to end
+    uint8_t* binv_raw = nullptr;
+    const int rc = balloc(p, &binv_raw, std::max<size_t>(inv_total, 1) * ts);
+    if (rc != FILL_OK) {
+      free_parts();
+      return rc;
+    }
+    B.binv = binv_raw;
+    hipError_t e = hipSuccess;
+    for (const InvPart& q : inv_parts)
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(binv_raw + q.off * ts, q.dev, q.n * ts, hipMemcpyDeviceToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    free_parts();
+    if (e != hipSuccess) return fail(FILL_EHIP, std::string("block set-up: ") + hipGetErrorString(e));
   }
   B.info.runs = (int)L.runs.size();
   B.info.blocks = B.nblocks;
@@ -731,7 +876,7 @@ int block_setup(fill_plan p) {
   B.info.block_entries = (int64_t)binv_logical;
   B.info.band_stream_values = (int64_t)L.stream_values;
   B.info.elem_bytes = (int)ts;
-  B.info.bytes = (int64_t)((L.fwd.size() + L.binv.size() + L.bidx.size() + 2 * L.bt_total) * ts +
+  B.info.bytes = (int64_t)((L.fwd.size() + inv_total + L.bidx.size() + 2 * L.bt_total) * ts +
                            (L.brow_off.size() + bpos.size() + L.boff.size() + L.bidx.size() + L.cst.size() +
                             L.cix.size() + L.kx_dup.size()) * sizeof(int) +
                            L.kx_off.size() * sizeof(size_t) + L.inb.size());
@@ -2267,6 +2412,7 @@ void fill_plan_destroy(fill_plan p) {
   if (p->h_sum) (void)hipHostFree(p->h_sum);
   if (p->h_st) (void)hipHostFree(p->h_st);
   if (p->par_host) (void)hipHostFree(p->par_host);
+  if (p->rocblas) (void)rocblas_destroy_handle(p->rocblas);
   delete p;
 }
 

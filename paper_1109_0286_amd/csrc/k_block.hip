@@ -450,7 +450,63 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(CombArgs<T> a) {
   }
 }
 
+// Blocks of one size class m (blist: the class's blocks), each C^-1
+// restricted to its n <= m pixels and padded with the identity to m x m,
+// column-major, the class's matrices stride apart:
+// A(i, j) = k(y_i - y_j, x_i - x_j) for i, j < n, k the periodic kernel of C^-1.
+__global__ __launch_bounds__(256) void block_assemble_kernel(double* A, size_t stride, const int* blist,
+                                                             const int* boff, const int* px, int m,
+                                                             const double* kmap, int nx, int ny) {
+  const int q = blockIdx.z, j = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  const int b = blist[q], o = boff[b], n = boff[b + 1] - o;
+  double v = (i == j) ? 1.0 : 0.0;
+  if (i < n && j < n) {
+    const int pi = px[o + i], pj = px[o + j];
+    const int dy = ((pi / nx - pj / nx) % ny + ny) % ny, dx = ((pi % nx - pj % nx) % nx + nx) % nx;
+    v = kmap[(size_t)dy * nx + dx];
+  }
+  A[(size_t)q * stride + (size_t)j * m + i] = v;
+}
+
+// The inverses held in the lower triangles of a class's matrices into dst:
+// block b's column j at dst + moff[b] + j ld, ld = 4 ceil(n / 4) (rows 0..n-1),
+// in the plan's precision.
+template <typename T>
+__global__ __launch_bounds__(256) void block_store_kernel(T* dst, const size_t* moff, const int* blist,
+                                                          const int* boff, const double* A, size_t stride, int m) {
+  const int q = blockIdx.z, j = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int b = blist[q], n = boff[b + 1] - boff[b];
+  if (i >= n || j >= n) return;
+  const double* Aq = A + (size_t)q * stride;
+  dst[moff[b] + (size_t)j * ((n + 3) / 4 * 4) + i] = (T)(i >= j ? Aq[(size_t)j * m + i] : Aq[(size_t)i * m + j]);
+}
+
 }  // namespace
+
+hipError_t launch_block_assemble(double* A, size_t stride, const int* blist, int count, const int* boff,
+                                 const int* px, int m, const double* kmap, int nx, int ny, hipStream_t s) {
+  if (count <= 0 || m <= 0) return hipSuccess;
+  if (count > 65535 || stride < (size_t)m * m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(block_assemble_kernel, dim3((m + 255) / 256, m, count), dim3(256), 0, s, A, stride, blist,
+                     boff, px, m, kmap, nx, ny);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_block_store(T* dst, const size_t* moff, const int* blist, int count, const int* boff,
+                              const double* A, size_t stride, int m, hipStream_t s) {
+  if (count <= 0 || m <= 0) return hipSuccess;
+  if (count > 65535 || stride < (size_t)m * m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(block_store_kernel<T>, dim3((m + 255) / 256, m, count), dim3(256), 0, s, dst, moff, blist, boff,
+                     A, stride, m);
+  return hipGetLastError();
+}
+template hipError_t launch_block_store<float>(float*, const size_t*, const int*, int, const int*, const double*,
+                                              size_t, int, hipStream_t);
+template hipError_t launch_block_store<double>(double*, const size_t*, const int*, int, const int*, const double*,
+                                               size_t, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_band_solve(const BandArgs<T>& a, int nruns, int max_hp, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

@@ -45,6 +45,17 @@ hipError_t launch_band_block(const BandArgs<T>& ba, const BlockArgs<T>& bk, int 
 template <typename T>
 hipError_t launch_combine(const CombArgs<T>& a, int nblk, int nprob, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
+// Set-up of the dense block inverses, one size class m at a time (blist:
+// count blocks with at most m pixels; boff, px: the blocks' pixel lists):
+// A holds count column-major m x m matrices stride apart, C^-1 on each
+// block's pixels from the kernel map kmap (FP64) padded with the identity;
+// the inverses from their lower triangles into dst at moff[b] (column
+// stride 4 ceil(n / 4)) in the plan's precision.
+hipError_t launch_block_assemble(double* A, size_t stride, const int* blist, int count, const int* boff,
+                                 const int* px, int m, const double* kmap, int nx, int ny, hipStream_t s);
+template <typename T>
+hipError_t launch_block_store(T* dst, const size_t* moff, const int* blist, int count, const int* boff,
+                              const double* A, size_t stride, int m, hipStream_t s);
 
 // Per-problem elementwise helpers over compact vectors (problem b: comp_off[b]..comp_off[b+1]).
 hipError_t launch_scale_to_f32(float* out, const double* in, const double* scale, const int* comp_off, int nmax,
