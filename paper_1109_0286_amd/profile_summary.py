@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 BENCH_ARGS = {
-    2048: ("--steps 5 --warmup 1 --no-cpu-baseline --batch 0 --no-extra",
+    2048: ("--steps 5 --warmup 1 --no-cpu-baseline --batch 0 --no-extra --no-compare",
            "--steps 1 --warmup 0 --no-cpu-baseline --batch 0 --no-extra --no-compare"),
     4096: ("--workload grid4096 --steps 2 --warmup 1", "--workload grid4096 --steps 1 --warmup 0"),
 }
