@@ -174,8 +174,7 @@ int fill_plan_set_inner_tol(fill_plan plan, double tol);
  * the same solution to rtol.  The fastest is FILL_PRECOND_BLOCK (9 CG
  * iterations at 2048^2 with a 10% band and 200 holes, against 312 - 378 with
  * the split form): it is not the default because it is not the paper's and
- * its set-up costs host time and memory (see below); select it for
- * throughput.
+ * its set-up costs time and memory (see below); select it for throughput.
  *   FILL_PRECOND_SPLIT  M^-1 = E E, E = Px C^{1/2} Px: equivalent to the split
  *                       system E A E u' = E v of Sec. 2.4 (two applies of E
  *                       per iteration, fused into five passes).
@@ -197,12 +196,17 @@ int fill_plan_set_inner_tol(fill_plan plan, double tol);
  *                       pieces over 1024 pixels are cut into 16 x 16 cells),
  *                       grown by 8 pixels into the mask, is solved exactly by a
  *                       dense inverse (at most 2048 pixels).  Selecting it
- *                       builds these on the host from the kernel of C^-1 (one
- *                       GPU apply), in the plan's precision; the time and
- *                       memory grow with the band height times nx and with
- *                       the sum of squared piece sizes.  It is rebuilt by
- *                       fill_plan_set_pk / fill_plan_set_bands.  Batched
- *                       plans build one per problem.  Spectra must satisfy
+ *                       builds these from the kernel of C^-1 (one GPU
+ *                       apply), in the plan's precision: the layout and the
+ *                       banded factors on the host (chunks of a factor that
+ *                       repeat, where its rows reach their Toeplitz limit,
+ *                       are stored once), the dense inverses on the device
+ *                       (rocSOLVER, FP64); the time and memory grow with the
+ *                       band height times nx and with the sum of squared
+ *                       piece sizes.  It is rebuilt by fill_plan_set_pk /
+ *                       fill_plan_set_bands.  Batched plans build one per
+ *                       problem, once for problems with identical masks and
+ *                       spectra (which then share it).  Spectra must satisfy
  *                       P(kx, ky) = P(kx, -ky), else FILL_EINVAL
  *                       (FILL_ENOTSPD if a factor is not positive definite).
  *                       Used with the standard CG recurrence.

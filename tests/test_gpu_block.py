@@ -14,6 +14,9 @@
 * graph replays are bitwise equal to direct launches; a new spectrum rebuilds
   it; a fully masked grid returns the unconstrained draw;
 * a batched plan (own masks and spectra per problem) matches the oracle;
+* a batched plan of identical problems (one shared set of factors and
+  inverses) gives each problem exactly what a plan of its own gives, holds
+  the set once, and one differing problem in it gets its own;
 * errors: spectra not symmetric in ky, FILL_OP_MINV without it.
 
 FP32 bar for M^-1: the band factors and block inverses are rounded to FP32
@@ -260,6 +263,40 @@ def test_batch_matches_oracle(F, prec, tol):
     st = bp.stats()
     assert all(s["status"] == 0 for s in st)
     assert max(s["iters_inner"] for s in st) < 60
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_identical_problems_share(F, prec):
+    # problems 0, 1, 3 identical (mask and spectrum), problem 2 with its own
+    # mask: the shared set must serve 0, 1, 3 exactly as their own plans do
+    n = 256
+    P = W.damped_power_law(n, n, 3.0, n / 8, 1e-7)
+    m0 = W.band_holes_mask(n, n, W.band_rows(n, 0.15), 14, 2.0, 8.0, 120)
+    m2 = W.band_holes_mask(n, n, W.band_rows(n, 0.08), 9, 2.0, 8.0, 121)
+    masks = np.stack([m0, m0, m2, m0])
+    ds = [W.observed_map(P, n, n, 130 + i, masks[i]) for i in range(4)]
+    seeds = [11, 12, 13, 14]
+    rtol = 1e-12 if prec == 0 else 1e-10
+    bp = F.BatchPlan(n, n, masks, P, prec=prec)
+    bp.set_precond(F.FILL_PRECOND_BLOCK)
+    xb = host(bp.realize(dev(np.stack(ds)), seeds, rtol))
+    ib = bp.block_info()
+    st = bp.stats()
+    bp.close()
+    infos = []
+    for i in range(4):
+        pl = F.Plan(n, n, masks[i], P, prec)
+        pl.set_precond(F.FILL_PRECOND_BLOCK)
+        xi = host(pl.realize(dev(ds[i]), seeds[i], rtol))
+        infos.append(pl.block_info())
+        sti = pl.stats()
+        pl.close()
+        assert st[i]["iters_inner"] == sti["iters_inner"], i
+        assert np.array_equal(xb[i], xi), (i, float(np.max(np.abs(xb[i] - xi))))
+    # logical sizes add up over the problems; the stored set counts once
+    assert ib["block_entries"] == sum(v["block_entries"] for v in infos)
+    assert ib["band_stream_values"] == sum(v["band_stream_values"] for v in infos)
+    assert ib["bytes"] < infos[0]["bytes"] * 2 + infos[2]["bytes"]
 
 
 def test_errors(F):
