@@ -555,6 +555,14 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
   C v[E];
 
   constexpr bool CG1 = MODE == R2C_CG1UPDATE;
+  // Band runs (a.runs): rows past a run's end (its padding to a multiple of
+  // 32) get an exact zero spectrum.  The two-rows-per-line transform leaves
+  // there the rounding residue of the partner row's separation, which the
+  // banded solve would carry into M^-1 r.
+  __shared__ unsigned char s_empty[ROWS];
+  if constexpr (r2c_is_compact<MODE>()) {
+    if (a.runs != nullptr && t < ROWS) s_empty[t] = a.row_off[y0 + t + 1] == a.row_off[y0 + t];
+  }
   // first batch of loads: the row offsets, the state, the partials
   int c0 = 0, c1 = 0;
   if constexpr (r2c_is_compact<MODE>()) {
@@ -744,6 +752,9 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
       const C zm = ln[lpad<PL>(N - kx)];
       if (r & 1) out = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
       else out = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    }
+    if constexpr (r2c_is_compact<MODE>()) {
+      if (a.runs != nullptr && s_empty[r]) out = C{T(0), T(0)};
     }
     a.Xt[(size_t)kx * ldx + y0 + r] = out;
   }
