@@ -38,6 +38,23 @@ __device__ __forceinline__ double half_lane(double v, bool) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Lane U of the caller's half in FP32 as mr lo + mi hi, with the lane's
+// constants (mr, mi) = (1, 0) in lanes 0..31 and (0, 1) in lanes 32..63: the
+// same value as the select (one factor is exactly 0, the other exactly 1),
+// but the two lane reads feed a multiply and an FMA that each take one of
+// them as a scalar operand, where a select (its mask on the scalar bus too)
+// needs both copied to vector registers first.
+template <int U>
+__device__ __forceinline__ float half_mix(float v, float mr, float mi) {
+  const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), U));
+  const float up = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + U));
+  return __builtin_fmaf(mi, up, mr * lo);
+}
+template <int U>
+__device__ __forceinline__ double half_mix(double v, double, double) {
+  return half_lane<U>(v, false);
+}
+
 // Calls fn(std::integral_constant<int, U>) for U = B .. E-1 in order.
 template <int B, int E, typename Fn>
 __device__ __forceinline__ void static_for(Fn&& fn) {
@@ -127,21 +144,30 @@ __device__ __forceinline__ void band_solve_column(const BandArgs<T>& a, int run,
   // element i at the steps i where k is the head).  The element that enters
   // lane k's slot during a chunk (c0 + 32 + k) is read from LDS at the
   // chunk's start.  The set loaded for chunk c held chunk c - 2.
+  // FP32 steps read the next head from the FMA result (up): the head lane of
+  // step u + 1 is not the head of step u, so its up is its new w_, and the
+  // lane read does not wait for the select.
+  const T mr = half ? T(0) : T(1), mi = half ? T(1) : T(0);
   auto fwd_chunk = [&](const T (&f)[32], T (&fn)[32], int c0) {
     if (c0 + 32 < hp) {
       const int c = (c0 >> 5) + 1;
       if (!(c - 2 >= s0 && c <= s0 + dd)) load32(fn, F + 32 * stored_chunk(c, s0, dd));
     }
     const T nxt = (c0 + 32 < hp) ? s[c0 + 32 + k] : T(0);
-    T zo = w_, dg = T(1);  // this lane's finished element of the chunk (c0 + k) and its D^-2
+    // D^-2 of this lane's element c0 + k: its own stream's entry k of the chunk
+    const T dg = F[32 * stored_chunk(c0 >> 5, s0, dd) + k];
+    T zo = w_;  // this lane's finished element of the chunk (c0 + k)
+    T src = w_;
     static_for<0, 32>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
-      const T z = half_lane<u>(w_, half);
+      T z;
+      if constexpr (sizeof(T) == 4) z = half_mix<u>(src, mr, mi);
+      else z = half_lane<u>(w_, half);
       const bool head = k == u;
       const T up = w_ - f[u] * z;
       zo = head ? w_ : zo;
-      dg = head ? f[u] : dg;
       w_ = head ? nxt : up;
+      src = up;
     });
     s[c0 + k] = zo * dg;
   };
@@ -188,13 +214,17 @@ __device__ __forceinline__ void band_solve_column(const BandArgs<T>& a, int run,
     }
     const T nxt = (c0 + 64 <= hp) ? s[hp - 64 - c0 + k] : T(0);
     T xo = w_;  // this lane's finished element of the chunk (hp - 32 - c0 + k)
+    T src = w_;
     static_for<0, 32>([&](auto uc) {
       constexpr int u = decltype(uc)::value, hl = 31 - u;  // head lane of step i = hp - 1 - (c0 + u)
-      const T x = half_lane<hl>(w_, half);
+      T x;
+      if constexpr (sizeof(T) == 4) x = half_mix<hl>(src, mr, mi);
+      else x = half_lane<hl>(w_, half);
       const bool head = k == hl;
       const T up = w_ - f[u] * x;
       xo = head ? w_ : xo;
       w_ = head ? nxt : up;
+      src = up;
     });
     s[hp - 32 - c0 + k] = xo;
   };
