@@ -82,6 +82,7 @@ typedef struct {
   int elem_bytes;         /* 4 (FP32-operator plan) or 8 (FP64 plan) */
   int64_t band_stream_values; /* sum over runs of the values of their banded factors as stored
                                  (repeating chunks of the factor rows stored once) */
+  int halo_min, halo_max;     /* the halos of the problems' blocks (fill_plan_set_block_halo) */
 } fill_block_info;
 
 /* Recurrences of the inner CG (fill_plan_set_cg). */
@@ -231,6 +232,24 @@ int fill_plan_set_precond(fill_plan plan, int mode);
  * recurrence.  Returns FILL_EINVAL for an unknown variant.
  */
 int fill_plan_set_cg(fill_plan plan, int variant);
+
+/*
+ * Halo of the block preconditioner's pieces: each piece of the mask outside
+ * the band runs (or each TILE x TILE cell of a large piece) is grown by
+ * `halo` pixels (Chebyshev, periodic) within the mask before its dense block
+ * is inverted, so that neighbouring pieces and the band overlap (additive
+ * Schwarz).  A wider halo couples them over more rows (fewer CG iterations)
+ * for more dense entries per apply.
+ *   halo in [0, 14]         that halo for every problem;
+ *   FILL_BLOCK_HALO_AUTO    (default) per problem the largest of 14, 12 and 10
+ *                           whose blocks hold at most nx*ny/2 more inverse
+ *                           entries than with halo 8, else 8.
+ * A built block preconditioner is rebuilt.  FILL_EINVAL for other values.
+ * Callers: tuning of the block preconditioner (Sec. 2.4 leaves the
+ * preconditioner open; this one is this library's).
+ */
+#define FILL_BLOCK_HALO_AUTO (-1)
+int fill_plan_set_block_halo(fill_plan plan, int halo);
 
 /*
  * Size of the plan's block preconditioner (its runs, blocks and memory), for

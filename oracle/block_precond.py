@@ -40,9 +40,14 @@ FP32 factors, whose rounding the truncation's conditioning amplifies):
    grown block (step 4) would hold more than NBMAX pixels, is cut into cells by
    the absolute TILE x TILE grid, otherwise it is one cell.
 4. Each cell grows into a block: every masked pixel (band rows included)
-   within Chebyshev distance HALO (periodic) of the cell.  The block's part of
-   M^-1 r is A_b^-1 r_b, A_b = A restricted to the block's pixels.
+   within Chebyshev distance h (periodic) of the cell, h the halo (HALO = 8
+   unless given).  The block's part of M^-1 r is A_b^-1 r_b, A_b = A
+   restricted to the block's pixels.
 5. M^-1 r = sum of the band parts and the block parts (overlaps add).
+6. The library's default halo (auto_halo): the largest of 14, 12, 10 whose
+   blocks (steps 3-4 with that h) hold at most floor(ny nx / 2) more inverse
+   entries than those of h = 8, counting n * 4 ceil(n / 4) entries for a
+   block of n pixels; else 8.
 
 Each part is symmetric positive definite on its pixels and every masked pixel
 is covered, so M^-1 is SPD.
@@ -55,7 +60,7 @@ import scipy.fft as sfft
 import scipy.ndimage as ndi
 
 __all__ = ["BW", "HALO", "TILE", "CMAX", "NBMAX", "PIVOT_MIN", "PIVOT_MIN_F32", "safely_pd", "kernel_cinv", "band_runs", "band_symbols", "cells", "blocks",
-           "BlockPrecond", "pcg_block"]
+           "block_entries", "auto_halo", "BlockPrecond", "pcg_block"]
 
 BW, HALO, TILE, CMAX, NBMAX = 32, 8, 16, 1024, 2048
 PIVOT_MIN = 1e-9
@@ -122,14 +127,14 @@ def _components(sel: np.ndarray) -> list:
     return [np.array(c) for _, c in sorted(comps.items())]
 
 
-def cells(mask: np.ndarray, runs: list) -> list:
+def cells(mask: np.ndarray, runs: list, halo: int = HALO) -> list:
     """Cells (arrays of (y, x)) of the masked pixels outside the band runs."""
     sel = mask != 0
     for y0, h in runs:
         sel[y0:y0 + h] = False
     out = []
     for c in _components(sel):
-        if len(c) <= CMAX and len(blocks(mask, [c])[0]) <= NBMAX:
+        if len(c) <= CMAX and len(blocks(mask, [c], halo)[0]) <= NBMAX:
             out.append(c)
             continue
         key = (c[:, 0] // TILE) * (mask.shape[1] // TILE + 1) + c[:, 1] // TILE
@@ -138,20 +143,35 @@ def cells(mask: np.ndarray, runs: list) -> list:
     return out
 
 
-def blocks(mask: np.ndarray, cell_list: list) -> list:
-    """Each cell grown by HALO (Chebyshev, periodic) within the mask: sorted
-    flat pixel indices."""
+def blocks(mask: np.ndarray, cell_list: list, halo: int = HALO) -> list:
+    """Each cell grown by the halo (Chebyshev, periodic) within the mask:
+    sorted flat pixel indices."""
     ny, nx = mask.shape
     m = mask != 0
     out = []
     for c in cell_list:
         grown = np.zeros_like(m)
-        for dy in range(-HALO, HALO + 1):
-            for dx in range(-HALO, HALO + 1):
+        for dy in range(-halo, halo + 1):
+            for dx in range(-halo, halo + 1):
                 grown[(c[:, 0] + dy) % ny, (c[:, 1] + dx) % nx] = True
         ys, xs = np.nonzero(grown & m)
         out.append(np.sort(ys * nx + xs))
     return out
+
+
+def block_entries(block_list: list) -> int:
+    """Inverse entries of the blocks: n * 4 ceil(n / 4) for n pixels."""
+    return sum(len(b) * (-(-len(b) // 4) * 4) for b in block_list)
+
+
+def auto_halo(mask: np.ndarray) -> int:
+    """The default halo of step 6."""
+    runs = band_runs(mask)
+    base = block_entries(blocks(mask, cells(mask, runs, HALO), HALO))
+    for h in (14, 12, 10):
+        if block_entries(blocks(mask, cells(mask, runs, h), h)) <= base + mask.size // 2:
+            return h
+    return HALO
 
 
 def safely_pd(T: np.ndarray, pivot_min: float = PIVOT_MIN) -> bool:
@@ -166,10 +186,13 @@ def safely_pd(T: np.ndarray, pivot_min: float = PIVOT_MIN) -> bool:
 
 class BlockPrecond:
     """M^-1 of the definition above for one mask and spectrum (FP64
-    arithmetic; pivot_min selects the threshold of the FP64 or FP32 plans)."""
+    arithmetic; pivot_min selects the threshold of the FP64 or FP32 plans;
+    halo: the blocks' h, or "auto" for step 6's choice)."""
 
-    def __init__(self, mask: np.ndarray, P: np.ndarray, bw: int = BW, pivot_min: float = PIVOT_MIN):
+    def __init__(self, mask: np.ndarray, P: np.ndarray, bw: int = BW, pivot_min: float = PIVOT_MIN,
+                 halo=HALO):
         self.mask = mask
+        self.halo = auto_halo(mask) if halo == "auto" else int(halo)
         ny, nx = mask.shape
         self.shape = (ny, nx)
         k = kernel_cinv(P)
@@ -184,8 +207,8 @@ class BlockPrecond:
                 if not safely_pd(Ts[kx], pivot_min):
                     Ts[kx] += 2.0 * np.abs(t[bw:h, kx]).sum() * np.eye(h)
             self.band_T.append(Ts)
-        self.cells = cells(mask, self.runs)
-        self.blocks = blocks(mask, self.cells)
+        self.cells = cells(mask, self.runs, self.halo)
+        self.blocks = blocks(mask, self.cells, self.halo)
         self.block_A = []
         for b in self.blocks:
             y, x = b // nx, b % nx

@@ -26,8 +26,12 @@ template <typename F> void parallel_for(int n, F&& f) {
 
 }  // namespace
 
-int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double pivot_min, bool f32, Layout* L,
-                 std::string* err) {
+int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double pivot_min, bool f32, int halo,
+                 Layout* L, std::string* err) {
+  if (halo != HALO_AUTO && (halo < 0 || halo > HALO_MAX)) {
+    *err = "block preconditioner: halo out of range";
+    return -1;
+  }
   L->nx = nx;
   L->ny = ny;
   const size_t npix = (size_t)nx * ny;
@@ -180,81 +184,107 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double
     }
   }
 
-  // ---- cells: pieces of the masked pixels outside the runs
+  // ---- cells: pieces of the masked pixels outside the runs, grown by h
   auto other = [&](size_t q) { return mask[q] && !in_run[q / nx]; };
-  std::vector<int> piece(npix, -1);
-  std::vector<std::vector<int>> cells;  // flat pixel indices
   std::vector<int> stamp(npix, -1);
   int stamp_id = 0;
-  auto grow = [&](const std::vector<int>& cell, std::vector<int>* out) {
-    const int id = stamp_id++;
-    out->clear();
-    for (int q : cell) {
-      const int y = q / nx, x = q % nx;
-      for (int dy = -HALO; dy <= HALO; ++dy)
-        for (int dx = -HALO; dx <= HALO; ++dx) {
-          const int yy = ((y + dy) % ny + ny) % ny, xx = ((x + dx) % nx + nx) % nx;
-          const int qq = yy * nx + xx;
-          if (mask[qq] && stamp[qq] != id) {
-            stamp[qq] = id;
-            out->push_back(qq);
+  auto make_blocks = [&](int h, std::vector<std::vector<int>>* blocks) -> bool {
+    blocks->clear();
+    std::vector<int> piece(npix, -1);
+    auto grow = [&](const std::vector<int>& cell, std::vector<int>* out) {
+      const int id = stamp_id++;
+      out->clear();
+      for (int q : cell) {
+        const int y = q / nx, x = q % nx;
+        for (int dy = -h; dy <= h; ++dy)
+          for (int dx = -h; dx <= h; ++dx) {
+            const int yy = ((y + dy) % ny + ny) % ny, xx = ((x + dx) % nx + nx) % nx;
+            const int qq = yy * nx + xx;
+            if (mask[qq] && stamp[qq] != id) {
+              stamp[qq] = id;
+              out->push_back(qq);
+            }
           }
+      }
+      std::sort(out->begin(), out->end());
+    };
+    std::vector<int> grown;
+    int npieces = 0;
+    for (size_t q0 = 0; q0 < npix; ++q0) {
+      if (!other(q0) || piece[q0] >= 0) continue;
+      std::vector<int> comp, stack{(int)q0};
+      piece[q0] = npieces;
+      while (!stack.empty()) {
+        const int q = stack.back();
+        stack.pop_back();
+        comp.push_back(q);
+        const int y = q / nx, x = q % nx;
+        const int nb[4] = {((y + 1) % ny) * nx + x, ((y + ny - 1) % ny) * nx + x, y * nx + (x + 1) % nx,
+                           y * nx + (x + nx - 1) % nx};
+        for (int qq : nb)
+          if (other(qq) && piece[qq] < 0) {
+            piece[qq] = npieces;
+            stack.push_back(qq);
+          }
+      }
+      ++npieces;
+      bool whole = (int)comp.size() <= CMAX;
+      if (whole) {
+        grow(comp, &grown);
+        whole = (int)grown.size() <= NBMAX;
+      }
+      if (whole) {
+        blocks->push_back(grown);
+        continue;
+      }
+      // cut along the absolute TILE grid
+      std::sort(comp.begin(), comp.end(), [&](int a, int b) {
+        const long ka = (long)(a / nx / TILE) * (nx / TILE + 1) + (a % nx) / TILE;
+        const long kb = (long)(b / nx / TILE) * (nx / TILE + 1) + (b % nx) / TILE;
+        return ka != kb ? ka < kb : a < b;
+      });
+      size_t s = 0;
+      while (s < comp.size()) {
+        const long key = (long)(comp[s] / nx / TILE) * (nx / TILE + 1) + (comp[s] % nx) / TILE;
+        size_t e = s;
+        std::vector<int> cell;
+        while (e < comp.size() &&
+               (long)(comp[e] / nx / TILE) * (nx / TILE + 1) + (comp[e] % nx) / TILE == key)
+          cell.push_back(comp[e++]);
+        grow(cell, &grown);
+        if ((int)grown.size() > NBMAX) {
+          *err = "block preconditioner: a grown cell exceeds the block size limit";
+          return false;
         }
+        blocks->push_back(grown);
+        s = e;
+      }
     }
-    std::sort(out->begin(), out->end());
+    return true;
+  };
+  auto entries = [](const std::vector<std::vector<int>>& b) {
+    size_t e = 0;
+    for (const auto& v : b) e += v.size() * (size_t)block_ld((int)v.size());
+    return e;
   };
   std::vector<std::vector<int>> blocks;
-  std::vector<int> grown;
-  int npieces = 0;
-  for (size_t q0 = 0; q0 < npix; ++q0) {
-    if (!other(q0) || piece[q0] >= 0) continue;
-    std::vector<int> comp, stack{(int)q0};
-    piece[q0] = npieces;
-    while (!stack.empty()) {
-      const int q = stack.back();
-      stack.pop_back();
-      comp.push_back(q);
-      const int y = q / nx, x = q % nx;
-      const int nb[4] = {((y + 1) % ny) * nx + x, ((y + ny - 1) % ny) * nx + x, y * nx + (x + 1) % nx,
-                         y * nx + (x + nx - 1) % nx};
-      for (int qq : nb)
-        if (other(qq) && piece[qq] < 0) {
-          piece[qq] = npieces;
-          stack.push_back(qq);
-        }
-    }
-    ++npieces;
-    bool whole = (int)comp.size() <= CMAX;
-    if (whole) {
-      grow(comp, &grown);
-      whole = (int)grown.size() <= NBMAX;
-    }
-    if (whole) {
-      blocks.push_back(grown);
-      continue;
-    }
-    // cut along the absolute TILE grid
-    std::sort(comp.begin(), comp.end(), [&](int a, int b) {
-      const long ka = (long)(a / nx / TILE) * (nx / TILE + 1) + (a % nx) / TILE;
-      const long kb = (long)(b / nx / TILE) * (nx / TILE + 1) + (b % nx) / TILE;
-      return ka != kb ? ka < kb : a < b;
-    });
-    size_t s = 0;
-    while (s < comp.size()) {
-      const long key = (long)(comp[s] / nx / TILE) * (nx / TILE + 1) + (comp[s] % nx) / TILE;
-      size_t e = s;
-      std::vector<int> cell;
-      while (e < comp.size() &&
-             (long)(comp[e] / nx / TILE) * (nx / TILE + 1) + (comp[e] % nx) / TILE == key)
-        cell.push_back(comp[e++]);
-      grow(cell, &grown);
-      if ((int)grown.size() > NBMAX) {
-        *err = "block preconditioner: a grown cell exceeds the block size limit";
-        return -1;
+  if (halo == HALO_AUTO) {
+    // the widest candidate whose extra inverse entries stay within npix / 2
+    if (!make_blocks(HALO, &blocks)) return -1;
+    const size_t e0 = entries(blocks);
+    L->halo = HALO;
+    std::vector<std::vector<int>> cand;
+    for (int h : {HALO_MAX, 12, 10}) {
+      if (!make_blocks(h, &cand)) return -1;
+      if (entries(cand) <= e0 + npix / 2) {
+        blocks.swap(cand);
+        L->halo = h;
+        break;
       }
-      blocks.push_back(grown);
-      s = e;
     }
+  } else {
+    if (!make_blocks(halo, &blocks)) return -1;
+    L->halo = halo;
   }
 
   // ---- block layout (the dense inverses are computed on the device)

@@ -15,9 +15,15 @@
 //   cells       connected pieces (4-neighbours, periodic) of the masked pixels
 //               outside the runs; a piece of more than CMAX pixels, or whose
 //               grown block would exceed NBMAX, is cut by the TILE x TILE grid;
-//   blocks      each cell grown by HALO (Chebyshev, periodic) within the mask,
-//               with the dense inverse of C^-1 restricted to its pixels (the
-//               layout is built here, the inverses on the device).
+//   blocks      each cell grown by a halo h (Chebyshev, periodic) within the
+//               mask, with the dense inverse of C^-1 restricted to its pixels
+//               (the layout is built here, the inverses on the device); h is
+//               given, or chosen (auto_halo): the largest of 14, 12, 10 whose
+//               blocks hold at most npix / 2 more inverse entries than those
+//               of h = HALO, else HALO.  A wider halo couples the pieces to
+//               the band and to each other over more rows (fewer CG
+//               iterations); the cap keeps the extra product work per
+//               iteration at about half an entry per pixel.
 //
 // The applies of the band factors run as two sequential substitutions, one
 // wave per (run, kx): lanes 0..31 carry the real parts, 32..63 the imaginary
@@ -35,10 +41,13 @@
 namespace fillb {
 
 constexpr int BW = 32;       // band bandwidth (one window lane per coupled row)
-constexpr int HALO = 8;      // Chebyshev growth of each cell into the mask
+constexpr int HALO = 8;      // Chebyshev growth of each cell into the mask (the reference choice)
+constexpr int HALO_MAX = 14; // widest halo: a grown TILE x TILE cell always fits a block
+constexpr int HALO_AUTO = -1;
 constexpr int TILE = 16;     // cell grid for large pieces
 constexpr int CMAX = 1024;   // largest piece kept whole
 constexpr int NBMAX = 2048;  // largest block (dense inverse)
+static_assert((TILE + 2 * HALO_MAX) * (TILE + 2 * HALO_MAX) <= NBMAX, "a grown cell must fit a block");
 // band truncation kept unshifted if every Cholesky pivot exceeds this times
 // its diagonal: FP64 factors, and FP32 factors (whose rounding, relative 2^-24,
 // is amplified by up to the truncation's condition number, which the pivot
@@ -87,6 +96,7 @@ struct Layout {
   std::vector<int> cix;        // entries: positions in seg (one per column chunk of each covering block)
   std::vector<uint8_t> inb;    // 1 if the element lies in a band run
   int max_run_pixels = 0;
+  int halo = HALO;             // the blocks' halo
 };
 
 // mask: ny*nx (1 = masked); tsym: ny*(nx/2+1), tsym[d*(nx/2+1) + kx] =
@@ -94,9 +104,10 @@ struct Layout {
 // (PIVOT_MIN or PIVOT_MIN_F32); f32: the factor is used in FP32 (chunks of
 // the streams are shared when their values rounded to FP32 are equal; FP64:
 // when they are equal).  Returns 0, or -1 with *err set (a band factor is
-// not positive definite, or a block is too large).
-int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double pivot_min, bool f32, Layout* out,
-                 std::string* err);
+// not positive definite, or a block is too large).  halo: 0 .. HALO_MAX, or
+// HALO_AUTO (the rule above).
+int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double pivot_min, bool f32, int halo,
+                 Layout* out, std::string* err);
 
 // The stored chunk of chunk c of a (run, kx) whose chunks s0 .. s0 + d share
 // chunk s0's storage.

@@ -125,6 +125,7 @@ struct BlockDev {
 
 struct fill_plan_s {
   rocblas_handle rocblas = nullptr;  // block inverses at set-up (created on first use)
+  int block_halo = fillb::HALO_AUTO;  // halo of the block preconditioner's pieces (or the automatic choice)
   int nx = 0, ny = 0, ncol = 0, prec = 0, nprob = 1, npk = 1;
   int device = 0;  // the HIP device current at creation
   size_t npix = 0, nt = 0;
@@ -651,7 +652,7 @@ int block_layout_for(fill_plan p, int b, fillb::Layout* L, void** inv) {
   std::string err;
   const double pivot_min = p->prec == FILL_PREC_FP32_OP ? fillb::PIVOT_MIN_F32 : fillb::PIVOT_MIN;
   if (fillb::build_layout(nx, ny, p->hmask.data() + (size_t)b * npix, tsym.data(), pivot_min,
-                          p->prec == FILL_PREC_FP32_OP, L, &err) != 0) {
+                          p->prec == FILL_PREC_FP32_OP, p->block_halo, L, &err) != 0) {
     release();
     return fail(FILL_ENOTSPD, "problem " + std::to_string(b) + ": " + err);
   }
@@ -875,6 +876,11 @@ int block_setup(fill_plan p) {
   B.info.block_pixels = (int64_t)L.bidx.size();
   B.info.block_entries = (int64_t)binv_logical;
   B.info.band_stream_values = (int64_t)L.stream_values;
+  B.info.halo_min = B.info.halo_max = kept.empty() ? fillb::HALO : kept[0].halo;
+  for (const fillb::Layout& k : kept) {
+    B.info.halo_min = std::min(B.info.halo_min, k.halo);
+    B.info.halo_max = std::max(B.info.halo_max, k.halo);
+  }
   B.info.elem_bytes = (int)ts;
   B.info.bytes = (int64_t)((L.fwd.size() + inv_total + L.bidx.size() + 2 * L.bt_total) * ts +
                            (L.brow_off.size() + bpos.size() + L.boff.size() + L.bidx.size() + L.cst.size() +
@@ -2327,6 +2333,17 @@ int fill_plan_set_precond(fill_plan p, int mode) {
   if (mode == FILL_PRECOND_BLOCK && !p->blk.built) FILL_TRY(block_setup(p));
   p->precond = mode;
   return FILL_OK;
+}
+
+int fill_plan_set_block_halo(fill_plan p, int halo) {
+  g_last_error.clear();
+  if (!p) return fail(FILL_EINVAL, "NULL plan");
+  if (halo != FILL_BLOCK_HALO_AUTO && (halo < 0 || halo > fillb::HALO_MAX))
+    return fail(FILL_EINVAL, "halo must be FILL_BLOCK_HALO_AUTO or in [0, 14]");
+  static_assert(FILL_BLOCK_HALO_AUTO == fillb::HALO_AUTO && fillb::HALO_MAX == 14, "halo range of the header");
+  if (halo == p->block_halo) return FILL_OK;
+  p->block_halo = halo;
+  return block_follow_pk(p);  // rebuilds a built block preconditioner
 }
 
 int fill_get_block_info(fill_plan p, fill_block_info* out) {

@@ -50,13 +50,14 @@ EXPORTS = (
     "fill_strips_mean", "fill_strips_mask", "fill_strips_plan", "fill_strips_last_error", "fill_strips_destroy",
     "fill_strips_refine", "fill_laplace", "fill_plan_set_cg", "fill_get_block_info",
     "fill_realize_unconstrained_noalloc", "fill_group_create", "fill_group_realize", "fill_group_last_graph",
-    "fill_group_destroy", "fill_plan_set_warm_start",
+    "fill_group_destroy", "fill_plan_set_warm_start", "fill_plan_set_block_halo",
 )
 
 FILL_PRECOND_NONE = 0
 FILL_PRECOND_SPLIT = 1
 FILL_PRECOND_CXX = 2
 FILL_PRECOND_BLOCK = 3
+FILL_BLOCK_HALO_AUTO = -1
 
 FILL_CG_STANDARD = 0
 FILL_CG_SINGLE_REDUCTION = 1
@@ -80,7 +81,7 @@ class fill_stats(C.Structure):
 class BlockInfo(C.Structure):
     _fields_ = [("runs", C.c_int), ("blocks", C.c_int), ("band_rows", C.c_int64), ("block_pixels", C.c_int64),
                 ("block_entries", C.c_int64), ("bytes", C.c_int64), ("elem_bytes", C.c_int),
-                ("band_stream_values", C.c_int64)]
+                ("band_stream_values", C.c_int64), ("halo_min", C.c_int), ("halo_max", C.c_int)]
 
 
 class FillError(RuntimeError):
@@ -114,6 +115,7 @@ def _load() -> C.CDLL:
         "fill_plan_set_max_iter": (i32, [vp, i32]),
         "fill_plan_set_inner_tol": (i32, [vp, dbl]),
         "fill_plan_set_precond": (i32, [vp, i32]),
+        "fill_plan_set_block_halo": (i32, [vp, i32]),
         "fill_plan_set_cg": (i32, [vp, i32]),
         "fill_get_block_info": (i32, [vp, C.POINTER(BlockInfo)]),
         "fill_plan_set_graph": (i32, [vp, i32]),
@@ -327,10 +329,15 @@ def fill_plan_set_precond(plan, mode):
     return _check(_lib.fill_plan_set_precond(plan, int(mode)), "fill_plan_set_precond")
 
 
+def fill_plan_set_block_halo(plan, halo):
+    """halo: 0..14, or FILL_BLOCK_HALO_AUTO (the default choice per problem)."""
+    return _check(_lib.fill_plan_set_block_halo(plan, int(halo)), "fill_plan_set_block_halo")
+
+
 def fill_get_block_info(plan) -> dict:
     """Runs, blocks, padded band rows, block pixels, inverse entries, bytes,
-    element size and stored band factor values of the plan's block
-    preconditioner."""
+    element size, stored band factor values and the blocks' halos of the
+    plan's block preconditioner."""
     out = BlockInfo()
     _check(_lib.fill_get_block_info(plan, C.byref(out)), "fill_get_block_info")
     return {f: getattr(out, f) for f, _ in BlockInfo._fields_}
@@ -497,6 +504,10 @@ class Plan:
     def set_cg(self, variant):
         """Inner-CG recurrence: FILL_CG_STANDARD (default) or FILL_CG_SINGLE_REDUCTION."""
         fill_plan_set_cg(self.handle, variant)
+
+    def set_block_halo(self, halo):
+        """Halo of the block preconditioner's pieces: 0..14 or FILL_BLOCK_HALO_AUTO (default)."""
+        fill_plan_set_block_halo(self.handle, halo)
 
     def block_info(self) -> dict:
         """Size of the block preconditioner (FILL_PRECOND_BLOCK must be selected)."""
@@ -674,6 +685,10 @@ class BatchPlan:
     def set_cg(self, variant):
         """Inner-CG recurrence: FILL_CG_STANDARD (default) or FILL_CG_SINGLE_REDUCTION."""
         fill_plan_set_cg(self.handle, variant)
+
+    def set_block_halo(self, halo):
+        """Halo of the block preconditioner's pieces: 0..14 or FILL_BLOCK_HALO_AUTO (default)."""
+        fill_plan_set_block_halo(self.handle, halo)
 
     def block_info(self) -> dict:
         """Size of the block preconditioner (FILL_PRECOND_BLOCK must be selected)."""

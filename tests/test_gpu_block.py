@@ -107,19 +107,42 @@ def plan_block(F, mask, P, prec):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-3)])
 def test_minv_matches_oracle(F, name, prec, tol):
     mask, P = case(name)
-    M = B.BlockPrecond(mask, P, pivot_min=B.PIVOT_MIN if prec == 0 else B.PIVOT_MIN_F32)
+    M = B.BlockPrecond(mask, P, pivot_min=B.PIVOT_MIN if prec == 0 else B.PIVOT_MIN_F32, halo="auto")
     if name == "two":
         assert M.runs == [(20, 40), (150, 20)]
     rng = np.random.default_rng(11)
     r = np.where(mask != 0, rng.standard_normal(mask.shape), 0.0)
     ref = M.apply(r)
     plan = plan_block(F, mask, P, prec)
+    info = plan.block_info()
+    # the library's default halo is the oracle's choice (step 6 of its definition)
+    assert info["halo_min"] == info["halo_max"] == M.halo
+    assert info["blocks"] == len(M.blocks) and info["block_entries"] == B.block_entries(M.blocks)
     got = host(plan.apply(F.FILL_OP_MINV, dev(r)))
     m = mask != 0
     err = rel(got, ref, m)
     print(f"M^-1 {name} prec {prec}: rel err {err:.2e}")
     assert err < tol
     assert np.all(got[~m] == 0.0)
+
+
+@pytest.mark.parametrize("halo", [0, 8, 12, 14])
+def test_minv_fixed_halo_matches_oracle(F, halo):
+    mask, P = case("mix")
+    M = B.BlockPrecond(mask, P, halo=halo)
+    r = np.where(mask != 0, np.random.default_rng(12).standard_normal(mask.shape), 0.0)
+    plan = plan_block(F, mask, P, 0)
+    plan.set_block_halo(halo)  # rebuilds the built preconditioner
+    info = plan.block_info()
+    assert info["halo_min"] == info["halo_max"] == halo and info["blocks"] == len(M.blocks)
+    assert info["block_entries"] == B.block_entries(M.blocks)
+    err = rel(host(plan.apply(F.FILL_OP_MINV, dev(r))), M.apply(r), mask != 0)
+    print(f"M^-1 halo {halo}: rel err {err:.2e}")
+    assert err < 1e-9
+    for bad in (-2, 15):
+        with pytest.raises(F.FillError):
+            plan.set_block_halo(bad)
+    assert plan.block_info() == info
 
 
 @pytest.mark.parametrize("nx,ny,seed", [(256, 256, 71), (768, 512, 72), (1024, 128, 73), (384, 1536, 74)])
@@ -220,7 +243,7 @@ def test_new_spectrum_rebuilds(F):
     ref = OF.fill_realize(d, mask, P2, 3, 1e-13)
     assert rel(x, ref.x_out, mask != 0) < 1e-9
     got = host(plan.apply(F.FILL_OP_MINV, dev(np.where(mask != 0, 1.0, 0.0))))
-    want = B.BlockPrecond(mask, P2).apply(np.where(mask != 0, 1.0, 0.0))
+    want = B.BlockPrecond(mask, P2, halo="auto").apply(np.where(mask != 0, 1.0, 0.0))
     assert rel(got, want, mask != 0) < 1e-9
 
 

@@ -87,13 +87,13 @@ def test_grid2048_matches_oracle_pixelwise(F, grid2048, prec, rtol, tol):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-3)])
 def test_grid2048_minv_matches_oracle(F, grid2048, prec, tol):
     p, _ = grid2048
-    M = B.BlockPrecond(p.mask, p.P, pivot_min=B.PIVOT_MIN if prec == 0 else B.PIVOT_MIN_F32)
-    assert M.runs == [(921, 205)]
+    M = B.BlockPrecond(p.mask, p.P, pivot_min=B.PIVOT_MIN if prec == 0 else B.PIVOT_MIN_F32, halo="auto")
+    assert M.runs == [(921, 205)] and M.halo == 14
     r = np.where(p.mask != 0, np.random.default_rng(5).standard_normal(p.mask.shape), 0.0)
     want = M.apply(r)
     plan = block_plan(F, p, prec)
     info = plan.block_info()
-    assert info["band_rows"] == 224 and info["blocks"] == len(M.blocks)
+    assert info["band_rows"] == 224 and info["blocks"] == len(M.blocks) and info["halo_min"] == info["halo_max"] == 14
     got = host(plan.apply(F.FILL_OP_MINV, dev(r)))
     m = p.mask != 0
     err = rel(got, want, m)

@@ -240,6 +240,38 @@ def test_structure_rules():
     assert ys.min() == 60 - B.HALO and ys.max() == 62
 
 
+def test_halo_rule_counts_by_hand():
+    """Step 6 of the definition on masks whose block sizes follow by hand."""
+    # isolated holes: their pieces do not grow (the halo only takes masked
+    # pixels), so every halo costs the same and the widest is chosen
+    mask = np.zeros((64, 64), np.uint8)
+    mask[10:13, 10:13] = 1
+    mask[40:42, 30:35] = 1
+    assert B.block_entries(B.blocks(mask, B.cells(mask, []), 14)) == 9 * 12 + 10 * 12
+    assert B.auto_halo(mask) == 14
+    # a 3 x 3 hole right under a 20-row band: its block takes the band
+    # pixels within Chebyshev distance h, (3 + 2h) columns by h rows
+    mask = np.zeros((128, 64), np.uint8)
+    mask[40:60] = 1
+    mask[60:63, 20:23] = 1
+    runs = B.band_runs(mask)
+    assert runs == [(40, 20)]
+    for h in (8, 10, 12, 14):
+        (blk,) = B.blocks(mask, B.cells(mask, runs, h), h)
+        n = 9 + (3 + 2 * h) * h
+        assert len(blk) == n
+    entries = {h: n * (-(-n // 4) * 4) for h, n in ((h, 9 + (3 + 2 * h) * h) for h in (8, 10, 12, 14))}
+    # 128 * 64 / 2 = 4096 entries of slack: h = 10 adds 239*240 - 161*164 = 30956
+    assert all(entries[h] - entries[8] > 4096 for h in (10, 12, 14))
+    assert B.auto_halo(mask) == 8
+    # with a wider grid the same growth fits the slack: 1024 x 256 / 2 = 131072
+    big = np.zeros((1024, 256), np.uint8)
+    big[40:60] = 1
+    big[60:63, 20:23] = 1
+    assert entries[12] - entries[8] <= 131072 < entries[14] - entries[8]
+    assert B.auto_halo(big) == 12
+
+
 def test_pcg_block_reaches_dense_solution():
     p = W.make_problem("grid64")
     s = OF.unconstrained_realization(p.P, p.seed)
