@@ -241,9 +241,9 @@ int fill_plan_set_cg(fill_plan plan, int variant);
  * Schwarz).  A wider halo couples them over more rows (fewer CG iterations)
  * for more dense entries per apply.
  *   halo in [0, 14]         that halo for every problem;
- *   FILL_BLOCK_HALO_AUTO    (default) per problem the largest of 14, 12 and 10
- *                           whose blocks hold at most nx*ny/2 more inverse
- *                           entries than with halo 8, else 8.
+ *   FILL_BLOCK_HALO_AUTO    (default) per problem from 8 up by 2 (to 14) while
+ *                           the blocks hold at most nx*ny/2 more inverse
+ *                           entries than with halo 8.
  * A built block preconditioner is rebuilt.  FILL_EINVAL for other values.
  * Callers: tuning of the block preconditioner (Sec. 2.4 leaves the
  * preconditioner open; this one is this library's).

@@ -44,10 +44,10 @@ FP32 factors, whose rounding the truncation's conditioning amplifies):
    unless given).  The block's part of M^-1 r is A_b^-1 r_b, A_b = A
    restricted to the block's pixels.
 5. M^-1 r = sum of the band parts and the block parts (overlaps add).
-6. The library's default halo (auto_halo): the largest of 14, 12, 10 whose
-   blocks (steps 3-4 with that h) hold at most floor(ny nx / 2) more inverse
-   entries than those of h = 8, counting n * 4 ceil(n / 4) entries for a
-   block of n pixels; else 8.
+6. The library's default halo (auto_halo): h = 8, then 10, 12, 14 in turn
+   for as long as the blocks (steps 3-4 with that h) hold at most
+   floor(ny nx / 2) more inverse entries than those of h = 8, counting
+   n * 4 ceil(n / 4) entries for a block of n pixels.
 
 Each part is symmetric positive definite on its pixels and every masked pixel
 is covered, so M^-1 is SPD.
@@ -168,10 +168,12 @@ def auto_halo(mask: np.ndarray) -> int:
     """The default halo of step 6."""
     runs = band_runs(mask)
     base = block_entries(blocks(mask, cells(mask, runs, HALO), HALO))
-    for h in (14, 12, 10):
-        if block_entries(blocks(mask, cells(mask, runs, h), h)) <= base + mask.size // 2:
-            return h
-    return HALO
+    best = HALO
+    for h in (10, 12, 14):
+        if block_entries(blocks(mask, cells(mask, runs, h), h)) > base + mask.size // 2:
+            break
+        best = h
+    return best
 
 
 def safely_pd(T: np.ndarray, pivot_min: float = PIVOT_MIN) -> bool:

@@ -186,16 +186,32 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double
 
   // ---- cells: pieces of the masked pixels outside the runs, grown by h
   auto other = [&](size_t q) { return mask[q] && !in_run[q / nx]; };
-  std::vector<int> stamp(npix, -1);
+  std::vector<int> stamp(npix, -1), incell(npix, -1);
   int stamp_id = 0;
   auto make_blocks = [&](int h, std::vector<std::vector<int>>* blocks) -> bool {
     blocks->clear();
     std::vector<int> piece(npix, -1);
+    // The cell and every masked pixel within distance h of it.  A pixel
+    // within h of the cell is within h of one of the cell's edge pixels
+    // (those with a neighbour, diagonals included, outside the cell) or in
+    // the cell itself: a shortest king's path from the cell pixel leaves the
+    // cell through an edge pixel, which is closer.  So only the edge pixels'
+    // squares are visited.
     auto grow = [&](const std::vector<int>& cell, std::vector<int>* out) {
       const int id = stamp_id++;
       out->clear();
+      for (int q : cell) incell[q] = id;
+      for (int q : cell) {
+        stamp[q] = id;
+        out->push_back(q);
+      }
       for (int q : cell) {
         const int y = q / nx, x = q % nx;
+        bool edge = false;
+        for (int dy = -1; dy <= 1 && !edge; ++dy)
+          for (int dx = -1; dx <= 1 && !edge; ++dx)
+            edge = incell[(size_t)((y + dy + ny) % ny) * nx + (x + dx + nx) % nx] != id;
+        if (!edge) continue;
         for (int dy = -h; dy <= h; ++dy)
           for (int dx = -h; dx <= h; ++dx) {
             const int yy = ((y + dy) % ny + ny) % ny, xx = ((x + dx) % nx + nx) % nx;
@@ -269,18 +285,17 @@ int build_layout(int nx, int ny, const uint8_t* mask, const double* tsym, double
   };
   std::vector<std::vector<int>> blocks;
   if (halo == HALO_AUTO) {
-    // the widest candidate whose extra inverse entries stay within npix / 2
+    // widen from HALO by 2 while the inverse entries stay within npix / 2
+    // of those at HALO
     if (!make_blocks(HALO, &blocks)) return -1;
     const size_t e0 = entries(blocks);
     L->halo = HALO;
     std::vector<std::vector<int>> cand;
-    for (int h : {HALO_MAX, 12, 10}) {
+    for (int h = HALO + 2; h <= HALO_MAX; h += 2) {
       if (!make_blocks(h, &cand)) return -1;
-      if (entries(cand) <= e0 + npix / 2) {
-        blocks.swap(cand);
-        L->halo = h;
-        break;
-      }
+      if (entries(cand) > e0 + npix / 2) break;
+      blocks.swap(cand);
+      L->halo = h;
     }
   } else {
     if (!make_blocks(halo, &blocks)) return -1;

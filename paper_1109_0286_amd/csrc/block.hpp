@@ -18,9 +18,9 @@
 //   blocks      each cell grown by a halo h (Chebyshev, periodic) within the
 //               mask, with the dense inverse of C^-1 restricted to its pixels
 //               (the layout is built here, the inverses on the device); h is
-//               given, or chosen (auto_halo): the largest of 14, 12, 10 whose
-//               blocks hold at most npix / 2 more inverse entries than those
-//               of h = HALO, else HALO.  A wider halo couples the pieces to
+//               given, or chosen: from h = HALO up by 2 (to HALO_MAX) while
+//               the blocks hold at most npix / 2 more inverse entries than
+//               those of h = HALO.  A wider halo couples the pieces to
 //               the band and to each other over more rows (fewer CG
 //               iterations); the cap keeps the extra product work per
 //               iteration at about half an entry per pixel.
