@@ -126,6 +126,11 @@ struct BlockDev {
 struct fill_plan_s {
   rocblas_handle rocblas = nullptr;  // block inverses at set-up (created on first use)
   int block_halo = fillb::HALO_AUTO;  // halo of the block preconditioner's pieces (or the automatic choice)
+  struct {
+    const double* part;  // the last iteration's r.r partials (or null)
+    int nb;              // partial slots per problem
+    bool first;          // the solve's first inner solve
+  } after{nullptr, 0, false};  // an inner solve's accounting, launched with the update of u
   int nx = 0, ny = 0, ncol = 0, prec = 0, nprob = 1, npk = 1;
   int device = 0;  // the HIP device current at creation
   size_t npix = 0, nt = 0;
@@ -1158,7 +1163,7 @@ int inner_pcg_cg1(fill_plan p, bool record, int fixed) {
     std::vector<int> iters, status;
     FILL_TRY(run_chunks(p, kChunk, kChunk, chunk, exec, nullptr, nb, iters, status));
   }
-  HIP_TRY(launch_ctl_after(refine_args(p), nullptr, nb, (size_t)p->ny, record, p->stream));
+  p->after = {nullptr, nb, record};  // accounted for with the caller's update of u
   return FILL_OK;
 }
 
@@ -1282,7 +1287,7 @@ int inner_pcg(fill_plan p, bool record, int fixed) {
     for (int b = 0; b < np; ++b) mx = std::max(mx, iters[b]);
     p->pred_iters[sizeof(T) == 4][std::min(p->cur_outer, 3)] = mx;
   }
-  HIP_TRY(launch_ctl_after(refine_args(p), p->part1, nb, (size_t)p->ny, record, p->stream));
+  p->after = {p->part1, nb, record};  // accounted for with the caller's update of u
   return FILL_OK;
 }
 
@@ -1301,12 +1306,14 @@ int refine_step(fill_plan p, bool first, int fixed, bool warm = false) {
     HIP_TRY(launch_scale_init_f64(p->v64.r, from_v ? p->b : p->res, p->dp.scale, p->comp_off, p->v64.x, p->v64.p,
                                   from_v ? p->u : nullptr, p->n_m_max, np, p->stream));
     FILL_TRY(inner_pcg<double>(p, first, fixed));
-    HIP_TRY(launch_axpy_f64(p->u, p->v64.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
+    HIP_TRY(launch_axpy_after_f64(p->u, p->v64.x, p->comp_off, refine_args(p), p->after.part, p->after.nb,
+                                  (size_t)p->ny, p->after.first, p->n_m_max, p->stream));
   } else {
     HIP_TRY(launch_scale_init_f32(p->v32.r, from_v ? p->b : p->res, p->dp.scale, p->comp_off, p->v32.x, p->v32.p,
                                   from_v ? p->u : nullptr, p->n_m_max, np, p->stream));
     FILL_TRY(inner_pcg<float>(p, first, fixed));
-    HIP_TRY(launch_axpy_f32(p->u, p->v32.x, p->dp.unscale, p->comp_off, p->n_m_max, np, p->stream));
+    HIP_TRY(launch_axpy_after_f32(p->u, p->v32.x, p->comp_off, refine_args(p), p->after.part, p->after.nb,
+                                  (size_t)p->ny, p->after.first, p->n_m_max, p->stream));
   }
   RowArgs<double> ai = row_base<double>(p, np), ao = row_base<double>(p, np);
   ai.v0 = p->u;

@@ -182,9 +182,9 @@ __device__ __forceinline__ bool rr_met(const CGScalars& c, const double* rr_part
   return rr <= c.tol2;  // valid in thread 0
 }
 
-__global__ __launch_bounds__(RT) void k_ctl_after(RefineArgs a, const double* rr_part, int nb, size_t stride,
-                                                  int first) {
-  const int b = blockIdx.x;
+// The accounting of problem b's inner solve (a workgroup of RT threads).
+__device__ __forceinline__ void ctl_after_one(const RefineArgs& a, const double* rr_part, int nb, size_t stride,
+                                              int first, int b) {
   if (!a.active[b]) return;  // no inner solve ran for this problem
   const CGScalars& c = a.sc[b];
   const bool check = !c.done && rr_part;
@@ -207,6 +207,30 @@ __global__ __launch_bounds__(RT) void k_ctl_after(RefineArgs a, const double* rr
     s.done = 1;
     s.status = -6;
   }
+}
+
+__global__ __launch_bounds__(RT) void k_ctl_after(RefineArgs a, const double* rr_part, int nb, size_t stride,
+                                                  int first) {
+  ctl_after_one(a, rr_part, nb, stride, first, blockIdx.x);
+}
+
+// u += unscale x (the inner solution into the FP64 solution) with the inner
+// solve's accounting in the same launch: the last workgroup of each grid row
+// takes problem blockIdx.y's accounting, the others the update (the two
+// touch different data: u and the refinement state).
+template <typename TX>
+__global__ __launch_bounds__(RT) void k_axpy_after(double* y, const TX* x, const int* comp_off, RefineArgs a,
+                                                   const double* rr_part, int nb, size_t stride, int first) {
+  const int b = blockIdx.y;
+  const int nw = gridDim.x - 1;
+  if ((int)blockIdx.x == nw) {
+    ctl_after_one(a, rr_part, nb, stride, first, b);
+    return;
+  }
+  const int c0 = comp_off[b], c1 = comp_off[b + 1];
+  const double s = a.unscale[b];
+  if (s == 0.0) return;
+  for (int c = c0 + blockIdx.x * RT + threadIdx.x; c < c1; c += nw * RT) y[c] += s * (double)x[c];
 }
 
 __global__ __launch_bounds__(RT) void k_rr_check(CGScalars* sc, const double* rr_part, int nb, size_t stride) {
@@ -289,6 +313,22 @@ hipError_t launch_ctl_after(const RefineArgs& a, const double* rr_part, int nb, 
                             hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_after, dim3(a.nprob), dim3(RT), 0, s, a, rr_part, nb, stride, first ? 1 : 0);
   return hipGetLastError();
+}
+template <typename TX>
+hipError_t launch_axpy_after_t(double* u, const TX* x, const int* comp_off, const RefineArgs& a,
+                               const double* rr_part, int nb, size_t stride, bool first, int nmax, hipStream_t s) {
+  const dim3 g = grid_for(nmax, a.nprob);
+  hipLaunchKernelGGL((k_axpy_after<TX>), dim3(g.x + 1, g.y), dim3(RT), 0, s, u, x, comp_off, a, rr_part, nb, stride,
+                     first ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_axpy_after_f32(double* u, const float* x, const int* comp_off, const RefineArgs& a,
+                                 const double* rr_part, int nb, size_t stride, bool first, int nmax, hipStream_t s) {
+  return launch_axpy_after_t<float>(u, x, comp_off, a, rr_part, nb, stride, first, nmax, s);
+}
+hipError_t launch_axpy_after_f64(double* u, const double* x, const int* comp_off, const RefineArgs& a,
+                                 const double* rr_part, int nb, size_t stride, bool first, int nmax, hipStream_t s) {
+  return launch_axpy_after_t<double>(u, x, comp_off, a, rr_part, nb, stride, first, nmax, s);
 }
 hipError_t launch_rr_check(CGScalars* sc, const double* rr_part, int nb, size_t stride, int nprob, hipStream_t s) {
   hipLaunchKernelGGL(k_rr_check, dim3(nprob), dim3(RT), 0, s, sc, rr_part, nb, stride);

@@ -86,6 +86,12 @@ hipError_t launch_ctl(const RefineArgs& a, const double* part, size_t stride, in
 // null) meet its tolerance counts as converged.
 hipError_t launch_ctl_after(const RefineArgs& a, const double* rr_part, int nb, size_t stride, bool first,
                             hipStream_t s);
+// u += unscale x over every problem's range together with launch_ctl_after's
+// accounting (one launch).
+hipError_t launch_axpy_after_f32(double* u, const float* x, const int* comp_off, const RefineArgs& a,
+                                 const double* rr_part, int nb, size_t stride, bool first, int nmax, hipStream_t s);
+hipError_t launch_axpy_after_f64(double* u, const double* x, const int* comp_off, const RefineArgs& a,
+                                 const double* rr_part, int nb, size_t stride, bool first, int nmax, hipStream_t s);
 // Between inner-CG chunks: stop every problem whose last r.r partials meet
 // its tolerance (the same test, in the same summation order, as above).
 hipError_t launch_rr_check(CGScalars* sc, const double* rr_part, int nb, size_t stride, int nprob, hipStream_t s);
