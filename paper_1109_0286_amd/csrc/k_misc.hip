@@ -55,16 +55,6 @@ __global__ void k_scale_init(TO* out, const double* in, const double* scale, con
   }
 }
 
-template <typename TX>
-__global__ void k_axpy(double* y, const TX* x, const double* a, const int* comp_off) {
-  const int b = blockIdx.y;
-  const int c0 = comp_off[b], c1 = comp_off[b + 1];
-  const double s = a[b];
-  if (s == 0.0) return;
-  for (int c = c0 + blockIdx.x * blockDim.x + threadIdx.x; c < c1; c += gridDim.x * blockDim.x)
-    y[c] += s * (double)x[c];
-}
-
 __global__ void k_scatter_add(double* const* full, const double* c, const int* pos, const int* comp_off,
                               const SolveState* gate, int nprob) {
   if (gate)
@@ -209,11 +199,6 @@ __device__ __forceinline__ void ctl_after_one(const RefineArgs& a, const double*
   }
 }
 
-__global__ __launch_bounds__(RT) void k_ctl_after(RefineArgs a, const double* rr_part, int nb, size_t stride,
-                                                  int first) {
-  ctl_after_one(a, rr_part, nb, stride, first, blockIdx.x);
-}
-
 // u += unscale x (the inner solution into the FP64 solution) with the inner
 // solve's accounting in the same launch: the last workgroup of each grid row
 // takes problem blockIdx.y's accounting, the others the update (the two
@@ -290,16 +275,6 @@ hipError_t launch_scale_init_f64(double* out, const double* in, const double* sc
                      zu);
   return hipGetLastError();
 }
-hipError_t launch_axpy_f64(double* y, const double* x, const double* a, const int* comp_off, int nmax, int nprob,
-                           hipStream_t s) {
-  hipLaunchKernelGGL((k_axpy<double>), grid_for(nmax, nprob), dim3(256), 0, s, y, x, a, comp_off);
-  return hipGetLastError();
-}
-hipError_t launch_axpy_f32(double* y, const float* x, const double* a, const int* comp_off, int nmax, int nprob,
-                           hipStream_t s) {
-  hipLaunchKernelGGL((k_axpy<float>), grid_for(nmax, nprob), dim3(256), 0, s, y, x, a, comp_off);
-  return hipGetLastError();
-}
 hipError_t launch_scatter_add(double* const* full, const double* c, const int* pos, const int* comp_off, int nmax,
                               int nprob, hipStream_t s, const SolveState* gate) {
   hipLaunchKernelGGL(k_scatter_add, grid_for(nmax, nprob), dim3(256), 0, s, full, c, pos, comp_off, gate, nprob);
@@ -307,11 +282,6 @@ hipError_t launch_scatter_add(double* const* full, const double* c, const int* p
 }
 hipError_t launch_ctl(const RefineArgs& a, const double* part, size_t stride, int n, bool begin, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl, dim3(a.nprob), dim3(RT), 0, s, a, part, stride, n, begin ? 1 : 0);
-  return hipGetLastError();
-}
-hipError_t launch_ctl_after(const RefineArgs& a, const double* rr_part, int nb, size_t stride, bool first,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_after, dim3(a.nprob), dim3(RT), 0, s, a, rr_part, nb, stride, first ? 1 : 0);
   return hipGetLastError();
 }
 template <typename TX>

@@ -67,10 +67,6 @@ hipError_t launch_scale_init_f32(float* out, const double* in, const double* sca
                                  float* z1, double* zu, int nmax, int nprob, hipStream_t s);
 hipError_t launch_scale_init_f64(double* out, const double* in, const double* scale, const int* comp_off, double* z0,
                                  double* z1, double* zu, int nmax, int nprob, hipStream_t s);
-hipError_t launch_axpy_f64(double* y, const double* x, const double* a, const int* comp_off, int nmax, int nprob,
-                           hipStream_t s);
-hipError_t launch_axpy_f32(double* y, const float* x, const double* a, const int* comp_off, int nmax, int nprob,
-                           hipStream_t s);
 struct SolveState;
 // gate (may be null): skip unless every one of the nprob states is done
 hipError_t launch_scatter_add(double* const* full, const double* c, const int* pos, const int* comp_off, int nmax,
@@ -81,13 +77,10 @@ hipError_t launch_scatter_add(double* const* full, const double* c, const int* p
 // unscale, tol2, cap and the CG scalars of the next inner solve; done and
 // status for problems that stop).
 hipError_t launch_ctl(const RefineArgs& a, const double* part, size_t stride, int n, bool begin, hipStream_t s);
-// After an inner solve: iterations and status from the CG scalars; a problem
-// not yet stopped whose last r.r partials (rr_part, nb per problem; may be
-// null) meet its tolerance counts as converged.
-hipError_t launch_ctl_after(const RefineArgs& a, const double* rr_part, int nb, size_t stride, bool first,
-                            hipStream_t s);
-// u += unscale x over every problem's range together with launch_ctl_after's
-// accounting (one launch).
+// After an inner solve, in one launch: u += unscale x over every problem's
+// range, and the solve's accounting (iterations and status from the CG
+// scalars; a problem not yet stopped whose last r.r partials, rr_part with nb
+// per problem or null, meet its tolerance counts as converged).
 hipError_t launch_axpy_after_f32(double* u, const float* x, const int* comp_off, const RefineArgs& a,
                                  const double* rr_part, int nb, size_t stride, bool first, int nmax, hipStream_t s);
 hipError_t launch_axpy_after_f64(double* u, const double* x, const int* comp_off, const RefineArgs& a,
