@@ -291,11 +291,13 @@ def test_batch_matches_oracle(F, prec, tol):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_identical_problems_share(F, prec):
     # problems 0, 1, 3 identical (mask and spectrum), problem 2 with its own
-    # mask: the shared set must serve 0, 1, 3 exactly as their own plans do
+    # mask: the shared set must serve 0, 1, 3 exactly as their own plans do;
+    # the default halos differ (8 and 14): each problem keeps its own
     n = 256
     P = W.damped_power_law(n, n, 3.0, n / 8, 1e-7)
     m0 = W.band_holes_mask(n, n, W.band_rows(n, 0.15), 14, 2.0, 8.0, 120)
-    m2 = W.band_holes_mask(n, n, W.band_rows(n, 0.08), 9, 2.0, 8.0, 121)
+    m2 = W.band_holes_mask(n, n, W.band_rows(n, 0.08), 9, 2.0, 8.0, 129)
+    assert B.auto_halo(m0) == 8 and B.auto_halo(m2) == 14
     masks = np.stack([m0, m0, m2, m0])
     ds = [W.observed_map(P, n, n, 130 + i, masks[i]) for i in range(4)]
     seeds = [11, 12, 13, 14]
@@ -316,6 +318,8 @@ def test_identical_problems_share(F, prec):
         pl.close()
         assert st[i]["iters_inner"] == sti["iters_inner"], i
         assert np.array_equal(xb[i], xi), (i, float(np.max(np.abs(xb[i] - xi))))
+    assert [v["halo_min"] for v in infos] == [v["halo_max"] for v in infos] == [8, 8, 14, 8]
+    assert ib["halo_min"] == 8 and ib["halo_max"] == 14
     # logical sizes add up over the problems; the stored set counts once
     assert ib["block_entries"] == sum(v["block_entries"] for v in infos)
     assert ib["band_stream_values"] == sum(v["band_stream_values"] for v in infos)
