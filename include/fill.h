@@ -424,9 +424,11 @@ void fill_plan_destroy(fill_plan plan);
  *   d_obs   device, ny*nx doubles; values on masked pixels are ignored (may be
  *           0 or NaN, Sec. 3 sets them to zero).
  *   seed    key of the white noise: Philox4x64-10, key (seed, 0x52), counter
- *           (j, 0, 0, 0) for pixel pair j = i/2 of row-major index i, two
- *           normals per block by Box-Muller (words 0,1 -> pixel 2j,
- *           words 2,3 -> pixel 2j+1, u = ((w >> 11) + 0.5) 2^-53).
+ *           (j, 0, 0, 0) for pixels 4j .. 4j+3 of row-major index i
+ *           (j = i/4), four normals per block by Box-Muller, two from each
+ *           word pair (words 0,1 -> pixels 4j, 4j+1; words 2,3 -> 4j+2,
+ *           4j+3; radius sqrt(-2 ln u_a), angle 2 pi u_b, cosine then sine;
+ *           u = ((w >> 11) + 0.5) 2^-53).
  *   x_out   device, ny*nx doubles (may not alias d_obs): observed pixels are
  *           bitwise copies of d_obs; masked pixels are s + u with s = C^{1/2} w
  *           and u = M (y - s_y).

@@ -30,10 +30,11 @@ Readings of the paper used here (ambiguous or garbled passages):
   relative to ||v||, recomputed from scratch at the end;
 * initial guess u = 0;
 * the white noise is drawn with Philox4x64-10 (Salmon et al., SC'11),
-  key = (seed, stream), counter = (j, 0, 0, 0) for the pixel pair j = i // 2
-  of row-major pixel index i; each block of four words gives two normals by
-  Box-Muller, pixel 2j from words (0, 1) and pixel 2j+1 from words (2, 3),
-  u = ((w >> 11) + 0.5) * 2^-53, n = sqrt(-2 ln u_a) cos(2 pi u_b).
+  key = (seed, stream), counter = (j, 0, 0, 0) for the pixels 4j .. 4j+3
+  (j = i // 4 of row-major pixel index i); each block of four words gives
+  four normals by Box-Muller, both outputs of each word pair: words (0, 1)
+  give pixels 4j, 4j+1 and words (2, 3) pixels 4j+2, 4j+3 as r cos t and
+  r sin t, u = ((w >> 11) + 0.5) * 2^-53, r = sqrt(-2 ln u_a), t = 2 pi u_b.
 """
 
 from __future__ import annotations
@@ -106,15 +107,21 @@ def _unit_open(w: np.ndarray) -> np.ndarray:
 
 
 def white_noise(nx: int, ny: int, seed: int, stream: int = REALIZATION_STREAM) -> np.ndarray:
-    """w ~ N(0, I) on the (ny, nx) grid, from the counter-based generator above."""
+    """w ~ N(0, I) on the (ny, nx) grid, from the counter-based generator
+    above: block j (counter (j, 0, 0, 0)) gives pixels 4j .. 4j+3, two by
+    Box-Muller from each pair of its words (radius from the first, angle from
+    the second: the cosine and the sine)."""
     n = nx * ny
-    assert n % 2 == 0
-    j = np.arange(n // 2, dtype=np.uint64)
+    assert n % 4 == 0
+    j = np.arange(n // 4, dtype=np.uint64)
     z = np.zeros_like(j)
     w0, w1, w2, w3 = philox4x64_10(j, z, z, z, np.uint64(seed), np.uint64(stream))
     out = np.empty(n, dtype=np.float64)
-    out[0::2] = np.sqrt(-2.0 * np.log(_unit_open(w0))) * np.cos(2.0 * np.pi * _unit_open(w1))
-    out[1::2] = np.sqrt(-2.0 * np.log(_unit_open(w2))) * np.cos(2.0 * np.pi * _unit_open(w3))
+    for k, (wa, wb) in enumerate(((w0, w1), (w2, w3))):
+        r = np.sqrt(-2.0 * np.log(_unit_open(wa)))
+        th = 2.0 * np.pi * _unit_open(wb)
+        out[2 * k::4] = r * np.cos(th)
+        out[2 * k + 1::4] = r * np.sin(th)
     return out.reshape(ny, nx)
 
 

@@ -416,15 +416,16 @@ __device__ __forceinline__ double unit_open(uint64_t w) {
   return ((double)(w >> 11) + 0.5) * 0x1.0p-53;
 }
 
-// Standard normal at row-major pixel index i for (seed, stream).
-// Box-Muller: one standard normal from two 64-bit words.
-__device__ __forceinline__ double box_muller(uint64_t a, uint64_t b) {
-  return sqrt(-2.0 * log(unit_open(a))) * cos(2.0 * 3.14159265358979323846 * unit_open(b));
-}
-
-__device__ __forceinline__ double white_noise_at(uint64_t i, uint64_t seed, uint64_t stream) {
-  const u64x4 w = philox4x64_10(i >> 1, 0, 0, 0, seed, stream);
-  return (i & 1) ? box_muller(w.w2, w.w3) : box_muller(w.w0, w.w1);
+// Box-Muller: two independent standard normals from two 64-bit words, the
+// radius from the first and the angle from the second (*c: the cosine one,
+// *s: the sine one).  Pixels 4j .. 4j+3 come from Philox block j: words 0, 1
+// give 4j (cosine) and 4j+1 (sine), words 2, 3 give 4j+2 and 4j+3.
+__device__ __forceinline__ void box_muller2(uint64_t a, uint64_t b, double* c, double* s) {
+  const double r = sqrt(-2.0 * log(unit_open(a)));
+  double sn, cs;
+  sincos(2.0 * 3.14159265358979323846 * unit_open(b), &sn, &cs);
+  *c = r * cs;
+  *s = r * sn;
 }
 
 // ---------------------------------------------------------------------------

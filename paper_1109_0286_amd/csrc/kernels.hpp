@@ -711,13 +711,20 @@ __global__ __launch_bounds__((RowCfg<T, N>::THREADS)) void r2c_kernel(RowArgs<T>
     }
     tw_stage<PL>(twq, a.tw, t, NT);  // after the row loads: one round trip for both
   } else {
-    // white noise: pixels 2j and 2j+1 share one Philox block, so each thread
-    // draws whole pairs of the row block into LDS, then takes its elements
-    const uint64_t pair0 = ((uint64_t)y0 * a.nx) >> 1;  // nx is even
-    for (int j = t; j < ROWS * N / 2; j += NT) {
-      const u64x4 w = philox4x64_10(pair0 + j, 0, 0, 0, a.seed, a.stream);
-      ldr[2 * j] = (T)box_muller(w.w0, w.w1);
-      ldr[2 * j + 1] = (T)box_muller(w.w2, w.w3);
+    // white noise: pixels 4j .. 4j+3 share one Philox block (two Box-Muller
+    // pairs), so each thread draws whole blocks of the row block into LDS,
+    // then takes its elements
+    static_assert((ROWS * N) % 4 == 0, "noise blocks of four pixels");
+    const uint64_t blk0 = ((uint64_t)y0 * a.nx) >> 2;  // rows of 4k pixels start a block
+    for (int j = t; j < ROWS * N / 4; j += NT) {
+      const u64x4 w = philox4x64_10(blk0 + j, 0, 0, 0, a.seed, a.stream);
+      double n0, n1, n2, n3;
+      box_muller2(w.w0, w.w1, &n0, &n1);
+      box_muller2(w.w2, w.w3, &n2, &n3);
+      ldr[4 * j] = (T)n0;
+      ldr[4 * j + 1] = (T)n1;
+      ldr[4 * j + 2] = (T)n2;
+      ldr[4 * j + 3] = (T)n3;
     }
     tw_stage<PL>(twq, a.tw, t, NT);
     __syncthreads();

@@ -62,31 +62,41 @@ def test_white_noise_is_standard_normal():
     assert abs(w.mean()) < 5 / np.sqrt(w.size)
     assert abs(w.var() - 1) < 5 * np.sqrt(2 / w.size)
     assert st.kstest(w.ravel(), "norm").pvalue > 1e-4
-    # the two pixels of a pair come from different words
+    # the two pixels of a Box-Muller pair (cosine and sine of one angle) and
+    # the two pairs of a block are uncorrelated
     c = np.corrcoef(w.ravel()[0::2], w.ravel()[1::2])[0, 1]
     assert abs(c) < 5 / np.sqrt(w.size / 2)
+    c4 = np.corrcoef(w.ravel()[0::4], w.ravel()[2::4])[0, 1]
+    assert abs(c4) < 5 / np.sqrt(w.size / 4)
+    # squares of a pair: r^2 (cos^2 + sin^2) = -2 ln u is exponential with mean 2
+    q = w.ravel()[0::2] ** 2 + w.ravel()[1::2] ** 2
+    assert st.kstest(q / 2.0, "expon").pvalue > 1e-4
     # different seeds are uncorrelated
     c2 = np.corrcoef(w.ravel(), O.white_noise(256, 128, seed=8).ravel())[0, 1]
     assert abs(c2) < 5 / np.sqrt(w.size)
 
 
 def _white_noise_pin_error(noise=None):
-    """Largest deviation of white_noise from pixels 2j, 2j+1 recomputed one by
-    one from numpy's independent Philox words (counter one behind, see above)
-    with the math module's log and cos, relative to max(1, |value|)."""
+    """Largest deviation of white_noise from pixels 4j .. 4j+3 recomputed one
+    by one from numpy's independent Philox words (counter one behind, see
+    above) with the math module's log, cos and sin, relative to
+    max(1, |value|)."""
     import math
     nx, ny, seed = 64, 32, 2 ** 61 + 11
     w = (noise or O.white_noise)(nx, ny, seed).ravel()
     worst = 0.0
-    # (pair 0 is out of reach: numpy's counter -1 carries into its second word)
-    for j in (1, 2, 517, nx * ny // 2 - 1):
+    # (block 0 is out of reach: numpy's counter -1 carries into its second word)
+    for j in (1, 2, 257, nx * ny // 4 - 1):
         bg = np.random.Philox(key=np.array([seed, O.REALIZATION_STREAM], dtype=np.uint64),
                               counter=np.array([j - 1, 0, 0, 0], dtype=np.uint64))
         words = [int(v) for v in bg.random_raw(4)]
         u = [((x >> 11) + 0.5) * 2.0 ** -53 for x in words]
-        a = math.sqrt(-2.0 * math.log(u[0])) * math.cos(2.0 * math.pi * u[1])
-        b = math.sqrt(-2.0 * math.log(u[2])) * math.cos(2.0 * math.pi * u[3])
-        worst = max(worst, abs(w[2 * j] - a) / max(1.0, abs(a)), abs(w[2 * j + 1] - b) / max(1.0, abs(b)))
+        want = []
+        for a, b in ((0, 1), (2, 3)):
+            r, th = math.sqrt(-2.0 * math.log(u[a])), 2.0 * math.pi * u[b]
+            want += [r * math.cos(th), r * math.sin(th)]
+        for k in range(4):
+            worst = max(worst, abs(w[4 * j + k] - want[k]) / max(1.0, abs(want[k])))
     return worst
 
 
@@ -354,20 +364,26 @@ def test_mutation_missing_normalisation_is_caught(monkeypatch):
 
 
 def test_mutation_white_noise_mapping_is_caught():
-    # sin for cos, or the word pairs of the two pixels swapped, fail the exact pin
-    def noise(nx, ny, seed, swap=False, sin=False):
-        j = np.arange(nx * ny // 2, dtype=np.uint64)
+    # cosine and sine exchanged, the word pairs of a block swapped, or radius
+    # and angle words exchanged: each fails the exact pin
+    def noise(nx, ny, seed, swap=False, trig=False, ra=False):
+        j = np.arange(nx * ny // 4, dtype=np.uint64)
         z = np.zeros_like(j)
-        w0, w1, w2, w3 = O.philox4x64_10(j, z, z, z, np.uint64(seed), np.uint64(O.REALIZATION_STREAM))
+        w = list(O.philox4x64_10(j, z, z, z, np.uint64(seed), np.uint64(O.REALIZATION_STREAM)))
         if swap:
-            w0, w1, w2, w3 = w2, w3, w0, w1
-        un = [((x >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53 for x in (w0, w1, w2, w3)]
-        trig = np.sin if sin else np.cos
+            w = [w[2], w[3], w[0], w[1]]
+        if ra:
+            w = [w[1], w[0], w[3], w[2]]
+        un = [((x >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53 for x in w]
+        f0, f1 = (np.sin, np.cos) if trig else (np.cos, np.sin)
         out = np.empty(nx * ny)
-        out[0::2] = np.sqrt(-2.0 * np.log(un[0])) * trig(2.0 * np.pi * un[1])
-        out[1::2] = np.sqrt(-2.0 * np.log(un[2])) * trig(2.0 * np.pi * un[3])
+        for k in range(2):
+            r, th = np.sqrt(-2.0 * np.log(un[2 * k])), 2.0 * np.pi * un[2 * k + 1]
+            out[2 * k::4] = r * f0(th)
+            out[2 * k + 1::4] = r * f1(th)
         return out.reshape(ny, nx)
 
     assert _white_noise_pin_error(noise) <= 4e-16  # the helper's own control
-    assert _white_noise_pin_error(lambda a, b, c: noise(a, b, c, sin=True)) > 1e-3
+    assert _white_noise_pin_error(lambda a, b, c: noise(a, b, c, trig=True)) > 1e-3
+    assert _white_noise_pin_error(lambda a, b, c: noise(a, b, c, ra=True)) > 1e-3
     assert _white_noise_pin_error(lambda a, b, c: noise(a, b, c, swap=True)) > 1e-3
